@@ -1,0 +1,242 @@
+/*
+ * pssgp -- parallel state-space Gaussian-process regression on MI355X (gfx950).
+ *
+ * C ABI of libpssgp.so. Implements the method of "Temporal Gaussian Process
+ * Regression in Logarithmic Time" (Corenflos, Zhao, Sarkka): a temporal GP
+ * with a state-space covariance (section 2, eq. ssmodel) is discretised per
+ * time step (section 4.3, eq. ss-gp-formation of the supplement), the Kalman
+ * filter is run as a parallel prefix scan over the associative elements
+ * (A, b, C, eta, J) with missing measurements (section 3), the RTS smoother
+ * as a reverse scan over (E, g, L) (supplement, Proposition 2), and the
+ * log-likelihood and its gradient are reduced on the device.
+ *
+ * Conventions shared by every entry point:
+ *  - Return value: 0 on success, a negative PSSGP_E* code on an argument
+ *    error (detected on the host, nothing is launched; see
+ *    pssgp_last_error()). Faults found in the data on the device (unsorted
+ *    times, non-finite inputs, a non-positive innovation variance, a failed
+ *    Cholesky factorisation) set bits of the status word in the workspace,
+ *    read with pssgp_status().
+ *  - Pointers named t, y, mask, noise_k, m, P, f_mean, f_var, F, Q, loglik,
+ *    grad, ws and offsets are DEVICE pointers; pssgp_model, pssgp_options
+ *    and the small host arrays named *_host are HOST memory. The caller owns
+ *    every buffer; the library allocates nothing per call.
+ *  - stream is a hipStream_t (NULL = the default stream). Calls are ordered
+ *    on that stream and do not synchronise, except pssgp_status().
+ *  - Time stamps t are FP64 and non-decreasing (equal times are allowed:
+ *    a zero step has F = I, Q = 0). Test points are steps with mask 0
+ *    (missing measurement, section 3); y there is ignored and may be NaN.
+ *  - dtype selects the scan precision: PSSGP_F32 keeps the discretisation
+ *    and element construction in FP64 and runs the scans in FP32 with a
+ *    compensated FP32 log-likelihood sum reduced across tiles in FP64;
+ *    PSSGP_F64 runs everything in FP64. y, m, P, f_mean, f_var use dtype.
+ *  - State moments are in the library's state coordinates:
+ *    x_canonical = diag(T) z with T from pssgp_state_basis(), where the
+ *    canonical coordinates are the companion form (f, f', f'', ...) of
+ *    each kernel component, concatenated for sums.
+ *  - Covariances are stored packed: entry e of the upper triangle in
+ *    row-major order ((0,0), (0,1), ..., (0,d-1), (1,1), ...), and arrays of
+ *    per-step quantities are entry-major: X[e * n + k].
+ *  - The workspace (ws, ws_bytes) must hold pssgp_workspace_bytes() bytes
+ *    for the same model, n, dtype, operation and options; its contents
+ *    need no initialisation and are scratch after the call, except the
+ *    status word.
+ *  - Calls that share a workspace must not overlap in time.
+ */
+#ifndef PSSGP_H
+#define PSSGP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    PSSGP_OK = 0,
+    PSSGP_EINVAL = -1,       /* bad argument (NULL pointer, n < 0, bad dtype, ...) */
+    PSSGP_EUNSUPPORTED = -2, /* model shape not compiled in (see pssgp_model) */
+    PSSGP_EWORKSPACE = -3,   /* workspace too small */
+    PSSGP_EDEVICE = -4,      /* HIP runtime error */
+    PSSGP_ENODEVICE = -5,    /* no HIP device */
+    PSSGP_EMODEL = -6        /* hyperparameters out of range */
+};
+
+/* Kernel components (paper section 2: Matern covariances have an exact
+ * state-space form; the RBF covariance is approximated in the spectral
+ * domain by a Taylor series of the given order, section 5.1 uses order 6). */
+enum { PSSGP_MATERN12 = 1, PSSGP_MATERN32 = 2, PSSGP_MATERN52 = 3, PSSGP_RBF = 4 };
+
+typedef struct pssgp_component {
+    int32_t kind;        /* PSSGP_MATERN12/32/52 or PSSGP_RBF */
+    int32_t order;       /* RBF: Taylor order = state size, 1..6; ignored otherwise */
+    double lengthscale;  /* > 0 */
+    double variance;     /* > 0 */
+} pssgp_component;
+
+/* Sum of 1 or 2 components, total state size d <= 8 (e.g. Matern-3/2 +
+ * RBF order 6 gives d = 8); noise_var > 0 is the measurement noise
+ * variance sigma_n^2 of eq. gp-def (a per-step variance can be passed as
+ * noise_k instead). */
+typedef struct pssgp_model {
+    int32_t n_comp;
+    int32_t reserved;
+    pssgp_component comp[4];
+    double noise_var;
+} pssgp_model;
+
+typedef enum { PSSGP_F32 = 0, PSSGP_F64 = 1 } pssgp_dtype;
+
+typedef struct pssgp_options {
+    uint32_t chunk;          /* steps per lane, 0 = default (16); 1..64 */
+    uint32_t deterministic;  /* 1: every tile waits for its predecessor's inclusive
+                                prefix, making results bitwise reproducible */
+    uint32_t reserved[6];
+} pssgp_options;
+
+typedef enum {
+    PSSGP_OP_FILTER = 1,
+    PSSGP_OP_SMOOTH = 2,
+    PSSGP_OP_LOGLIK = 3,
+    PSSGP_OP_LOGLIK_GRAD = 4,
+    PSSGP_OP_DISCRETIZE = 5
+} pssgp_op;
+
+/* Status word bits set on the device. */
+enum {
+    PSSGP_STATUS_UNSORTED = 1u,     /* t[k] < t[k-1] */
+    PSSGP_STATUS_NONFINITE = 2u,    /* NaN/Inf in t or an observed y */
+    PSSGP_STATUS_BAD_S = 4u,        /* innovation variance <= 0 or not finite */
+    PSSGP_STATUS_CHOLESKY = 8u      /* smoother: predicted covariance not positive definite */
+};
+
+/* Library version (major * 10000 + minor * 100 + patch). */
+int pssgp_version(void);
+
+/* Message of the last error returned on this host thread (never NULL). */
+const char *pssgp_last_error(void);
+
+/* State size d of the model, or a negative error code. */
+int pssgp_state_dim(const pssgp_model *model);
+
+/* Diagonal basis change of the library's state coordinates:
+ * x_canonical = diag(tdiag_host) z; tdiag_host has d entries (host). */
+int pssgp_state_basis(const pssgp_model *model, double *tdiag_host);
+
+/* The continuous model in the library's state coordinates (host arrays):
+ * generator G (d*d row-major), stationary covariance Pinf (d*d) and
+ * observation row H (d), i.e. dx/dt = G x + L w, f = H x with
+ * G Pinf + Pinf G^T + L Qc L^T = 0 (paper section 2, eq. ssmodel, and
+ * section 4.1). Any pointer may be NULL. For inspection and tests; the
+ * kernels build the same matrices internally. */
+int pssgp_model_matrices(const pssgp_model *model, double *G_host, double *Pinf_host, double *H_host);
+
+/* Bytes of workspace needed by operation op (pssgp_op) for n steps. */
+size_t pssgp_workspace_bytes(const pssgp_model *model, int64_t n, pssgp_dtype dtype, int op,
+                             const pssgp_options *opts);
+
+/*
+ * Discretisation (supplement, eq. ss-gp-formation; paper section 4.3):
+ * for every step k >= 1, F[k] = exp((t[k] - t[k-1]) G) and
+ * Q[k] = int_0^dt exp(sG) L Qc L^T exp(sG)^T ds, computed in FP64 as
+ * Q = Pinf - F Pinf F^T (stationarity). Step 0 has no predecessor and gets
+ * F[0] = 0, Q[0] = Pinf, the first filter element of section 3.
+ * F: device double[n][d][d] row-major; Q: device double[NS][n] packed
+ * entry-major (NS = d(d+1)/2). Workspace: pssgp_workspace_bytes(...,
+ * PSSGP_OP_DISCRETIZE) (holds the status word).
+ */
+int pssgp_discretize(const pssgp_model *model, const double *t, int64_t n, double *F, double *Q,
+                     void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Parallel Kalman filter (section 3): builds the elements (A, b, C, eta, J)
+ * of every step (missing steps: A = F, b = 0, C = Q, eta = J = 0; observed:
+ * supplement proof of Proposition 1; step 0: A = 0), runs one decoupled
+ * look-back prefix scan with the filtering operator, and returns the
+ * filter means m (device dtype[d][n], entry-major) and covariances P
+ * (device dtype[NS][n], packed entry-major): b*_k and C*_k, Proposition 1.
+ * m and P may be NULL (log-likelihood only). loglik (device double[1],
+ * nullable) receives sum over observed steps of
+ * -1/2 (log 2 pi + log S_k + v_k^2 / S_k) with the innovation v_k and its
+ * variance S_k (prediction-error decomposition). noise_k (device
+ * double[n], nullable) overrides model->noise_var per step (eq. gp-def).
+ */
+int pssgp_filter(const pssgp_model *model, const double *t, const void *y, const uint8_t *mask,
+                 const double *noise_k, int64_t n, pssgp_dtype dtype, void *m, void *P,
+                 double *loglik, void *ws, size_t ws_bytes, const pssgp_options *opts,
+                 void *stream);
+
+/*
+ * Parallel RTS smoother (supplement, eq. smoother and Proposition 2): from
+ * the filter moments (m, P) of pssgp_filter, builds (E_k, g_k, L_k)
+ * (E_k = P_k F_k^T (F_k P_k F_k^T + Q_k)^-1, g_k = m_k - E_k F_k m_k,
+ * L_k = P_k - E_k F_k P_k, last step (0, m, P)), runs one reverse
+ * decoupled look-back scan and writes the posterior mean and variance of
+ * f = H x at every step (f_mean, f_var: device dtype[n]) -- at the test
+ * (missing) steps these are the GP predictions (supplement, Lemma 1). ms,
+ * Ps (nullable) receive the full smoothed state moments in the layout of
+ * m, P.
+ */
+int pssgp_smooth(const pssgp_model *model, const double *t, const void *m, const void *P,
+                 int64_t n, pssgp_dtype dtype, void *f_mean, void *f_var, void *ms, void *Ps,
+                 void *ws, size_t ws_bytes, const pssgp_options *opts, void *stream);
+
+/* Log-likelihood only: pssgp_filter without state outputs. */
+int pssgp_loglik(const pssgp_model *model, const double *t, const void *y, const uint8_t *mask,
+                 const double *noise_k, int64_t n, pssgp_dtype dtype, double *loglik, void *ws,
+                 size_t ws_bytes, const pssgp_options *opts, void *stream);
+
+/*
+ * Log-likelihood and its gradient (the paper differentiates the parallel
+ * filter by automatic differentiation, sections 2 and 4.4 item 6; here a
+ * hand-written reverse-mode adjoint): a forward filter scan that stores one
+ * (m, P) checkpoint per lane chunk, then a reverse scan over the affine
+ * adjoint maps (mbar_k, Pbar_k) -> (mbar_{k-1}, Pbar_{k-1}) that recomputes
+ * the forward quantities from the checkpoints and contracts them with the
+ * parameter derivatives of F, Q, Pinf and R. grad (device double[2 n_comp
+ * + 1]) receives d loglik / d (ell_0, var_0, ell_1, var_1, ..., noise_var).
+ * noise_k must be NULL (the noise-variance derivative is for the scalar
+ * noise_var).
+ */
+int pssgp_loglik_grad(const pssgp_model *model, const double *t, const void *y,
+                      const uint8_t *mask, int64_t n, pssgp_dtype dtype, double *loglik,
+                      double *grad, void *ws, size_t ws_bytes, const pssgp_options *opts,
+                      void *stream);
+
+/*
+ * Batched form: n_series independent series concatenated along the time
+ * axis, series s occupying steps [offsets[s], offsets[s+1]) (offsets:
+ * device int64[n_series + 1], offsets[0] = 0, non-decreasing;
+ * offsets_host: the same values in host memory, used to lay out the
+ * launch). models_host[s] is series s's model; all series must have the
+ * same state size and component kinds (their hyperparameters and noise may
+ * differ). One launch processes all series: a series start is a filter
+ * element with A = 0 and a series end a smoother element with E = 0, so the
+ * scans restart at series boundaries without segment flags. loglik: device
+ * double[n_series]. Outputs as in pssgp_filter / pssgp_smooth at the
+ * concatenated positions.
+ */
+int pssgp_batched_filter(const pssgp_model *models_host, int64_t n_series, const int64_t *offsets,
+                         const int64_t *offsets_host, const double *t, const void *y,
+                         const uint8_t *mask, pssgp_dtype dtype, void *m, void *P, double *loglik,
+                         void *ws, size_t ws_bytes, const pssgp_options *opts, void *stream);
+
+int pssgp_batched_smooth(const pssgp_model *models_host, int64_t n_series, const int64_t *offsets,
+                         const int64_t *offsets_host, const double *t, const void *m,
+                         const void *P, pssgp_dtype dtype, void *f_mean, void *f_var, void *ws,
+                         size_t ws_bytes, const pssgp_options *opts, void *stream);
+
+size_t pssgp_batched_workspace_bytes(const pssgp_model *models_host, int64_t n_series,
+                                     int64_t n_total, pssgp_dtype dtype, int op,
+                                     const pssgp_options *opts);
+
+/* Status word of the most recent call that used workspace ws (read after
+ * synchronising stream); bits: PSSGP_STATUS_*. */
+int pssgp_status(void *ws, void *stream, uint32_t *bits_host);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PSSGP_H */

@@ -1,0 +1,396 @@
+"""Parallel state-space GP regression on MI355X: Python binding of libpssgp.so.
+
+Temporal Gaussian-process regression in logarithmic span (Corenflos, Zhao,
+Sarkka): the GP is written as a linear SDE, discretised per time step, and
+the Kalman filter and RTS smoother run as parallel prefix scans over their
+associative elements; test points are missing measurements on the merged
+time grid. Every step of the computation runs in the HIP kernels of
+``libpssgp.so``; this module only marshals torch tensors (device memory and
+the current stream) into the C ABI of ``include/pssgp.h``. Importing works
+without a GPU; the calls need a HIP device and raise otherwise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpssgp.so")
+
+MATERN12, MATERN32, MATERN52, RBF = 1, 2, 3, 4
+F32, F64 = 0, 1
+OP_FILTER, OP_SMOOTH, OP_LOGLIK, OP_LOGLIK_GRAD, OP_DISCRETIZE = 1, 2, 3, 4, 5
+STATUS_UNSORTED, STATUS_NONFINITE, STATUS_BAD_S, STATUS_CHOLESKY = 1, 2, 4, 8
+
+_ERRORS = {-1: "EINVAL", -2: "EUNSUPPORTED", -3: "EWORKSPACE", -4: "EDEVICE", -5: "ENODEVICE",
+           -6: "EMODEL"}
+
+
+class PssgpError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (_ERRORS.get(code, "?"), code, msg))
+        self.code = code
+
+
+class Component(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("lengthscale", ctypes.c_double), ("variance", ctypes.c_double)]
+
+
+class Model(ctypes.Structure):
+    _fields_ = [("n_comp", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("comp", Component * 4), ("noise_var", ctypes.c_double)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("chunk", ctypes.c_uint32), ("deterministic", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 6)]
+
+
+_lib = None
+
+# (name, restype, argtypes) of every exported entry point
+_VP, _I64, _SZ = ctypes.c_void_p, ctypes.c_int64, ctypes.c_size_t
+_MP = ctypes.POINTER(Model)
+_OP = ctypes.POINTER(Options)
+SIGNATURES = [
+    ("pssgp_version", ctypes.c_int, []),
+    ("pssgp_last_error", ctypes.c_char_p, []),
+    ("pssgp_state_dim", ctypes.c_int, [_MP]),
+    ("pssgp_state_basis", ctypes.c_int, [_MP, _VP]),
+    ("pssgp_model_matrices", ctypes.c_int, [_MP, _VP, _VP, _VP]),
+    ("pssgp_workspace_bytes", _SZ, [_MP, _I64, ctypes.c_int, ctypes.c_int, _OP]),
+    ("pssgp_discretize", ctypes.c_int, [_MP, _VP, _I64, _VP, _VP, _VP, _SZ, _VP]),
+    ("pssgp_filter", ctypes.c_int, [_MP, _VP, _VP, _VP, _VP, _I64, ctypes.c_int, _VP, _VP, _VP, _VP,
+                                    _SZ, _OP, _VP]),
+    ("pssgp_smooth", ctypes.c_int, [_MP, _VP, _VP, _VP, _I64, ctypes.c_int, _VP, _VP, _VP, _VP, _VP,
+                                    _SZ, _OP, _VP]),
+    ("pssgp_loglik", ctypes.c_int, [_MP, _VP, _VP, _VP, _VP, _I64, ctypes.c_int, _VP, _VP, _SZ, _OP,
+                                    _VP]),
+    ("pssgp_loglik_grad", ctypes.c_int, [_MP, _VP, _VP, _VP, _I64, ctypes.c_int, _VP, _VP, _VP, _SZ,
+                                         _OP, _VP]),
+    ("pssgp_batched_filter", ctypes.c_int, [_MP, _I64, _VP, _VP, _VP, _VP, _VP, ctypes.c_int, _VP, _VP,
+                                            _VP, _VP, _SZ, _OP, _VP]),
+    ("pssgp_batched_smooth", ctypes.c_int, [_MP, _I64, _VP, _VP, _VP, _VP, _VP, ctypes.c_int, _VP, _VP,
+                                            _VP, _SZ, _OP, _VP]),
+    ("pssgp_batched_workspace_bytes", _SZ, [_MP, _I64, _I64, ctypes.c_int, ctypes.c_int, _OP]),
+    ("pssgp_status", ctypes.c_int, [_VP, _VP, ctypes.POINTER(ctypes.c_uint32)]),
+]
+
+
+def lib() -> ctypes.CDLL:
+    """Load libpssgp.so (built by ``build()``); fails loudly when absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libpssgp.so is not built (run paper_2102_09964_amd.build.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            f = getattr(L, name)  # AttributeError: the library misses an entry point
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def build():
+    from .build import build as _b
+    return _b()
+
+
+def _check(rc):
+    if rc != 0:
+        raise PssgpError(rc, lib().pssgp_last_error().decode())
+
+
+def make_model(components, noise_var) -> Model:
+    """components: list of (kind, order, lengthscale, variance)."""
+    m = Model()
+    m.n_comp = len(components)
+    if not 1 <= m.n_comp <= 4:
+        raise ValueError("1 to 4 components")
+    for i, (kind, order, ell, var) in enumerate(components):
+        m.comp[i].kind = int(kind)
+        m.comp[i].order = int(order)
+        m.comp[i].lengthscale = float(ell)
+        m.comp[i].variance = float(var)
+    m.noise_var = float(noise_var)
+    return m
+
+
+def _as_model(model):
+    if isinstance(model, Model):
+        return model
+    if isinstance(model, dict):
+        return make_model(model["components"], model["noise_var"])
+    raise TypeError("model must be a Model or a dict with 'components' and 'noise_var'")
+
+
+def make_options(chunk=0, deterministic=False) -> Options:
+    o = Options()
+    o.chunk = int(chunk)
+    o.deterministic = 1 if deterministic else 0
+    return o
+
+
+def state_dim(model) -> int:
+    d = lib().pssgp_state_dim(ctypes.byref(_as_model(model)))
+    if d < 0:
+        _check(d)
+    return d
+
+
+def state_basis(model) -> np.ndarray:
+    """Diagonal T with x_canonical = diag(T) z for the library's state z."""
+    m = _as_model(model)
+    d = state_dim(m)
+    out = np.empty(d)
+    _check(lib().pssgp_state_basis(ctypes.byref(m), out.ctypes.data))
+    return out
+
+
+def model_matrices(model):
+    """(G, Pinf, H) of the continuous model in the library's coordinates."""
+    m = _as_model(model)
+    d = state_dim(m)
+    G, P, H = np.empty((d, d)), np.empty((d, d)), np.empty(d)
+    _check(lib().pssgp_model_matrices(ctypes.byref(m), G.ctypes.data, P.ctypes.data, H.ctypes.data))
+    return G, P, H
+
+
+def workspace_bytes(model, n, dtype, op, options=None) -> int:
+    return int(lib().pssgp_workspace_bytes(ctypes.byref(_as_model(model)), int(n), int(dtype), int(op),
+                                           ctypes.byref(options) if options is not None else None))
+
+
+# ---------------------------------------------------------------- torch helpers
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dt(dtype):
+    torch = _torch()
+    if dtype in (F32, torch.float32, "f32", "float32"):
+        return F32, torch.float32
+    if dtype in (F64, torch.float64, "f64", "float64"):
+        return F64, torch.float64
+    raise ValueError("dtype must be float32 or float64")
+
+
+def _stream():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _p(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dev(x, dtype, device):
+    torch = _torch()
+    if x is None:
+        return None
+    if isinstance(x, torch.Tensor):
+        return x.to(device=device, dtype=dtype).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device=device)
+
+
+def _require_gpu():
+    torch = _torch()
+    if not torch.cuda.is_available():
+        raise PssgpError(-5, "no HIP device: the pssgp kernels need an MI355X")
+
+
+def alloc_workspace(model, n, dtype, op, options=None, device="cuda"):
+    torch = _torch()
+    nb = workspace_bytes(model, n, dtype, op, options)
+    if nb == 0:
+        _check(-1)
+    return torch.empty(nb, dtype=torch.uint8, device=device)
+
+
+def status(ws) -> int:
+    """Device status bits of the last call that used workspace ws (syncs)."""
+    bits = ctypes.c_uint32(0)
+    _check(lib().pssgp_status(_p(ws), _stream(), ctypes.byref(bits)))
+    return bits.value
+
+
+def discretize(model, t, device="cuda"):
+    """F: (n, d, d) float64, Q: (NS, n) float64 packed upper (library basis)."""
+    _require_gpu()
+    torch = _torch()
+    m = _as_model(model)
+    d = state_dim(m)
+    t = _dev(t, torch.float64, device)
+    n = t.shape[0]
+    F = torch.empty((n, d, d), dtype=torch.float64, device=device)
+    Q = torch.empty((d * (d + 1) // 2, n), dtype=torch.float64, device=device)
+    ws = alloc_workspace(m, n, F64, OP_DISCRETIZE, device=device)
+    _check(lib().pssgp_discretize(ctypes.byref(m), _p(t), n, _p(F), _p(Q), _p(ws), ws.numel(), _stream()))
+    return F, Q
+
+
+def filter(model, t, y, mask=None, noise_k=None, dtype="float32", moments=True, options=None,
+           ws=None, device="cuda"):
+    """Parallel Kalman filter. Returns dict with 'loglik' (float64 tensor [1])
+    and, if moments, 'm' (d, n) and 'P' (NS, n) packed upper, entry-major."""
+    _require_gpu()
+    torch = _torch()
+    m = _as_model(model)
+    code, tdt = _dt(dtype)
+    d = state_dim(m)
+    t = _dev(t, torch.float64, device)
+    n = t.shape[0]
+    y = _dev(y, tdt, device)
+    mask = _dev(mask, torch.uint8, device)
+    noise_k = _dev(noise_k, torch.float64, device)
+    op = OP_FILTER if moments else OP_LOGLIK
+    if ws is None:
+        ws = alloc_workspace(m, n, code, op, options, device)
+    out = {"loglik": torch.empty(1, dtype=torch.float64, device=device), "ws": ws}
+    if moments:
+        out["m"] = torch.empty((d, n), dtype=tdt, device=device)
+        out["P"] = torch.empty((d * (d + 1) // 2, n), dtype=tdt, device=device)
+        rc = lib().pssgp_filter(ctypes.byref(m), _p(t), _p(y), _p(mask), _p(noise_k), n, code,
+                                _p(out["m"]), _p(out["P"]), _p(out["loglik"]), _p(ws), ws.numel(),
+                                ctypes.byref(options) if options is not None else None, _stream())
+    else:
+        rc = lib().pssgp_loglik(ctypes.byref(m), _p(t), _p(y), _p(mask), _p(noise_k), n, code,
+                                _p(out["loglik"]), _p(ws), ws.numel(),
+                                ctypes.byref(options) if options is not None else None, _stream())
+    _check(rc)
+    return out
+
+
+def smooth(model, t, m_f, P_f, dtype="float32", full_state=False, options=None, ws=None, device="cuda"):
+    """Parallel RTS smoother from filter moments. Returns dict with 'f_mean',
+    'f_var' (n,) and, if full_state, 'ms' (d, n), 'Ps' (NS, n)."""
+    _require_gpu()
+    torch = _torch()
+    mdl = _as_model(model)
+    code, tdt = _dt(dtype)
+    d = state_dim(mdl)
+    t = _dev(t, torch.float64, device)
+    n = t.shape[0]
+    m_f = _dev(m_f, tdt, device)
+    P_f = _dev(P_f, tdt, device)
+    if ws is None:
+        ws = alloc_workspace(mdl, n, code, OP_SMOOTH, options, device)
+    out = {"f_mean": torch.empty(n, dtype=tdt, device=device),
+           "f_var": torch.empty(n, dtype=tdt, device=device), "ws": ws}
+    ms = Ps = None
+    if full_state:
+        ms = out["ms"] = torch.empty((d, n), dtype=tdt, device=device)
+        Ps = out["Ps"] = torch.empty((d * (d + 1) // 2, n), dtype=tdt, device=device)
+    _check(lib().pssgp_smooth(ctypes.byref(mdl), _p(t), _p(m_f), _p(P_f), n, code, _p(out["f_mean"]),
+                              _p(out["f_var"]), _p(ms), _p(Ps), _p(ws), ws.numel(),
+                              ctypes.byref(options) if options is not None else None, _stream()))
+    return out
+
+
+def predict(model, t, y, mask=None, dtype="float32", options=None, device="cuda"):
+    """Filter + smoother on a merged grid (test points: mask 0). Returns
+    dict with 'f_mean', 'f_var', 'loglik'."""
+    f = filter(model, t, y, mask, dtype=dtype, options=options, device=device)
+    s = smooth(model, t, f["m"], f["P"], dtype=dtype, options=options, device=device)
+    return {"f_mean": s["f_mean"], "f_var": s["f_var"], "loglik": f["loglik"], "m": f["m"], "P": f["P"]}
+
+
+def loglik(model, t, y, mask=None, noise_k=None, dtype="float32", options=None, device="cuda"):
+    return filter(model, t, y, mask, noise_k, dtype, moments=False, options=options, device=device)["loglik"]
+
+
+def loglik_grad(model, t, y, mask=None, dtype="float32", options=None, ws=None, device="cuda"):
+    """Log-likelihood and its gradient with respect to
+    (ell_0, var_0, ell_1, var_1, ..., noise_var)."""
+    _require_gpu()
+    torch = _torch()
+    m = _as_model(model)
+    code, tdt = _dt(dtype)
+    t = _dev(t, torch.float64, device)
+    n = t.shape[0]
+    y = _dev(y, tdt, device)
+    mask = _dev(mask, torch.uint8, device)
+    if ws is None:
+        ws = alloc_workspace(m, n, code, OP_LOGLIK_GRAD, options, device)
+    ll = torch.empty(1, dtype=torch.float64, device=device)
+    g = torch.empty(2 * m.n_comp + 1, dtype=torch.float64, device=device)
+    _check(lib().pssgp_loglik_grad(ctypes.byref(m), _p(t), _p(y), _p(mask), n, code, _p(ll), _p(g), _p(ws),
+                                   ws.numel(), ctypes.byref(options) if options is not None else None,
+                                   _stream()))
+    return ll, g
+
+
+def unpack_sym(Pp, d):
+    """(NS, n) packed upper entry-major -> (n, d, d) symmetric (torch or numpy)."""
+    iu = [(i, j) for i in range(d) for j in range(i, d)]
+    if hasattr(Pp, "detach"):
+        torch = _torch()
+        n = Pp.shape[1]
+        out = torch.empty((n, d, d), dtype=Pp.dtype, device=Pp.device)
+        for e, (i, j) in enumerate(iu):
+            out[:, i, j] = Pp[e]
+            out[:, j, i] = Pp[e]
+        return out
+    n = Pp.shape[1]
+    out = np.empty((n, d, d), dtype=Pp.dtype)
+    for e, (i, j) in enumerate(iu):
+        out[:, i, j] = Pp[e]
+        out[:, j, i] = Pp[e]
+    return out
+
+
+def _theta_of(model):
+    th = []
+    for c in range(model.n_comp):
+        th += [model.comp[c].lengthscale, model.comp[c].variance]
+    return th + [model.noise_var]
+
+
+def _model_with_theta(model, theta):
+    comps = [(model.comp[c].kind, model.comp[c].order, float(theta[2 * c]), float(theta[2 * c + 1]))
+             for c in range(model.n_comp)]
+    return make_model(comps, float(theta[-1]))
+
+
+def _make_autograd():
+    torch = _torch()
+
+    class LogLikelihood(torch.autograd.Function):
+        """loglik(theta) with the hand-written adjoint as its backward.
+
+        theta: float64 tensor (ell_0, var_0, ..., noise_var); the remaining
+        arguments are fixed data. Forward runs the filter scan with
+        checkpoints and the reverse adjoint scan together; backward scales the
+        stored gradient by the incoming gradient."""
+
+        @staticmethod
+        def forward(ctx, theta, kinds_orders, t, y, mask, dtype):
+            th = theta.detach().cpu().double().numpy()
+            comps = [(k, o, th[2 * i], th[2 * i + 1]) for i, (k, o) in enumerate(kinds_orders)]
+            ll, g = loglik_grad(make_model(comps, th[-1]), t, y, mask, dtype=dtype, device=t.device)
+            ctx.save_for_backward(g.to(theta.device))
+            return ll.to(theta.device).reshape(())
+
+        @staticmethod
+        def backward(ctx, gout):
+            (g,) = ctx.saved_tensors
+            return gout * g, None, None, None, None, None
+
+    return LogLikelihood
+
+
+_autograd_cls = None
+
+
+def loglik_autograd(theta, kinds_orders, t, y, mask=None, dtype="float32"):
+    """Differentiable log-likelihood: theta -> loglik (torch.autograd)."""
+    global _autograd_cls
+    if _autograd_cls is None:
+        _autograd_cls = _make_autograd()
+    return _autograd_cls.apply(theta, kinds_orders, t, y, mask, dtype)

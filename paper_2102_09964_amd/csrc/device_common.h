@@ -1,0 +1,465 @@
+// Device building blocks shared by the scan kernels: the compile-time block
+// layout of the state, FP64 discretisation, fixed-size register linear
+// algebra, wave-level shuffles and the workspace control block.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/pssgp.h"
+#include "launch.h"
+#include "model.h"
+
+#define PSSGP_WAVE 64
+
+// ------------------------------------------------------------------ layout
+
+// State layout fixed at compile time: up to two diagonal blocks of sizes B0
+// and B1 (B1 = 0: one block). All matrix indices in the kernels are
+// compile-time constants so that the state lives in registers.
+template <int B0, int B1>
+struct Layout {
+    static constexpr int D = B0 + B1;
+    static constexpr int NB = (B1 > 0) ? 2 : 1;
+    static constexpr int NS = D * (D + 1) / 2;
+    __host__ __device__ static constexpr int bdim(int b) { return b == 0 ? B0 : B1; }
+    __host__ __device__ static constexpr int boff(int b) { return b == 0 ? 0 : B0; }
+    // block of a state index
+    __host__ __device__ static constexpr int blk_of(int i) { return i < B0 ? 0 : 1; }
+    __host__ __device__ static constexpr bool same_blk(int i, int j) { return blk_of(i) == blk_of(j); }
+};
+
+// packed upper-triangular index, row-major
+template <int D>
+__host__ __device__ constexpr int sidx(int i, int j)
+{
+    return i <= j ? i * D - i * (i - 1) / 2 + (j - i) : j * D - j * (j - 1) / 2 + (i - j);
+}
+
+// ------------------------------------------------------------------ control block
+
+enum : uint32_t { FLAG_NONE = 0, FLAG_AGG = 1, FLAG_INCL = 2 };
+
+__device__ __forceinline__ uint32_t flag_load_acquire(const uint32_t *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void flag_store_release(uint32_t *p, uint32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t ticket_next(uint32_t *p)
+{
+    return __hip_atomic_fetch_add(p, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void status_or(uint32_t *p, uint32_t bits)
+{
+    __hip_atomic_fetch_or(p, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ------------------------------------------------------------------ FP64 discretisation
+
+// exp(s G1) of one companion-structured block by scaling and squaring a
+// truncated Taylor series: x = s ||G1||_1 is brought to at most 1/2 by j
+// halvings, the series is summed by Horner's rule to a degree K chosen so
+// that the remainder bound x^(K+1) / (K+1)! is below 1e-16, each Horner step
+// multiplying by the sparse G1 (superdiagonal and last row), and the result
+// is squared j times. Accurate to a few units of FP64 rounding for every s.
+template <int dc>
+__device__ __forceinline__ void expm_companion(const DevBlock &bk, double s, double (&X)[dc][dc])
+{
+    const double x = s * bk.gnorm;
+    int j = 0;
+    if (x > 0.5) {
+        j = ilogb(x) + 2;  // 2^(j-1) > x, so x / 2^j < 1/2
+        j = j > 60 ? 60 : j;
+    }
+    const double ss = ldexp(s, -j);
+    const double xr = ldexp(x, -j);
+    const int K = xr <= 0.01 ? 6 : (xr <= 0.05 ? 8 : (xr <= 0.15 ? 10 : (xr <= 0.3 ? 13 : 15)));
+#pragma unroll
+    for (int i = 0; i < dc; i++)
+#pragma unroll
+        for (int c = 0; c < dc; c++) X[i][c] = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+    for (int k = 15; k >= 1; k--) {
+        if (k <= K) {
+            const double f = ss / k;
+            double Y[dc][dc];
+#pragma unroll
+            for (int c = 0; c < dc; c++) {
+#pragma unroll
+                for (int i = 0; i + 1 < dc; i++) Y[i][c] = bk.gsup[i] * X[i + 1][c];
+                double acc = 0.0;
+#pragma unroll
+                for (int m = 0; m < dc; m++) acc = fma(bk.glast[m], X[m][c], acc);
+                Y[dc - 1][c] = acc;
+            }
+#pragma unroll
+            for (int i = 0; i < dc; i++)
+#pragma unroll
+                for (int c = 0; c < dc; c++) X[i][c] = fma(f, Y[i][c], (i == c) ? 1.0 : 0.0);
+        }
+    }
+    for (int r = 0; r < j; r++) {
+        double Y[dc][dc];
+#pragma unroll
+        for (int i = 0; i < dc; i++)
+#pragma unroll
+            for (int c = 0; c < dc; c++) {
+                double acc = 0.0;
+#pragma unroll
+                for (int m = 0; m < dc; m++) acc = fma(X[i][m], X[m][c], acc);
+                Y[i][c] = acc;
+            }
+#pragma unroll
+        for (int i = 0; i < dc; i++)
+#pragma unroll
+            for (int c = 0; c < dc; c++) X[i][c] = Y[i][c];
+    }
+}
+
+// Transition F = exp(dt G) and process noise Q = Pinf - F Pinf F^T of one
+// step (supplement eq. ss-gp-formation; stationarity gives the Q form).
+// first: step 0, F = 0 and Q = Pinf (first filter element, section 3).
+// ACC selects the Taylor evaluation for RBF blocks (full FP64 accuracy)
+// instead of the spectral expansion (faster, about 1e-12 absolute).
+template <class LY, int b, bool ACC>
+__device__ __forceinline__ void disc_block(const DevModel &mdl, double dt,
+                                           double (&F)[LY::D][LY::D], double (&Q)[LY::D][LY::D])
+{
+    constexpr int dc = LY::bdim(b);
+    constexpr int o = LY::boff(b);
+    const DevBlock &bk = mdl.blk[b];
+    const double s = dt * bk.inv_ell;
+    if (ACC && bk.kind == BLK_RBF) {
+        double X[dc][dc];
+        expm_companion<dc>(bk, s, X);
+#pragma unroll
+        for (int i = 0; i < dc; i++)
+#pragma unroll
+            for (int j = 0; j < dc; j++) F[o + i][o + j] = X[i][j];
+    } else {
+        double phi[dc];
+        if (bk.kind == BLK_MATERN) {
+            double p = exp(-bk.lam * s);
+#pragma unroll
+            for (int j = 0; j < dc; j++) {
+                phi[j] = p;
+                p *= s;
+            }
+        } else {
+            // RBF Taylor blocks: dc / 2 conjugate pairs and dc % 2 real roots
+#pragma unroll
+            for (int p = 0; p < dc / 2; p++) {
+                const double e = exp(bk.alpha[p] * s);
+                double sn, cs;
+                sincos(bk.beta[p] * s, &sn, &cs);
+                phi[2 * p] = e * cs;
+                phi[2 * p + 1] = e * sn;
+            }
+            if (dc % 2) phi[dc - 1] = exp(bk.alpha[dc / 2] * s);
+        }
+        const double *M = mdl.fcoef + bk.fc_off;
+#pragma unroll
+        for (int i = 0; i < dc; i++)
+#pragma unroll
+            for (int j = 0; j < dc; j++) {
+                double acc = 0.0;
+#pragma unroll
+                for (int r = 0; r < dc; r++) acc = fma(phi[r], M[r * dc * dc + i * dc + j], acc);
+                F[o + i][o + j] = acc;
+            }
+    }
+    // Q block = Pinf_b - F_b Pinf_b F_b^T
+    double FP[dc][dc];
+#pragma unroll
+    for (int i = 0; i < dc; i++)
+#pragma unroll
+        for (int j = 0; j < dc; j++) {
+            double acc = 0.0;
+#pragma unroll
+            for (int k = 0; k < dc; k++) acc = fma(F[o + i][o + k], mdl.Pinf[(o + k) * LY::D + o + j], acc);
+            FP[i][j] = acc;
+        }
+#pragma unroll
+    for (int i = 0; i < dc; i++)
+#pragma unroll
+        for (int j = i; j < dc; j++) {
+            double acc = mdl.Pinf[(o + i) * LY::D + o + j];
+#pragma unroll
+            for (int k = 0; k < dc; k++) acc = fma(-FP[i][k], F[o + j][o + k], acc);
+            Q[o + i][o + j] = acc;
+            Q[o + j][o + i] = acc;
+        }
+}
+
+template <class LY, bool ACC>
+__device__ __forceinline__ void discretize(const DevModel &mdl, double dt, bool first,
+                                           double (&F)[LY::D][LY::D], double (&Q)[LY::D][LY::D])
+{
+    constexpr int D = LY::D;
+#pragma unroll
+    for (int i = 0; i < D; i++)
+#pragma unroll
+        for (int j = 0; j < D; j++) { F[i][j] = 0.0; Q[i][j] = 0.0; }
+    disc_block<LY, 0, ACC>(mdl, dt, F, Q);
+    if constexpr (LY::NB > 1) disc_block<LY, 1, ACC>(mdl, dt, F, Q);
+    // exact special cases: a zero step is the identity map, step 0 is the prior
+    const bool zero = (dt == 0.0);
+#pragma unroll
+    for (int i = 0; i < D; i++)
+#pragma unroll
+        for (int j = 0; j < D; j++) {
+            const double fid = (i == j) ? 1.0 : 0.0;
+            F[i][j] = first ? 0.0 : (zero ? fid : F[i][j]);
+            Q[i][j] = first ? mdl.Pinf[i * D + j] : (zero ? 0.0 : Q[i][j]);
+        }
+}
+
+// ------------------------------------------------------------------ register linear algebra
+
+template <int D, typename T>
+__device__ __forceinline__ void mat_zero(T (&A)[D][D])
+{
+#pragma unroll
+    for (int i = 0; i < D; i++)
+#pragma unroll
+        for (int j = 0; j < D; j++) A[i][j] = T(0);
+}
+
+template <int D, typename T>
+__device__ __forceinline__ void mat_eye(T (&A)[D][D])
+{
+#pragma unroll
+    for (int i = 0; i < D; i++)
+#pragma unroll
+        for (int j = 0; j < D; j++) A[i][j] = (i == j) ? T(1) : T(0);
+}
+
+// C = A B
+template <int D, typename T>
+__device__ __forceinline__ void mat_mul(const T (&A)[D][D], const T (&B)[D][D], T (&C)[D][D])
+{
+#pragma unroll
+    for (int i = 0; i < D; i++)
+#pragma unroll
+        for (int j = 0; j < D; j++) {
+            T acc = T(0);
+#pragma unroll
+            for (int k = 0; k < D; k++) acc = fma(A[i][k], B[k][j], acc);
+            C[i][j] = acc;
+        }
+}
+
+// C = A^T B
+template <int D, typename T>
+__device__ __forceinline__ void mat_tmul(const T (&A)[D][D], const T (&B)[D][D], T (&C)[D][D])
+{
+#pragma unroll
+    for (int i = 0; i < D; i++)
+#pragma unroll
+        for (int j = 0; j < D; j++) {
+            T acc = T(0);
+#pragma unroll
+            for (int k = 0; k < D; k++) acc = fma(A[k][i], B[k][j], acc);
+            C[i][j] = acc;
+        }
+}
+
+// S = X A^T + Y with S symmetric: only the upper triangle is computed and
+// mirrored (used as A P A^T + Q once X = A P is formed).
+template <int D, typename T>
+__device__ __forceinline__ void mat_mul_nt_sym_add(const T (&X)[D][D], const T (&A)[D][D],
+                                                   const T (&Y)[D][D], T (&S)[D][D])
+{
+#pragma unroll
+    for (int i = 0; i < D; i++)
+#pragma unroll
+        for (int j = i; j < D; j++) {
+            T acc = Y[i][j];
+#pragma unroll
+            for (int k = 0; k < D; k++) acc = fma(X[i][k], A[j][k], acc);
+            S[i][j] = acc;
+            S[j][i] = acc;
+        }
+}
+
+template <int D, typename T>
+__device__ __forceinline__ void mat_vec(const T (&A)[D][D], const T (&x)[D], T (&y)[D])
+{
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+        T acc = T(0);
+#pragma unroll
+        for (int k = 0; k < D; k++) acc = fma(A[i][k], x[k], acc);
+        y[i] = acc;
+    }
+}
+
+template <int D, typename T>
+__device__ __forceinline__ T dot(const T (&a)[D], const T (&b)[D])
+{
+    T acc = T(0);
+#pragma unroll
+    for (int k = 0; k < D; k++) acc = fma(a[k], b[k], acc);
+    return acc;
+}
+
+// LU factorisation with partial pivoting, kept in registers: the row
+// exchanges are recorded (piv[c] = row swapped with c at column c) and done
+// with selects so that every array index is a compile-time constant.
+template <int D, typename T>
+__device__ __forceinline__ void lu_factor(T (&M)[D][D], int (&piv)[D])
+{
+#pragma unroll
+    for (int c = 0; c < D; c++) {
+        int p = c;
+        T best = fabs(M[c][c]);
+#pragma unroll
+        for (int r = c + 1; r < D; r++) {
+            const T v = fabs(M[r][c]);
+            const bool take = v > best;
+            best = take ? v : best;
+            p = take ? r : p;
+        }
+        piv[c] = p;
+#pragma unroll
+        for (int r = c + 1; r < D; r++) {
+            const bool sw = (p == r);
+#pragma unroll
+            for (int j = 0; j < D; j++) {
+                const T a = M[c][j], b = M[r][j];
+                M[c][j] = sw ? b : a;
+                M[r][j] = sw ? a : b;
+            }
+        }
+        const T inv = T(1) / M[c][c];
+#pragma unroll
+        for (int r = c + 1; r < D; r++) {
+            const T f = M[r][c] * inv;
+            M[r][c] = f;
+#pragma unroll
+            for (int j = c + 1; j < D; j++) M[r][j] = fma(-f, M[c][j], M[r][j]);
+        }
+    }
+}
+
+// x <- M^-1 x with the factors of lu_factor.
+template <int D, typename T>
+__device__ __forceinline__ void lu_solve(const T (&LU)[D][D], const int (&piv)[D], T (&x)[D])
+{
+    // the row exchanges of the whole factorisation first (P x), then the
+    // unit lower and the upper triangular solves
+#pragma unroll
+    for (int c = 0; c < D; c++) {
+#pragma unroll
+        for (int r = c + 1; r < D; r++) {
+            const bool sw = (piv[c] == r);
+            const T a = x[c], b = x[r];
+            x[c] = sw ? b : a;
+            x[r] = sw ? a : b;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < D; c++)
+#pragma unroll
+        for (int r = c + 1; r < D; r++) x[r] = fma(-LU[r][c], x[c], x[r]);
+#pragma unroll
+    for (int c = D - 1; c >= 0; c--) {
+        T acc = x[c];
+#pragma unroll
+        for (int k = c + 1; k < D; k++) acc = fma(-LU[c][k], x[k], acc);
+        x[c] = acc / LU[c][c];
+    }
+}
+
+// Cholesky factor (lower) of an SPD matrix, in place in the lower triangle.
+// Returns false when a pivot is not positive.
+template <int D, typename T>
+__device__ __forceinline__ bool cholesky(T (&A)[D][D])
+{
+    bool ok = true;
+#pragma unroll
+    for (int j = 0; j < D; j++) {
+        T s = A[j][j];
+#pragma unroll
+        for (int k = 0; k < j; k++) s = fma(-A[j][k], A[j][k], s);
+        ok = ok && (s > T(0));
+        const T ljj = sqrt(s > T(0) ? s : T(1));
+        const T inv = T(1) / ljj;
+        A[j][j] = ljj;
+#pragma unroll
+        for (int i = j + 1; i < D; i++) {
+            T r = A[i][j];
+#pragma unroll
+            for (int k = 0; k < j; k++) r = fma(-A[i][k], A[j][k], r);
+            A[i][j] = r * inv;
+        }
+    }
+    return ok;
+}
+
+// X = A^-1 B given the Cholesky factor L of A (lower triangle of Lf).
+template <int D, typename T>
+__device__ __forceinline__ void chol_solve(const T (&Lf)[D][D], const T (&B)[D][D], T (&X)[D][D])
+{
+#pragma unroll
+    for (int j = 0; j < D; j++) {
+        T z[D];
+#pragma unroll
+        for (int i = 0; i < D; i++) {
+            T s = B[i][j];
+#pragma unroll
+            for (int k = 0; k < i; k++) s = fma(-Lf[i][k], z[k], s);
+            z[i] = s / Lf[i][i];
+        }
+#pragma unroll
+        for (int i = D - 1; i >= 0; i--) {
+            T s = z[i];
+#pragma unroll
+            for (int k = i + 1; k < D; k++) s = fma(-Lf[k][i], X[k][j], s);
+            X[i][j] = s / Lf[i][i];
+        }
+    }
+}
+
+// ------------------------------------------------------------------ shuffles
+
+__device__ __forceinline__ float shfl_up_t(float v, int o) { return __shfl_up(v, o, PSSGP_WAVE); }
+__device__ __forceinline__ double shfl_up_t(double v, int o) { return __shfl_up(v, o, PSSGP_WAVE); }
+__device__ __forceinline__ float shfl_down_t(float v, int o) { return __shfl_down(v, o, PSSGP_WAVE); }
+__device__ __forceinline__ double shfl_down_t(double v, int o) { return __shfl_down(v, o, PSSGP_WAVE); }
+
+// Neumaier-compensated accumulation.
+template <typename T>
+__device__ __forceinline__ void kahan_add(T &s, T &c, T x)
+{
+    const T t = s + x;
+    c += (fabs(s) >= fabs(x)) ? ((s - t) + x) : ((x - t) + s);
+    s = t;
+}
+
+// Sum of a double over the wave in a fixed tree order (deterministic).
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, PSSGP_WAVE);
+    return __shfl(v, 0, PSSGP_WAVE);
+}
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (PSSGP_WAVE - 1)); }
+
+// The model constants (up to ~3.5 KB, mostly the expansion matrices of the
+// transition) are copied from the kernel arguments into LDS once per
+// workgroup. Loops over steps start with a compiler barrier so that the
+// constants are re-read from LDS in every iteration instead of being held
+// in registers across the loop.
+__device__ __forceinline__ void model_to_lds(const DevModel &src, DevModel &dst)
+{
+    const uint32_t *s = (const uint32_t *)&src;
+    uint32_t *d = (uint32_t *)&dst;
+    for (int i = (int)threadIdx.x; i < (int)(sizeof(DevModel) / 4); i += (int)blockDim.x) d[i] = s[i];
+    __syncthreads();
+}
+
+#define PSSGP_RELOAD_CONSTANTS() asm volatile("" ::: "memory")

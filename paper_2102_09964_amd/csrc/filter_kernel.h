@@ -1,0 +1,297 @@
+// Parallel Kalman filter with missing measurements (paper section 3) as a
+// single-pass decoupled look-back prefix scan, and the discretisation map.
+//
+// Work decomposition: one wave (64 lanes) per tile, each lane owns `chunk`
+// consecutive steps. A tile is processed as
+//   A  each lane folds its steps into a chunk aggregate (the element of a
+//      step is built from the FP64 discretisation and rounded to the scan
+//      type T)
+//   B  wave-level inclusive scan of the 64 chunk aggregates (Kogge-Stone
+//      over lane shuffles) with the general operator; every lane stores its
+//      inclusive aggregate in the workspace
+//   C  the last lane publishes the tile aggregate, walks back over the
+//      predecessor tiles until one has published its inclusive prefix, then
+//      applies the aggregates of the tiles in between to it; it publishes the
+//      tile's own inclusive prefix and hands the carry to the wave via LDS
+//   D  each lane applies its exclusive lane prefix to the carry, which gives
+//      the filter moments just before its chunk (every prefix from step 0
+//      has A = 0, so only (b, C) are carried), then re-runs its steps as a
+//      plain Kalman filter, writing (m, P) and accumulating the
+//      log-likelihood terms with compensated summation.
+// Tiles are numbered by an atomic ticket, so a tile only waits on tiles that
+// are already running; the last tile to finish reduces the per-tile
+// log-likelihood partials in a fixed order.
+#pragma once
+#include "device_common.h"
+#include "filter_ops.h"
+#include "launch.h"
+
+enum : int { F_MOMENTS = 1, F_CKPT = 2 };
+
+template <typename T>
+struct FilterParams {
+    const double *t;
+    const T *y;
+    const uint8_t *mask;
+    const double *noise_k;
+    int64_t n;
+    int chunk;
+    int ntiles;
+    int deterministic;
+    T *m;
+    T *P;
+    double *loglik;
+    T *ck;
+    WsCtl *ctl;
+    uint32_t *flags;
+    T *aggp;
+    T *inclp;
+    T *lanep;
+    double *partials;
+};
+
+template <class LY, typename T>
+__device__ __forceinline__ void step_transition(const DevModel &mdl, const double *t, int64_t k,
+                                                T (&F)[LY::D][LY::D], T (&Q)[LY::D][LY::D],
+                                                uint32_t &bad)
+{
+    constexpr int D = LY::D;
+    double F64[D][D], Q64[D][D];
+    const double tk = t[k];
+    const double dt = (k > 0) ? tk - t[k - 1] : 0.0;
+    if (!(dt >= 0.0)) bad |= (dt < 0.0) ? PSSGP_STATUS_UNSORTED : PSSGP_STATUS_NONFINITE;
+    discretize<LY, sizeof(T) == 8>(mdl, dt, k == 0, F64, Q64);
+#pragma unroll
+    for (int i = 0; i < D; i++)
+#pragma unroll
+        for (int j = 0; j < D; j++) { F[i][j] = T(F64[i][j]); Q[i][j] = T(Q64[i][j]); }
+}
+
+template <class LY, typename T, typename CT, int MODE>
+__global__ __launch_bounds__(PSSGP_WAVE) void filter_scan_kernel(FilterParams<T> p, DevModel mdl_arg)
+{
+    constexpr int D = LY::D;
+    constexpr int AGG = AggLayout<D>::SIZE;
+    constexpr int INCL = AggLayout<D>::INCL;
+    __shared__ uint32_t s_tile;
+    __shared__ T s_carry[INCL];
+    __shared__ DevModel mdl;
+    const int lane = lane_id();
+    if (lane == 0) s_tile = ticket_next(&p.ctl->ticket);
+    model_to_lds(mdl_arg, mdl);
+    const int tile = (int)s_tile;
+    const int64_t chunk_id = (int64_t)tile * PSSGP_WAVE + lane;
+    const int64_t k0 = chunk_id * p.chunk;
+    const int64_t k1 = (k0 + p.chunk < p.n) ? k0 + p.chunk : p.n;
+    T h[D];
+#pragma unroll
+    for (int i = 0; i < D; i++) h[i] = T(mdl.H[i]);
+    uint32_t bad = 0;
+
+    // A: chunk aggregate
+    {
+        FAgg<D, T> agg;
+        agg_identity<D, T>(agg);
+        for (int64_t k = k0; k < k1; k++) {
+            PSSGP_RELOAD_CONSTANTS();
+            T F[D][D], Q[D][D];
+            step_transition<LY, T>(mdl, p.t, k, F, Q, bad);
+            const bool obs = p.mask ? (p.mask[k] != 0) : true;
+            const T yk = obs ? p.y[k] : T(0);
+            const T R = p.noise_k ? T(p.noise_k[k]) : T(mdl.R);
+            agg_fold<D, T>(agg, F, Q, h, R, yk, obs);
+        }
+        // B: wave inclusive scan
+        for (int o = 1; o < PSSGP_WAVE; o <<= 1) {
+            FAgg<D, T> other;
+            agg_shfl_up<D, T>(agg, other, o);
+            if (lane >= o) agg_combine<D, T, CT>(other, agg, agg);
+        }
+        agg_store<D, T>(p.lanep + (size_t)chunk_id * AGG, agg);
+    }
+    __syncthreads();
+
+    // C: decoupled look-back by the last lane
+    if (lane == PSSGP_WAVE - 1) {
+        const T *tagg = p.lanep + (size_t)chunk_id * AGG;
+        T cb[D], cC[D][D];
+#pragma unroll
+        for (int i = 0; i < D; i++) {
+            cb[i] = T(0);
+#pragma unroll
+            for (int j = 0; j < D; j++) cC[i][j] = T(0);
+        }
+        if (tile > 0) {
+            if (!p.deterministic) {
+                T *dst = p.aggp + (size_t)tile * AGG;
+                for (int i = 0; i < AGG; i++) dst[i] = tagg[i];
+                flag_store_release(&p.flags[tile], FLAG_AGG);
+            }
+            int j = tile - 1;
+            while (true) {
+                uint32_t f;
+                while ((f = flag_load_acquire(&p.flags[j])) == FLAG_NONE) __builtin_amdgcn_s_sleep(1);
+                if (f == FLAG_INCL) break;
+                j--;
+            }
+            moments_load<D, T>(p.inclp + (size_t)j * INCL, cb, cC);
+            for (int i = j + 1; i < tile; i++) {
+                FAgg<D, T> x;
+                agg_load<D, T>(p.aggp + (size_t)i * AGG, x);
+                moments_apply<D, T, CT>(cb, cC, x, cb, cC);
+            }
+        }
+        {
+            FAgg<D, T> x;
+            agg_load<D, T>(tagg, x);
+            T ib[D], iC[D][D];
+            moments_apply<D, T, CT>(cb, cC, x, ib, iC);
+            moments_store<D, T>(p.inclp + (size_t)tile * INCL, ib, iC);
+        }
+        flag_store_release(&p.flags[tile], FLAG_INCL);
+        moments_store<D, T>(s_carry, cb, cC);
+    }
+    __syncthreads();
+
+    T m[D], P[D][D];
+    moments_load<D, T>(s_carry, m, P);
+    if (lane > 0) {
+        FAgg<D, T> excl;
+        agg_load<D, T>(p.lanep + (size_t)(chunk_id - 1) * AGG, excl);
+        moments_apply<D, T, CT>(m, P, excl, m, P);
+    }
+    if constexpr ((MODE & F_CKPT) != 0) {
+        if (k0 < p.n) moments_store<D, T>(p.ck + (size_t)chunk_id * INCL, m, P);
+    }
+
+    // D: sequential Kalman filter over the chunk from the carried moments
+    T ls = T(0), lc = T(0);
+    for (int64_t k = k0; k < k1; k++) {
+        PSSGP_RELOAD_CONSTANTS();
+        T F[D][D], Q[D][D];
+        step_transition<LY, T>(mdl, p.t, k, F, Q, bad);
+        const bool obs = p.mask ? (p.mask[k] != 0) : true;
+        const T yk = obs ? p.y[k] : T(0);
+        const T R = p.noise_k ? T(p.noise_k[k]) : T(mdl.R);
+        T mp[D], FP[D][D], Pp[D][D], Ph[D];
+        mat_vec<D, T>(F, m, mp);
+        mat_mul<D, T>(F, P, FP);
+        mat_mul_nt_sym_add<D, T>(FP, F, Q, Pp);
+        mat_vec<D, T>(Pp, h, Ph);
+        const T S = dot<D, T>(h, Ph) + R;
+        const T v = yk - dot<D, T>(h, mp);
+        const T w = obs ? T(1) / S : T(0);
+        if (obs) {
+            if (!(S > T(0)) || !isfinite(S)) bad |= PSSGP_STATUS_BAD_S;
+            if (!isfinite(yk)) bad |= PSSGP_STATUS_NONFINITE;
+            const T term = T(-0.5) * (log(T(6.283185307179586) * S) + v * v * w);
+            kahan_add<T>(ls, lc, term);
+        }
+#pragma unroll
+        for (int i = 0; i < D; i++) m[i] = fma(Ph[i] * w, v, mp[i]);
+#pragma unroll
+        for (int i = 0; i < D; i++)
+#pragma unroll
+            for (int j = i; j < D; j++) {
+                const T c = fma(-Ph[i] * w, Ph[j], Pp[i][j]);
+                P[i][j] = c;
+                P[j][i] = c;
+            }
+        if constexpr ((MODE & F_MOMENTS) != 0) {
+#pragma unroll
+            for (int i = 0; i < D; i++) p.m[(size_t)i * p.n + k] = m[i];
+#pragma unroll
+            for (int i = 0; i < D; i++)
+#pragma unroll
+                for (int j = i; j < D; j++) p.P[(size_t)sidx<D>(i, j) * p.n + k] = P[i][j];
+        }
+    }
+    if (bad) status_or(&p.ctl->status, bad);
+
+    // log-likelihood: deterministic wave sum, tile partial, last tile reduces
+    const double tot = wave_sum((double)ls + (double)lc);
+    uint32_t prev = 0;
+    if (lane == 0) {
+        p.partials[tile] = tot;
+        prev = __hip_atomic_fetch_add(&p.ctl->done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    prev = __shfl(prev, 0, PSSGP_WAVE);
+    if (prev == (uint32_t)(p.ntiles - 1)) {
+        __threadfence();
+        double s = 0.0;
+        for (int i = lane; i < p.ntiles; i += PSSGP_WAVE)
+            s += __hip_atomic_load(&p.partials[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s = wave_sum(s);
+        if (lane == 0) *p.loglik = s;
+    }
+}
+
+// One thread per step: F[k] (row-major d*d) and Q[k] (packed, entry-major).
+template <class LY>
+__global__ __launch_bounds__(256) void discretize_kernel(DevModel mdl, const double *t, int64_t n,
+                                                         double *Fo, double *Qo, WsCtl *ctl)
+{
+    constexpr int D = LY::D;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    double F[D][D], Q[D][D];
+    const double dt = (k > 0) ? t[k] - t[k - 1] : 0.0;
+    if (!(dt >= 0.0)) status_or(&ctl->status, (dt < 0.0) ? PSSGP_STATUS_UNSORTED : PSSGP_STATUS_NONFINITE);
+    discretize<LY, true>(mdl, dt, k == 0, F, Q);
+#pragma unroll
+    for (int i = 0; i < D; i++)
+#pragma unroll
+        for (int j = 0; j < D; j++) Fo[(size_t)k * D * D + i * D + j] = F[i][j];
+#pragma unroll
+    for (int i = 0; i < D; i++)
+#pragma unroll
+        for (int j = i; j < D; j++) Qo[(size_t)sidx<D>(i, j) * n + k] = Q[i][j];
+}
+
+template <class LY, typename T, typename CT>
+int launch_filter_t(const DevModel &mdl, const FilterLaunch &a, hipStream_t s)
+{
+    FilterParams<T> p;
+    p.t = a.t;
+    p.y = (const T *)a.y;
+    p.mask = a.mask;
+    p.noise_k = a.noise_k;
+    p.n = a.n;
+    p.chunk = a.chunk;
+    p.ntiles = a.ntiles;
+    p.deterministic = a.deterministic;
+    p.m = (T *)a.m;
+    p.P = (T *)a.P;
+    p.loglik = a.loglik;
+    p.ck = (T *)a.ck;
+    p.ctl = a.ws.ctl;
+    p.flags = a.ws.flags;
+    p.aggp = (T *)a.ws.aggp;
+    p.inclp = (T *)a.ws.inclp;
+    p.lanep = (T *)a.ws.lanep;
+    p.partials = a.ws.partials;
+    dim3 grid(a.ntiles), block(PSSGP_WAVE);
+    if (a.m)
+        hipLaunchKernelGGL((filter_scan_kernel<LY, T, CT, F_MOMENTS>), grid, block, 0, s, p, mdl);
+    else if (a.ck)
+        hipLaunchKernelGGL((filter_scan_kernel<LY, T, CT, F_CKPT>), grid, block, 0, s, p, mdl);
+    else
+        hipLaunchKernelGGL((filter_scan_kernel<LY, T, CT, 0>), grid, block, 0, s, p, mdl);
+    return (int)hipGetLastError();
+}
+
+template <int B0, int B1>
+int launch_filter_layout(const DevModel &mdl, bool f64, const FilterLaunch &a, hipStream_t s)
+{
+    return f64 ? launch_filter_t<Layout<B0, B1>, double, double>(mdl, a, s)
+               : launch_filter_t<Layout<B0, B1>, float, float>(mdl, a, s);
+}
+
+template <int B0, int B1>
+int launch_discretize_layout(const DevModel &mdl, const double *t, int64_t n, double *F, double *Q,
+                             WsCtl *ctl, hipStream_t s)
+{
+    const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    hipLaunchKernelGGL((discretize_kernel<Layout<B0, B1>>), grid, block, 0, s, mdl, t, n, F, Q, ctl);
+    return (int)hipGetLastError();
+}

@@ -1,0 +1,375 @@
+// Filter elements (A, b, C, eta, J) and the associative filtering operator
+// of section 3 (paper), in registers.
+#pragma once
+#include "device_common.h"
+
+template <int D, typename T>
+struct FAgg {
+    T A[D][D];
+    T b[D];
+    T C[D][D];  // symmetric (both triangles kept equal)
+    T eta[D];
+    T J[D][D];  // symmetric
+};
+
+// Neutral element of the operator: (I, 0, 0, 0, 0).
+template <int D, typename T>
+__device__ __forceinline__ void agg_identity(FAgg<D, T> &a)
+{
+    mat_eye<D, T>(a.A);
+    mat_zero<D, T>(a.C);
+    mat_zero<D, T>(a.J);
+#pragma unroll
+    for (int i = 0; i < D; i++) { a.b[i] = T(0); a.eta[i] = T(0); }
+}
+
+// acc <- acc (x) e_k for the raw element e_k of one step. The aggregate
+// describes x_k | x_start, y (mean A x_start + b, covariance C) and the
+// information of y about x_start (eta, J). Folding one step is the Kalman
+// filter run for an unknown start state: predict (A, b, C) through (F, Q),
+// condition on y_k with S = H C' H^T + R, and add the information of y_k
+// about x_start, carried by v = (H A')^T, to (eta, J). This equals the
+// paper's operator applied to the observed / missing element of the step
+// (a rank-one J, so the (I + C J)^-1 of the operator reduces to the scalar
+// 1 / S). obs = false leaves the predicted triple and (eta, J) unchanged.
+template <int D, typename T>
+__device__ __forceinline__ void agg_fold(FAgg<D, T> &a, const T (&F)[D][D], const T (&Q)[D][D],
+                                         const T (&h)[D], T R, T y, bool obs)
+{
+    T A1[D][D], b1[D], FC[D][D], C1[D][D];
+    mat_mul<D, T>(F, a.A, A1);
+    mat_vec<D, T>(F, a.b, b1);
+    mat_mul<D, T>(F, a.C, FC);
+    mat_mul_nt_sym_add<D, T>(FC, F, Q, C1);
+    T Ch[D], v[D];
+    mat_vec<D, T>(C1, h, Ch);
+#pragma unroll
+    for (int j = 0; j < D; j++) {
+        T acc = T(0);
+#pragma unroll
+        for (int i = 0; i < D; i++) acc = fma(h[i], A1[i][j], acc);
+        v[j] = acc;
+    }
+    const T S = dot<D, T>(h, Ch) + R;
+    const T w = obs ? T(1) / S : T(0);
+    const T r = obs ? (y - dot<D, T>(h, b1)) : T(0);
+    T K[D];
+#pragma unroll
+    for (int i = 0; i < D; i++) K[i] = Ch[i] * w;
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+        a.b[i] = fma(K[i], r, b1[i]);
+        a.eta[i] = fma(v[i], r * w, a.eta[i]);
+#pragma unroll
+        for (int j = 0; j < D; j++) a.A[i][j] = fma(-K[i], v[j], A1[i][j]);
+    }
+#pragma unroll
+    for (int i = 0; i < D; i++)
+#pragma unroll
+        for (int j = i; j < D; j++) {
+            const T c = fma(-Ch[i], K[j], C1[i][j]);
+            a.C[i][j] = c;
+            a.C[j][i] = c;
+            const T jj = fma(v[i] * w, v[j], a.J[i][j]);
+            a.J[i][j] = jj;
+            a.J[j][i] = jj;
+        }
+}
+
+// General filtering operator (section 3): x (x) y, x earlier than y, with
+// M = I + C_x J_y. Every inverse is applied as a left solve with one LU
+// factorisation of M, one right-hand side at a time:
+//   A = A_y M^-1 A_x
+//   b = A_y M^-1 (b_x + C_x eta_y) + b_y
+//   C = A_y M^-1 C_x A_y^T + C_y
+//   J = A_x^T (J_y M^-1) A_x + J_x        ((I + J C)^-1 J = J (I + C J)^-1)
+//   eta = A_x^T (u - J_y M^-1 C_x u) + eta_x,  u = eta_y - J_y b_x
+//                                           ((I + J C)^-1 = I - J M^-1 C)
+// CT is the arithmetic type of the combine; out may alias y.
+template <int D, typename T, typename CT>
+__device__ __forceinline__ void agg_combine(const FAgg<D, T> &x, const FAgg<D, T> &y, FAgg<D, T> &out)
+{
+    CT M[D][D];
+    int piv[D];
+#pragma unroll
+    for (int i = 0; i < D; i++)
+#pragma unroll
+        for (int j = 0; j < D; j++) {
+            CT acc = (i == j) ? CT(1) : CT(0);
+#pragma unroll
+            for (int k = 0; k < D; k++) acc = fma(CT(x.C[i][k]), CT(y.J[k][j]), acc);
+            M[i][j] = acc;
+        }
+    lu_factor<D, CT>(M, piv);
+    // b and the u of eta (vectors first: they need y.b, y.eta before out aliases y)
+    CT u[D], z[D], w[D];
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+        CT acc = CT(y.eta[i]);
+#pragma unroll
+        for (int k = 0; k < D; k++) acc = fma(-CT(y.J[i][k]), CT(x.b[k]), acc);
+        u[i] = acc;
+    }
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+        CT ce = CT(x.b[i]), cu = CT(0);
+#pragma unroll
+        for (int k = 0; k < D; k++) {
+            ce = fma(CT(x.C[i][k]), CT(y.eta[k]), ce);
+            cu = fma(CT(x.C[i][k]), u[k], cu);
+        }
+        z[i] = ce;
+        w[i] = cu;
+    }
+    lu_solve<D, CT>(M, piv, z);
+    lu_solve<D, CT>(M, piv, w);
+    CT nb[D], ne[D];
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+        CT bb = CT(y.b[i]);
+#pragma unroll
+        for (int k = 0; k < D; k++) bb = fma(CT(y.A[i][k]), z[k], bb);
+        nb[i] = bb;
+        CT ue = u[i];
+#pragma unroll
+        for (int k = 0; k < D; k++) ue = fma(-CT(y.J[i][k]), w[k], ue);
+        u[i] = ue;
+    }
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+        CT e = CT(x.eta[i]);
+#pragma unroll
+        for (int k = 0; k < D; k++) e = fma(CT(x.A[k][i]), u[k], e);
+        ne[i] = e;
+    }
+    // C part: AZ = A_y M^-1 C_x, column by column
+    CT AZ[D][D];
+#pragma unroll
+    for (int j = 0; j < D; j++) {
+        CT col[D];
+#pragma unroll
+        for (int i = 0; i < D; i++) col[i] = CT(x.C[i][j]);
+        lu_solve<D, CT>(M, piv, col);
+#pragma unroll
+        for (int i = 0; i < D; i++) {
+            CT acc = CT(0);
+#pragma unroll
+            for (int k = 0; k < D; k++) acc = fma(CT(y.A[i][k]), col[k], acc);
+            AZ[i][j] = acc;
+        }
+    }
+    T nC[D][D];
+#pragma unroll
+    for (int i = 0; i < D; i++)
+#pragma unroll
+        for (int j = i; j < D; j++) {
+            CT acc = CT(y.C[i][j]);
+#pragma unroll
+            for (int k = 0; k < D; k++) acc = fma(AZ[i][k], CT(y.A[j][k]), acc);
+            nC[i][j] = T(acc);
+            nC[j][i] = T(acc);
+        }
+    // A and J parts: Z_A = M^-1 A_x column by column
+    T nA[D][D];
+    CT JZ[D][D];
+#pragma unroll
+    for (int j = 0; j < D; j++) {
+        CT col[D];
+#pragma unroll
+        for (int i = 0; i < D; i++) col[i] = CT(x.A[i][j]);
+        lu_solve<D, CT>(M, piv, col);
+#pragma unroll
+        for (int i = 0; i < D; i++) {
+            CT a = CT(0), jz = CT(0);
+#pragma unroll
+            for (int k = 0; k < D; k++) {
+                a = fma(CT(y.A[i][k]), col[k], a);
+                jz = fma(CT(y.J[i][k]), col[k], jz);
+            }
+            nA[i][j] = T(a);
+            JZ[i][j] = jz;
+        }
+    }
+    T nJ[D][D];
+#pragma unroll
+    for (int i = 0; i < D; i++)
+#pragma unroll
+        for (int j = i; j < D; j++) {
+            CT acc = CT(x.J[i][j]);
+#pragma unroll
+            for (int k = 0; k < D; k++) acc = fma(CT(x.A[k][i]), JZ[k][j], acc);
+            nJ[i][j] = T(acc);
+            nJ[j][i] = T(acc);
+        }
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+        out.b[i] = T(nb[i]);
+        out.eta[i] = T(ne[i]);
+#pragma unroll
+        for (int j = 0; j < D; j++) {
+            out.A[i][j] = nA[i][j];
+            out.C[i][j] = nC[i][j];
+            out.J[i][j] = nJ[i][j];
+        }
+    }
+}
+
+// (0, b, C, 0, 0) (x) y for a prefix whose A is 0 (every prefix that starts
+// at step 0, section 3, since A_1 = 0): only the filter moments are formed,
+//   b' = A_y M^-1 (b + C eta_y) + b_y,  C' = A_y M^-1 C A_y^T + C_y,
+// M = I + C J_y. bo, Co may alias bx, Cx.
+template <int D, typename T, typename CT>
+__device__ __forceinline__ void moments_apply(const T (&bx)[D], const T (&Cx)[D][D], const FAgg<D, T> &y,
+                                              T (&bo)[D], T (&Co)[D][D])
+{
+    CT M[D][D];
+    int piv[D];
+    CT z[D];
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+        CT ce = CT(bx[i]);
+#pragma unroll
+        for (int j = 0; j < D; j++) {
+            CT acc = (i == j) ? CT(1) : CT(0);
+#pragma unroll
+            for (int k = 0; k < D; k++) acc = fma(CT(Cx[i][k]), CT(y.J[k][j]), acc);
+            M[i][j] = acc;
+            ce = fma(CT(Cx[i][j]), CT(y.eta[j]), ce);
+        }
+        z[i] = ce;
+    }
+    lu_factor<D, CT>(M, piv);
+    lu_solve<D, CT>(M, piv, z);
+    CT AZ[D][D];
+#pragma unroll
+    for (int j = 0; j < D; j++) {
+        CT col[D];
+#pragma unroll
+        for (int i = 0; i < D; i++) col[i] = CT(Cx[i][j]);
+        lu_solve<D, CT>(M, piv, col);
+#pragma unroll
+        for (int i = 0; i < D; i++) {
+            CT acc = CT(0);
+#pragma unroll
+            for (int k = 0; k < D; k++) acc = fma(CT(y.A[i][k]), col[k], acc);
+            AZ[i][j] = acc;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+        CT bb = CT(y.b[i]);
+#pragma unroll
+        for (int k = 0; k < D; k++) bb = fma(CT(y.A[i][k]), z[k], bb);
+        bo[i] = T(bb);
+    }
+#pragma unroll
+    for (int i = 0; i < D; i++)
+#pragma unroll
+        for (int j = i; j < D; j++) {
+            CT acc = CT(y.C[i][j]);
+#pragma unroll
+            for (int k = 0; k < D; k++) acc = fma(AZ[i][k], CT(y.A[j][k]), acc);
+            Co[i][j] = T(acc);
+            Co[j][i] = T(acc);
+        }
+}
+
+template <int D, typename T>
+__device__ __forceinline__ void agg_shfl_up(const FAgg<D, T> &in, FAgg<D, T> &out, int o)
+{
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+        out.b[i] = shfl_up_t(in.b[i], o);
+        out.eta[i] = shfl_up_t(in.eta[i], o);
+#pragma unroll
+        for (int j = 0; j < D; j++) out.A[i][j] = shfl_up_t(in.A[i][j], o);
+#pragma unroll
+        for (int j = i; j < D; j++) {
+            out.C[i][j] = shfl_up_t(in.C[i][j], o);
+            out.C[j][i] = out.C[i][j];
+            out.J[i][j] = shfl_up_t(in.J[i][j], o);
+            out.J[j][i] = out.J[i][j];
+        }
+    }
+}
+
+// Global-memory layout of a published aggregate: A (D*D), b (D), C packed
+// (NS), eta (D), J packed (NS).
+template <int D>
+struct AggLayout {
+    static constexpr int NS = D * (D + 1) / 2;
+    static constexpr int SIZE = D * D + 2 * D + 2 * NS;
+    static constexpr int INCL = D + NS;  // (b, C) of a prefix from step 0
+};
+
+template <int D, typename T>
+__device__ __forceinline__ void agg_store(T *p, const FAgg<D, T> &a)
+{
+#pragma unroll
+    for (int i = 0; i < D; i++)
+#pragma unroll
+        for (int j = 0; j < D; j++) p[i * D + j] = a.A[i][j];
+    p += D * D;
+#pragma unroll
+    for (int i = 0; i < D; i++) p[i] = a.b[i];
+    p += D;
+#pragma unroll
+    for (int i = 0; i < D; i++)
+#pragma unroll
+        for (int j = i; j < D; j++) p[sidx<D>(i, j)] = a.C[i][j];
+    p += AggLayout<D>::NS;
+#pragma unroll
+    for (int i = 0; i < D; i++) p[i] = a.eta[i];
+    p += D;
+#pragma unroll
+    for (int i = 0; i < D; i++)
+#pragma unroll
+        for (int j = i; j < D; j++) p[sidx<D>(i, j)] = a.J[i][j];
+}
+
+template <int D, typename T>
+__device__ __forceinline__ void agg_load(const T *p, FAgg<D, T> &a)
+{
+#pragma unroll
+    for (int i = 0; i < D; i++)
+#pragma unroll
+        for (int j = 0; j < D; j++) a.A[i][j] = p[i * D + j];
+    p += D * D;
+#pragma unroll
+    for (int i = 0; i < D; i++) a.b[i] = p[i];
+    p += D;
+#pragma unroll
+    for (int i = 0; i < D; i++)
+#pragma unroll
+        for (int j = i; j < D; j++) { a.C[i][j] = p[sidx<D>(i, j)]; a.C[j][i] = a.C[i][j]; }
+    p += AggLayout<D>::NS;
+#pragma unroll
+    for (int i = 0; i < D; i++) a.eta[i] = p[i];
+    p += D;
+#pragma unroll
+    for (int i = 0; i < D; i++)
+#pragma unroll
+        for (int j = i; j < D; j++) { a.J[i][j] = p[sidx<D>(i, j)]; a.J[j][i] = a.J[i][j]; }
+}
+
+template <int D, typename T>
+__device__ __forceinline__ void moments_store(T *p, const T (&b)[D], const T (&C)[D][D])
+{
+#pragma unroll
+    for (int i = 0; i < D; i++) p[i] = b[i];
+#pragma unroll
+    for (int i = 0; i < D; i++)
+#pragma unroll
+        for (int j = i; j < D; j++) p[D + sidx<D>(i, j)] = C[i][j];
+}
+
+template <int D, typename T>
+__device__ __forceinline__ void moments_load(const T *p, T (&b)[D], T (&C)[D][D])
+{
+#pragma unroll
+    for (int i = 0; i < D; i++) b[i] = p[i];
+#pragma unroll
+    for (int i = 0; i < D; i++)
+#pragma unroll
+        for (int j = i; j < D; j++) { C[i][j] = p[D + sidx<D>(i, j)]; C[j][i] = C[i][j]; }
+}

@@ -1,0 +1,97 @@
+// Host-side launch interface between the C ABI (capi.cpp) and the kernel
+// translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "model.h"
+
+// Control block at the start of every workspace.
+struct WsCtl {
+    uint32_t ticket;   // dynamic tile order
+    uint32_t done;     // tiles finished (last-block reduction)
+    uint32_t status;   // PSSGP_STATUS_* bits
+    uint32_t pad[61];
+};
+
+// Block layouts (state sizes of up to two kernel components) compiled in.
+#ifndef PSSGP_LAYOUTS
+#define PSSGP_LAYOUTS(X) X(1, 0) X(2, 0) X(3, 0) X(4, 0) X(6, 0) X(2, 6) X(1, 2)
+#endif
+
+// Workspace pieces of one scan launch (all device pointers).
+struct ScanWs {
+    WsCtl *ctl;
+    uint32_t *flags;
+    void *aggp;      // per-tile aggregates
+    void *inclp;     // per-tile inclusive prefixes
+    void *lanep;     // per-lane inclusive aggregates within the tile
+    double *partials;  // per-tile partial sums (loglik, gradient)
+};
+
+struct FilterLaunch {
+    const double *t;
+    const void *y;
+    const uint8_t *mask;
+    const double *noise_k;
+    int64_t n;
+    int chunk;
+    int ntiles;
+    int deterministic;
+    void *m;         // nullable
+    void *P;         // nullable
+    double *loglik;  // nullable
+    void *ck;        // nullable: per-chunk checkpoints of the start moments
+    ScanWs ws;
+};
+
+struct SmoothLaunch {
+    const double *t;
+    const void *m;
+    const void *P;
+    int64_t n;
+    int chunk;
+    int ntiles;
+    int deterministic;
+    void *f_mean;
+    void *f_var;
+    void *ms;  // nullable
+    void *Ps;  // nullable
+    ScanWs ws;
+};
+
+struct GradLaunch {
+    const double *t;
+    const void *y;
+    const uint8_t *mask;
+    int64_t n;
+    int chunk;
+    int ntiles;
+    int deterministic;
+    const void *ck;     // checkpoints written by the forward filter
+    void *rec;          // per-step forward records (scratch)
+    double *grad;       // device [2 n_comp + 1]
+    ScanWs ws;
+};
+
+// Per-layout launchers, instantiated in one translation unit per layout.
+template <int B0, int B1>
+int launch_filter_layout(const DevModel &mdl, bool f64, const FilterLaunch &a, hipStream_t s);
+template <int B0, int B1>
+int launch_smoother_layout(const DevModel &mdl, bool f64, const SmoothLaunch &a, hipStream_t s);
+template <int B0, int B1>
+int launch_discretize_layout(const DevModel &mdl, const double *t, int64_t n, double *F, double *Q,
+                             WsCtl *ctl, hipStream_t s);
+template <int B0, int B1>
+int launch_grad_layout(const DevModel &mdl, bool f64, const GradLaunch &a, hipStream_t s);
+
+// Dispatchers: return hipSuccess or an error; -1 when the layout (b0, b1) is
+// not compiled in.
+int launch_filter(const DevModel &mdl, int b0, int b1, bool f64, const FilterLaunch &a, hipStream_t s);
+int launch_smoother(const DevModel &mdl, int b0, int b1, bool f64, const SmoothLaunch &a, hipStream_t s);
+int launch_discretize(const DevModel &mdl, int b0, int b1, const double *t, int64_t n, double *F,
+                      double *Q, WsCtl *ctl, hipStream_t s);
+int launch_grad(const DevModel &mdl, int b0, int b1, bool f64, const GradLaunch &a, hipStream_t s);
+int launch_ws_init(WsCtl *ctl, uint32_t *flags, int64_t nflags, double *zero_out, int nzero,
+                   hipStream_t s);
+bool layout_supported(int b0, int b1);

@@ -1,0 +1,138 @@
+"""C ABI checks that need no GPU: the library loads, exports every entry
+point declared in include/pssgp.h, builds the same continuous model as the
+oracle (a different construction: closed-form Matern covariances and a modal
+Lyapunov solve for the RBF Taylor model, versus the oracle's Kronecker
+solve), and rejects bad arguments on the host before touching a device.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2102_09964_amd as P
+from oracle.model import MATERN12, MATERN32, MATERN52, RBF, OracleModel
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "pssgp.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pssgp_\w+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = P.lib()
+    names = _declared()
+    assert len(names) >= 15
+    sig = {s[0] for s in P.SIGNATURES}
+    for name in names:
+        assert hasattr(L, name), name
+        assert name in sig, "binding misses " + name
+
+
+def test_version():
+    assert P.lib().pssgp_version() >= 100
+
+
+MODELS = [
+    [(MATERN12, 0, 0.3, 2.0)],
+    [(MATERN32, 0, 0.5, 1.0)],
+    [(MATERN52, 0, 1.0, 1.0)],
+    [(MATERN52, 0, 0.1, 3.0)],
+    [(RBF, 4, 0.7, 1.3)],
+    [(RBF, 6, 1.0, 1.0)],
+    [(MATERN32, 0, 2.0, 0.5), (RBF, 6, 0.5, 0.5)],
+    [(MATERN12, 0, 0.4, 1.0), (MATERN32, 0, 1.0, 0.5)],
+]
+
+
+@pytest.mark.parametrize("comps", MODELS)
+def test_model_matches_oracle_construction(comps):
+    m = P.make_model(comps, 0.01)
+    G, Pi, H = P.model_matrices(m)
+    T = P.state_basis(m)
+    om = OracleModel(comps, 0.01)
+    assert P.state_dim(m) == om.d
+    # x_canonical = diag(T) z
+    Gc = T[:, None] * G / T[None, :]
+    Pc = T[:, None] * Pi * T[None, :]
+    assert np.max(np.abs(Gc - om.G)) <= 1e-13 * np.max(np.abs(om.G))
+    assert np.max(np.abs(Pc - om.Pinf)) <= 1e-12 * np.max(np.abs(om.Pinf))
+    assert np.array_equal(H / T, om.H)
+    # the library basis is balanced: the stationary covariance is well scaled
+    ev = np.linalg.eigvalsh(Pi)
+    assert ev.min() > 0
+
+
+def test_state_dim_and_errors():
+    assert P.state_dim(P.make_model([(RBF, 6, 1.0, 1.0), (MATERN32, 0, 1.0, 1.0)], 0.1)) == 8
+    bad = [
+        (P.make_model([(7, 0, 1.0, 1.0)], 0.01), -1),               # unknown kind
+        (P.make_model([(RBF, 7, 1.0, 1.0)], 0.01), -2),             # order not supported
+        (P.make_model([(MATERN32, 0, -1.0, 1.0)], 0.01), -6),       # bad lengthscale
+        (P.make_model([(MATERN32, 0, 1.0, 0.0)], 0.01), -6),        # bad variance
+        (P.make_model([(MATERN32, 0, 1.0, 1.0)], 0.0), -6),         # bad noise
+        (P.make_model([(RBF, 6, 1.0, 1.0), (MATERN52, 0, 1.0, 1.0)], 0.01), -2),  # d = 9
+        (P.make_model([(MATERN12, 0, 1, 1)] * 3, 0.01), -2),        # three components
+    ]
+    for m, code in bad:
+        assert P.lib().pssgp_state_dim(ctypes.byref(m)) == code
+        assert P.lib().pssgp_last_error()
+
+
+def test_workspace_bytes_monotone():
+    m = P.make_model([(RBF, 6, 1.0, 1.0)], 0.01)
+    prev = 0
+    for n in [0, 1, 1000, 1 << 16, 1 << 22]:
+        b = P.workspace_bytes(m, n, P.F32, P.OP_FILTER)
+        assert b > 0 and b >= prev
+        prev = b
+    assert P.workspace_bytes(m, 1000, P.F64, P.OP_FILTER) > P.workspace_bytes(m, 1000, P.F32, P.OP_FILTER)
+    assert P.workspace_bytes(m, 1000, P.F32, P.OP_LOGLIK_GRAD) > P.workspace_bytes(m, 1000, P.F32, P.OP_LOGLIK)
+    assert P.workspace_bytes(m, -1, P.F32, P.OP_FILTER) == 0
+    assert P.workspace_bytes(m, 10, P.F32, 99) == 0
+
+
+def test_argument_errors_need_no_device():
+    """Validation happens on the host: these calls return before any HIP call
+    (the fake device pointers are never dereferenced)."""
+    L = P.lib()
+    m = P.make_model([(MATERN32, 0, 0.5, 1.0)], 0.01)
+    mp = ctypes.byref(m)
+    fake = ctypes.c_void_p(0x1000)
+    n = 100
+    need = P.workspace_bytes(m, n, P.F32, P.OP_FILTER)
+    # NULL workspace
+    assert L.pssgp_filter(mp, fake, fake, None, None, n, P.F32, fake, fake, fake, None, 0, None, None) == -1
+    # too small workspace
+    assert L.pssgp_filter(mp, fake, fake, None, None, n, P.F32, fake, fake, fake, fake, need - 1, None, None) == -3
+    # negative n, bad dtype
+    assert L.pssgp_filter(mp, fake, fake, None, None, -5, P.F32, fake, fake, fake, fake, need, None, None) == -1
+    assert L.pssgp_filter(mp, fake, fake, None, None, n, 7, fake, fake, fake, fake, need, None, None) == -1
+    # m without P, and nothing requested
+    assert L.pssgp_filter(mp, fake, fake, None, None, n, P.F32, fake, None, fake, fake, need, None, None) == -1
+    assert L.pssgp_filter(mp, fake, fake, None, None, n, P.F32, None, None, None, fake, need, None, None) == -1
+    # bad chunk option
+    o = P.make_options(chunk=65)
+    assert L.pssgp_filter(mp, fake, fake, None, None, n, P.F32, fake, fake, fake, fake, need, ctypes.byref(o),
+                          None) == -1
+    # NULL model
+    assert L.pssgp_filter(None, fake, fake, None, None, n, P.F32, fake, fake, fake, fake, need, None, None) == -1
+    # smoother: missing outputs, ms without Ps
+    ns = P.workspace_bytes(m, n, P.F32, P.OP_SMOOTH)
+    assert L.pssgp_smooth(mp, fake, fake, fake, n, P.F32, None, fake, None, None, fake, ns, None, None) == -1
+    assert L.pssgp_smooth(mp, fake, fake, fake, n, P.F32, fake, fake, fake, None, fake, ns, None, None) == -1
+    # loglik / grad without outputs
+    assert L.pssgp_loglik(mp, fake, fake, None, None, n, P.F32, None, fake, need, None, None) == -1
+    ng = P.workspace_bytes(m, n, P.F32, P.OP_LOGLIK_GRAD)
+    assert L.pssgp_loglik_grad(mp, fake, fake, None, n, P.F32, fake, None, fake, ng, None, None) == -1
+    # status needs a workspace and an output
+    assert L.pssgp_status(None, None, None) == -1
+    # unsupported model
+    m9 = P.make_model([(RBF, 6, 1.0, 1.0), (MATERN52, 0, 1.0, 1.0)], 0.01)
+    assert L.pssgp_filter(ctypes.byref(m9), fake, fake, None, None, n, P.F32, fake, fake, fake, fake, need, None,
+                          None) == -2
+    assert b"state size" in L.pssgp_last_error()
