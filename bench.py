@@ -1,0 +1,194 @@
+"""Benchmark of the parallel state-space GP hot path on one MI355X.
+
+One step = one pass of the whole path over one batch of synthetic input:
+parallel Kalman filter scan (discretisation, element construction, prefix
+scan, log-likelihood) followed by the parallel RTS smoother scan (posterior
+mean and variance of f at every step). The metric is time steps per second:
+series length / time per step, with the inputs resident in HBM.
+
+Default workload: RBF kernel through its order-6 Taylor state-space model
+(d = 6), 2^22 time stamps with log-normal gaps (median 0.01), the paper's
+noisy three-tone sinusoid, 20 % missing, FP32 scans with FP64
+discretisation and a compensated log-likelihood.
+
+The JSON line carries, besides the contract fields:
+* roofline: the dominant scan kernel's algorithmic HBM bytes per launch
+  divided by its mean duration (HIP events on the launch stream) against
+  the 8 TB/s HBM3E peak, plus its arithmetic rate against the FP32 vector
+  peak;
+* cpu_baseline: the sequential FP64 oracle on a bounded prefix of the same
+  workload, on one host core;
+* also: the same measurement for the other precision and the other
+  single-series workloads.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+
+WORKLOADS = {
+    "rbf6_lognormal": lambda: __import__("workloads").rbf6_lognormal(),
+    "matern52_exp": lambda: __import__("workloads").matern52_exp(),
+    "matern32_interp": lambda: __import__("workloads").matern32_interp(),
+    "sum_m32_rbf6": lambda: __import__("workloads").sum_m32_rbf6(),
+}
+
+
+def algorithmic_bytes(d, tsize, n):
+    """HBM bytes the path must move per launch (inputs read once, the filter
+    to smoother handover (m, P) written then read, outputs written)."""
+    mom = tsize * d * (d + 3) // 2
+    filt = n * (8 + tsize + 1 + mom)          # t, y, mask in; m, P out
+    smooth = n * (8 + mom + 2 * tsize)        # t, m, P in; f_mean, f_var out
+    return filt, smooth
+
+
+def algorithmic_flops(d):
+    """Arithmetic of the scans per step, counting the matrix products of the
+    method (2 flops per multiply-add): filter per-step fold and Kalman
+    update about 8 d^3, smoother element build, fold and apply about
+    19 d^3."""
+    return 8 * d ** 3, 19 * d ** 3
+
+
+def measure(w, dtype, steps, warmup, chunk=0):
+    import torch
+    import paper_2102_09964_amd as P
+    model = P.make_model(w["model"]["components"], w["model"]["noise_var"])
+    d = P.state_dim(model)
+    n = w["t"].shape[0]
+    tdt = getattr(torch, dtype)
+    t = torch.as_tensor(w["t"], dtype=torch.float64, device="cuda")
+    y = torch.as_tensor(np.nan_to_num(w["y"]), dtype=tdt, device="cuda")
+    mask = torch.as_tensor(w["mask"], dtype=torch.uint8, device="cuda")
+    opts = P.make_options(chunk=chunk) if chunk else None
+    pipe = P.Pipeline(model, n, dtype, options=opts)
+    for _ in range(warmup):
+        pipe.run(t, y, mask)
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    t0 = time.perf_counter()
+    for i in range(steps):
+        pipe.run(t, y, mask, events=evs[i])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / steps
+    f_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    s_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+    ll = float(pipe.loglik.cpu()[0])
+    status = (P.status(pipe.ws_f), P.status(pipe.ws_s))
+    tsize = 4 if dtype == "float32" else 8
+    fb, sb = algorithmic_bytes(d, tsize, n)
+    ff, sf = algorithmic_flops(d)
+    return {"n": n, "d": d, "ms_per_step": ms_step, "filter_ms": f_ms, "smoother_ms": s_ms,
+            "steps_per_s": n / (ms_step / 1e3), "loglik": ll, "status": status,
+            "filter_bytes": fb, "smoother_bytes": sb, "filter_flops": ff * n, "smoother_flops": sf * n}
+
+
+def roofline_of(m):
+    dom = "filter" if m["filter_ms"] >= m["smoother_ms"] else "smoother"
+    ms = m[dom + "_ms"]
+    gbs = m[dom + "_bytes"] / (ms / 1e3) / 1e9
+    tfl = m[dom + "_flops"] / (ms / 1e3) / 1e12
+    return {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 5), "traffic": None, "kernel": dom + "_scan",
+            "kernel_ms": round(ms, 4), "bytes_per_step": round(m[dom + "_bytes"] / m["n"], 1),
+            "alu_tflops": round(tfl, 3), "alu_frac_fp32_vector": round(tfl / FP32_VECTOR_PEAK_TFLOPS, 5)}
+
+
+def cpu_baseline(w, target_s=12.0):
+    """Sequential FP64 oracle (filter + smoother + log-likelihood) on a
+    prefix of the workload sized for about target_s seconds of one core."""
+    import oracle
+    from oracle.model import OracleModel
+    m = OracleModel(w["model"]["components"], w["model"]["noise_var"])
+    n_all = w["t"].shape[0]
+    probe = min(2000, n_all)
+    t0 = time.perf_counter()
+    oracle.run(m, w["t"][:probe], w["y"][:probe], w["mask"][:probe], filter_moments=False)
+    per = (time.perf_counter() - t0) / probe
+    n = int(min(n_all, max(probe, target_s / per)))
+    t0 = time.perf_counter()
+    oracle.run(m, w["t"][:n], w["y"][:n], w["mask"][:n], filter_moments=False)
+    dt = time.perf_counter() - t0
+    return {"value": round(n / dt, 1), "unit": "time steps/s", "cores": 1, "kind": "oracle",
+            "sample": "first %d of %d steps, filter+smoother+loglik, FP64 sequential C, %.1f s" % (n, n_all, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="rbf6_lognormal", choices=sorted(WORKLOADS))
+    ap.add_argument("--dtype", default="float32", choices=["float32", "float64"])
+    ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-also", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (the multi-GPU time sharding is a design, "
+              "see DESIGN.md); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py: no HIP device", file=sys.stderr)
+        sys.exit(1)
+    w = WORKLOADS[args.workload]()
+    m = measure(w, args.dtype, args.steps, args.warmup, args.chunk)
+    also = []
+    if not args.no_also:
+        other = "float64" if args.dtype == "float32" else "float32"
+        for name, dt in [(args.workload, other), ("matern52_exp", "float32"), ("matern52_exp", "float64"),
+                         ("matern32_interp", "float64"), ("sum_m32_rbf6", "float32")]:
+            if name == args.workload and dt == args.dtype:
+                continue
+            ww = w if name == args.workload else WORKLOADS[name]()
+            mm = measure(ww, dt, max(3, args.steps // 2), 2)
+            also.append({"workload": name, "dtype": dt, "n": mm["n"], "d": mm["d"],
+                         "steps_per_s": round(mm["steps_per_s"], 1), "ms_per_step": round(mm["ms_per_step"], 4),
+                         "filter_ms": round(mm["filter_ms"], 4), "smoother_ms": round(mm["smoother_ms"], 4),
+                         "roofline_frac": roofline_of(mm)["frac"]})
+    out = {
+        "metric": "time steps/sec, filter+smoother+loglik(+grad), FP32 vs FP64, d=2..8, 1 GPU",
+        "value": round(m["steps_per_s"], 1),
+        "unit": "time steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(m["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.dtype == "float32" else "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n_steps": m["n"], "state_dim": m["d"],
+                   "kernel": "RBF Taylor order 6" if args.workload == "rbf6_lognormal" else args.workload,
+                   "scan_dtype": args.dtype, "discretisation": "f64"},
+        "roofline": roofline_of(m),
+        "filter_ms": round(m["filter_ms"], 4),
+        "smoother_ms": round(m["smoother_ms"], 4),
+        "loglik": m["loglik"],
+        "status": list(m["status"]),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w)
+    if also:
+        out["also"] = also
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -394,3 +394,53 @@ def loglik_autograd(theta, kinds_orders, t, y, mask=None, dtype="float32"):
     if _autograd_cls is None:
         _autograd_cls = _make_autograd()
     return _autograd_cls.apply(theta, kinds_orders, t, y, mask, dtype)
+
+
+class Pipeline:
+    """Preallocated filter + smoother (+ log-likelihood) for a fixed model,
+    length and dtype: workspaces and outputs are allocated once, so that
+    ``run()`` only launches kernels (stream-ordered, no synchronisation).
+
+    Events bracketing the two scan launches are recorded on the current
+    stream when ``events`` is true, for per-kernel timing.
+    """
+
+    def __init__(self, model, n, dtype="float32", options=None, full_state=False, device="cuda"):
+        _require_gpu()
+        torch = _torch()
+        self.model = _as_model(model)
+        self.code, self.tdt = _dt(dtype)
+        self.n = int(n)
+        self.d = state_dim(self.model)
+        self.options = options
+        ns = self.d * (self.d + 1) // 2
+        self.ws_f = alloc_workspace(self.model, n, self.code, OP_FILTER, options, device)
+        self.ws_s = alloc_workspace(self.model, n, self.code, OP_SMOOTH, options, device)
+        self.m = torch.empty((self.d, n), dtype=self.tdt, device=device)
+        self.P = torch.empty((ns, n), dtype=self.tdt, device=device)
+        self.loglik = torch.empty(1, dtype=torch.float64, device=device)
+        self.f_mean = torch.empty(n, dtype=self.tdt, device=device)
+        self.f_var = torch.empty(n, dtype=self.tdt, device=device)
+        self.ms = torch.empty((self.d, n), dtype=self.tdt, device=device) if full_state else None
+        self.Ps = torch.empty((ns, n), dtype=self.tdt, device=device) if full_state else None
+        self.device = device
+
+    def run(self, t, y, mask=None, events=None):
+        """events: optional list of 3 torch.cuda.Event recorded before the
+        filter, between filter and smoother, and after the smoother."""
+        L = lib()
+        mp = ctypes.byref(self.model)
+        op = ctypes.byref(self.options) if self.options is not None else None
+        st = _stream()
+        if events:
+            events[0].record()
+        _check(L.pssgp_filter(mp, _p(t), _p(y), _p(mask), None, self.n, self.code, _p(self.m), _p(self.P),
+                              _p(self.loglik), _p(self.ws_f), self.ws_f.numel(), op, st))
+        if events:
+            events[1].record()
+        _check(L.pssgp_smooth(mp, _p(t), _p(self.m), _p(self.P), self.n, self.code, _p(self.f_mean),
+                              _p(self.f_var), _p(self.ms), _p(self.Ps), _p(self.ws_s), self.ws_s.numel(), op,
+                              st))
+        if events:
+            events[2].record()
+        return self.f_mean, self.f_var, self.loglik

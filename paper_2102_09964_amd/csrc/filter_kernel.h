@@ -181,12 +181,11 @@ __global__ __launch_bounds__(PSSGP_WAVE) void filter_scan_kernel(FilterParams<T>
         const T S = dot<D, T>(h, Ph) + R;
         const T v = yk - dot<D, T>(h, mp);
         const T w = obs ? T(1) / S : T(0);
-        if (obs) {
-            if (!(S > T(0)) || !isfinite(S)) bad |= PSSGP_STATUS_BAD_S;
-            if (!isfinite(yk)) bad |= PSSGP_STATUS_NONFINITE;
-            const T term = T(-0.5) * (log(T(6.283185307179586) * S) + v * v * w);
-            kahan_add<T>(ls, lc, term);
-        }
+        // branch-free: missing steps add an exact zero
+        bad |= (obs && (!(S > T(0)) || !isfinite(S))) ? PSSGP_STATUS_BAD_S : 0u;
+        bad |= (obs && !isfinite(yk)) ? PSSGP_STATUS_NONFINITE : 0u;
+        const T term = T(-0.5) * (log(T(6.283185307179586) * S) + v * v * w);
+        kahan_add<T>(ls, lc, obs ? term : T(0));
 #pragma unroll
         for (int i = 0; i < D; i++) m[i] = fma(Ph[i] * w, v, mp[i]);
 #pragma unroll

@@ -163,7 +163,10 @@ __device__ __forceinline__ void gl_load(const T *p, T (&g)[D], T (&L)[D][D])
         for (int j = i; j < D; j++) { L[i][j] = p[D + sidx<D>(i, j)]; L[j][i] = L[i][j]; }
 }
 
-// Smoother element of step k, computed in FP64 and rounded to T.
+// Smoother element of step k, computed in FP64 and rounded to T. The last
+// step's element (0, m, P) is formed without branching: its transition is
+// evaluated for a zero step (F = I, Q = 0) and the result replaced by
+// selects, so that every lane runs the same instruction stream.
 template <class LY, typename T>
 __device__ __forceinline__ void smoother_element(const DevModel &mdl, const double *t, const T *mf,
                                                  const T *Pf, int64_t n, int64_t k, int64_t last,
@@ -180,22 +183,15 @@ __device__ __forceinline__ void smoother_element(const DevModel &mdl, const doub
             P[i][j] = (double)Pf[(size_t)sidx<D>(i, j) * n + k];
             P[j][i] = P[i][j];
         }
-    if (k == last) {
-#pragma unroll
-        for (int i = 0; i < D; i++) {
-            e.g[i] = T(m[i]);
-#pragma unroll
-            for (int j = 0; j < D; j++) { e.E[i][j] = T(0); e.L[i][j] = T(P[i][j]); }
-        }
-        return;
-    }
-    const double dt = t[k + 1] - t[k];
+    const bool is_last = (k == last);
+    const int64_t kn = is_last ? k : k + 1;  // never reads past the series
+    const double dt = t[kn] - t[k];
     double F[D][D], Q[D][D];
     discretize<LY, sizeof(T) == 8>(mdl, dt, false, F, Q);
     double FP[D][D], Pp[D][D], X[D][D];
     mat_mul<D, double>(F, P, FP);
     mat_mul_nt_sym_add<D, double>(FP, F, Q, Pp);
-    if (!cholesky<D, double>(Pp)) bad |= PSSGP_STATUS_CHOLESKY;
+    if (!cholesky<D, double>(Pp) && !is_last) bad |= PSSGP_STATUS_CHOLESKY;
     chol_solve<D, double>(Pp, FP, X);  // X = Pp^-1 F P = E^T
     double Fm[D];
     mat_vec<D, double>(F, m, Fm);
@@ -204,9 +200,9 @@ __device__ __forceinline__ void smoother_element(const DevModel &mdl, const doub
         double acc = m[i];
 #pragma unroll
         for (int k2 = 0; k2 < D; k2++) acc = fma(-X[k2][i], Fm[k2], acc);
-        e.g[i] = T(acc);
+        e.g[i] = T(is_last ? m[i] : acc);
 #pragma unroll
-        for (int j = 0; j < D; j++) e.E[i][j] = T(X[j][i]);
+        for (int j = 0; j < D; j++) e.E[i][j] = T(is_last ? 0.0 : X[j][i]);
     }
     // L = P - E F P (symmetric in exact arithmetic; upper triangle mirrored)
 #pragma unroll
@@ -216,8 +212,9 @@ __device__ __forceinline__ void smoother_element(const DevModel &mdl, const doub
             double acc = P[i][j];
 #pragma unroll
             for (int k2 = 0; k2 < D; k2++) acc = fma(-X[k2][i], FP[k2][j], acc);
-            e.L[i][j] = T(acc);
-            e.L[j][i] = T(acc);
+            const T l = T(is_last ? P[i][j] : acc);
+            e.L[i][j] = l;
+            e.L[j][i] = l;
         }
 }
 

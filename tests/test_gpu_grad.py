@@ -1,0 +1,109 @@
+"""GPU parity of the log-likelihood gradient (hand-written adjoint scan)
+against the oracle's forward-mode sensitivities and central finite
+differences (h = 1e-6 relative) of the FP64 GPU log-likelihood.
+
+Tolerances: FP64 adjoint vs oracle 1e-8 (normwise relative over the
+parameter vector); FP32 adjoint vs oracle 1e-3; finite differences vs the
+FP64 adjoint 1e-5 (the difference quotient's own rounding error is about
+eps * |loglik| / h).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from oracle.model import MATERN12, MATERN32, MATERN52, RBF, OracleModel
+from tests.conftest import gpu_available
+
+pytestmark = pytest.mark.gpu
+
+if not gpu_available():
+    pytest.skip("needs a HIP device", allow_module_level=True)
+
+import torch  # noqa: E402
+
+import paper_2102_09964_amd as P  # noqa: E402
+
+CASES = [
+    ([(MATERN12, 0, 0.7, 1.3)], 0.02, 3000),
+    ([(MATERN32, 0, 0.5, 1.0)], 0.01, 3000),
+    ([(MATERN52, 0, 1.0, 1.0)], 0.01, 3000),
+    ([(RBF, 6, 1.0, 1.0)], 0.01, 1200),
+    ([(MATERN32, 0, 2.0, 0.5), (RBF, 6, 0.5, 0.5)], 0.01, 700),
+    ([(MATERN12, 0, 0.4, 1.0), (MATERN32, 0, 1.0, 0.5)], 0.01, 2000),
+]
+IDS = ["m12", "m32", "m52", "rbf6", "m32+rbf6", "m12+m32"]
+
+
+def _gpu(w, comps, noise, dtype, chunk=4):
+    m = P.make_model(comps, noise)
+    t = torch.as_tensor(w["t"], dtype=torch.float64, device="cuda")
+    y = torch.as_tensor(np.nan_to_num(w["y"]), dtype=getattr(torch, dtype), device="cuda")
+    mask = torch.as_tensor(w["mask"], dtype=torch.uint8, device="cuda")
+    ll, g = P.loglik_grad(m, t, y, mask, dtype=dtype, options=P.make_options(chunk=chunk))
+    return float(ll.cpu()[0]), g.cpu().numpy()
+
+
+def _oracle(w, comps, noise, dtype):
+    y = np.asarray(w["y"], np.float64)
+    if dtype == "float32":
+        y = y.astype(np.float32).astype(np.float64)
+    om = OracleModel(comps, noise, with_derivatives=True)
+    r = oracle.run(om, w["t"], y, w["mask"], gradient=True, smoother=False, filter_moments=False)
+    return r["loglik"], r["grad"]
+
+
+@pytest.mark.parametrize("comps,noise,n", CASES, ids=IDS)
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+def test_grad_vs_oracle(comps, noise, n, dtype):
+    w = workloads.random_series(n, comps, noise, missing=0.15, span=n * 0.02, gap="exponential", seed=n)
+    ll_o, g_o = _oracle(w, comps, noise, dtype)
+    ll_g, g_g = _gpu(w, comps, noise, dtype)
+    err = np.max(np.abs(g_g - g_o)) / np.max(np.abs(g_o))
+    lerr = abs(ll_g - ll_o) / abs(ll_o)
+    print(IDS[CASES.index((comps, noise, n))], dtype, "grad err %.2e loglik err %.2e" % (err, lerr), g_g, g_o,
+          flush=True)
+    tol = 1e-8 if dtype == "float64" else 1e-3
+    assert err <= tol
+    assert lerr <= (1e-9 if dtype == "float64" else 1e-5)
+
+
+def test_grad_vs_central_differences():
+    comps, noise = [(MATERN32, 0, 2.0, 0.5), (RBF, 6, 0.5, 0.5)], 0.01
+    w = workloads.sum_m32_rbf6(n=1 << 16)
+    _, g = _gpu(w, comps, noise, "float64", chunk=16)
+    theta = [2.0, 0.5, 0.5, 0.5, noise]
+    for p in range(len(theta)):
+        h = 1e-6 * theta[p]
+        tp, tm = list(theta), list(theta)
+        tp[p] += h
+        tm[p] -= h
+        cp = [(comps[0][0], 0, tp[0], tp[1]), (comps[1][0], 6, tp[2], tp[3])]
+        cm = [(comps[0][0], 0, tm[0], tm[1]), (comps[1][0], 6, tm[2], tm[3])]
+        lp, _ = _gpu(w, cp, tp[4], "float64", chunk=16)
+        lm, _ = _gpu(w, cm, tm[4], "float64", chunk=16)
+        fd = (lp - lm) / (2 * h)
+        print("param", p, "adjoint", g[p], "fd", fd, flush=True)
+        assert abs(fd - g[p]) <= 1e-5 * max(abs(g[p]), 1e-3 * np.max(np.abs(g)))
+
+
+def test_loglik_grad_loglik_matches_filter():
+    comps, noise = [(MATERN52, 0, 1.0, 1.0)], 0.01
+    w = workloads.matern52_exp(n=50000)
+    ll_g, _ = _gpu(w, comps, noise, "float32", chunk=16)
+    m = P.make_model(comps, noise)
+    ll_f = float(P.loglik(m, w["t"], np.nan_to_num(w["y"]), w["mask"], dtype="float32").cpu()[0])
+    assert ll_g == ll_f
+
+
+def test_autograd_function():
+    comps, noise = [(MATERN32, 0, 0.5, 1.0)], 0.01
+    w = workloads.random_series(4000, comps, noise, missing=0.1, span=40.0, seed=2)
+    t = torch.as_tensor(w["t"], dtype=torch.float64, device="cuda")
+    y = torch.as_tensor(np.nan_to_num(w["y"]), dtype=torch.float64, device="cuda")
+    mask = torch.as_tensor(w["mask"], dtype=torch.uint8, device="cuda")
+    theta = torch.tensor([0.5, 1.0, noise], dtype=torch.float64, requires_grad=True)
+    ll = P.loglik_autograd(theta, [(MATERN32, 0)], t, y, mask, dtype="float64")
+    ll.backward()
+    _, g_o = _oracle(w, comps, noise, "float64")
+    assert np.max(np.abs(theta.grad.numpy() - g_o)) <= 1e-8 * np.max(np.abs(g_o))
