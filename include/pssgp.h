@@ -207,29 +207,42 @@ int pssgp_loglik_grad(const pssgp_model *model, const double *t, const void *y,
 /*
  * Batched form: n_series independent series concatenated along the time
  * axis, series s occupying steps [offsets[s], offsets[s+1]) (offsets:
- * device int64[n_series + 1], offsets[0] = 0, non-decreasing;
- * offsets_host: the same values in host memory, used to lay out the
- * launch). models_host[s] is series s's model; all series must have the
- * same state size and component kinds (their hyperparameters and noise may
- * differ). One launch processes all series: a series start is a filter
- * element with A = 0 and a series end a smoother element with E = 0, so the
- * scans restart at series boundaries without segment flags. loglik: device
- * double[n_series]. Outputs as in pssgp_filter / pssgp_smooth at the
- * concatenated positions.
+ * device int64[n_series + 1], offsets[0] = 0, non-decreasing; offsets_host:
+ * the same values in host memory, used to lay out the launch). Series of
+ * one state layout form a group: groups_host[g] gives the kernel kind
+ * (single-component Matern-1/2, 3/2 or 5/2; lengthscale and variance
+ * ignored) and the series range [series_begin, series_end) of group g;
+ * n_groups is 1 or 2, the groups are contiguous, cover all series and have
+ * ascending state sizes. params: device double[n_series][3], per series
+ * (lengthscale, variance, noise_var). One persistent launch scans all
+ * series: a series start is a filter element with A = 0 (section 3) and a
+ * series end a smoother element with E = 0, so both scans restart at series
+ * boundaries without segment flags. m: device dtype[d_max][n_total], P:
+ * device dtype[NS_max][n_total] (d_max, NS_max of the largest group); a
+ * series of state size d uses rows [0, d) of m and the first d(d+1)/2 rows
+ * of P in its own packing. loglik: device double[n_series].
  */
-int pssgp_batched_filter(const pssgp_model *models_host, int64_t n_series, const int64_t *offsets,
-                         const int64_t *offsets_host, const double *t, const void *y,
-                         const uint8_t *mask, pssgp_dtype dtype, void *m, void *P, double *loglik,
-                         void *ws, size_t ws_bytes, const pssgp_options *opts, void *stream);
+typedef struct pssgp_batch_group {
+    pssgp_component kind;
+    int64_t series_begin;
+    int64_t series_end;
+} pssgp_batch_group;
 
-int pssgp_batched_smooth(const pssgp_model *models_host, int64_t n_series, const int64_t *offsets,
-                         const int64_t *offsets_host, const double *t, const void *m,
-                         const void *P, pssgp_dtype dtype, void *f_mean, void *f_var, void *ws,
-                         size_t ws_bytes, const pssgp_options *opts, void *stream);
+size_t pssgp_batched_workspace_bytes(const pssgp_batch_group *groups_host, int n_groups,
+                                     int64_t n_series, const int64_t *offsets_host,
+                                     pssgp_dtype dtype, int op, const pssgp_options *opts);
 
-size_t pssgp_batched_workspace_bytes(const pssgp_model *models_host, int64_t n_series,
-                                     int64_t n_total, pssgp_dtype dtype, int op,
-                                     const pssgp_options *opts);
+int pssgp_batched_filter(const pssgp_batch_group *groups_host, int n_groups, int64_t n_series,
+                         const int64_t *offsets, const int64_t *offsets_host, const double *params,
+                         const double *t, const void *y, const uint8_t *mask, pssgp_dtype dtype,
+                         void *m, void *P, double *loglik, void *ws, size_t ws_bytes,
+                         const pssgp_options *opts, void *stream);
+
+int pssgp_batched_smooth(const pssgp_batch_group *groups_host, int n_groups, int64_t n_series,
+                         const int64_t *offsets, const int64_t *offsets_host, const double *params,
+                         const double *t, const void *m, const void *P, pssgp_dtype dtype,
+                         void *f_mean, void *f_var, void *ws, size_t ws_bytes,
+                         const pssgp_options *opts, void *stream);
 
 /* Status word of the most recent call that used workspace ws (read after
  * synchronising stream); bits: PSSGP_STATUS_*. */

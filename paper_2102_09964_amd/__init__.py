@@ -44,6 +44,10 @@ class Model(ctypes.Structure):
                 ("comp", Component * 4), ("noise_var", ctypes.c_double)]
 
 
+class BatchGroup(ctypes.Structure):
+    _fields_ = [("kind", Component), ("series_begin", ctypes.c_int64), ("series_end", ctypes.c_int64)]
+
+
 class Options(ctypes.Structure):
     _fields_ = [("chunk", ctypes.c_uint32), ("deterministic", ctypes.c_uint32),
                 ("reserved", ctypes.c_uint32 * 6)]
@@ -71,11 +75,12 @@ SIGNATURES = [
                                     _VP]),
     ("pssgp_loglik_grad", ctypes.c_int, [_MP, _VP, _VP, _VP, _I64, ctypes.c_int, _VP, _VP, _VP, _SZ,
                                          _OP, _VP]),
-    ("pssgp_batched_filter", ctypes.c_int, [_MP, _I64, _VP, _VP, _VP, _VP, _VP, ctypes.c_int, _VP, _VP,
-                                            _VP, _VP, _SZ, _OP, _VP]),
-    ("pssgp_batched_smooth", ctypes.c_int, [_MP, _I64, _VP, _VP, _VP, _VP, _VP, ctypes.c_int, _VP, _VP,
-                                            _VP, _SZ, _OP, _VP]),
-    ("pssgp_batched_workspace_bytes", _SZ, [_MP, _I64, _I64, ctypes.c_int, ctypes.c_int, _OP]),
+    ("pssgp_batched_workspace_bytes", _SZ, [ctypes.c_void_p, ctypes.c_int, _I64, _VP, ctypes.c_int, ctypes.c_int,
+                                            _OP]),
+    ("pssgp_batched_filter", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _I64, _VP, _VP, _VP, _VP, _VP, _VP,
+                                            ctypes.c_int, _VP, _VP, _VP, _VP, _SZ, _OP, _VP]),
+    ("pssgp_batched_smooth", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _I64, _VP, _VP, _VP, _VP, _VP, _VP,
+                                            ctypes.c_int, _VP, _VP, _VP, _SZ, _OP, _VP]),
     ("pssgp_status", ctypes.c_int, [_VP, _VP, ctypes.POINTER(ctypes.c_uint32)]),
 ]
 
@@ -441,6 +446,85 @@ class Pipeline:
         _check(L.pssgp_smooth(mp, _p(t), _p(self.m), _p(self.P), self.n, self.code, _p(self.f_mean),
                               _p(self.f_var), _p(self.ms), _p(self.Ps), _p(self.ws_s), self.ws_s.numel(), op,
                               st))
+        if events:
+            events[2].record()
+        return self.f_mean, self.f_var, self.loglik
+
+
+_STATE_DIM = {MATERN12: 1, MATERN32: 2, MATERN52: 3}
+
+
+def batch_groups(kinds):
+    """Groups of consecutive series with the same (Matern) kind; kinds must be
+    sorted by state size. Returns a ctypes array of BatchGroup."""
+    kinds = [int(k) for k in kinds]
+    groups = []
+    start = 0
+    for i in range(1, len(kinds) + 1):
+        if i == len(kinds) or kinds[i] != kinds[start]:
+            groups.append((kinds[start], start, i))
+            start = i
+    arr = (BatchGroup * len(groups))()
+    for g, (k, a, b) in enumerate(groups):
+        arr[g].kind.kind = k
+        arr[g].series_begin = a
+        arr[g].series_end = b
+    return arr
+
+
+class BatchedPipeline:
+    """Preallocated batched filter + smoother over concatenated series.
+
+    kinds: per-series Matern kind (sorted by state size, at most two kinds);
+    offsets: int64 [n_series + 1]; params: float64 [n_series, 3] with
+    (lengthscale, variance, noise_var) per series.
+    """
+
+    def __init__(self, kinds, offsets, params, dtype="float32", options=None, device="cuda"):
+        _require_gpu()
+        torch = _torch()
+        self.groups = batch_groups(kinds)
+        self.ng = len(self.groups)
+        self.offsets_host = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+        self.ns = self.offsets_host.shape[0] - 1
+        self.n = int(self.offsets_host[-1])
+        self.offsets = torch.as_tensor(self.offsets_host, device=device)
+        self.params = _dev(np.asarray(params, dtype=np.float64).reshape(self.ns, 3), torch.float64, device)
+        self.code, self.tdt = _dt(dtype)
+        self.options = options
+        dmax = max(_STATE_DIM[int(k)] for k in kinds)
+        self.dmax = dmax
+        L = lib()
+        op = ctypes.byref(options) if options is not None else None
+        nb_f = L.pssgp_batched_workspace_bytes(self.groups, self.ng, self.ns, self.offsets_host.ctypes.data,
+                                               self.code, OP_FILTER, op)
+        nb_s = L.pssgp_batched_workspace_bytes(self.groups, self.ng, self.ns, self.offsets_host.ctypes.data,
+                                               self.code, OP_SMOOTH, op)
+        if nb_f == 0 or nb_s == 0:
+            raise PssgpError(-1, L.pssgp_last_error().decode())
+        self.ws_f = torch.empty(nb_f, dtype=torch.uint8, device=device)
+        self.ws_s = torch.empty(nb_s, dtype=torch.uint8, device=device)
+        self.m = torch.empty((dmax, self.n), dtype=self.tdt, device=device)
+        self.P = torch.empty((dmax * (dmax + 1) // 2, self.n), dtype=self.tdt, device=device)
+        self.loglik = torch.empty(self.ns, dtype=torch.float64, device=device)
+        self.f_mean = torch.empty(self.n, dtype=self.tdt, device=device)
+        self.f_var = torch.empty(self.n, dtype=self.tdt, device=device)
+
+    def run(self, t, y, mask=None, events=None):
+        L = lib()
+        op = ctypes.byref(self.options) if self.options is not None else None
+        st = _stream()
+        oh = self.offsets_host.ctypes.data
+        if events:
+            events[0].record()
+        _check(L.pssgp_batched_filter(self.groups, self.ng, self.ns, _p(self.offsets), oh, _p(self.params), _p(t),
+                                      _p(y), _p(mask), self.code, _p(self.m), _p(self.P), _p(self.loglik),
+                                      _p(self.ws_f), self.ws_f.numel(), op, st))
+        if events:
+            events[1].record()
+        _check(L.pssgp_batched_smooth(self.groups, self.ng, self.ns, _p(self.offsets), oh, _p(self.params), _p(t),
+                                      _p(self.m), _p(self.P), self.code, _p(self.f_mean), _p(self.f_var),
+                                      _p(self.ws_s), self.ws_s.numel(), op, st))
         if events:
             events[2].record()
         return self.f_mean, self.f_var, self.loglik

@@ -1,0 +1,212 @@
+// Batched form: thousands of independent series of uneven lengths and
+// hyperparameters in one persistent launch per scan.
+//
+// The series are concatenated along the time axis. A series start is a
+// filter element with A = 0 (the prior element of section 3) and a series
+// end a smoother element with E = 0 (the last element of the smoother), so
+// both scans restart at series boundaries through their elements alone:
+// tiles and lane chunks may straddle series without any segment flags.
+// Series of the same state layout form a group; up to two groups (ascending
+// state size) share one launch, each tile running the code of its group's
+// layout. The kernels are persistent: a fixed grid of workgroups keeps
+// taking tile tickets until all tiles of both groups are done.
+//
+// The per-series hyperparameters (length-scale, variance, noise variance)
+// come from a device table; the model constants of a group are those of
+// unit length-scale and unit variance, scaled per step. The per-step
+// log-likelihood terms are written out and summed per series, one wave per
+// series in a fixed order, by a second kernel.
+#include "filter_kernel.h"
+#include "launch.h"
+#include "smoother_kernel.h"
+
+namespace {
+
+template <class LY>
+__device__ void unpack_batch_model(const BatchModel &bm, DevModel &m)
+{
+    constexpr int D = LY::D;
+    if (threadIdx.x == 0) {
+        m.d = D;
+        m.nblk = 1;
+        m.R = 0.0;
+        m.blk[0] = bm.blk;
+        m.blk[0].off = 0;
+        m.blk[0].fc_off = 0;
+        for (int i = 0; i < D; i++) {
+            m.H[i] = bm.H[i];
+            for (int j = 0; j < D; j++) m.Pinf[i * D + j] = bm.Pinf1[i * D + j];
+        }
+        for (int i = 0; i < D * D * D; i++) m.fcoef[i] = bm.fcoef[i];
+    }
+}
+
+__device__ __forceinline__ void series_view(ManySeries &sv, const BatchLaunch &a, const BatchGroup &g, int64_t k0)
+{
+    sv.off = a.offsets;
+    sv.prm = a.params;
+    sv.s_lo = g.s_begin;
+    sv.s_hi = g.s_end;
+    sv.locate(k0 < g.k_end ? k0 : g.k_end - 1);
+}
+
+template <class LA, class LB, typename T>
+__global__ __launch_bounds__(PSSGP_WAVE) void batched_filter_kernel(FilterParams<T> p, BatchLaunch a)
+{
+    constexpr int INCL = AggLayout<(LA::D > LB::D ? LA::D : LB::D)>::INCL;
+    __shared__ DevModel mdl0, mdl1;
+    __shared__ T s_carry[INCL];
+    __shared__ uint32_t s_tile;
+    unpack_batch_model<LA>(a.bm[0], mdl0);
+    if (a.ngroups > 1) unpack_batch_model<LB>(a.bm[1], mdl1);
+    const int lane = lane_id();
+    while (true) {
+        __syncthreads();
+        if (lane == 0) s_tile = ticket_next(&p.ctl->ticket);
+        __syncthreads();
+        const int slot = (int)s_tile;
+        if (slot >= a.total_tiles) break;
+        const int gi = (a.ngroups > 1 && slot >= a.g[1].slot_base) ? 1 : 0;
+        const BatchGroup &g = a.g[gi];
+        const int tile = slot - g.slot_base;
+        TileRange tr{g.k_begin, g.k_end, g.ntiles, g.slot_base};
+        ManySeries sv;
+        series_view(sv, a, g, g.k_begin + ((int64_t)tile * PSSGP_WAVE + lane) * p.chunk);
+        double ll = 0.0;
+        if (gi == 0)
+            filter_tile<LA, T, T, F_MOMENTS, ManySeries>(p, mdl0, sv, tr, tile, s_carry, ll);
+        else
+            filter_tile<LB, T, T, F_MOMENTS, ManySeries>(p, mdl1, sv, tr, tile, s_carry, ll);
+    }
+}
+
+template <class LA, class LB, typename T>
+__global__ __launch_bounds__(PSSGP_WAVE) void batched_smoother_kernel(SmoothParams<T> p, BatchLaunch a)
+{
+    constexpr int INCL = SAggLayout<(LA::D > LB::D ? LA::D : LB::D)>::INCL;
+    __shared__ DevModel mdl0, mdl1;
+    __shared__ T s_carry[INCL];
+    __shared__ uint32_t s_tile;
+    unpack_batch_model<LA>(a.bm[0], mdl0);
+    if (a.ngroups > 1) unpack_batch_model<LB>(a.bm[1], mdl1);
+    const int lane = lane_id();
+    while (true) {
+        __syncthreads();
+        if (lane == 0) s_tile = ticket_next(&p.ctl->ticket);
+        __syncthreads();
+        const int ticket = (int)s_tile;
+        if (ticket >= a.total_tiles) break;
+        const int slot = a.total_tiles - 1 - ticket;  // from the end
+        const int gi = (a.ngroups > 1 && slot >= a.g[1].slot_base) ? 1 : 0;
+        const BatchGroup &g = a.g[gi];
+        const int tile = slot - g.slot_base;
+        STileRange tr{g.k_begin, g.k_end, g.ntiles, g.slot_base};
+        ManySeries sv;
+        series_view(sv, a, g, g.k_begin + ((int64_t)tile * PSSGP_WAVE + lane) * p.chunk);
+        if (gi == 0)
+            smoother_tile<LA, T, false, ManySeries>(p, mdl0, sv, tr, tile, s_carry);
+        else
+            smoother_tile<LB, T, false, ManySeries>(p, mdl1, sv, tr, tile, s_carry);
+    }
+}
+
+// One wave per series: sum of its per-step log-likelihood terms in FP64,
+// lanes strided over the steps, then a fixed-order wave tree.
+template <typename T>
+__global__ __launch_bounds__(256) void series_loglik_kernel(const T *terms, const int64_t *off, int64_t n_series,
+                                                           double *out)
+{
+    const int64_t s = (int64_t)blockIdx.x * (blockDim.x / PSSGP_WAVE) + threadIdx.x / PSSGP_WAVE;
+    const int lane = lane_id();
+    double acc = 0.0;
+    if (s < n_series)
+        for (int64_t k = off[s] + lane; k < off[s + 1]; k += PSSGP_WAVE) acc += (double)terms[k];
+    acc = wave_sum(acc);
+    if (s < n_series && lane == 0) out[s] = acc;
+}
+
+template <class LA, class LB, typename T>
+int launch_bf(const BatchLaunch &a, hipStream_t s)
+{
+    FilterParams<T> p;
+    p.t = a.t;
+    p.y = (const T *)a.y;
+    p.mask = a.mask;
+    p.noise_k = nullptr;
+    p.n = a.n;
+    p.chunk = a.chunk;
+    p.ntiles = a.total_tiles;
+    p.deterministic = a.deterministic;
+    p.m = (T *)a.m;
+    p.P = (T *)a.P;
+    p.loglik = nullptr;
+    p.ck = nullptr;
+    p.ll_terms = (T *)a.ll_terms;
+    p.ctl = a.ws.ctl;
+    p.flags = a.ws.flags;
+    p.aggp = (T *)a.ws.aggp;
+    p.inclp = (T *)a.ws.inclp;
+    p.lanep = (T *)a.ws.lanep;
+    p.partials = a.ws.partials;
+    hipLaunchKernelGGL((batched_filter_kernel<LA, LB, T>), dim3(a.grid), dim3(PSSGP_WAVE), 0, s, p, a);
+    int rc = (int)hipGetLastError();
+    if (rc) return rc;
+    const int per_block = 256 / PSSGP_WAVE;
+    const dim3 grid((unsigned)((a.n_series + per_block - 1) / per_block));
+    hipLaunchKernelGGL((series_loglik_kernel<T>), grid, dim3(256), 0, s, (const T *)a.ll_terms, a.offsets,
+                       a.n_series, a.loglik);
+    return (int)hipGetLastError();
+}
+
+template <class LA, class LB, typename T>
+int launch_bs(const BatchLaunch &a, hipStream_t s)
+{
+    SmoothParams<T> p;
+    p.t = a.t;
+    p.m = (const T *)a.m;
+    p.P = (const T *)a.P;
+    p.n = a.n;
+    p.chunk = a.chunk;
+    p.ntiles = a.total_tiles;
+    p.deterministic = a.deterministic;
+    p.f_mean = (T *)a.f_mean;
+    p.f_var = (T *)a.f_var;
+    p.ms = nullptr;
+    p.Ps = nullptr;
+    p.ctl = a.ws.ctl;
+    p.flags = a.ws.flags;
+    p.aggp = (T *)a.ws.aggp;
+    p.inclp = (T *)a.ws.inclp;
+    p.lanep = (T *)a.ws.lanep;
+    hipLaunchKernelGGL((batched_smoother_kernel<LA, LB, T>), dim3(a.grid), dim3(PSSGP_WAVE), 0, s, p, a);
+    return (int)hipGetLastError();
+}
+
+// (d0, d1) with d1 = d0 for a single group
+#define PSSGP_BATCH_PAIRS(X) X(1, 1) X(2, 2) X(3, 3) X(1, 2) X(1, 3) X(2, 3)
+
+}  // namespace
+
+int launch_batched_filter(const BatchLaunch &a, bool f64, hipStream_t s)
+{
+    const int d0 = a.bm[0].d, d1 = a.ngroups > 1 ? a.bm[1].d : d0;
+#define X(A, B)                                                                                   \
+    if (d0 == A && d1 == B)                                                                       \
+        return f64 ? launch_bf<Layout<A, 0>, Layout<B, 0>, double>(a, s)                          \
+                   : launch_bf<Layout<A, 0>, Layout<B, 0>, float>(a, s);
+    PSSGP_BATCH_PAIRS(X)
+#undef X
+    return -1;
+}
+
+int launch_batched_smooth(const BatchLaunch &a, bool f64, hipStream_t s)
+{
+    const int d0 = a.bm[0].d, d1 = a.ngroups > 1 ? a.bm[1].d : d0;
+#define X(A, B)                                                                                   \
+    if (d0 == A && d1 == B)                                                                       \
+        return f64 ? launch_bs<Layout<A, 0>, Layout<B, 0>, double>(a, s)                          \
+                   : launch_bs<Layout<A, 0>, Layout<B, 0>, float>(a, s);
+    PSSGP_BATCH_PAIRS(X)
+#undef X
+    return -1;
+}

@@ -204,6 +204,197 @@ int run_filter(const pssgp_model *model, const double *t, const void *y, const u
     return check_launch(launch_filter(dm, b0, b1, dtype == PSSGP_F64, a, s), "filter launch");
 }
 
+struct BatchPlan {
+    int ngroups = 0, dmax = 0, chunk = kDefaultChunk, total_tiles = 0;
+    size_t tsize = 4;
+    BatchGroup g[2];
+    BatchModel bm[2];
+    size_t off_flags = 0, off_agg = 0, off_incl = 0, off_lane = 0, off_part = 0, off_terms = 0, total = 0;
+};
+
+int make_batch_plan(const pssgp_batch_group *groups, int ngroups, int64_t n_series, const int64_t *off,
+                    pssgp_dtype dtype, int op, const pssgp_options *opts, BatchPlan &bp)
+{
+    if (!groups || ngroups < 1 || ngroups > 2 || n_series < 1 || !off) {
+        pssgp_set_error("batched: 1 or 2 groups, n_series >= 1 and host offsets are required");
+        return PSSGP_EINVAL;
+    }
+    if (dtype != PSSGP_F32 && dtype != PSSGP_F64) {
+        pssgp_set_error("dtype must be PSSGP_F32 or PSSGP_F64");
+        return PSSGP_EINVAL;
+    }
+    if (opts && opts->chunk > 64) {
+        pssgp_set_error("options.chunk must be <= 64");
+        return PSSGP_EINVAL;
+    }
+    if (off[0] != 0) {
+        pssgp_set_error("batched: offsets[0] must be 0");
+        return PSSGP_EINVAL;
+    }
+    for (int64_t s = 0; s < n_series; s++)
+        if (off[s + 1] < off[s]) {
+            pssgp_set_error("batched: offsets must be non-decreasing");
+            return PSSGP_EINVAL;
+        }
+    bp.ngroups = ngroups;
+    bp.chunk = chunk_of(opts);
+    bp.tsize = dtype == PSSGP_F64 ? 8 : 4;
+    int64_t expect = 0;
+    int prev_d = 0;
+    for (int gi = 0; gi < ngroups; gi++) {
+        const pssgp_batch_group &G = groups[gi];
+        if (G.kind.kind < PSSGP_MATERN12 || G.kind.kind > PSSGP_MATERN52) {
+            pssgp_set_error("batched: group %d must be a single Matern component", gi);
+            return PSSGP_EUNSUPPORTED;
+        }
+        if (G.series_begin != expect || G.series_end < G.series_begin || G.series_end > n_series) {
+            pssgp_set_error("batched: groups must be contiguous and cover all series");
+            return PSSGP_EINVAL;
+        }
+        expect = G.series_end;
+        pssgp_model um;
+        std::memset(&um, 0, sizeof(um));
+        um.n_comp = 1;
+        um.comp[0].kind = G.kind.kind;
+        um.comp[0].order = 0;
+        um.comp[0].lengthscale = 1.0;
+        um.comp[0].variance = 1.0;
+        um.noise_var = 1.0;
+        DevModel dm;
+        int d = pssgp_build_devmodel(&um, &dm, nullptr);
+        if (d < 0) return d;
+        if (d <= prev_d) {
+            pssgp_set_error("batched: groups must have ascending state sizes");
+            return PSSGP_EUNSUPPORTED;
+        }
+        prev_d = d;
+        BatchModel &bm = bp.bm[gi];
+        std::memset(&bm, 0, sizeof(bm));
+        bm.d = d;
+        bm.blk = dm.blk[0];
+        for (int i = 0; i < d; i++) {
+            bm.H[i] = dm.H[i];
+            for (int j = 0; j < d; j++) bm.Pinf1[i * d + j] = dm.Pinf[i * d + j];
+        }
+        for (int i = 0; i < d * d * d; i++) bm.fcoef[i] = dm.fcoef[i];
+        BatchGroup &g = bp.g[gi];
+        g.s_begin = G.series_begin;
+        g.s_end = G.series_end;
+        g.k_begin = off[G.series_begin];
+        g.k_end = off[G.series_end];
+        const int64_t per_tile = (int64_t)64 * bp.chunk;
+        g.ntiles = (int)((g.k_end - g.k_begin + per_tile - 1) / per_tile);
+        g.slot_base = bp.total_tiles;
+        bp.total_tiles += g.ntiles;
+        bp.dmax = d;
+    }
+    if (expect != n_series) {
+        pssgp_set_error("batched: groups must cover all series");
+        return PSSGP_EINVAL;
+    }
+    const int d = bp.dmax;
+    const size_t nt = (size_t)(bp.total_tiles > 0 ? bp.total_tiles : 1);
+    const int64_t n = off[n_series];
+    size_t o = ctl_bytes();
+    auto take = [&](size_t bytes) {
+        size_t r = o;
+        o = align_up(o + bytes);
+        return r;
+    };
+    bp.off_flags = take(nt * sizeof(uint32_t));
+    const int agg = (op == PSSGP_OP_SMOOTH) ? smooth_agg_elems(d) : filter_agg_elems(d);
+    const int incl = (op == PSSGP_OP_SMOOTH) ? smooth_incl_elems(d) : filter_incl_elems(d);
+    bp.off_agg = take(nt * agg * bp.tsize);
+    bp.off_incl = take(nt * incl * bp.tsize);
+    bp.off_lane = take(nt * 64 * agg * bp.tsize);
+    bp.off_part = take(nt * sizeof(double) * 3);
+    if (op != PSSGP_OP_SMOOTH) bp.off_terms = take((size_t)(n > 0 ? n : 1) * bp.tsize);
+    bp.total = o;
+    return PSSGP_OK;
+}
+
+int persistent_grid(int total_tiles)
+{
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+            cus = v;
+        else
+            cus = 256;
+    }
+    const int cap = cus * 4;  // resident one-wave workgroups at the kernels' register use
+    return total_tiles < cap ? (total_tiles > 0 ? total_tiles : 1) : cap;
+}
+
+int run_batched(const pssgp_batch_group *groups, int ngroups, int64_t n_series, const int64_t *offsets,
+                const int64_t *offsets_host, const double *params, const double *t, const void *y,
+                const uint8_t *mask, pssgp_dtype dtype, void *m, void *P, double *loglik, void *f_mean,
+                void *f_var, void *ws, size_t ws_bytes, const pssgp_options *opts, void *stream, int op)
+{
+    BatchPlan bp;
+    int rc = make_batch_plan(groups, ngroups, n_series, offsets_host, dtype, op, opts, bp);
+    if (rc) return rc;
+    if (!offsets || !params || !t || !m || !P) {
+        pssgp_set_error("batched: offsets, params, t, m and P must be device pointers");
+        return PSSGP_EINVAL;
+    }
+    if (op == PSSGP_OP_FILTER && (!y || !loglik)) {
+        pssgp_set_error("batched filter: y and loglik must be device pointers");
+        return PSSGP_EINVAL;
+    }
+    if (op == PSSGP_OP_SMOOTH && (!f_mean || !f_var)) {
+        pssgp_set_error("batched smoother: f_mean and f_var must be device pointers");
+        return PSSGP_EINVAL;
+    }
+    if (!ws) {
+        pssgp_set_error("workspace is NULL");
+        return PSSGP_EINVAL;
+    }
+    if (ws_bytes < bp.total) {
+        pssgp_set_error("workspace too small: %zu < %zu bytes", ws_bytes, bp.total);
+        return PSSGP_EWORKSPACE;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    char *b = (char *)ws;
+    BatchLaunch a;
+    std::memset(&a, 0, sizeof(a));
+    a.ngroups = bp.ngroups;
+    for (int i = 0; i < 2; i++) { a.g[i] = bp.g[i]; a.bm[i] = bp.bm[i]; }
+    a.total_tiles = bp.total_tiles;
+    a.grid = persistent_grid(bp.total_tiles);
+    a.offsets = offsets;
+    a.params = params;
+    a.n_series = n_series;
+    a.n = offsets_host[n_series];
+    a.chunk = bp.chunk;
+    a.deterministic = (opts && opts->deterministic) ? 1 : 0;
+    a.t = t;
+    a.y = y;
+    a.mask = mask;
+    a.m = m;
+    a.P = P;
+    a.f_mean = f_mean;
+    a.f_var = f_var;
+    a.loglik = loglik;
+    a.ll_terms = bp.off_terms ? b + bp.off_terms : nullptr;
+    a.ws.ctl = (WsCtl *)b;
+    a.ws.flags = (uint32_t *)(b + bp.off_flags);
+    a.ws.aggp = b + bp.off_agg;
+    a.ws.inclp = b + bp.off_incl;
+    a.ws.lanep = b + bp.off_lane;
+    a.ws.partials = (double *)(b + bp.off_part);
+    const bool zero_ll = (op == PSSGP_OP_FILTER && a.n == 0);
+    rc = launch_ws_init(a.ws.ctl, a.ws.flags, bp.total_tiles, zero_ll ? loglik : nullptr,
+                        zero_ll ? (int)n_series : 0, s);
+    if ((rc = hip_err((hipError_t)rc, "workspace init"))) return rc;
+    if (a.n == 0) return PSSGP_OK;
+    const bool f64 = dtype == PSSGP_F64;
+    rc = (op == PSSGP_OP_FILTER) ? launch_batched_filter(a, f64, s) : launch_batched_smooth(a, f64, s);
+    return check_launch(rc, "batched launch");
+}
+
 }  // namespace
 
 extern "C" {
@@ -393,26 +584,34 @@ int pssgp_loglik_grad(const pssgp_model *model, const double *t, const void *y, 
     return check_launch(launch_grad(dm, b0, b1, dtype == PSSGP_F64, g, s), "adjoint launch");
 }
 
-int pssgp_batched_filter(const pssgp_model *, int64_t, const int64_t *, const int64_t *, const double *,
-                         const void *, const uint8_t *, pssgp_dtype, void *, void *, double *, void *,
-                         size_t, const pssgp_options *, void *)
+size_t pssgp_batched_workspace_bytes(const pssgp_batch_group *groups_host, int n_groups, int64_t n_series,
+                                     const int64_t *offsets_host, pssgp_dtype dtype, int op,
+                                     const pssgp_options *opts)
 {
-    pssgp_set_error("batched filter not available in this build");
-    return PSSGP_EUNSUPPORTED;
+    if (op != PSSGP_OP_FILTER && op != PSSGP_OP_SMOOTH) return 0;
+    BatchPlan bp;
+    if (make_batch_plan(groups_host, n_groups, n_series, offsets_host, dtype, op, opts, bp)) return 0;
+    return bp.total;
 }
 
-int pssgp_batched_smooth(const pssgp_model *, int64_t, const int64_t *, const int64_t *, const double *,
-                         const void *, const void *, pssgp_dtype, void *, void *, void *, size_t,
-                         const pssgp_options *, void *)
+int pssgp_batched_filter(const pssgp_batch_group *groups_host, int n_groups, int64_t n_series,
+                         const int64_t *offsets, const int64_t *offsets_host, const double *params,
+                         const double *t, const void *y, const uint8_t *mask, pssgp_dtype dtype, void *m,
+                         void *P, double *loglik, void *ws, size_t ws_bytes, const pssgp_options *opts,
+                         void *stream)
 {
-    pssgp_set_error("batched smoother not available in this build");
-    return PSSGP_EUNSUPPORTED;
+    return run_batched(groups_host, n_groups, n_series, offsets, offsets_host, params, t, y, mask, dtype, m, P,
+                       loglik, nullptr, nullptr, ws, ws_bytes, opts, stream, PSSGP_OP_FILTER);
 }
 
-size_t pssgp_batched_workspace_bytes(const pssgp_model *, int64_t, int64_t, pssgp_dtype, int,
-                                     const pssgp_options *)
+int pssgp_batched_smooth(const pssgp_batch_group *groups_host, int n_groups, int64_t n_series,
+                         const int64_t *offsets, const int64_t *offsets_host, const double *params,
+                         const double *t, const void *m, const void *P, pssgp_dtype dtype, void *f_mean,
+                         void *f_var, void *ws, size_t ws_bytes, const pssgp_options *opts, void *stream)
 {
-    return 0;
+    return run_batched(groups_host, n_groups, n_series, offsets, offsets_host, params, t, nullptr, nullptr,
+                       dtype, (void *)m, (void *)P, nullptr, f_mean, f_var, ws, ws_bytes, opts, stream,
+                       PSSGP_OP_SMOOTH);
 }
 
 int pssgp_status(void *ws, void *stream, uint32_t *bits_host)

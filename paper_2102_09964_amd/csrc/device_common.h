@@ -123,14 +123,32 @@ __device__ __forceinline__ void expm_companion(const DevBlock &bk, double s, dou
 // first: step 0, F = 0 and Q = Pinf (first filter element, section 3).
 // ACC selects the Taylor evaluation for RBF blocks (full FP64 accuracy)
 // instead of the spectral expansion (faster, about 1e-12 absolute).
+// Per-step scales: inverse length-scale of each block and a multiplier of
+// the stationary covariance (1 for a single series, whose constants already
+// hold the variances; the series variance for the batched form, whose
+// constants hold the unit-variance covariance).
+struct StepScale {
+    double inv_ell[PSSGP_MAXBLK];
+    double var_mult;
+};
+
+__device__ __forceinline__ StepScale model_scale(const DevModel &mdl)
+{
+    StepScale sc;
+    sc.inv_ell[0] = mdl.blk[0].inv_ell;
+    sc.inv_ell[1] = mdl.blk[1].inv_ell;
+    sc.var_mult = 1.0;
+    return sc;
+}
+
 template <class LY, int b, bool ACC>
-__device__ __forceinline__ void disc_block(const DevModel &mdl, double dt,
+__device__ __forceinline__ void disc_block(const DevModel &mdl, const StepScale &sc, double dt,
                                            double (&F)[LY::D][LY::D], double (&Q)[LY::D][LY::D])
 {
     constexpr int dc = LY::bdim(b);
     constexpr int o = LY::boff(b);
     const DevBlock &bk = mdl.blk[b];
-    const double s = dt * bk.inv_ell;
+    const double s = dt * sc.inv_ell[b];
     if (ACC && bk.kind == BLK_RBF) {
         double X[dc][dc];
         expm_companion<dc>(bk, s, X);
@@ -188,13 +206,13 @@ __device__ __forceinline__ void disc_block(const DevModel &mdl, double dt,
             double acc = mdl.Pinf[(o + i) * LY::D + o + j];
 #pragma unroll
             for (int k = 0; k < dc; k++) acc = fma(-FP[i][k], F[o + j][o + k], acc);
-            Q[o + i][o + j] = acc;
-            Q[o + j][o + i] = acc;
+            Q[o + i][o + j] = acc * sc.var_mult;
+            Q[o + j][o + i] = acc * sc.var_mult;
         }
 }
 
 template <class LY, bool ACC>
-__device__ __forceinline__ void discretize(const DevModel &mdl, double dt, bool first,
+__device__ __forceinline__ void discretize(const DevModel &mdl, const StepScale &sc, double dt, bool first,
                                            double (&F)[LY::D][LY::D], double (&Q)[LY::D][LY::D])
 {
     constexpr int D = LY::D;
@@ -202,8 +220,8 @@ __device__ __forceinline__ void discretize(const DevModel &mdl, double dt, bool 
     for (int i = 0; i < D; i++)
 #pragma unroll
         for (int j = 0; j < D; j++) { F[i][j] = 0.0; Q[i][j] = 0.0; }
-    disc_block<LY, 0, ACC>(mdl, dt, F, Q);
-    if constexpr (LY::NB > 1) disc_block<LY, 1, ACC>(mdl, dt, F, Q);
+    disc_block<LY, 0, ACC>(mdl, sc, dt, F, Q);
+    if constexpr (LY::NB > 1) disc_block<LY, 1, ACC>(mdl, sc, dt, F, Q);
     // exact special cases: a zero step is the identity map, step 0 is the prior
     const bool zero = (dt == 0.0);
 #pragma unroll
@@ -212,7 +230,7 @@ __device__ __forceinline__ void discretize(const DevModel &mdl, double dt, bool 
         for (int j = 0; j < D; j++) {
             const double fid = (i == j) ? 1.0 : 0.0;
             F[i][j] = first ? 0.0 : (zero ? fid : F[i][j]);
-            Q[i][j] = first ? mdl.Pinf[i * D + j] : (zero ? 0.0 : Q[i][j]);
+            Q[i][j] = first ? mdl.Pinf[i * D + j] * sc.var_mult : (zero ? 0.0 : Q[i][j]);
         }
 }
 
@@ -463,3 +481,65 @@ __device__ __forceinline__ void model_to_lds(const DevModel &src, DevModel &dst)
 }
 
 #define PSSGP_RELOAD_CONSTANTS() asm volatile("" ::: "memory")
+
+// ------------------------------------------------------------------ series views
+//
+// The scans see their input through a series view that gives, per step, the
+// model scales, whether the step starts a series (its filter element is the
+// prior one, A = 0) and whether it ends one (its smoother element is
+// (0, m, P)). One series: the whole array. Batched: series s covers steps
+// [offsets[s], offsets[s+1]) of the concatenation and has its own
+// (length-scale, variance, noise variance); the scans restart at series
+// boundaries through these elements alone, with no segment flags.
+
+struct OneSeries {
+    int64_t n;
+    StepScale sc;
+    double R;
+    __device__ __forceinline__ void init(const DevModel &mdl, int64_t n_)
+    {
+        n = n_;
+        sc = model_scale(mdl);
+        R = mdl.R;
+    }
+    __device__ __forceinline__ void seek(int64_t) {}
+    __device__ __forceinline__ bool first(int64_t k) const { return k == 0; }
+    __device__ __forceinline__ bool last(int64_t k) const { return k == n - 1; }
+};
+
+struct ManySeries {
+    const int64_t *off;     // [n_series + 1]
+    const double *prm;      // [n_series][3]: lengthscale, variance, noise variance
+    int64_t s_lo, s_hi;     // series range of this group
+    int64_t s, beg, end;    // current series and its step range
+    StepScale sc;
+    double R;
+    __device__ __forceinline__ void load()
+    {
+        beg = off[s];
+        end = off[s + 1];
+        sc.inv_ell[0] = 1.0 / prm[3 * s];
+        sc.inv_ell[1] = 0.0;
+        sc.var_mult = prm[3 * s + 1];
+        R = prm[3 * s + 2];
+    }
+    // position on the series containing step k (binary search)
+    __device__ __forceinline__ void locate(int64_t k)
+    {
+        int64_t lo = s_lo, hi = s_hi - 1;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (off[mid] <= k) lo = mid; else hi = mid - 1;
+        }
+        s = lo;
+        load();
+    }
+    // move to the series containing step k (k next to the current position)
+    __device__ __forceinline__ void seek(int64_t k)
+    {
+        while (k >= end && s + 1 < s_hi) { s++; load(); }
+        while (k < beg && s > s_lo) { s--; load(); }
+    }
+    __device__ __forceinline__ bool first(int64_t k) const { return k == beg; }
+    __device__ __forceinline__ bool last(int64_t k) const { return k == end - 1; }
+};

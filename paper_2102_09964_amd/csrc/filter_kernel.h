@@ -14,13 +14,16 @@
 //      applies the aggregates of the tiles in between to it; it publishes the
 //      tile's own inclusive prefix and hands the carry to the wave via LDS
 //   D  each lane applies its exclusive lane prefix to the carry, which gives
-//      the filter moments just before its chunk (every prefix from step 0
-//      has A = 0, so only (b, C) are carried), then re-runs its steps as a
-//      plain Kalman filter, writing (m, P) and accumulating the
+//      the filter moments just before its chunk (every prefix from a series
+//      start has A = 0, so only (b, C) are carried), then re-runs its steps
+//      as a plain Kalman filter, writing (m, P) and accumulating the
 //      log-likelihood terms with compensated summation.
 // Tiles are numbered by an atomic ticket, so a tile only waits on tiles that
-// are already running; the last tile to finish reduces the per-tile
-// log-likelihood partials in a fixed order.
+// are already running. One series: the last tile to finish reduces the
+// per-tile log-likelihood partials in a fixed order. Batched: the kernel is
+// persistent (each workgroup keeps taking tickets), covers up to two groups
+// of series with different state layouts, and writes per-step
+// log-likelihood terms that a second kernel sums per series.
 #pragma once
 #include "device_common.h"
 #include "filter_ops.h"
@@ -42,6 +45,7 @@ struct FilterParams {
     T *P;
     double *loglik;
     T *ck;
+    T *ll_terms;  // batched: per-step log-likelihood terms
     WsCtl *ctl;
     uint32_t *flags;
     T *aggp;
@@ -50,58 +54,65 @@ struct FilterParams {
     double *partials;
 };
 
-template <class LY, typename T>
-__device__ __forceinline__ void step_transition(const DevModel &mdl, const double *t, int64_t k,
+// Tile geometry: steps [k_begin, k_end) split into ntiles tiles; workspace
+// tile slots start at slot_base.
+struct TileRange {
+    int64_t k_begin, k_end;
+    int ntiles;
+    int slot_base;
+};
+
+template <class LY, typename T, class SV>
+__device__ __forceinline__ void step_transition(const DevModel &mdl, const SV &sv, const double *t, int64_t k,
                                                 T (&F)[LY::D][LY::D], T (&Q)[LY::D][LY::D],
                                                 uint32_t &bad)
 {
     constexpr int D = LY::D;
     double F64[D][D], Q64[D][D];
+    const bool first = sv.first(k);
     const double tk = t[k];
-    const double dt = (k > 0) ? tk - t[k - 1] : 0.0;
+    const double dt = tk - t[first ? k : k - 1];  // 0 at a series start (never reads before it)
     if (!(dt >= 0.0)) bad |= (dt < 0.0) ? PSSGP_STATUS_UNSORTED : PSSGP_STATUS_NONFINITE;
-    discretize<LY, sizeof(T) == 8>(mdl, dt, k == 0, F64, Q64);
+    discretize<LY, sizeof(T) == 8>(mdl, sv.sc, dt, first, F64, Q64);
 #pragma unroll
     for (int i = 0; i < D; i++)
 #pragma unroll
         for (int j = 0; j < D; j++) { F[i][j] = T(F64[i][j]); Q[i][j] = T(Q64[i][j]); }
 }
 
-template <class LY, typename T, typename CT, int MODE>
-__global__ __launch_bounds__(PSSGP_WAVE) void filter_scan_kernel(FilterParams<T> p, DevModel mdl_arg)
+// One tile of the filter scan. ll_out receives this lane's compensated
+// log-likelihood partial.
+template <class LY, typename T, typename CT, int MODE, class SV>
+__device__ __forceinline__ void filter_tile(const FilterParams<T> &p, const DevModel &mdl, SV &sv,
+                                            const TileRange &tr, int tile, T *s_carry, double &ll_out)
 {
     constexpr int D = LY::D;
     constexpr int AGG = AggLayout<D>::SIZE;
     constexpr int INCL = AggLayout<D>::INCL;
-    __shared__ uint32_t s_tile;
-    __shared__ T s_carry[INCL];
-    __shared__ DevModel mdl;
     const int lane = lane_id();
-    if (lane == 0) s_tile = ticket_next(&p.ctl->ticket);
-    model_to_lds(mdl_arg, mdl);
-    const int tile = (int)s_tile;
-    const int64_t chunk_id = (int64_t)tile * PSSGP_WAVE + lane;
-    const int64_t k0 = chunk_id * p.chunk;
-    const int64_t k1 = (k0 + p.chunk < p.n) ? k0 + p.chunk : p.n;
+    const int slot = tr.slot_base + tile;
+    const int64_t chunk_id = (int64_t)slot * PSSGP_WAVE + lane;
+    const int64_t k0 = tr.k_begin + ((int64_t)tile * PSSGP_WAVE + lane) * p.chunk;
+    const int64_t k1 = (k0 + p.chunk < tr.k_end) ? k0 + p.chunk : tr.k_end;
     T h[D];
 #pragma unroll
     for (int i = 0; i < D; i++) h[i] = T(mdl.H[i]);
     uint32_t bad = 0;
 
-    // A: chunk aggregate
+    // A: chunk aggregate; B: wave inclusive scan
     {
         FAgg<D, T> agg;
         agg_identity<D, T>(agg);
         for (int64_t k = k0; k < k1; k++) {
             PSSGP_RELOAD_CONSTANTS();
+            sv.seek(k);
             T F[D][D], Q[D][D];
-            step_transition<LY, T>(mdl, p.t, k, F, Q, bad);
+            step_transition<LY, T, SV>(mdl, sv, p.t, k, F, Q, bad);
             const bool obs = p.mask ? (p.mask[k] != 0) : true;
             const T yk = obs ? p.y[k] : T(0);
-            const T R = p.noise_k ? T(p.noise_k[k]) : T(mdl.R);
+            const T R = p.noise_k ? T(p.noise_k[k]) : T(sv.R);
             agg_fold<D, T>(agg, F, Q, h, R, yk, obs);
         }
-        // B: wave inclusive scan
         for (int o = 1; o < PSSGP_WAVE; o <<= 1) {
             FAgg<D, T> other;
             agg_shfl_up<D, T>(agg, other, o);
@@ -123,11 +134,11 @@ __global__ __launch_bounds__(PSSGP_WAVE) void filter_scan_kernel(FilterParams<T>
         }
         if (tile > 0) {
             if (!p.deterministic) {
-                T *dst = p.aggp + (size_t)tile * AGG;
+                T *dst = p.aggp + (size_t)slot * AGG;
                 for (int i = 0; i < AGG; i++) dst[i] = tagg[i];
-                flag_store_release(&p.flags[tile], FLAG_AGG);
+                flag_store_release(&p.flags[slot], FLAG_AGG);
             }
-            int j = tile - 1;
+            int j = slot - 1;
             while (true) {
                 uint32_t f;
                 while ((f = flag_load_acquire(&p.flags[j])) == FLAG_NONE) __builtin_amdgcn_s_sleep(1);
@@ -135,7 +146,7 @@ __global__ __launch_bounds__(PSSGP_WAVE) void filter_scan_kernel(FilterParams<T>
                 j--;
             }
             moments_load<D, T>(p.inclp + (size_t)j * INCL, cb, cC);
-            for (int i = j + 1; i < tile; i++) {
+            for (int i = j + 1; i < slot; i++) {
                 FAgg<D, T> x;
                 agg_load<D, T>(p.aggp + (size_t)i * AGG, x);
                 moments_apply<D, T, CT>(cb, cC, x, cb, cC);
@@ -146,9 +157,9 @@ __global__ __launch_bounds__(PSSGP_WAVE) void filter_scan_kernel(FilterParams<T>
             agg_load<D, T>(tagg, x);
             T ib[D], iC[D][D];
             moments_apply<D, T, CT>(cb, cC, x, ib, iC);
-            moments_store<D, T>(p.inclp + (size_t)tile * INCL, ib, iC);
+            moments_store<D, T>(p.inclp + (size_t)slot * INCL, ib, iC);
         }
-        flag_store_release(&p.flags[tile], FLAG_INCL);
+        flag_store_release(&p.flags[slot], FLAG_INCL);
         moments_store<D, T>(s_carry, cb, cC);
     }
     __syncthreads();
@@ -161,18 +172,19 @@ __global__ __launch_bounds__(PSSGP_WAVE) void filter_scan_kernel(FilterParams<T>
         moments_apply<D, T, CT>(m, P, excl, m, P);
     }
     if constexpr ((MODE & F_CKPT) != 0) {
-        if (k0 < p.n) moments_store<D, T>(p.ck + (size_t)chunk_id * INCL, m, P);
+        if (k0 < tr.k_end) moments_store<D, T>(p.ck + (size_t)chunk_id * INCL, m, P);
     }
 
     // D: sequential Kalman filter over the chunk from the carried moments
     T ls = T(0), lc = T(0);
     for (int64_t k = k0; k < k1; k++) {
         PSSGP_RELOAD_CONSTANTS();
+        sv.seek(k);
         T F[D][D], Q[D][D];
-        step_transition<LY, T>(mdl, p.t, k, F, Q, bad);
+        step_transition<LY, T, SV>(mdl, sv, p.t, k, F, Q, bad);
         const bool obs = p.mask ? (p.mask[k] != 0) : true;
         const T yk = obs ? p.y[k] : T(0);
-        const T R = p.noise_k ? T(p.noise_k[k]) : T(mdl.R);
+        const T R = p.noise_k ? T(p.noise_k[k]) : T(sv.R);
         T mp[D], FP[D][D], Pp[D][D], Ph[D];
         mat_vec<D, T>(F, m, mp);
         mat_mul<D, T>(F, P, FP);
@@ -184,8 +196,9 @@ __global__ __launch_bounds__(PSSGP_WAVE) void filter_scan_kernel(FilterParams<T>
         // branch-free: missing steps add an exact zero
         bad |= (obs && (!(S > T(0)) || !isfinite(S))) ? PSSGP_STATUS_BAD_S : 0u;
         bad |= (obs && !isfinite(yk)) ? PSSGP_STATUS_NONFINITE : 0u;
-        const T term = T(-0.5) * (log(T(6.283185307179586) * S) + v * v * w);
-        kahan_add<T>(ls, lc, obs ? term : T(0));
+        const T term = obs ? T(-0.5) * (log(T(6.283185307179586) * S) + v * v * w) : T(0);
+        if (p.ll_terms) p.ll_terms[k] = term;
+        kahan_add<T>(ls, lc, term);
 #pragma unroll
         for (int i = 0; i < D; i++) m[i] = fma(Ph[i] * w, v, mp[i]);
 #pragma unroll
@@ -206,9 +219,27 @@ __global__ __launch_bounds__(PSSGP_WAVE) void filter_scan_kernel(FilterParams<T>
         }
     }
     if (bad) status_or(&p.ctl->status, bad);
+    ll_out = (double)ls + (double)lc;
+}
+
+template <class LY, typename T, typename CT, int MODE>
+__global__ __launch_bounds__(PSSGP_WAVE) void filter_scan_kernel(FilterParams<T> p, DevModel mdl_arg)
+{
+    __shared__ uint32_t s_tile;
+    __shared__ T s_carry[AggLayout<LY::D>::INCL];
+    __shared__ DevModel mdl;
+    const int lane = lane_id();
+    if (lane == 0) s_tile = ticket_next(&p.ctl->ticket);
+    model_to_lds(mdl_arg, mdl);
+    const int tile = (int)s_tile;
+    OneSeries sv;
+    sv.init(mdl, p.n);
+    TileRange tr{0, p.n, p.ntiles, 0};
+    double ll = 0.0;
+    filter_tile<LY, T, CT, MODE, OneSeries>(p, mdl, sv, tr, tile, s_carry, ll);
 
     // log-likelihood: deterministic wave sum, tile partial, last tile reduces
-    const double tot = wave_sum((double)ls + (double)lc);
+    const double tot = wave_sum(ll);
     uint32_t prev = 0;
     if (lane == 0) {
         p.partials[tile] = tot;
@@ -236,7 +267,7 @@ __global__ __launch_bounds__(256) void discretize_kernel(DevModel mdl, const dou
     double F[D][D], Q[D][D];
     const double dt = (k > 0) ? t[k] - t[k - 1] : 0.0;
     if (!(dt >= 0.0)) status_or(&ctl->status, (dt < 0.0) ? PSSGP_STATUS_UNSORTED : PSSGP_STATUS_NONFINITE);
-    discretize<LY, true>(mdl, dt, k == 0, F, Q);
+    discretize<LY, true>(mdl, model_scale(mdl), dt, k == 0, F, Q);
 #pragma unroll
     for (int i = 0; i < D; i++)
 #pragma unroll
@@ -247,8 +278,8 @@ __global__ __launch_bounds__(256) void discretize_kernel(DevModel mdl, const dou
         for (int j = i; j < D; j++) Qo[(size_t)sidx<D>(i, j) * n + k] = Q[i][j];
 }
 
-template <class LY, typename T, typename CT>
-int launch_filter_t(const DevModel &mdl, const FilterLaunch &a, hipStream_t s)
+template <class LY, typename T>
+FilterParams<T> filter_params(const FilterLaunch &a)
 {
     FilterParams<T> p;
     p.t = a.t;
@@ -263,12 +294,20 @@ int launch_filter_t(const DevModel &mdl, const FilterLaunch &a, hipStream_t s)
     p.P = (T *)a.P;
     p.loglik = a.loglik;
     p.ck = (T *)a.ck;
+    p.ll_terms = nullptr;
     p.ctl = a.ws.ctl;
     p.flags = a.ws.flags;
     p.aggp = (T *)a.ws.aggp;
     p.inclp = (T *)a.ws.inclp;
     p.lanep = (T *)a.ws.lanep;
     p.partials = a.ws.partials;
+    return p;
+}
+
+template <class LY, typename T, typename CT>
+int launch_filter_t(const DevModel &mdl, const FilterLaunch &a, hipStream_t s)
+{
+    FilterParams<T> p = filter_params<LY, T>(a);
     dim3 grid(a.ntiles), block(PSSGP_WAVE);
     if (a.m)
         hipLaunchKernelGGL((filter_scan_kernel<LY, T, CT, F_MOMENTS>), grid, block, 0, s, p, mdl);

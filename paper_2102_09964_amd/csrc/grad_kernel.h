@@ -171,7 +171,7 @@ __global__ __launch_bounds__(PSSGP_WAVE) void grad_scan_kernel(GradParams<T> p, 
             {
                 double F64[D][D], Q64[D][D];
                 const double dt = (k > 0) ? p.t[k] - p.t[k - 1] : 0.0;
-                discretize<LY, sizeof(T) == 8>(mdl, dt, k == 0, F64, Q64);
+                discretize<LY, sizeof(T) == 8>(mdl, model_scale(mdl), dt, k == 0, F64, Q64);
 #pragma unroll
                 for (int i = 0; i < D; i++)
 #pragma unroll
@@ -312,7 +312,7 @@ __global__ __launch_bounds__(PSSGP_WAVE) void grad_scan_kernel(GradParams<T> p, 
         PSSGP_RELOAD_CONSTANTS();
         const double dt = (k > 0) ? p.t[k] - p.t[k - 1] : 0.0;
         double F64[D][D], Q64[D][D];
-        discretize<LY, sizeof(T) == 8>(mdl, dt, k == 0, F64, Q64);
+        discretize<LY, sizeof(T) == 8>(mdl, model_scale(mdl), dt, k == 0, F64, Q64);
         const bool obs = p.mask ? (p.mask[k] != 0) : true;
         const T *rp = p.rec + (size_t)k * REC;
         T mu[D], Pi[D][D], K[D];

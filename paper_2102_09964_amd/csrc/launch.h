@@ -74,6 +74,53 @@ struct GradLaunch {
     ScanWs ws;
 };
 
+// Batched form: up to two groups of series sharing a single-component
+// Matern layout (d <= 3, ascending d); per group a compact model whose
+// covariance constants are for unit variance (the series variance is
+// applied per step).
+struct BatchModel {
+    int32_t d;
+    int32_t pad;
+    DevBlock blk;
+    double Pinf1[9];   // unit-variance stationary covariance, d*d row-major
+    double fcoef[27];  // expansion matrices of the block
+    double H[3];
+};
+
+struct BatchGroup {
+    int64_t k_begin, k_end;  // step range of the group
+    int64_t s_begin, s_end;  // series range of the group
+    int ntiles;
+    int slot_base;
+};
+
+struct BatchLaunch {
+    int ngroups;
+    BatchGroup g[2];
+    BatchModel bm[2];
+    int total_tiles;
+    int grid;                 // persistent workgroups
+    const int64_t *offsets;   // device [n_series + 1]
+    const double *params;     // device [n_series][3]
+    int64_t n_series;
+    int64_t n;                // total steps
+    int chunk;
+    int deterministic;
+    const double *t;
+    const void *y;
+    const uint8_t *mask;
+    void *m;
+    void *P;
+    void *f_mean;
+    void *f_var;
+    double *loglik;           // device [n_series]
+    void *ll_terms;           // workspace: per-step terms
+    ScanWs ws;
+};
+
+int launch_batched_filter(const BatchLaunch &a, bool f64, hipStream_t s);
+int launch_batched_smooth(const BatchLaunch &a, bool f64, hipStream_t s);
+
 // Per-layout launchers, instantiated in one translation unit per layout.
 template <int B0, int B1>
 int launch_filter_layout(const DevModel &mdl, bool f64, const FilterLaunch &a, hipStream_t s);

@@ -167,9 +167,9 @@ __device__ __forceinline__ void gl_load(const T *p, T (&g)[D], T (&L)[D][D])
 // step's element (0, m, P) is formed without branching: its transition is
 // evaluated for a zero step (F = I, Q = 0) and the result replaced by
 // selects, so that every lane runs the same instruction stream.
-template <class LY, typename T>
-__device__ __forceinline__ void smoother_element(const DevModel &mdl, const double *t, const T *mf,
-                                                 const T *Pf, int64_t n, int64_t k, int64_t last,
+template <class LY, typename T, class SV>
+__device__ __forceinline__ void smoother_element(const DevModel &mdl, const SV &sv, const double *t, const T *mf,
+                                                 const T *Pf, int64_t n, int64_t k,
                                                  SAgg<LY::D, T> &e, uint32_t &bad)
 {
     constexpr int D = LY::D;
@@ -183,11 +183,11 @@ __device__ __forceinline__ void smoother_element(const DevModel &mdl, const doub
             P[i][j] = (double)Pf[(size_t)sidx<D>(i, j) * n + k];
             P[j][i] = P[i][j];
         }
-    const bool is_last = (k == last);
+    const bool is_last = sv.last(k);
     const int64_t kn = is_last ? k : k + 1;  // never reads past the series
     const double dt = t[kn] - t[k];
     double F[D][D], Q[D][D];
-    discretize<LY, sizeof(T) == 8>(mdl, dt, false, F, Q);
+    discretize<LY, sizeof(T) == 8>(mdl, sv.sc, dt, false, F, Q);
     double FP[D][D], Pp[D][D], X[D][D];
     mat_mul<D, double>(F, P, FP);
     mat_mul_nt_sym_add<D, double>(FP, F, Q, Pp);
@@ -238,23 +238,26 @@ struct SmoothParams {
     T *lanep;
 };
 
-template <class LY, typename T, bool FULL>
-__global__ __launch_bounds__(PSSGP_WAVE) void smoother_scan_kernel(SmoothParams<T> p, DevModel mdl_arg)
+struct STileRange {
+    int64_t k_begin, k_end;
+    int ntiles;
+    int slot_base;
+};
+
+// One tile of the smoother scan (tile numbered from the start of its range;
+// the look-forward walks to higher slots up to the range's last tile).
+template <class LY, typename T, bool FULL, class SV>
+__device__ __forceinline__ void smoother_tile(const SmoothParams<T> &p, const DevModel &mdl, SV &sv,
+                                              const STileRange &tr, int tile, T *s_carry)
 {
     constexpr int D = LY::D;
     constexpr int AGG = SAggLayout<D>::SIZE;
     constexpr int INCL = SAggLayout<D>::INCL;
-    __shared__ uint32_t s_tile;
-    __shared__ T s_carry[INCL];
-    __shared__ DevModel mdl;
     const int lane = lane_id();
-    if (lane == 0) s_tile = (uint32_t)p.ntiles - 1u - ticket_next(&p.ctl->ticket);
-    model_to_lds(mdl_arg, mdl);
-    const int tile = (int)s_tile;
-    const int64_t chunk_id = (int64_t)tile * PSSGP_WAVE + lane;
-    const int64_t k0 = chunk_id * p.chunk;
-    const int64_t k1 = (k0 + p.chunk < p.n) ? k0 + p.chunk : p.n;
-    const int64_t last = p.n - 1;
+    const int slot = tr.slot_base + tile;
+    const int64_t chunk_id = (int64_t)slot * PSSGP_WAVE + lane;
+    const int64_t k0 = tr.k_begin + ((int64_t)tile * PSSGP_WAVE + lane) * p.chunk;
+    const int64_t k1 = (k0 + p.chunk < tr.k_end) ? k0 + p.chunk : tr.k_end;
     uint32_t bad = 0;
     T h[D];
 #pragma unroll
@@ -266,8 +269,9 @@ __global__ __launch_bounds__(PSSGP_WAVE) void smoother_scan_kernel(SmoothParams<
         sagg_identity<D, T>(agg);
         for (int64_t k = k1 - 1; k >= k0; k--) {
             PSSGP_RELOAD_CONSTANTS();
+            sv.seek(k);
             SAgg<D, T> e;
-            smoother_element<LY, T>(mdl, p.t, p.m, p.P, p.n, k, last, e, bad);
+            smoother_element<LY, T, SV>(mdl, sv, p.t, p.m, p.P, p.n, k, e, bad);
             sagg_combine<D, T>(e, agg, agg);
         }
         for (int o = 1; o < PSSGP_WAVE; o <<= 1) {
@@ -289,13 +293,13 @@ __global__ __launch_bounds__(PSSGP_WAVE) void smoother_scan_kernel(SmoothParams<
 #pragma unroll
             for (int j = 0; j < D; j++) cL[i][j] = T(0);
         }
-        if (tile < p.ntiles - 1) {
+        if (tile < tr.ntiles - 1) {
             if (!p.deterministic) {
-                T *dst = p.aggp + (size_t)tile * AGG;
+                T *dst = p.aggp + (size_t)slot * AGG;
                 for (int i = 0; i < AGG; i++) dst[i] = tagg[i];
-                flag_store_release(&p.flags[tile], FLAG_AGG);
+                flag_store_release(&p.flags[slot], FLAG_AGG);
             }
-            int j = tile + 1;
+            int j = slot + 1;
             while (true) {
                 uint32_t f;
                 while ((f = flag_load_acquire(&p.flags[j])) == FLAG_NONE) __builtin_amdgcn_s_sleep(1);
@@ -303,7 +307,7 @@ __global__ __launch_bounds__(PSSGP_WAVE) void smoother_scan_kernel(SmoothParams<
                 j++;
             }
             gl_load<D, T>(p.inclp + (size_t)j * INCL, cg, cL);
-            for (int i = j - 1; i > tile; i--) {
+            for (int i = j - 1; i > slot; i--) {
                 SAgg<D, T> x;
                 sagg_load<D, T>(p.aggp + (size_t)i * AGG, x);
                 sagg_apply<D, T>(x, cg, cL, cg, cL);
@@ -314,9 +318,9 @@ __global__ __launch_bounds__(PSSGP_WAVE) void smoother_scan_kernel(SmoothParams<
             sagg_load<D, T>(tagg, x);
             T ig[D], iL[D][D];
             sagg_apply<D, T>(x, cg, cL, ig, iL);
-            gl_store<D, T>(p.inclp + (size_t)tile * INCL, ig, iL);
+            gl_store<D, T>(p.inclp + (size_t)slot * INCL, ig, iL);
         }
-        flag_store_release(&p.flags[tile], FLAG_INCL);
+        flag_store_release(&p.flags[slot], FLAG_INCL);
         gl_store<D, T>(s_carry, cg, cL);
     }
     __syncthreads();
@@ -332,8 +336,9 @@ __global__ __launch_bounds__(PSSGP_WAVE) void smoother_scan_kernel(SmoothParams<
     // D: backward RTS recursion over the chunk
     for (int64_t k = k1 - 1; k >= k0; k--) {
         PSSGP_RELOAD_CONSTANTS();
+        sv.seek(k);
         SAgg<D, T> e;
-        smoother_element<LY, T>(mdl, p.t, p.m, p.P, p.n, k, last, e, bad);
+        smoother_element<LY, T, SV>(mdl, sv, p.t, p.m, p.P, p.n, k, e, bad);
         sagg_apply<D, T>(e, ms, Ps, ms, Ps);
         T Ph[D];
         mat_vec<D, T>(Ps, h, Ph);
@@ -349,6 +354,21 @@ __global__ __launch_bounds__(PSSGP_WAVE) void smoother_scan_kernel(SmoothParams<
         }
     }
     if (bad) status_or(&p.ctl->status, bad);
+}
+
+template <class LY, typename T, bool FULL>
+__global__ __launch_bounds__(PSSGP_WAVE) void smoother_scan_kernel(SmoothParams<T> p, DevModel mdl_arg)
+{
+    __shared__ uint32_t s_tile;
+    __shared__ T s_carry[SAggLayout<LY::D>::INCL];
+    __shared__ DevModel mdl;
+    const int lane = lane_id();
+    if (lane == 0) s_tile = (uint32_t)p.ntiles - 1u - ticket_next(&p.ctl->ticket);
+    model_to_lds(mdl_arg, mdl);
+    OneSeries sv;
+    sv.init(mdl, p.n);
+    STileRange tr{0, p.n, p.ntiles, 0};
+    smoother_tile<LY, T, FULL, OneSeries>(p, mdl, sv, tr, (int)s_tile, s_carry);
 }
 
 template <class LY, typename T>

@@ -1,0 +1,159 @@
+"""GPU parity of the batched form (many independent series of uneven
+lengths and hyperparameters, two state layouts, one persistent launch per
+scan) against the oracle run series by series, and replay of the batched
+pipeline captured in a HIP graph.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from oracle.model import OracleModel
+from tests.conftest import gpu_available
+from tests.parity import rel
+
+pytestmark = pytest.mark.gpu
+
+if not gpu_available():
+    pytest.skip("needs a HIP device", allow_module_level=True)
+
+import torch  # noqa: E402
+
+import paper_2102_09964_amd as P  # noqa: E402
+
+
+def _batch(n_series=48, min_len=40, max_len=3000, missing=0.1, seed=0):
+    return workloads.batched_matern(n_series=n_series, min_len=min_len, max_len=max_len, missing=missing,
+                                    seed_extra=seed)
+
+
+def _oracle(w, dtype):
+    y = np.asarray(w["y"], np.float64)
+    if dtype == "float32":
+        y = y.astype(np.float32).astype(np.float64)
+    models = [OracleModel(m["components"], m["noise_var"]) for m in w["models"]]
+    return oracle.run_batched(models, w["offsets"], w["t"], y, w["mask"], threads=8)
+
+
+def _gpu(w, dtype, options=None, pipe=None):
+    tdt = getattr(torch, dtype)
+    pipe = pipe or P.BatchedPipeline(w["kinds"], w["offsets"], w["params"], dtype=dtype, options=options)
+    t = torch.as_tensor(w["t"], dtype=torch.float64, device="cuda")
+    y = torch.as_tensor(np.nan_to_num(w["y"]), dtype=tdt, device="cuda")
+    mask = torch.as_tensor(w["mask"], dtype=torch.uint8, device="cuda")
+    fm, fv, ll = pipe.run(t, y, mask)
+    torch.cuda.synchronize()
+    return {"f_mean": fm.double().cpu().numpy(), "f_var": fv.double().cpu().numpy(),
+            "loglik": ll.cpu().numpy(), "status": (P.status(pipe.ws_f), P.status(pipe.ws_s))}, pipe
+
+
+def _check(g, o, off, dtype):
+    tol = {"float64": (1e-9, 1e-9), "float32": (1e-4, 1e-5)}[dtype]
+    worst = {"f_mean": 0.0, "f_var": 0.0, "loglik": 0.0}
+    for s in range(len(off) - 1):
+        a, b = off[s], off[s + 1]
+        worst["f_mean"] = max(worst["f_mean"], rel(g["f_mean"][a:b], o["f_mean"][a:b]))
+        worst["f_var"] = max(worst["f_var"], rel(g["f_var"][a:b], o["f_var"][a:b]))
+        worst["loglik"] = max(worst["loglik"], abs(g["loglik"][s] - o["loglik"][s]) / abs(o["loglik"][s]))
+    print(dtype, {k: "%.2e" % v for k, v in worst.items()}, flush=True)
+    assert worst["f_mean"] <= tol[0] and worst["f_var"] <= tol[0] and worst["loglik"] <= tol[1], worst
+
+
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+def test_batched_vs_oracle(dtype):
+    w = _batch()
+    assert set(np.unique(w["kinds"])) == {P.MATERN32, P.MATERN52}
+    o = _oracle(w, dtype)
+    g, _ = _gpu(w, dtype)
+    assert g["status"] == (0, 0)
+    _check(g, o, w["offsets"], dtype)
+
+
+@pytest.mark.parametrize("chunk", [1, 5, 64])
+def test_batched_chunks(chunk):
+    w = _batch(n_series=30, min_len=3, max_len=900, seed=chunk)
+    o = _oracle(w, "float64")
+    g, _ = _gpu(w, "float64", options=P.make_options(chunk=chunk))
+    _check(g, o, w["offsets"], "float64")
+
+
+def test_batched_single_kind_and_short_series():
+    w = _batch(n_series=64, min_len=1, max_len=40, seed=3)
+    keep = w["kinds"] == P.MATERN52
+    idx = np.nonzero(keep)[0]
+    off = [0]
+    sel = []
+    for s in idx:
+        a, b = w["offsets"][s], w["offsets"][s + 1]
+        sel.append(np.arange(a, b))
+        off.append(off[-1] + (b - a))
+    sel = np.concatenate(sel)
+    w2 = {"t": w["t"][sel], "y": w["y"][sel], "mask": w["mask"][sel], "offsets": np.array(off),
+          "kinds": w["kinds"][idx], "params": w["params"][idx], "models": [w["models"][s] for s in idx]}
+    o = _oracle(w2, "float64")
+    g, _ = _gpu(w2, "float64")
+    _check(g, o, w2["offsets"], "float64")
+
+
+def test_batched_equals_single_series_path():
+    w = _batch(n_series=6, min_len=2000, max_len=5000, seed=9)
+    g, _ = _gpu(w, "float32")
+    for s in range(6):
+        a, b = w["offsets"][s], w["offsets"][s + 1]
+        r = P.predict(w["models"][s], w["t"][a:b], np.nan_to_num(w["y"][a:b]), w["mask"][a:b], dtype="float32")
+        assert rel(g["f_mean"][a:b], r["f_mean"].double().cpu().numpy()) <= 1e-5
+        assert abs(g["loglik"][s] - float(r["loglik"].cpu()[0])) <= 1e-6 * abs(g["loglik"][s])
+
+
+def test_batched_deterministic_and_graph_replay():
+    w = _batch(n_series=40, min_len=500, max_len=20000, seed=4)
+    opt = P.make_options(deterministic=True)
+    eager, pipe = _gpu(w, "float32", options=opt)
+    again, _ = _gpu(w, "float32", options=opt, pipe=pipe)
+    assert np.array_equal(eager["f_mean"], again["f_mean"]) and np.array_equal(eager["loglik"], again["loglik"])
+    t = torch.as_tensor(w["t"], dtype=torch.float64, device="cuda")
+    y = torch.as_tensor(np.nan_to_num(w["y"]), dtype=torch.float32, device="cuda")
+    mask = torch.as_tensor(w["mask"], dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(stream):
+        with torch.cuda.graph(graph, stream=stream):
+            pipe.run(t, y, mask)
+    torch.cuda.current_stream().wait_stream(stream)
+    for rep in range(3):
+        pipe.f_mean.zero_()
+        pipe.loglik.zero_()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(pipe.f_mean.double().cpu().numpy(), eager["f_mean"]), rep
+        assert np.array_equal(pipe.loglik.cpu().numpy(), eager["loglik"]), rep
+        # eager work between replays
+        _gpu(w, "float32", options=opt, pipe=pipe)
+
+
+def test_single_series_graph_replay():
+    w = workloads.random_series(30000, [(P.RBF, 6, 1.0, 1.0)], 0.01, missing=0.2, span=300.0, seed=7)
+    model = P.make_model(w["model"]["components"], 0.01)
+    opt = P.make_options(deterministic=True)
+    pipe = P.Pipeline(model, len(w["t"]), "float32", options=opt)
+    t = torch.as_tensor(w["t"], dtype=torch.float64, device="cuda")
+    y = torch.as_tensor(np.nan_to_num(w["y"]), dtype=torch.float32, device="cuda")
+    mask = torch.as_tensor(w["mask"], dtype=torch.uint8, device="cuda")
+    pipe.run(t, y, mask)
+    torch.cuda.synchronize()
+    ref = (pipe.f_mean.clone(), pipe.f_var.clone(), pipe.loglik.clone())
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(stream):
+        with torch.cuda.graph(graph, stream=stream):
+            pipe.run(t, y, mask)
+    torch.cuda.current_stream().wait_stream(stream)
+    for rep in range(3):
+        pipe.f_mean.zero_()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(pipe.f_mean, ref[0]) and torch.equal(pipe.loglik, ref[2]), rep
+        pipe.run(t, y, mask)
+        torch.cuda.synchronize()

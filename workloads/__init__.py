@@ -102,7 +102,9 @@ def batched_matern(n_series: int = 4096, min_len: int = 256, max_len: int = 6553
     offsets = np.zeros(n_series + 1, np.int64)
     offsets[1:] = np.cumsum(lens)
     total = int(offsets[-1])
-    kinds = np.where(rng.uniform(size=n_series) < 0.5, MATERN32, MATERN52)
+    # kinds drawn with probability 1/2 each, then listed Matern-3/2 first so
+    # that each kind occupies a contiguous range of series
+    kinds = np.sort(np.where(rng.uniform(size=n_series) < 0.5, MATERN32, MATERN52))
     ells = np.exp(rng.uniform(np.log(0.1), np.log(10.0), n_series))
     noises = np.exp(rng.uniform(np.log(1e-4), np.log(1e-1), n_series))
     freqs = rng.uniform(0.1, 2.0, n_series)
@@ -118,8 +120,9 @@ def batched_matern(n_series: int = 4096, min_len: int = 256, max_len: int = 6553
     mask = (rng.uniform(size=total) >= missing).astype(np.uint8)
     models = [{"components": [(int(kinds[s]), 0, float(ells[s]), 1.0)], "noise_var": float(noises[s])}
               for s in range(n_series)]
+    params = np.stack([ells, np.ones(n_series), noises], axis=1)
     return {"name": "batched_matern", "t": t, "y": y, "mask": mask, "offsets": offsets,
-            "models": models}
+            "models": models, "kinds": kinds, "params": params}
 
 
 def sum_m32_rbf6(n: int = 1 << 20, missing: float = 0.1, seed_extra: int = 0):
