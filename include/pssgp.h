@@ -100,7 +100,8 @@ typedef enum {
     PSSGP_OP_SMOOTH = 2,
     PSSGP_OP_LOGLIK = 3,
     PSSGP_OP_LOGLIK_GRAD = 4,
-    PSSGP_OP_DISCRETIZE = 5
+    PSSGP_OP_DISCRETIZE = 5,
+    PSSGP_OP_PLAIN = 6
 } pssgp_op;
 
 /* Status word bits set on the device. */
@@ -181,6 +182,21 @@ int pssgp_filter(const pssgp_model *model, const double *t, const void *y, const
 int pssgp_smooth(const pssgp_model *model, const double *t, const void *m, const void *P,
                  int64_t n, pssgp_dtype dtype, void *f_mean, void *f_var, void *ms, void *Ps,
                  void *ws, size_t ws_bytes, const pssgp_options *opts, void *stream);
+
+/*
+ * Plain FP64 GPU scan (reference point for the fused scans): the same
+ * filter, log-likelihood and smoother with every element materialised in
+ * HBM in FP64 and a work-efficient (Blelloch) scan, one launch per level of
+ * the up-sweep and of the down-sweep (section 3 and supplement
+ * Propositions 1-2 in their textbook parallel form). All data FP64: y
+ * double[n], m double[d][n], P double[NS][n], f_mean, f_var double[n],
+ * loglik double[1]. Workspace: pssgp_workspace_bytes(..., PSSGP_F64,
+ * PSSGP_OP_PLAIN, NULL), which holds two element arrays padded to a power
+ * of two.
+ */
+int pssgp_plain_predict(const pssgp_model *model, const double *t, const double *y,
+                        const uint8_t *mask, int64_t n, double *m, double *P, double *f_mean,
+                        double *f_var, double *loglik, void *ws, size_t ws_bytes, void *stream);
 
 /* Log-likelihood only: pssgp_filter without state outputs. */
 int pssgp_loglik(const pssgp_model *model, const double *t, const void *y, const uint8_t *mask,

@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libpssgp.so")
 
 MATERN12, MATERN32, MATERN52, RBF = 1, 2, 3, 4
 F32, F64 = 0, 1
-OP_FILTER, OP_SMOOTH, OP_LOGLIK, OP_LOGLIK_GRAD, OP_DISCRETIZE = 1, 2, 3, 4, 5
+OP_FILTER, OP_SMOOTH, OP_LOGLIK, OP_LOGLIK_GRAD, OP_DISCRETIZE, OP_PLAIN = 1, 2, 3, 4, 5, 6
 STATUS_UNSORTED, STATUS_NONFINITE, STATUS_BAD_S, STATUS_CHOLESKY = 1, 2, 4, 8
 
 _ERRORS = {-1: "EINVAL", -2: "EUNSUPPORTED", -3: "EWORKSPACE", -4: "EDEVICE", -5: "ENODEVICE",
@@ -82,6 +82,7 @@ SIGNATURES = [
     ("pssgp_batched_smooth", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _I64, _VP, _VP, _VP, _VP, _VP, _VP,
                                             ctypes.c_int, _VP, _VP, _VP, _SZ, _OP, _VP]),
     ("pssgp_status", ctypes.c_int, [_VP, _VP, ctypes.POINTER(ctypes.c_uint32)]),
+    ("pssgp_plain_predict", ctypes.c_int, [_MP, _VP, _VP, _VP, _I64, _VP, _VP, _VP, _VP, _VP, _VP, _SZ, _VP]),
 ]
 
 
@@ -304,6 +305,30 @@ def predict(model, t, y, mask=None, dtype="float32", options=None, device="cuda"
     f = filter(model, t, y, mask, dtype=dtype, options=options, device=device)
     s = smooth(model, t, f["m"], f["P"], dtype=dtype, options=options, device=device)
     return {"f_mean": s["f_mean"], "f_var": s["f_var"], "loglik": f["loglik"], "m": f["m"], "P": f["P"]}
+
+
+def plain_predict(model, t, y, mask=None, ws=None, device="cuda"):
+    """Filter, log-likelihood and smoother through the plain FP64 scan
+    (materialised elements, one launch per scan level). Same outputs as
+    ``predict`` in FP64."""
+    _require_gpu()
+    torch = _torch()
+    m = _as_model(model)
+    t = _dev(t, torch.float64, device)
+    n = t.shape[0]
+    y = _dev(y, torch.float64, device)
+    mask = _dev(mask, torch.uint8, device)
+    d = state_dim(m)
+    if ws is None:
+        ws = alloc_workspace(m, n, F64, OP_PLAIN, None, device)
+    mm = torch.empty((d, n), dtype=torch.float64, device=device)
+    PP = torch.empty((d * (d + 1) // 2, n), dtype=torch.float64, device=device)
+    fm = torch.empty(n, dtype=torch.float64, device=device)
+    fv = torch.empty(n, dtype=torch.float64, device=device)
+    ll = torch.empty(1, dtype=torch.float64, device=device)
+    _check(lib().pssgp_plain_predict(ctypes.byref(m), _p(t), _p(y), _p(mask), n, _p(mm), _p(PP), _p(fm), _p(fv),
+                                     _p(ll), _p(ws), ws.numel(), _stream()))
+    return {"f_mean": fm, "f_var": fv, "loglik": ll, "m": mm, "P": PP}
 
 
 def loglik(model, t, y, mask=None, noise_k=None, dtype="float32", options=None, device="cuda"):

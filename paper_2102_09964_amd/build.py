@@ -27,8 +27,8 @@ CFLAGS = ["-O3", "--offload-arch=" + ARCH, "-std=c++17", "-fPIC",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           ] + (["-DPSSGP_WITH_GRAD"] if os.path.exists(os.path.join(CSRC, "inst_grad.hip")) else [])
 
-INST_UNITS = ["inst_filter.hip", "inst_smoother.hip", "inst_grad.hip"]
-PLAIN_UNITS = ["model.cpp", "capi.cpp", "dispatch.hip", "batched.hip", "plain_f64.hip"]
+INST_UNITS = ["inst_filter.hip", "inst_smoother.hip", "inst_grad.hip", "inst_plain.hip"]
+PLAIN_UNITS = ["model.cpp", "capi.cpp", "dispatch.hip", "batched.hip"]
 
 
 def layouts():

@@ -62,6 +62,16 @@ Plan make_plan(int d, int ncomp, int64_t n, pssgp_dtype dtype, int op, const pss
         p.total = off;
         return p;
     }
+    if (op == PSSGP_OP_PLAIN) {
+        int64_t n2 = 1;
+        while (n2 < n) n2 <<= 1;
+        const size_t elem = (size_t)(3 * d * d + 2 * d) * sizeof(double);  // one filter element
+        p.off_agg = take((size_t)n2 * elem);
+        p.off_incl = take((size_t)n2 * elem);
+        p.off_part = take((size_t)(n > 0 ? n : 1) * sizeof(double));
+        p.total = off;
+        return p;
+    }
     p.off_flags = take(nt * sizeof(uint32_t));
     if (op == PSSGP_OP_SMOOTH) {
         p.off_agg = take(nt * smooth_agg_elems(d) * p.tsize);
@@ -440,7 +450,7 @@ size_t pssgp_workspace_bytes(const pssgp_model *model, int64_t n, pssgp_dtype dt
                              const pssgp_options *opts)
 {
     int d = pssgp_build_devmodel(model, nullptr, nullptr);
-    if (d < 0 || n < 0 || op < PSSGP_OP_FILTER || op > PSSGP_OP_DISCRETIZE) return 0;
+    if (d < 0 || n < 0 || op < PSSGP_OP_FILTER || op > PSSGP_OP_PLAIN) return 0;
     return make_plan(d, model->n_comp, n, dtype, op, opts).total;
 }
 
@@ -463,6 +473,43 @@ int pssgp_discretize(const pssgp_model *model, const double *t, int64_t n, doubl
     if ((rc = hip_err((hipError_t)rc, "workspace init"))) return rc;
     if (n == 0) return PSSGP_OK;
     return check_launch(launch_discretize(dm, b0, b1, t, n, F, Q, sw.ctl, s), "discretize launch");
+}
+
+int pssgp_plain_predict(const pssgp_model *model, const double *t, const double *y, const uint8_t *mask,
+                        int64_t n, double *m, double *P, double *f_mean, double *f_var, double *loglik, void *ws,
+                        size_t ws_bytes, void *stream)
+{
+    DevModel dm;
+    int b0, b1;
+    int rc = prepare(model, n, PSSGP_F64, dm, b0, b1);
+    if (rc) return rc;
+    if (n > 0 && (!t || !y || !m || !P || !f_mean || !f_var || !loglik)) {
+        pssgp_set_error("t, y, m, P, f_mean, f_var and loglik must be device pointers");
+        return PSSGP_EINVAL;
+    }
+    Plan p = make_plan(dm.d, dm.nblk, n, PSSGP_F64, PSSGP_OP_PLAIN, nullptr);
+    if ((rc = check_ws(ws, ws_bytes, p))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    char *b = (char *)ws;
+    rc = launch_ws_init((WsCtl *)b, nullptr, 0, n == 0 ? loglik : nullptr, n == 0 && loglik ? 1 : 0, s);
+    if ((rc = hip_err((hipError_t)rc, "workspace init"))) return rc;
+    if (n == 0) return PSSGP_OK;
+    PlainLaunch a;
+    a.t = t;
+    a.y = y;
+    a.mask = mask;
+    a.n = n;
+    a.n2 = 1;
+    while (a.n2 < n) a.n2 <<= 1;
+    a.m = m;
+    a.P = P;
+    a.f_mean = f_mean;
+    a.f_var = f_var;
+    a.loglik = loglik;
+    a.X = b + p.off_agg;
+    a.Xraw = b + p.off_incl;
+    a.terms = (double *)(b + p.off_part);
+    return check_launch(launch_plain(dm, b0, b1, a, s), "plain launch");
 }
 
 int pssgp_filter(const pssgp_model *model, const double *t, const void *y, const uint8_t *mask,

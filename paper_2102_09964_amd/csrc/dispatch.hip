@@ -63,6 +63,15 @@ int launch_grad(const DevModel &mdl, int b0, int b1, bool f64, const GradLaunch 
     return -1;
 }
 
+int launch_plain(const DevModel &mdl, int b0, int b1, const PlainLaunch &a, hipStream_t s)
+{
+#define X(A0, A1) \
+    if (b0 == A0 && b1 == A1) return launch_plain_layout<A0, A1>(mdl, a, s);
+    PSSGP_LAYOUTS(X)
+#undef X
+    return -1;
+}
+
 int launch_ws_init(WsCtl *ctl, uint32_t *flags, int64_t nflags, double *zero_out, int nzero, hipStream_t s)
 {
     int64_t cnt = nflags > 3 ? nflags : 3;

@@ -131,6 +131,24 @@ int launch_discretize_layout(const DevModel &mdl, const double *t, int64_t n, do
                              WsCtl *ctl, hipStream_t s);
 template <int B0, int B1>
 int launch_grad_layout(const DevModel &mdl, bool f64, const GradLaunch &a, hipStream_t s);
+// Plain FP64 baseline: element arrays and outputs
+struct PlainLaunch {
+    const double *t;
+    const double *y;
+    const uint8_t *mask;
+    int64_t n;
+    int64_t n2;
+    double *m;
+    double *P;
+    double *f_mean;
+    double *f_var;
+    double *loglik;
+    void *X;      // n2 filter elements
+    void *Xraw;   // n2 filter elements
+    double *terms;
+};
+template <int B0, int B1>
+int launch_plain_layout(const DevModel &mdl, const PlainLaunch &a, hipStream_t s);
 
 // Dispatchers: return hipSuccess or an error; -1 when the layout (b0, b1) is
 // not compiled in.
@@ -139,6 +157,7 @@ int launch_smoother(const DevModel &mdl, int b0, int b1, bool f64, const SmoothL
 int launch_discretize(const DevModel &mdl, int b0, int b1, const double *t, int64_t n, double *F,
                       double *Q, WsCtl *ctl, hipStream_t s);
 int launch_grad(const DevModel &mdl, int b0, int b1, bool f64, const GradLaunch &a, hipStream_t s);
+int launch_plain(const DevModel &mdl, int b0, int b1, const PlainLaunch &a, hipStream_t s);
 int launch_ws_init(WsCtl *ctl, uint32_t *flags, int64_t nflags, double *zero_out, int nzero,
                    hipStream_t s);
 bool layout_supported(int b0, int b1);

@@ -145,3 +145,25 @@ def test_discretize_matches_oracle(comps):
         Qb = Qo / (T[:, None] * T[None, :])
         assert np.max(np.abs(F[k] - Fb)) <= 1e-11 * max(1.0, np.max(np.abs(Fb))), (k, dts[k - 1])
         assert np.max(np.abs(Q[k] - Qb)) <= 1e-11 * qscale, (k, dts[k - 1])
+
+
+@pytest.mark.parametrize("layout", ["m32", "m52", "rbf6", "sum"])
+@pytest.mark.parametrize("n", [1, 777, 5000])
+def test_plain_baseline_vs_oracle(layout, n):
+    """The plain FP64 scan (materialised elements, Blelloch levels) against
+    the oracle: filter moments, smoother outputs and log-likelihood."""
+    comps = {"m32": [(MATERN32, 0, 0.7, 1.3)], "m52": [(MATERN52, 0, 1.1, 0.8)],
+             "rbf6": [(RBF, 6, 1.0, 1.0)], "sum": [(MATERN32, 0, 2.0, 0.5), (RBF, 6, 0.5, 0.5)]}[layout]
+    w = workloads.random_series(n, comps, 0.01, missing=0.2, span=max(n / 100.0, 1.0), gap="exponential", seed=n)
+    print("plain", layout, n, flush=True)
+    o = run_oracle(w, "float64")
+    model = P.make_model(comps, 0.01)
+    d = P.state_dim(model)
+    T = P.state_basis(model)
+    g = P.plain_predict(model, w["t"], np.nan_to_num(w["y"]), w["mask"])
+    torch.cuda.synchronize()
+    out = {"loglik": float(g["loglik"].cpu()[0]), "f_mean": g["f_mean"].cpu().numpy(),
+           "f_var": g["f_var"].cpu().numpy(), "H": P.model_matrices(model)[2] / T,
+           "mf": g["m"].cpu().numpy().T * T[None, :],
+           "Pf": P.unpack_sym(g["P"].cpu().numpy(), d) * T[None, :, None] * T[None, None, :]}
+    check(compare(out, o, "float64"), "float64", "plain %s n=%d" % (layout, n))
