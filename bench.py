@@ -97,6 +97,31 @@ def measure(w, dtype, steps, warmup, chunk=0):
             "filter_bytes": fb, "smoother_bytes": sb, "filter_flops": ff * n, "smoother_flops": sf * n}
 
 
+def measure_plain(w, steps, warmup):
+    """The plain FP64 GPU scan (materialised elements, one launch per scan
+    level) on the same workload: the reference point for the fused scans."""
+    import torch
+    import paper_2102_09964_amd as P
+    model = P.make_model(w["model"]["components"], w["model"]["noise_var"])
+    n = w["t"].shape[0]
+    t = torch.as_tensor(w["t"], dtype=torch.float64, device="cuda")
+    y = torch.as_tensor(np.nan_to_num(w["y"]), dtype=torch.float64, device="cuda")
+    mask = torch.as_tensor(w["mask"], dtype=torch.uint8, device="cuda")
+    ws = P.alloc_workspace(model, n, P.F64, P.OP_PLAIN)
+    for _ in range(warmup):
+        r = P.plain_predict(model, t, y, mask, ws=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = P.plain_predict(model, t, y, mask, ws=ws)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    ll = float(r["loglik"].cpu()[0])
+    del ws, r
+    torch.cuda.empty_cache()
+    return {"steps_per_s": round(n / (ms / 1e3), 1), "ms_per_step": round(ms, 4), "loglik": ll}
+
+
 def roofline_of(m):
     dom = "filter" if m["filter_ms"] >= m["smoother_ms"] else "smoother"
     ms = m[dom + "_ms"]
@@ -137,10 +162,11 @@ def main():
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-also", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (the multi-GPU time sharding is a design, "
-              "see DESIGN.md); use --gpus 1", file=sys.stderr)
+        print("bench.py: runs on one GPU only; sharding the time axis over several GPUs is designed "
+              "but not implemented. Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():
@@ -183,6 +209,10 @@ def main():
         "loglik": m["loglik"],
         "status": list(m["status"]),
     }
+    if not args.no_plain:
+        pl = measure_plain(w, 3, 1)
+        pl["speedup_of_value"] = round(m["steps_per_s"] / pl["steps_per_s"], 2)
+        out["plain_f64_gpu_scan"] = pl
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     if also:
