@@ -1,5 +1,5 @@
 // Batched form: thousands of independent series of uneven lengths and
-// hyperparameters in one persistent launch per scan.
+// hyperparameters in one set of launches per scan.
 //
 // The series are concatenated along the time axis. A series start is a
 // filter element with A = 0 (the prior element of section 3) and a series
@@ -7,9 +7,8 @@
 // both scans restart at series boundaries through their elements alone:
 // tiles and lane chunks may straddle series without any segment flags.
 // Series of the same state layout form a group; up to two groups (ascending
-// state size) share one launch, each tile running the code of its group's
-// layout. The kernels are persistent: a fixed grid of workgroups keeps
-// taking tile tickets until all tiles of both groups are done.
+// state size) share the fold and finish launches, each tile running the code
+// of its group's layout; the carry pass runs once per group.
 //
 // The per-series hyperparameters (length-scale, variance, noise variance)
 // come from a device table; the model constants of a group are those of
@@ -50,63 +49,68 @@ __device__ __forceinline__ void series_view(ManySeries &sv, const BatchLaunch &a
     sv.locate(k0 < g.k_end ? k0 : g.k_end - 1);
 }
 
-template <class LA, class LB, typename T>
+// Group of a tile slot (slots of group 1 follow those of group 0).
+__device__ __forceinline__ int group_of(const BatchLaunch &a, int slot)
+{
+    return (a.ngroups > 1 && slot >= a.g[1].slot_base) ? 1 : 0;
+}
+
+template <class LA, class LB, typename T, bool FINISH>
 __global__ __launch_bounds__(PSSGP_WAVE) void batched_filter_kernel(FilterParams<T> p, BatchLaunch a)
 {
-    constexpr int INCL = AggLayout<(LA::D > LB::D ? LA::D : LB::D)>::INCL;
-    __shared__ DevModel mdl0, mdl1;
-    __shared__ T s_carry[INCL];
-    __shared__ uint32_t s_tile;
-    unpack_batch_model<LA>(a.bm[0], mdl0);
-    if (a.ngroups > 1) unpack_batch_model<LB>(a.bm[1], mdl1);
-    const int lane = lane_id();
-    while (true) {
-        __syncthreads();
-        if (lane == 0) s_tile = ticket_next(&p.ctl->ticket);
-        __syncthreads();
-        const int slot = (int)s_tile;
-        if (slot >= a.total_tiles) break;
-        const int gi = (a.ngroups > 1 && slot >= a.g[1].slot_base) ? 1 : 0;
-        const BatchGroup &g = a.g[gi];
-        const int tile = slot - g.slot_base;
-        TileRange tr{g.k_begin, g.k_end, g.ntiles, g.slot_base};
-        ManySeries sv;
-        series_view(sv, a, g, g.k_begin + ((int64_t)tile * PSSGP_WAVE + lane) * p.chunk);
+    __shared__ DevModel mdl;
+    const int slot = (int)blockIdx.x;
+    const int gi = group_of(a, slot);
+    if (gi == 0)
+        unpack_batch_model<LA>(a.bm[0], mdl);
+    else
+        unpack_batch_model<LB>(a.bm[1], mdl);
+    __syncthreads();
+    const BatchGroup &g = a.g[gi];
+    const int tile = slot - g.slot_base;
+    TileRange tr{g.k_begin, g.k_end, g.ntiles, g.slot_base};
+    ManySeries sv;
+    series_view(sv, a, g, g.k_begin + ((int64_t)tile * PSSGP_WAVE + lane_id()) * p.chunk);
+    if constexpr (FINISH) {
         double ll = 0.0;
         if (gi == 0)
-            filter_tile<LA, T, T, F_MOMENTS, ManySeries>(p, mdl0, sv, tr, tile, s_carry, ll);
+            filter_tile_finish<LA, T, T, F_MOMENTS, ManySeries>(p, mdl, sv, tr, tile, ll);
         else
-            filter_tile<LB, T, T, F_MOMENTS, ManySeries>(p, mdl1, sv, tr, tile, s_carry, ll);
+            filter_tile_finish<LB, T, T, F_MOMENTS, ManySeries>(p, mdl, sv, tr, tile, ll);
+    } else {
+        if (gi == 0)
+            filter_tile_fold<LA, T, T, ManySeries>(p, mdl, sv, tr, tile);
+        else
+            filter_tile_fold<LB, T, T, ManySeries>(p, mdl, sv, tr, tile);
     }
 }
 
-template <class LA, class LB, typename T>
+template <class LA, class LB, typename T, bool FINISH>
 __global__ __launch_bounds__(PSSGP_WAVE) void batched_smoother_kernel(SmoothParams<T> p, BatchLaunch a)
 {
-    constexpr int INCL = SAggLayout<(LA::D > LB::D ? LA::D : LB::D)>::INCL;
-    __shared__ DevModel mdl0, mdl1;
-    __shared__ T s_carry[INCL];
-    __shared__ uint32_t s_tile;
-    unpack_batch_model<LA>(a.bm[0], mdl0);
-    if (a.ngroups > 1) unpack_batch_model<LB>(a.bm[1], mdl1);
-    const int lane = lane_id();
-    while (true) {
-        __syncthreads();
-        if (lane == 0) s_tile = ticket_next(&p.ctl->ticket);
-        __syncthreads();
-        const int ticket = (int)s_tile;
-        if (ticket >= a.total_tiles) break;
-        const int slot = a.total_tiles - 1 - ticket;  // from the end
-        const int gi = (a.ngroups > 1 && slot >= a.g[1].slot_base) ? 1 : 0;
-        const BatchGroup &g = a.g[gi];
-        const int tile = slot - g.slot_base;
-        STileRange tr{g.k_begin, g.k_end, g.ntiles, g.slot_base};
-        ManySeries sv;
-        series_view(sv, a, g, g.k_begin + ((int64_t)tile * PSSGP_WAVE + lane) * p.chunk);
+    __shared__ DevModel mdl;
+    const int slot = (int)blockIdx.x;
+    const int gi = group_of(a, slot);
+    if (gi == 0)
+        unpack_batch_model<LA>(a.bm[0], mdl);
+    else
+        unpack_batch_model<LB>(a.bm[1], mdl);
+    __syncthreads();
+    const BatchGroup &g = a.g[gi];
+    const int tile = slot - g.slot_base;
+    STileRange tr{g.k_begin, g.k_end, g.ntiles, g.slot_base};
+    ManySeries sv;
+    series_view(sv, a, g, g.k_begin + ((int64_t)tile * PSSGP_WAVE + lane_id()) * p.chunk);
+    if constexpr (FINISH) {
         if (gi == 0)
-            smoother_tile<LA, T, false, ManySeries>(p, mdl0, sv, tr, tile, s_carry);
+            smoother_tile_finish<LA, T, false, ManySeries>(p, mdl, sv, tr, tile);
         else
-            smoother_tile<LB, T, false, ManySeries>(p, mdl1, sv, tr, tile, s_carry);
+            smoother_tile_finish<LB, T, false, ManySeries>(p, mdl, sv, tr, tile);
+    } else {
+        if (gi == 0)
+            smoother_tile_fold<LA, T, ManySeries>(p, mdl, sv, tr, tile);
+        else
+            smoother_tile_fold<LB, T, ManySeries>(p, mdl, sv, tr, tile);
     }
 }
 
@@ -136,24 +140,33 @@ int launch_bf(const BatchLaunch &a, hipStream_t s)
     p.n = a.n;
     p.chunk = a.chunk;
     p.ntiles = a.total_tiles;
-    p.deterministic = a.deterministic;
     p.m = (T *)a.m;
     p.P = (T *)a.P;
     p.loglik = nullptr;
     p.ck = nullptr;
     p.ll_terms = (T *)a.ll_terms;
     p.ctl = a.ws.ctl;
-    p.flags = a.ws.flags;
-    p.aggp = (T *)a.ws.aggp;
     p.inclp = (T *)a.ws.inclp;
     p.lanep = (T *)a.ws.lanep;
     p.partials = a.ws.partials;
-    hipLaunchKernelGGL((batched_filter_kernel<LA, LB, T>), dim3(a.grid), dim3(PSSGP_WAVE), 0, s, p, a);
+    const dim3 grid(a.total_tiles), block(PSSGP_WAVE);
+    hipLaunchKernelGGL((batched_filter_kernel<LA, LB, T, false>), grid, block, 0, s, p, a);
     int rc = (int)hipGetLastError();
     if (rc) return rc;
+    rc = launch_tile_scan<FilterScanOps<LA::D, T>>(a.ws.lanep, PSSGP_WAVE - 1, a.g[0].slot_base, a.g[0].ntiles, false,
+                                                   a.ws.inclp, s);
+    if (rc) return rc;
+    if (a.ngroups > 1) {
+        rc = launch_tile_scan<FilterScanOps<LB::D, T>>(a.ws.lanep, PSSGP_WAVE - 1, a.g[1].slot_base, a.g[1].ntiles,
+                                                       false, a.ws.inclp, s);
+        if (rc) return rc;
+    }
+    hipLaunchKernelGGL((batched_filter_kernel<LA, LB, T, true>), grid, block, 0, s, p, a);
+    rc = (int)hipGetLastError();
+    if (rc) return rc;
     const int per_block = 256 / PSSGP_WAVE;
-    const dim3 grid((unsigned)((a.n_series + per_block - 1) / per_block));
-    hipLaunchKernelGGL((series_loglik_kernel<T>), grid, dim3(256), 0, s, (const T *)a.ll_terms, a.offsets,
+    const dim3 lgrid((unsigned)((a.n_series + per_block - 1) / per_block));
+    hipLaunchKernelGGL((series_loglik_kernel<T>), lgrid, dim3(256), 0, s, (const T *)a.ll_terms, a.offsets,
                        a.n_series, a.loglik);
     return (int)hipGetLastError();
 }
@@ -168,17 +181,26 @@ int launch_bs(const BatchLaunch &a, hipStream_t s)
     p.n = a.n;
     p.chunk = a.chunk;
     p.ntiles = a.total_tiles;
-    p.deterministic = a.deterministic;
     p.f_mean = (T *)a.f_mean;
     p.f_var = (T *)a.f_var;
     p.ms = nullptr;
     p.Ps = nullptr;
     p.ctl = a.ws.ctl;
-    p.flags = a.ws.flags;
-    p.aggp = (T *)a.ws.aggp;
     p.inclp = (T *)a.ws.inclp;
     p.lanep = (T *)a.ws.lanep;
-    hipLaunchKernelGGL((batched_smoother_kernel<LA, LB, T>), dim3(a.grid), dim3(PSSGP_WAVE), 0, s, p, a);
+    const dim3 grid(a.total_tiles), block(PSSGP_WAVE);
+    hipLaunchKernelGGL((batched_smoother_kernel<LA, LB, T, false>), grid, block, 0, s, p, a);
+    int rc = (int)hipGetLastError();
+    if (rc) return rc;
+    rc = launch_tile_scan<SmootherScanOps<LA::D, T>>(a.ws.lanep, 0, a.g[0].slot_base, a.g[0].ntiles, true,
+                                                     a.ws.inclp, s);
+    if (rc) return rc;
+    if (a.ngroups > 1) {
+        rc = launch_tile_scan<SmootherScanOps<LB::D, T>>(a.ws.lanep, 0, a.g[1].slot_base, a.g[1].ntiles, true,
+                                                         a.ws.inclp, s);
+        if (rc) return rc;
+    }
+    hipLaunchKernelGGL((batched_smoother_kernel<LA, LB, T, true>), grid, block, 0, s, p, a);
     return (int)hipGetLastError();
 }
 

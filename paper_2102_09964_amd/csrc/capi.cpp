@@ -22,8 +22,9 @@ size_t ctl_bytes() { return 256; }
 struct Plan {
     int d = 0, ns = 0, chunk = kDefaultChunk, ntiles = 0;
     size_t tsize = 4;
-    size_t off_flags = 0, off_agg = 0, off_incl = 0, off_lane = 0, off_part = 0, off_ck = 0, off_rec = 0;
-    size_t off_flags2 = 0, off_agg2 = 0, off_incl2 = 0, off_lane2 = 0, off_part2 = 0;
+    size_t off_incl = 0, off_lane = 0, off_part = 0, off_ck = 0, off_rec = 0;
+    size_t off_incl2 = 0, off_lane2 = 0, off_part2 = 0;
+    size_t off_x = 0, off_xraw = 0;  // plain baseline element arrays
     size_t total = 0;
 };
 
@@ -66,19 +67,16 @@ Plan make_plan(int d, int ncomp, int64_t n, pssgp_dtype dtype, int op, const pss
         int64_t n2 = 1;
         while (n2 < n) n2 <<= 1;
         const size_t elem = (size_t)(3 * d * d + 2 * d) * sizeof(double);  // one filter element
-        p.off_agg = take((size_t)n2 * elem);
-        p.off_incl = take((size_t)n2 * elem);
+        p.off_x = take((size_t)n2 * elem);
+        p.off_xraw = take((size_t)n2 * elem);
         p.off_part = take((size_t)(n > 0 ? n : 1) * sizeof(double));
         p.total = off;
         return p;
     }
-    p.off_flags = take(nt * sizeof(uint32_t));
     if (op == PSSGP_OP_SMOOTH) {
-        p.off_agg = take(nt * smooth_agg_elems(d) * p.tsize);
         p.off_incl = take(nt * smooth_incl_elems(d) * p.tsize);
         p.off_lane = take(nt * 64 * smooth_agg_elems(d) * p.tsize);
     } else {
-        p.off_agg = take(nt * filter_agg_elems(d) * p.tsize);
         p.off_incl = take(nt * filter_incl_elems(d) * p.tsize);
         p.off_lane = take(nt * 64 * filter_agg_elems(d) * p.tsize);
     }
@@ -86,8 +84,6 @@ Plan make_plan(int d, int ncomp, int64_t n, pssgp_dtype dtype, int op, const pss
     if (op == PSSGP_OP_LOGLIK_GRAD) {
         p.off_ck = take(nt * 64 * filter_incl_elems(d) * p.tsize);
         p.off_rec = take((size_t)(n > 0 ? n : 1) * grad_rec_elems(d) * p.tsize);
-        p.off_flags2 = take(nt * sizeof(uint32_t));
-        p.off_agg2 = take(nt * grad_agg_elems(d) * p.tsize);
         p.off_incl2 = take(nt * (d + d * (d + 1) / 2) * p.tsize);
         p.off_lane2 = take(nt * 64 * grad_agg_elems(d) * p.tsize);
         p.off_part2 = take(nt * sizeof(double) * n_params(ncomp));
@@ -159,8 +155,6 @@ ScanWs scan_ws(void *ws, const Plan &p, bool second = false)
     char *b = (char *)ws;
     ScanWs s;
     s.ctl = (WsCtl *)b;
-    s.flags = (uint32_t *)(b + (second ? p.off_flags2 : p.off_flags));
-    s.aggp = b + (second ? p.off_agg2 : p.off_agg);
     s.inclp = b + (second ? p.off_incl2 : p.off_incl);
     s.lanep = b + (second ? p.off_lane2 : p.off_lane);
     s.partials = (double *)(b + (second ? p.off_part2 : p.off_part));
@@ -192,7 +186,7 @@ int run_filter(const pssgp_model *model, const double *t, const void *y, const u
     if ((rc = check_ws(ws, ws_bytes, p))) return rc;
     hipStream_t s = (hipStream_t)stream;
     ScanWs sw = scan_ws(ws, p);
-    rc = launch_ws_init(sw.ctl, sw.flags, p.ntiles, n == 0 ? loglik : nullptr, n == 0 && loglik ? 1 : 0, s);
+    rc = launch_ws_init(sw.ctl, n == 0 ? loglik : nullptr, n == 0 && loglik ? 1 : 0, s);
     if ((rc = hip_err((hipError_t)rc, "workspace init"))) return rc;
     if (n == 0) return PSSGP_OK;
     FilterLaunch a;
@@ -203,7 +197,6 @@ int run_filter(const pssgp_model *model, const double *t, const void *y, const u
     a.n = n;
     a.chunk = p.chunk;
     a.ntiles = p.ntiles;
-    a.deterministic = (opts && opts->deterministic) ? 1 : 0;
     a.m = m;
     a.P = P;
     // the kernel always reduces the log-likelihood; without a caller buffer
@@ -219,7 +212,7 @@ struct BatchPlan {
     size_t tsize = 4;
     BatchGroup g[2];
     BatchModel bm[2];
-    size_t off_flags = 0, off_agg = 0, off_incl = 0, off_lane = 0, off_part = 0, off_terms = 0, total = 0;
+    size_t off_incl = 0, off_lane = 0, off_part = 0, off_terms = 0, total = 0;
 };
 
 int make_batch_plan(const pssgp_batch_group *groups, int ngroups, int64_t n_series, const int64_t *off,
@@ -311,31 +304,14 @@ int make_batch_plan(const pssgp_batch_group *groups, int ngroups, int64_t n_seri
         o = align_up(o + bytes);
         return r;
     };
-    bp.off_flags = take(nt * sizeof(uint32_t));
     const int agg = (op == PSSGP_OP_SMOOTH) ? smooth_agg_elems(d) : filter_agg_elems(d);
     const int incl = (op == PSSGP_OP_SMOOTH) ? smooth_incl_elems(d) : filter_incl_elems(d);
-    bp.off_agg = take(nt * agg * bp.tsize);
     bp.off_incl = take(nt * incl * bp.tsize);
     bp.off_lane = take(nt * 64 * agg * bp.tsize);
     bp.off_part = take(nt * sizeof(double) * 3);
     if (op != PSSGP_OP_SMOOTH) bp.off_terms = take((size_t)(n > 0 ? n : 1) * bp.tsize);
     bp.total = o;
     return PSSGP_OK;
-}
-
-int persistent_grid(int total_tiles)
-{
-    static int cus = 0;
-    if (cus == 0) {
-        int dev = 0, v = 0;
-        if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
-            cus = v;
-        else
-            cus = 256;
-    }
-    const int cap = cus * 4;  // resident one-wave workgroups at the kernels' register use
-    return total_tiles < cap ? (total_tiles > 0 ? total_tiles : 1) : cap;
 }
 
 int run_batched(const pssgp_batch_group *groups, int ngroups, int64_t n_series, const int64_t *offsets,
@@ -373,13 +349,11 @@ int run_batched(const pssgp_batch_group *groups, int ngroups, int64_t n_series, 
     a.ngroups = bp.ngroups;
     for (int i = 0; i < 2; i++) { a.g[i] = bp.g[i]; a.bm[i] = bp.bm[i]; }
     a.total_tiles = bp.total_tiles;
-    a.grid = persistent_grid(bp.total_tiles);
     a.offsets = offsets;
     a.params = params;
     a.n_series = n_series;
     a.n = offsets_host[n_series];
     a.chunk = bp.chunk;
-    a.deterministic = (opts && opts->deterministic) ? 1 : 0;
     a.t = t;
     a.y = y;
     a.mask = mask;
@@ -390,13 +364,11 @@ int run_batched(const pssgp_batch_group *groups, int ngroups, int64_t n_series, 
     a.loglik = loglik;
     a.ll_terms = bp.off_terms ? b + bp.off_terms : nullptr;
     a.ws.ctl = (WsCtl *)b;
-    a.ws.flags = (uint32_t *)(b + bp.off_flags);
-    a.ws.aggp = b + bp.off_agg;
     a.ws.inclp = b + bp.off_incl;
     a.ws.lanep = b + bp.off_lane;
     a.ws.partials = (double *)(b + bp.off_part);
     const bool zero_ll = (op == PSSGP_OP_FILTER && a.n == 0);
-    rc = launch_ws_init(a.ws.ctl, a.ws.flags, bp.total_tiles, zero_ll ? loglik : nullptr,
+    rc = launch_ws_init(a.ws.ctl, zero_ll ? loglik : nullptr,
                         zero_ll ? (int)n_series : 0, s);
     if ((rc = hip_err((hipError_t)rc, "workspace init"))) return rc;
     if (a.n == 0) return PSSGP_OK;
@@ -469,7 +441,7 @@ int pssgp_discretize(const pssgp_model *model, const double *t, int64_t n, doubl
     if ((rc = check_ws(ws, ws_bytes, p))) return rc;
     hipStream_t s = (hipStream_t)stream;
     ScanWs sw = scan_ws(ws, p);
-    rc = launch_ws_init(sw.ctl, nullptr, 0, nullptr, 0, s);
+    rc = launch_ws_init(sw.ctl, nullptr, 0, s);
     if ((rc = hip_err((hipError_t)rc, "workspace init"))) return rc;
     if (n == 0) return PSSGP_OK;
     return check_launch(launch_discretize(dm, b0, b1, t, n, F, Q, sw.ctl, s), "discretize launch");
@@ -491,7 +463,7 @@ int pssgp_plain_predict(const pssgp_model *model, const double *t, const double 
     if ((rc = check_ws(ws, ws_bytes, p))) return rc;
     hipStream_t s = (hipStream_t)stream;
     char *b = (char *)ws;
-    rc = launch_ws_init((WsCtl *)b, nullptr, 0, n == 0 ? loglik : nullptr, n == 0 && loglik ? 1 : 0, s);
+    rc = launch_ws_init((WsCtl *)b, n == 0 ? loglik : nullptr, n == 0 && loglik ? 1 : 0, s);
     if ((rc = hip_err((hipError_t)rc, "workspace init"))) return rc;
     if (n == 0) return PSSGP_OK;
     PlainLaunch a;
@@ -506,8 +478,8 @@ int pssgp_plain_predict(const pssgp_model *model, const double *t, const double 
     a.f_mean = f_mean;
     a.f_var = f_var;
     a.loglik = loglik;
-    a.X = b + p.off_agg;
-    a.Xraw = b + p.off_incl;
+    a.X = b + p.off_x;
+    a.Xraw = b + p.off_xraw;
     a.terms = (double *)(b + p.off_part);
     return check_launch(launch_plain(dm, b0, b1, a, s), "plain launch");
 }
@@ -553,7 +525,7 @@ int pssgp_smooth(const pssgp_model *model, const double *t, const void *m, const
     if ((rc = check_ws(ws, ws_bytes, p))) return rc;
     hipStream_t s = (hipStream_t)stream;
     ScanWs sw = scan_ws(ws, p);
-    rc = launch_ws_init(sw.ctl, sw.flags, p.ntiles, nullptr, 0, s);
+    rc = launch_ws_init(sw.ctl, nullptr, 0, s);
     if ((rc = hip_err((hipError_t)rc, "workspace init"))) return rc;
     if (n == 0) return PSSGP_OK;
     SmoothLaunch a;
@@ -563,7 +535,6 @@ int pssgp_smooth(const pssgp_model *model, const double *t, const void *m, const
     a.n = n;
     a.chunk = p.chunk;
     a.ntiles = p.ntiles;
-    a.deterministic = (opts && opts->deterministic) ? 1 : 0;
     a.f_mean = f_mean;
     a.f_var = f_var;
     a.ms = ms;
@@ -591,10 +562,10 @@ int pssgp_loglik_grad(const pssgp_model *model, const double *t, const void *y, 
     char *b = (char *)ws;
     ScanWs sw = scan_ws(ws, p);
     const int np = n_params(dm.nblk);
-    rc = launch_ws_init(sw.ctl, sw.flags, p.ntiles, n == 0 ? loglik : nullptr, n == 0 ? 1 : 0, s);
+    rc = launch_ws_init(sw.ctl, n == 0 ? loglik : nullptr, n == 0 ? 1 : 0, s);
     if ((rc = hip_err((hipError_t)rc, "workspace init"))) return rc;
     if (n == 0) {
-        rc = launch_ws_init(sw.ctl, nullptr, 0, grad, np, s);
+        rc = launch_ws_init(sw.ctl, grad, np, s);
         return hip_err((hipError_t)rc, "workspace init");
     }
     FilterLaunch a;
@@ -605,7 +576,6 @@ int pssgp_loglik_grad(const pssgp_model *model, const double *t, const void *y, 
     a.n = n;
     a.chunk = p.chunk;
     a.ntiles = p.ntiles;
-    a.deterministic = (opts && opts->deterministic) ? 1 : 0;
     a.m = nullptr;
     a.P = nullptr;
     a.loglik = loglik;
@@ -614,7 +584,7 @@ int pssgp_loglik_grad(const pssgp_model *model, const double *t, const void *y, 
     rc = check_launch(launch_filter(dm, b0, b1, dtype == PSSGP_F64, a, s), "filter launch");
     if (rc) return rc;
     ScanWs sw2 = scan_ws(ws, p, true);
-    rc = launch_ws_init(sw2.ctl, sw2.flags, p.ntiles, nullptr, 0, s);
+    rc = launch_ws_init(sw2.ctl, nullptr, 0, s, /*keep_status=*/true);
     if ((rc = hip_err((hipError_t)rc, "workspace init"))) return rc;
     GradLaunch g;
     g.t = t;
@@ -623,7 +593,6 @@ int pssgp_loglik_grad(const pssgp_model *model, const double *t, const void *y, 
     g.n = n;
     g.chunk = p.chunk;
     g.ntiles = p.ntiles;
-    g.deterministic = a.deterministic;
     g.ck = b + p.off_ck;
     g.rec = b + p.off_rec;
     g.grad = grad;

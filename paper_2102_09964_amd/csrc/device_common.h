@@ -37,20 +37,6 @@ __host__ __device__ constexpr int sidx(int i, int j)
 
 // ------------------------------------------------------------------ control block
 
-enum : uint32_t { FLAG_NONE = 0, FLAG_AGG = 1, FLAG_INCL = 2 };
-
-__device__ __forceinline__ uint32_t flag_load_acquire(const uint32_t *p)
-{
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void flag_store_release(uint32_t *p, uint32_t v)
-{
-    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ uint32_t ticket_next(uint32_t *p)
-{
-    return __hip_atomic_fetch_add(p, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 __device__ __forceinline__ void status_or(uint32_t *p, uint32_t bits)
 {
     __hip_atomic_fetch_or(p, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -4,11 +4,11 @@
 
 namespace {
 
-__global__ void ws_init_kernel(WsCtl *ctl, uint32_t *flags, int64_t nflags, double *zero_out, int nzero)
+__global__ void ws_init_kernel(WsCtl *ctl, double *zero_out, int nzero, int keep_status)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < 3) (&ctl->ticket)[i] = 0u;
-    if (flags && i < nflags) flags[i] = 0u;
+    if (i == 0) ctl->done = 0u;
+    if (i == 1 && !keep_status) ctl->status = 0u;
     if (zero_out && i < nzero) zero_out[i] = 0.0;
 }
 
@@ -72,11 +72,11 @@ int launch_plain(const DevModel &mdl, int b0, int b1, const PlainLaunch &a, hipS
     return -1;
 }
 
-int launch_ws_init(WsCtl *ctl, uint32_t *flags, int64_t nflags, double *zero_out, int nzero, hipStream_t s)
+int launch_ws_init(WsCtl *ctl, double *zero_out, int nzero, hipStream_t s, bool keep_status)
 {
-    int64_t cnt = nflags > 3 ? nflags : 3;
+    int64_t cnt = nzero > 2 ? nzero : 2;
     if (nzero > cnt) cnt = nzero;
     const dim3 grid((unsigned)((cnt + 255) / 256)), block(256);
-    hipLaunchKernelGGL(ws_init_kernel, grid, block, 0, s, ctl, flags, nflags, zero_out, nzero);
+    hipLaunchKernelGGL(ws_init_kernel, grid, block, 0, s, ctl, zero_out, nzero, keep_status ? 1 : 0);
     return (int)hipGetLastError();
 }

@@ -1,33 +1,30 @@
 // Parallel Kalman filter with missing measurements (paper section 3) as a
-// single-pass decoupled look-back prefix scan, and the discretisation map.
+// three-pass scan, and the discretisation map.
 //
 // Work decomposition: one wave (64 lanes) per tile, each lane owns `chunk`
-// consecutive steps. A tile is processed as
-//   A  each lane folds its steps into a chunk aggregate (the element of a
-//      step is built from the FP64 discretisation and rounded to the scan
-//      type T)
-//   B  wave-level inclusive scan of the 64 chunk aggregates (Kogge-Stone
-//      over lane shuffles) with the general operator; every lane stores its
-//      inclusive aggregate in the workspace
-//   C  the last lane publishes the tile aggregate, walks back over the
-//      predecessor tiles until one has published its inclusive prefix, then
-//      applies the aggregates of the tiles in between to it; it publishes the
-//      tile's own inclusive prefix and hands the carry to the wave via LDS
-//   D  each lane applies its exclusive lane prefix to the carry, which gives
-//      the filter moments just before its chunk (every prefix from a series
-//      start has A = 0, so only (b, C) are carried), then re-runs its steps
-//      as a plain Kalman filter, writing (m, P) and accumulating the
-//      log-likelihood terms with compensated summation.
-// Tiles are numbered by an atomic ticket, so a tile only waits on tiles that
-// are already running. One series: the last tile to finish reduces the
-// per-tile log-likelihood partials in a fixed order. Batched: the kernel is
-// persistent (each workgroup keeps taking tickets), covers up to two groups
-// of series with different state layouts, and writes per-step
-// log-likelihood terms that a second kernel sums per series.
+// consecutive steps.
+//   fold    each lane folds its steps into a chunk aggregate (the element of
+//           a step is built from the FP64 discretisation and rounded to the
+//           scan type T); wave-level inclusive scan of the 64 chunk
+//           aggregates (Kogge-Stone over lane shuffles) with the general
+//           operator; every lane stores its inclusive aggregate
+//   carry   one workgroup scans the tile aggregates and stores the filter
+//           moments entering every tile (tile_scan.h)
+//   finish  each lane applies its exclusive lane prefix to the tile's carry,
+//           which gives the filter moments just before its chunk, then
+//           re-runs its steps as a plain Kalman filter, writing (m, P) and
+//           accumulating the log-likelihood terms with compensated
+//           summation.
+// One series: the last tile to finish reduces the per-tile log-likelihood
+// partials in a fixed order. Batched: the fold and finish grids cover up to
+// two groups of series with different state layouts (one carry scan per
+// group) and write per-step log-likelihood terms that a second kernel sums
+// per series.
 #pragma once
 #include "device_common.h"
 #include "filter_ops.h"
 #include "launch.h"
+#include "tile_scan.h"
 
 enum : int { F_MOMENTS = 1, F_CKPT = 2 };
 
@@ -40,15 +37,12 @@ struct FilterParams {
     int64_t n;
     int chunk;
     int ntiles;
-    int deterministic;
     T *m;
     T *P;
     double *loglik;
     T *ck;
     T *ll_terms;  // batched: per-step log-likelihood terms
     WsCtl *ctl;
-    uint32_t *flags;
-    T *aggp;
     T *inclp;
     T *lanep;
     double *partials;
@@ -80,11 +74,53 @@ __device__ __forceinline__ void step_transition(const DevModel &mdl, const SV &s
         for (int j = 0; j < D; j++) { F[i][j] = T(F64[i][j]); Q[i][j] = T(Q64[i][j]); }
 }
 
-// One tile of the filter scan. ll_out receives this lane's compensated
-// log-likelihood partial.
+// Fold pass of one tile: each lane folds its chunk into an aggregate, the
+// wave scans the 64 chunk aggregates (inclusive, time order) and stores them
+// at lanep; lane 63 then holds the tile aggregate.
+template <class LY, typename T, typename CT, class SV>
+__device__ __forceinline__ void filter_tile_fold(const FilterParams<T> &p, const DevModel &mdl, SV &sv,
+                                                 const TileRange &tr, int tile)
+{
+    constexpr int D = LY::D;
+    constexpr int AGG = AggLayout<D>::SIZE;
+    const int lane = lane_id();
+    const int slot = tr.slot_base + tile;
+    const int64_t chunk_id = (int64_t)slot * PSSGP_WAVE + lane;
+    const int64_t k0 = tr.k_begin + ((int64_t)tile * PSSGP_WAVE + lane) * p.chunk;
+    const int64_t k1 = (k0 + p.chunk < tr.k_end) ? k0 + p.chunk : tr.k_end;
+    T h[D];
+#pragma unroll
+    for (int i = 0; i < D; i++) h[i] = T(mdl.H[i]);
+    uint32_t bad = 0;  // reported by the finish pass, which sees the same steps
+    FAgg<D, T> agg;
+    agg_identity<D, T>(agg);
+    for (int64_t k = k0; k < k1; k++) {
+        PSSGP_RELOAD_CONSTANTS();
+        sv.seek(k);
+        T F[D][D], Q[D][D];
+        step_transition<LY, T, SV>(mdl, sv, p.t, k, F, Q, bad);
+        const bool obs = p.mask ? (p.mask[k] != 0) : true;
+        const T yk = obs ? p.y[k] : T(0);
+        const T R = p.noise_k ? T(p.noise_k[k]) : T(sv.R);
+        agg_fold<D, T>(agg, F, Q, h, R, yk, obs);
+    }
+    for (int o = 1; o < PSSGP_WAVE; o <<= 1) {
+        FAgg<D, T> other;
+        agg_shfl_up<D, T>(agg, other, o);
+        if (lane >= o) agg_combine<D, T, CT>(other, agg, agg);
+    }
+    agg_store<D, T>(p.lanep + (size_t)chunk_id * AGG, agg);
+}
+
+// Finish pass of one tile: each lane takes the moments entering the tile
+// (carry pass), applies its exclusive lane prefix (every prefix from a
+// series start has A = 0, so only (b, C) are carried) and re-runs its steps
+// as a plain Kalman filter, writing (m, P) and accumulating the
+// log-likelihood terms with compensated summation. ll_out receives this
+// lane's partial.
 template <class LY, typename T, typename CT, int MODE, class SV>
-__device__ __forceinline__ void filter_tile(const FilterParams<T> &p, const DevModel &mdl, SV &sv,
-                                            const TileRange &tr, int tile, T *s_carry, double &ll_out)
+__device__ __forceinline__ void filter_tile_finish(const FilterParams<T> &p, const DevModel &mdl, SV &sv,
+                                                   const TileRange &tr, int tile, double &ll_out)
 {
     constexpr int D = LY::D;
     constexpr int AGG = AggLayout<D>::SIZE;
@@ -99,73 +135,8 @@ __device__ __forceinline__ void filter_tile(const FilterParams<T> &p, const DevM
     for (int i = 0; i < D; i++) h[i] = T(mdl.H[i]);
     uint32_t bad = 0;
 
-    // A: chunk aggregate; B: wave inclusive scan
-    {
-        FAgg<D, T> agg;
-        agg_identity<D, T>(agg);
-        for (int64_t k = k0; k < k1; k++) {
-            PSSGP_RELOAD_CONSTANTS();
-            sv.seek(k);
-            T F[D][D], Q[D][D];
-            step_transition<LY, T, SV>(mdl, sv, p.t, k, F, Q, bad);
-            const bool obs = p.mask ? (p.mask[k] != 0) : true;
-            const T yk = obs ? p.y[k] : T(0);
-            const T R = p.noise_k ? T(p.noise_k[k]) : T(sv.R);
-            agg_fold<D, T>(agg, F, Q, h, R, yk, obs);
-        }
-        for (int o = 1; o < PSSGP_WAVE; o <<= 1) {
-            FAgg<D, T> other;
-            agg_shfl_up<D, T>(agg, other, o);
-            if (lane >= o) agg_combine<D, T, CT>(other, agg, agg);
-        }
-        agg_store<D, T>(p.lanep + (size_t)chunk_id * AGG, agg);
-    }
-    __syncthreads();
-
-    // C: decoupled look-back by the last lane
-    if (lane == PSSGP_WAVE - 1) {
-        const T *tagg = p.lanep + (size_t)chunk_id * AGG;
-        T cb[D], cC[D][D];
-#pragma unroll
-        for (int i = 0; i < D; i++) {
-            cb[i] = T(0);
-#pragma unroll
-            for (int j = 0; j < D; j++) cC[i][j] = T(0);
-        }
-        if (tile > 0) {
-            if (!p.deterministic) {
-                T *dst = p.aggp + (size_t)slot * AGG;
-                for (int i = 0; i < AGG; i++) dst[i] = tagg[i];
-                flag_store_release(&p.flags[slot], FLAG_AGG);
-            }
-            int j = slot - 1;
-            while (true) {
-                uint32_t f;
-                while ((f = flag_load_acquire(&p.flags[j])) == FLAG_NONE) __builtin_amdgcn_s_sleep(1);
-                if (f == FLAG_INCL) break;
-                j--;
-            }
-            moments_load<D, T>(p.inclp + (size_t)j * INCL, cb, cC);
-            for (int i = j + 1; i < slot; i++) {
-                FAgg<D, T> x;
-                agg_load<D, T>(p.aggp + (size_t)i * AGG, x);
-                moments_apply<D, T, CT>(cb, cC, x, cb, cC);
-            }
-        }
-        {
-            FAgg<D, T> x;
-            agg_load<D, T>(tagg, x);
-            T ib[D], iC[D][D];
-            moments_apply<D, T, CT>(cb, cC, x, ib, iC);
-            moments_store<D, T>(p.inclp + (size_t)slot * INCL, ib, iC);
-        }
-        flag_store_release(&p.flags[slot], FLAG_INCL);
-        moments_store<D, T>(s_carry, cb, cC);
-    }
-    __syncthreads();
-
     T m[D], P[D][D];
-    moments_load<D, T>(s_carry, m, P);
+    moments_load<D, T>(p.inclp + (size_t)slot * INCL, m, P);
     if (lane > 0) {
         FAgg<D, T> excl;
         agg_load<D, T>(p.lanep + (size_t)(chunk_id - 1) * AGG, excl);
@@ -175,7 +146,6 @@ __device__ __forceinline__ void filter_tile(const FilterParams<T> &p, const DevM
         if (k0 < tr.k_end) moments_store<D, T>(p.ck + (size_t)chunk_id * INCL, m, P);
     }
 
-    // D: sequential Kalman filter over the chunk from the carried moments
     T ls = T(0), lc = T(0);
     for (int64_t k = k0; k < k1; k++) {
         PSSGP_RELOAD_CONSTANTS();
@@ -222,23 +192,32 @@ __device__ __forceinline__ void filter_tile(const FilterParams<T> &p, const DevM
     ll_out = (double)ls + (double)lc;
 }
 
-template <class LY, typename T, typename CT, int MODE>
-__global__ __launch_bounds__(PSSGP_WAVE) void filter_scan_kernel(FilterParams<T> p, DevModel mdl_arg)
+template <class LY, typename T, typename CT>
+__global__ __launch_bounds__(PSSGP_WAVE) void filter_fold_kernel(FilterParams<T> p, DevModel mdl_arg)
 {
-    __shared__ uint32_t s_tile;
-    __shared__ T s_carry[AggLayout<LY::D>::INCL];
+    __shared__ DevModel mdl;
+    model_to_lds(mdl_arg, mdl);
+    OneSeries sv;
+    sv.init(mdl, p.n);
+    TileRange tr{0, p.n, p.ntiles, 0};
+    filter_tile_fold<LY, T, CT, OneSeries>(p, mdl, sv, tr, (int)blockIdx.x);
+}
+
+template <class LY, typename T, typename CT, int MODE>
+__global__ __launch_bounds__(PSSGP_WAVE) void filter_finish_kernel(FilterParams<T> p, DevModel mdl_arg)
+{
     __shared__ DevModel mdl;
     const int lane = lane_id();
-    if (lane == 0) s_tile = ticket_next(&p.ctl->ticket);
+    const int tile = (int)blockIdx.x;
     model_to_lds(mdl_arg, mdl);
-    const int tile = (int)s_tile;
     OneSeries sv;
     sv.init(mdl, p.n);
     TileRange tr{0, p.n, p.ntiles, 0};
     double ll = 0.0;
-    filter_tile<LY, T, CT, MODE, OneSeries>(p, mdl, sv, tr, tile, s_carry, ll);
+    filter_tile_finish<LY, T, CT, MODE, OneSeries>(p, mdl, sv, tr, tile, ll);
 
-    // log-likelihood: deterministic wave sum, tile partial, last tile reduces
+    // log-likelihood: deterministic wave sum, tile partial, the last tile to
+    // finish reduces the partials in a fixed order (no waiting involved)
     const double tot = wave_sum(ll);
     uint32_t prev = 0;
     if (lane == 0) {
@@ -289,15 +268,12 @@ FilterParams<T> filter_params(const FilterLaunch &a)
     p.n = a.n;
     p.chunk = a.chunk;
     p.ntiles = a.ntiles;
-    p.deterministic = a.deterministic;
     p.m = (T *)a.m;
     p.P = (T *)a.P;
     p.loglik = a.loglik;
     p.ck = (T *)a.ck;
     p.ll_terms = nullptr;
     p.ctl = a.ws.ctl;
-    p.flags = a.ws.flags;
-    p.aggp = (T *)a.ws.aggp;
     p.inclp = (T *)a.ws.inclp;
     p.lanep = (T *)a.ws.lanep;
     p.partials = a.ws.partials;
@@ -308,13 +284,18 @@ template <class LY, typename T, typename CT>
 int launch_filter_t(const DevModel &mdl, const FilterLaunch &a, hipStream_t s)
 {
     FilterParams<T> p = filter_params<LY, T>(a);
-    dim3 grid(a.ntiles), block(PSSGP_WAVE);
+    const dim3 grid(a.ntiles), block(PSSGP_WAVE);
+    hipLaunchKernelGGL((filter_fold_kernel<LY, T, CT>), grid, block, 0, s, p, mdl);
+    int rc = (int)hipGetLastError();
+    if (rc) return rc;
+    rc = launch_tile_scan<FilterScanOps<LY::D, T>>(a.ws.lanep, PSSGP_WAVE - 1, 0, a.ntiles, false, a.ws.inclp, s);
+    if (rc) return rc;
     if (a.m)
-        hipLaunchKernelGGL((filter_scan_kernel<LY, T, CT, F_MOMENTS>), grid, block, 0, s, p, mdl);
+        hipLaunchKernelGGL((filter_finish_kernel<LY, T, CT, F_MOMENTS>), grid, block, 0, s, p, mdl);
     else if (a.ck)
-        hipLaunchKernelGGL((filter_scan_kernel<LY, T, CT, F_CKPT>), grid, block, 0, s, p, mdl);
+        hipLaunchKernelGGL((filter_finish_kernel<LY, T, CT, F_CKPT>), grid, block, 0, s, p, mdl);
     else
-        hipLaunchKernelGGL((filter_scan_kernel<LY, T, CT, 0>), grid, block, 0, s, p, mdl);
+        hipLaunchKernelGGL((filter_finish_kernel<LY, T, CT, 0>), grid, block, 0, s, p, mdl);
     return (int)hipGetLastError();
 }
 

@@ -1,5 +1,5 @@
 // Gradient of the log-likelihood by a reverse-mode adjoint of the filter,
-// run as a single-pass reverse decoupled look-back scan.
+// run as a three-pass reverse scan (tile_scan.h).
 //
 // The paper obtains the gradient by automatic differentiation through the
 // parallel filter (sections 2 and 4.4, item 6). Here the adjoint is written
@@ -27,21 +27,23 @@
 // where G1_c, Q_c, Pinf_c are restricted to component c.
 //
 // Memory: the forward filter stores one checkpoint (m, P) per lane chunk.
-// Per tile (one wave, `chunk` steps per lane):
-//   A  each lane re-runs the filter over its chunk from its checkpoint,
-//      writes the per-step forward quantities (mu, Pi, K, S, v) to a scratch
-//      record, and composes its adjoint elements left to right
-//   B  wave-level inclusive suffix scan of the chunk maps
-//   C  lane 0 looks forward over successor tiles for the adjoint at the tile
-//      end (as in the smoother)
-//   D  each lane walks its chunk backwards from its carried adjoint, reading
-//      the records, and accumulates the parameter contractions in FP64; the
-//      per-tile partials are reduced by the last tile in a fixed order.
+// One wave per tile, `chunk` steps per lane:
+//   fold    each lane re-runs the filter over its chunk from its checkpoint,
+//           writes the per-step forward quantities (mu, Pi, K, S, v) to a
+//           scratch record, and composes its adjoint elements left to right;
+//           wave-level inclusive suffix scan of the chunk maps
+//   carry   one workgroup scans the tile maps from the end and stores the
+//           adjoint after every tile
+//   finish  each lane walks its chunk backwards from its carried adjoint,
+//           reading the records, and accumulates the parameter contractions
+//           in FP64; the per-tile partials are reduced by the last tile in a
+//           fixed order.
 #pragma once
 #include "device_common.h"
 #include "launch.h"
 #include "filter_ops.h"
-#include "smoother_kernel.h"
+#include "smoother_ops.h"
+#include "tile_scan.h"
 
 // adjoint composition x (x) y (out may alias x or y)
 template <int D, typename T>
@@ -101,6 +103,27 @@ __device__ __forceinline__ void adj_apply(const SAgg<D, T> &x, T (&mb)[D], T (&P
     }
 }
 
+// Carry-pass operations of the adjoint scan (reverse time order).
+template <int D_, typename T_>
+struct AdjointScanOps {
+    static constexpr int D = D_;
+    using T = T_;
+    using Agg = SAgg<D, T>;
+    static constexpr int AGG = SAggLayout<D>::SIZE;
+    static constexpr int MOM = SAggLayout<D>::INCL;
+    static __device__ __forceinline__ void identity(Agg &a) { sagg_identity<D, T>(a); }
+    static __device__ __forceinline__ void load(const T *p, Agg &a) { sagg_load<D, T>(p, a); }
+    static __device__ __forceinline__ void extend(const Agg &acc, const Agg &nx, Agg &out)
+    {
+        adj_combine<D, T>(nx, acc, out);
+    }
+    static __device__ __forceinline__ void apply(T (&v)[D], T (&M)[D][D], const Agg &x) { adj_apply<D, T>(x, v, M); }
+    static __device__ __forceinline__ void mom_store(T *p, const T (&v)[D], const T (&M)[D][D])
+    {
+        gl_store<D, T>(p, v, M);
+    }
+};
+
 template <typename T>
 struct GradParams {
     const double *t;
@@ -109,13 +132,10 @@ struct GradParams {
     int64_t n;
     int chunk;
     int ntiles;
-    int deterministic;
     const T *ck;
     T *rec;
     double *grad;
     WsCtl *ctl;
-    uint32_t *flags;
-    T *aggp;
     T *inclp;
     T *lanep;
     double *partials;
@@ -129,7 +149,7 @@ struct RecLayout {
 };
 
 template <class LY, typename T>
-__global__ __launch_bounds__(PSSGP_WAVE) void grad_scan_kernel(GradParams<T> p, DevModel mdl_arg)
+__global__ __launch_bounds__(PSSGP_WAVE) void grad_fold_kernel(GradParams<T> p, DevModel mdl_arg)
 {
     constexpr int D = LY::D;
     constexpr int NS = LY::NS;
@@ -137,13 +157,10 @@ __global__ __launch_bounds__(PSSGP_WAVE) void grad_scan_kernel(GradParams<T> p, 
     constexpr int INCL = SAggLayout<D>::INCL;
     constexpr int REC = RecLayout<D>::SIZE;
     constexpr int NP = 2 * LY::NB + 1;
-    __shared__ uint32_t s_tile;
-    __shared__ T s_carry[INCL];
     __shared__ DevModel mdl;
     const int lane = lane_id();
-    if (lane == 0) s_tile = (uint32_t)p.ntiles - 1u - ticket_next(&p.ctl->ticket);
     model_to_lds(mdl_arg, mdl);
-    const int tile = (int)s_tile;
+    const int tile = (int)blockIdx.x;
     const int64_t chunk_id = (int64_t)tile * PSSGP_WAVE + lane;
     const int64_t k0 = chunk_id * p.chunk;
     const int64_t k1 = (k0 + p.chunk < p.n) ? k0 + p.chunk : p.n;
@@ -153,7 +170,7 @@ __global__ __launch_bounds__(PSSGP_WAVE) void grad_scan_kernel(GradParams<T> p, 
     const T R = T(mdl.R);
     uint32_t bad = 0;
 
-    // A: forward recompute from the checkpoint, records, chunk adjoint map
+    // forward recompute from the checkpoint, records, chunk adjoint map
     {
         SAgg<D, T> agg;
         sagg_identity<D, T>(agg);
@@ -246,7 +263,7 @@ __global__ __launch_bounds__(PSSGP_WAVE) void grad_scan_kernel(GradParams<T> p, 
                 for (int j = 0; j < D; j++) agg.E[i][j] = fma(-wv[i], K[j], X[i][j]);
             }
         }
-        // B: wave inclusive suffix scan
+        // wave inclusive suffix scan
         for (int o = 1; o < PSSGP_WAVE; o <<= 1) {
             SAgg<D, T> other;
             sagg_shfl_down<D, T>(agg, other, o);
@@ -254,52 +271,34 @@ __global__ __launch_bounds__(PSSGP_WAVE) void grad_scan_kernel(GradParams<T> p, 
         }
         sagg_store<D, T>(p.lanep + (size_t)chunk_id * AGG, agg);
     }
-    __syncthreads();
+    (void)bad;
+}
 
-    // C: look-forward by lane 0
-    if (lane == 0) {
-        const T *tagg = p.lanep + (size_t)chunk_id * AGG;
-        T cg[D], cL[D][D];
+template <class LY, typename T>
+__global__ __launch_bounds__(PSSGP_WAVE) void grad_finish_kernel(GradParams<T> p, DevModel mdl_arg)
+{
+    constexpr int D = LY::D;
+    constexpr int NS = LY::NS;
+    constexpr int AGG = SAggLayout<D>::SIZE;
+    constexpr int INCL = SAggLayout<D>::INCL;
+    constexpr int REC = RecLayout<D>::SIZE;
+    constexpr int NP = 2 * LY::NB + 1;
+    __shared__ DevModel mdl;
+    const int lane = lane_id();
+    model_to_lds(mdl_arg, mdl);
+    const int tile = (int)blockIdx.x;
+    const int64_t chunk_id = (int64_t)tile * PSSGP_WAVE + lane;
+    const int64_t k0 = chunk_id * p.chunk;
+    const int64_t k1 = (k0 + p.chunk < p.n) ? k0 + p.chunk : p.n;
+    T h[D];
 #pragma unroll
-        for (int i = 0; i < D; i++) {
-            cg[i] = T(0);
-#pragma unroll
-            for (int j = 0; j < D; j++) cL[i][j] = T(0);
-        }
-        if (tile < p.ntiles - 1) {
-            if (!p.deterministic) {
-                T *dst = p.aggp + (size_t)tile * AGG;
-                for (int i = 0; i < AGG; i++) dst[i] = tagg[i];
-                flag_store_release(&p.flags[tile], FLAG_AGG);
-            }
-            int j = tile + 1;
-            while (true) {
-                uint32_t f;
-                while ((f = flag_load_acquire(&p.flags[j])) == FLAG_NONE) __builtin_amdgcn_s_sleep(1);
-                if (f == FLAG_INCL) break;
-                j++;
-            }
-            gl_load<D, T>(p.inclp + (size_t)j * INCL, cg, cL);
-            for (int i = j - 1; i > tile; i--) {
-                SAgg<D, T> x;
-                sagg_load<D, T>(p.aggp + (size_t)i * AGG, x);
-                adj_apply<D, T>(x, cg, cL);
-            }
-        }
-        gl_store<D, T>(s_carry, cg, cL);
-        {
-            SAgg<D, T> x;
-            sagg_load<D, T>(tagg, x);
-            adj_apply<D, T>(x, cg, cL);
-            gl_store<D, T>(p.inclp + (size_t)tile * INCL, cg, cL);
-        }
-        flag_store_release(&p.flags[tile], FLAG_INCL);
-    }
-    __syncthreads();
+    for (int i = 0; i < D; i++) h[i] = T(mdl.H[i]);
+    const T R = T(mdl.R);
+    uint32_t bad = 0;
 
-    // D: backward sweep with the parameter contractions
+    // backward sweep from the carried adjoint with the parameter contractions
     T mb[D], Pb[D][D];
-    gl_load<D, T>(s_carry, mb, Pb);
+    gl_load<D, T>(p.inclp + (size_t)tile * INCL, mb, Pb);
     if (lane < PSSGP_WAVE - 1) {
         SAgg<D, T> excl;
         sagg_load<D, T>(p.lanep + (size_t)(chunk_id + 1) * AGG, excl);
@@ -457,18 +456,20 @@ int launch_grad_t(const DevModel &mdl, const GradLaunch &a, hipStream_t s)
     p.n = a.n;
     p.chunk = a.chunk;
     p.ntiles = a.ntiles;
-    p.deterministic = a.deterministic;
     p.ck = (const T *)a.ck;
     p.rec = (T *)a.rec;
     p.grad = a.grad;
     p.ctl = a.ws.ctl;
-    p.flags = a.ws.flags;
-    p.aggp = (T *)a.ws.aggp;
     p.inclp = (T *)a.ws.inclp;
     p.lanep = (T *)a.ws.lanep;
     p.partials = a.ws.partials;
-    dim3 grid(a.ntiles), block(PSSGP_WAVE);
-    hipLaunchKernelGGL((grad_scan_kernel<LY, T>), grid, block, 0, s, p, mdl);
+    const dim3 grid(a.ntiles), block(PSSGP_WAVE);
+    hipLaunchKernelGGL((grad_fold_kernel<LY, T>), grid, block, 0, s, p, mdl);
+    int rc = (int)hipGetLastError();
+    if (rc) return rc;
+    rc = launch_tile_scan<AdjointScanOps<LY::D, T>>(a.ws.lanep, 0, 0, a.ntiles, true, a.ws.inclp, s);
+    if (rc) return rc;
+    hipLaunchKernelGGL((grad_finish_kernel<LY, T>), grid, block, 0, s, p, mdl);
     return (int)hipGetLastError();
 }
 

@@ -8,10 +8,9 @@
 
 // Control block at the start of every workspace.
 struct WsCtl {
-    uint32_t ticket;   // dynamic tile order
     uint32_t done;     // tiles finished (last-block reduction)
     uint32_t status;   // PSSGP_STATUS_* bits
-    uint32_t pad[61];
+    uint32_t pad[62];
 };
 
 // Block layouts (state sizes of up to two kernel components) compiled in.
@@ -22,9 +21,7 @@ struct WsCtl {
 // Workspace pieces of one scan launch (all device pointers).
 struct ScanWs {
     WsCtl *ctl;
-    uint32_t *flags;
-    void *aggp;      // per-tile aggregates
-    void *inclp;     // per-tile inclusive prefixes
+    void *inclp;     // per-tile carries (moments entering the tile)
     void *lanep;     // per-lane inclusive aggregates within the tile
     double *partials;  // per-tile partial sums (loglik, gradient)
 };
@@ -37,7 +34,6 @@ struct FilterLaunch {
     int64_t n;
     int chunk;
     int ntiles;
-    int deterministic;
     void *m;         // nullable
     void *P;         // nullable
     double *loglik;  // nullable
@@ -52,7 +48,6 @@ struct SmoothLaunch {
     int64_t n;
     int chunk;
     int ntiles;
-    int deterministic;
     void *f_mean;
     void *f_var;
     void *ms;  // nullable
@@ -67,7 +62,6 @@ struct GradLaunch {
     int64_t n;
     int chunk;
     int ntiles;
-    int deterministic;
     const void *ck;     // checkpoints written by the forward filter
     void *rec;          // per-step forward records (scratch)
     double *grad;       // device [2 n_comp + 1]
@@ -99,13 +93,11 @@ struct BatchLaunch {
     BatchGroup g[2];
     BatchModel bm[2];
     int total_tiles;
-    int grid;                 // persistent workgroups
     const int64_t *offsets;   // device [n_series + 1]
     const double *params;     // device [n_series][3]
     int64_t n_series;
     int64_t n;                // total steps
     int chunk;
-    int deterministic;
     const double *t;
     const void *y;
     const uint8_t *mask;
@@ -158,6 +150,8 @@ int launch_discretize(const DevModel &mdl, int b0, int b1, const double *t, int6
                       double *Q, WsCtl *ctl, hipStream_t s);
 int launch_grad(const DevModel &mdl, int b0, int b1, bool f64, const GradLaunch &a, hipStream_t s);
 int launch_plain(const DevModel &mdl, int b0, int b1, const PlainLaunch &a, hipStream_t s);
-int launch_ws_init(WsCtl *ctl, uint32_t *flags, int64_t nflags, double *zero_out, int nzero,
-                   hipStream_t s);
+// Zeroes the control block (keep_status: only the tile counter, so that a
+// second pass of the same call keeps the first one's status bits) and
+// zero_out[0, nzero).
+int launch_ws_init(WsCtl *ctl, double *zero_out, int nzero, hipStream_t s, bool keep_status = false);
 bool layout_supported(int b0, int b1);
