@@ -56,9 +56,11 @@ struct TileRange {
     int slot_base;
 };
 
+// Transition of step k in the scan type: Dl = F - I (F = 0 at a series
+// start, so Dl = -I there) and Q, both from the FP64 discretisation.
 template <class LY, typename T, class SV>
 __device__ __forceinline__ void step_transition(const DevModel &mdl, const SV &sv, const double *t, int64_t k,
-                                                T (&F)[LY::D][LY::D], T (&Q)[LY::D][LY::D],
+                                                T (&Dl)[LY::D][LY::D], T (&Q)[LY::D][LY::D],
                                                 uint32_t &bad)
 {
     constexpr int D = LY::D;
@@ -71,7 +73,10 @@ __device__ __forceinline__ void step_transition(const DevModel &mdl, const SV &s
 #pragma unroll
     for (int i = 0; i < D; i++)
 #pragma unroll
-        for (int j = 0; j < D; j++) { F[i][j] = T(F64[i][j]); Q[i][j] = T(Q64[i][j]); }
+        for (int j = 0; j < D; j++) {
+            Dl[i][j] = T(F64[i][j] - (i == j ? 1.0 : 0.0));
+            Q[i][j] = T(Q64[i][j]);
+        }
 }
 
 // Fold pass of one tile: each lane folds its chunk into an aggregate, the
@@ -97,12 +102,12 @@ __device__ __forceinline__ void filter_tile_fold(const FilterParams<T> &p, const
     for (int64_t k = k0; k < k1; k++) {
         PSSGP_RELOAD_CONSTANTS();
         sv.seek(k);
-        T F[D][D], Q[D][D];
-        step_transition<LY, T, SV>(mdl, sv, p.t, k, F, Q, bad);
+        T Dl[D][D], Q[D][D];
+        step_transition<LY, T, SV>(mdl, sv, p.t, k, Dl, Q, bad);
         const bool obs = p.mask ? (p.mask[k] != 0) : true;
         const T yk = obs ? p.y[k] : T(0);
         const T R = p.noise_k ? T(p.noise_k[k]) : T(sv.R);
-        agg_fold<D, T>(agg, F, Q, h, R, yk, obs);
+        agg_fold<D, T>(agg, Dl, Q, h, R, yk, obs);
     }
     for (int o = 1; o < PSSGP_WAVE; o <<= 1) {
         FAgg<D, T> other;
@@ -150,15 +155,32 @@ __device__ __forceinline__ void filter_tile_finish(const FilterParams<T> &p, con
     for (int64_t k = k0; k < k1; k++) {
         PSSGP_RELOAD_CONSTANTS();
         sv.seek(k);
-        T F[D][D], Q[D][D];
-        step_transition<LY, T, SV>(mdl, sv, p.t, k, F, Q, bad);
+        T Dl[D][D], Q[D][D];
+        step_transition<LY, T, SV>(mdl, sv, p.t, k, Dl, Q, bad);
         const bool obs = p.mask ? (p.mask[k] != 0) : true;
         const T yk = obs ? p.y[k] : T(0);
         const T R = p.noise_k ? T(p.noise_k[k]) : T(sv.R);
-        T mp[D], FP[D][D], Pp[D][D], Ph[D];
-        mat_vec<D, T>(F, m, mp);
-        mat_mul<D, T>(F, P, FP);
-        mat_mul_nt_sym_add<D, T>(FP, F, Q, Pp);
+        // predict with Dl = F - I: mp = m + Dl m, Pp = P + X + X^T + X Dl^T + Q
+        T mp[D], X[D][D], Pp[D][D], Ph[D];
+#pragma unroll
+        for (int i = 0; i < D; i++) {
+            T acc = m[i];
+#pragma unroll
+            for (int k2 = 0; k2 < D; k2++) acc = fma(Dl[i][k2], m[k2], acc);
+            mp[i] = acc;
+        }
+        mat_mul<D, T>(Dl, P, X);
+#pragma unroll
+        for (int i = 0; i < D; i++)
+#pragma unroll
+            for (int j = i; j < D; j++) {
+                T acc = T(0);
+#pragma unroll
+                for (int k2 = 0; k2 < D; k2++) acc = fma(X[i][k2], Dl[j][k2], acc);
+                const T c = P[i][j] + ((X[i][j] + X[j][i]) + acc) + Q[i][j];
+                Pp[i][j] = c;
+                Pp[j][i] = c;
+            }
         mat_vec<D, T>(Pp, h, Ph);
         const T S = dot<D, T>(h, Ph) + R;
         const T v = yk - dot<D, T>(h, mp);
@@ -169,13 +191,17 @@ __device__ __forceinline__ void filter_tile_finish(const FilterParams<T> &p, con
         const T term = obs ? T(-0.5) * (log(T(6.283185307179586) * S) + v * v * w) : T(0);
         if (p.ll_terms) p.ll_terms[k] = term;
         kahan_add<T>(ls, lc, term);
+        // update, symmetric (Joseph) form: P = Pp - K c^T - c K^T + S K K^T
+        T K[D];
 #pragma unroll
-        for (int i = 0; i < D; i++) m[i] = fma(Ph[i] * w, v, mp[i]);
+        for (int i = 0; i < D; i++) K[i] = Ph[i] * w;
+#pragma unroll
+        for (int i = 0; i < D; i++) m[i] = fma(K[i], v, mp[i]);
 #pragma unroll
         for (int i = 0; i < D; i++)
 #pragma unroll
             for (int j = i; j < D; j++) {
-                const T c = fma(-Ph[i] * w, Ph[j], Pp[i][j]);
+                const T c = fma(S * K[i], K[j], fma(-Ph[i], K[j], fma(-K[i], Ph[j], Pp[i][j])));
                 P[i][j] = c;
                 P[j][i] = c;
             }

@@ -32,15 +32,47 @@ __device__ __forceinline__ void agg_identity(FAgg<D, T> &a)
 // paper's operator applied to the observed / missing element of the step
 // (a rank-one J, so the (I + C J)^-1 of the operator reduces to the scalar
 // 1 / S). obs = false leaves the predicted triple and (eta, J) unchanged.
+//
+// The transition comes as Dl = F - I, so that short steps (F close to I)
+// keep their increment to full relative precision: F X = X + Dl X and
+// F C F^T = C + X + X^T + X Dl^T with X = Dl C. The conditioned covariance
+// is formed symmetrically, C' - K c^T - c K^T + S K K^T with c = C' H^T and
+// K = c / S (the rank-one form of the Joseph update), which keeps it
+// accurate when the measurement noise is small against the prior.
 template <int D, typename T>
-__device__ __forceinline__ void agg_fold(FAgg<D, T> &a, const T (&F)[D][D], const T (&Q)[D][D],
+__device__ __forceinline__ void agg_fold(FAgg<D, T> &a, const T (&Dl)[D][D], const T (&Q)[D][D],
                                          const T (&h)[D], T R, T y, bool obs)
 {
-    T A1[D][D], b1[D], FC[D][D], C1[D][D];
-    mat_mul<D, T>(F, a.A, A1);
-    mat_vec<D, T>(F, a.b, b1);
-    mat_mul<D, T>(F, a.C, FC);
-    mat_mul_nt_sym_add<D, T>(FC, F, Q, C1);
+    T A1[D][D], b1[D], X[D][D], C1[D][D];
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+        T acc = a.b[i];
+#pragma unroll
+        for (int k = 0; k < D; k++) acc = fma(Dl[i][k], a.b[k], acc);
+        b1[i] = acc;
+#pragma unroll
+        for (int j = 0; j < D; j++) {
+            T aa = a.A[i][j], xx = T(0);
+#pragma unroll
+            for (int k = 0; k < D; k++) {
+                aa = fma(Dl[i][k], a.A[k][j], aa);
+                xx = fma(Dl[i][k], a.C[k][j], xx);
+            }
+            A1[i][j] = aa;
+            X[i][j] = xx;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < D; i++)
+#pragma unroll
+        for (int j = i; j < D; j++) {
+            T acc = T(0);
+#pragma unroll
+            for (int k = 0; k < D; k++) acc = fma(X[i][k], Dl[j][k], acc);
+            const T c = a.C[i][j] + ((X[i][j] + X[j][i]) + acc) + Q[i][j];
+            C1[i][j] = c;
+            C1[j][i] = c;
+        }
     T Ch[D], v[D];
     mat_vec<D, T>(C1, h, Ch);
 #pragma unroll
@@ -67,7 +99,7 @@ __device__ __forceinline__ void agg_fold(FAgg<D, T> &a, const T (&F)[D][D], cons
     for (int i = 0; i < D; i++)
 #pragma unroll
         for (int j = i; j < D; j++) {
-            const T c = fma(-Ch[i], K[j], C1[i][j]);
+            const T c = fma(S * K[i], K[j], fma(-Ch[i], K[j], fma(-K[i], Ch[j], C1[i][j])));
             a.C[i][j] = c;
             a.C[j][i] = c;
             const T jj = fma(v[i] * w, v[j], a.J[i][j]);

@@ -30,6 +30,8 @@ __global__ __launch_bounds__(128) void plain_filter_elements(DevModel mdl, const
         discretize<LY, true>(mdl, model_scale(mdl), dt, i == 0, F, Q);
         for (int j = 0; j < D; j++) h[j] = mdl.H[j];
         const bool obs = mask ? (mask[i] != 0) : true;
+#pragma unroll
+        for (int r = 0; r < D; r++) F[r][r] -= 1.0;  // F - I
         agg_fold<D, double>(e, F, Q, h, mdl.R, obs ? y[i] : 0.0, obs);
     }
     X[i] = e;
