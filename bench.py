@@ -36,7 +36,6 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-FP32_VECTOR_PEAK_TFLOPS = 157.3
 
 WORKLOADS = {
     "rbf6_lognormal": lambda: __import__("workloads").rbf6_lognormal(),
@@ -46,21 +45,47 @@ WORKLOADS = {
 }
 
 
+FP32_UNPACKED_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (= FP64 vector)
+
+PASSES = ("filter_fold", "filter_carry", "filter_finish", "smoother_fold", "smoother_carry", "smoother_finish")
+
+
+def pass_costs(d, tsize, chunk):
+    """Algorithmic HBM bytes and flops per time step of every pass (2 flops
+    per multiply-add; the FP64 transition and smoother elements and the FP32
+    scan algebra both count, since with packed FP32 disabled both run at the
+    same vector rate). Bytes: inputs read once, the filter-to-smoother
+    handover (m, P) written then read, outputs written, and the per-lane
+    aggregates of the fold passes (one per chunk of steps)."""
+    ns = d * (d + 1) // 2
+    mom = tsize * (d + ns)
+    fagg = tsize * (d * d + 2 * d + 2 * ns) / chunk
+    sagg = tsize * (d * d + d + ns) / chunk
+    disc = d ** 3 + ns * ns + ns                     # F - I by the expansion, Q by the pair sums
+    kf = d ** 3 + ns * d + 2 * d * d + 4 * ns        # predict in F - I form, Joseph update
+    fold = 2 * d ** 3 + ns * d + 3 * d * d + 4 * ns  # unknown-start fold of one step
+    combine = 5 * d ** 3                             # general operator (lane scan, per chunk)
+    selem = 3 * d ** 3 + 2 * ns * d + 2 * d * d      # smoother element (Cholesky form)
+    scomb = 2 * d ** 3 + ns * d
+    sapply = d ** 3 + ns * d + 2 * d * d
+    out = {
+        "filter_fold": (9 + tsize + fagg, 2 * (disc + fold + 6 * combine / chunk)),
+        "filter_carry": (0.0, 0.0),
+        "filter_finish": (9 + tsize + fagg + mom, 2 * (disc + kf)),
+        "smoother_fold": (8 + mom + sagg, 2 * (disc + selem + scomb + 6 * scomb / chunk)),
+        "smoother_carry": (0.0, 0.0),
+        "smoother_finish": (8 + mom + sagg + 2 * tsize, 2 * (disc + selem + sapply)),
+    }
+    return out
+
+
 def algorithmic_bytes(d, tsize, n):
-    """HBM bytes the path must move per launch (inputs read once, the filter
-    to smoother handover (m, P) written then read, outputs written)."""
+    """HBM bytes the path must move per step pass (inputs read once, the
+    filter to smoother handover (m, P) written then read, outputs written)."""
     mom = tsize * d * (d + 3) // 2
     filt = n * (8 + tsize + 1 + mom)          # t, y, mask in; m, P out
     smooth = n * (8 + mom + 2 * tsize)        # t, m, P in; f_mean, f_var out
     return filt, smooth
-
-
-def algorithmic_flops(d):
-    """Arithmetic of the scans per step, counting the matrix products of the
-    method (2 flops per multiply-add): filter per-step fold and Kalman
-    update about 8 d^3, smoother element build, fold and apply about
-    19 d^3."""
-    return 8 * d ** 3, 19 * d ** 3
 
 
 def measure(w, dtype, steps, warmup, chunk=0):
@@ -78,23 +103,38 @@ def measure(w, dtype, steps, warmup, chunk=0):
     for _ in range(warmup):
         pipe.run(t, y, mask)
     torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    # whole-step timing: wall clock over the timed steps (stream-ordered,
+    # synchronised on both sides)
     t0 = time.perf_counter()
     for i in range(steps):
-        pipe.run(t, y, mask, events=evs[i])
+        pipe.run(t, y, mask)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / steps
-    f_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
-    s_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+    # per-pass timing: HIP events recorded by the library on the launch
+    # stream around every pass, in a second timed run of the same steps
+    evs = [[[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(2)] for _ in range(steps)]
+    for i in range(steps):
+        for grp in evs[i]:
+            for e in grp:
+                P.event_handle(e)
+    torch.cuda.synchronize()
+    for i in range(steps):
+        pipe.run(t, y, mask, pass_events=evs[i])
+    torch.cuda.synchronize()
+    pass_ms = {}
+    for g, scan in enumerate(("filter", "smoother")):
+        for j, name in enumerate(("fold", "carry", "finish")):
+            pass_ms[scan + "_" + name] = float(np.mean([e[g][j].elapsed_time(e[g][j + 1]) for e in evs]))
     ll = float(pipe.loglik.cpu()[0])
     status = (P.status(pipe.ws_f), P.status(pipe.ws_s))
     tsize = 4 if dtype == "float32" else 8
     fb, sb = algorithmic_bytes(d, tsize, n)
-    ff, sf = algorithmic_flops(d)
-    return {"n": n, "d": d, "ms_per_step": ms_step, "filter_ms": f_ms, "smoother_ms": s_ms,
-            "steps_per_s": n / (ms_step / 1e3), "loglik": ll, "status": status,
-            "filter_bytes": fb, "smoother_bytes": sb, "filter_flops": ff * n, "smoother_flops": sf * n}
+    return {"n": n, "d": d, "tsize": tsize, "chunk": chunk or 16, "ms_per_step": ms_step,
+            "filter_ms": sum(v for k, v in pass_ms.items() if k.startswith("filter")),
+            "smoother_ms": sum(v for k, v in pass_ms.items() if k.startswith("smoother")),
+            "pass_ms": pass_ms, "steps_per_s": n / (ms_step / 1e3), "loglik": ll, "status": status,
+            "filter_bytes": fb, "smoother_bytes": sb}
 
 
 def measure_plain(w, steps, warmup):
@@ -123,14 +163,32 @@ def measure_plain(w, steps, warmup):
 
 
 def roofline_of(m):
-    dom = "filter" if m["filter_ms"] >= m["smoother_ms"] else "smoother"
-    ms = m[dom + "_ms"]
-    gbs = m[dom + "_bytes"] / (ms / 1e3) / 1e9
-    tfl = m[dom + "_flops"] / (ms / 1e3) / 1e12
-    return {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(gbs / HBM_PEAK_GBS, 5), "traffic": None, "kernel": dom + "_scan",
-            "kernel_ms": round(ms, 4), "bytes_per_step": round(m[dom + "_bytes"] / m["n"], 1),
-            "alu_tflops": round(tfl, 3), "alu_frac_fp32_vector": round(tfl / FP32_VECTOR_PEAK_TFLOPS, 5)}
+    """Roofline of the dominant pass (longest mean duration): its
+    algorithmic flops and bytes per launch over that duration, against the
+    vector ALU peak and the HBM peak; `bound` is the roofline the pass's
+    arithmetic intensity puts it under."""
+    costs = pass_costs(m["d"], m["tsize"], m["chunk"])
+    dom = max(m["pass_ms"], key=lambda k: m["pass_ms"][k])
+    ms = m["pass_ms"][dom]
+    bpstep, fpstep = costs[dom]
+    gbs = bpstep * m["n"] / (ms / 1e3) / 1e9
+    tfl = fpstep * m["n"] / (ms / 1e3) / 1e12
+    intensity = fpstep / bpstep if bpstep else float("inf")
+    ridge = FP32_UNPACKED_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
+    alu = intensity >= ridge
+    out = {"bound": "alu" if alu else "hbm",
+           "achieved": round(tfl if alu else gbs, 3),
+           "peak": FP32_UNPACKED_PEAK_TFLOPS if alu else HBM_PEAK_GBS,
+           "unit": "TFLOP/s" if alu else "GB/s",
+           "frac": round(tfl / FP32_UNPACKED_PEAK_TFLOPS if alu else gbs / HBM_PEAK_GBS, 5),
+           "traffic": None,
+           "kernel": dom, "kernel_ms": round(ms, 4),
+           "flops_per_step": round(fpstep, 1), "bytes_per_step": round(bpstep, 1),
+           "achieved_gbs": round(gbs, 2), "hbm_frac": round(gbs / HBM_PEAK_GBS, 5),
+           "achieved_tflops": round(tfl, 3),
+           "path_hbm_frac": round((m["filter_bytes"] + m["smoother_bytes"]) / (m["ms_per_step"] / 1e3) / 1e9
+                                  / HBM_PEAK_GBS, 5)}
+    return out
 
 
 def cpu_baseline(w, target_s=12.0):
@@ -186,7 +244,8 @@ def main():
             also.append({"workload": name, "dtype": dt, "n": mm["n"], "d": mm["d"],
                          "steps_per_s": round(mm["steps_per_s"], 1), "ms_per_step": round(mm["ms_per_step"], 4),
                          "filter_ms": round(mm["filter_ms"], 4), "smoother_ms": round(mm["smoother_ms"], 4),
-                         "roofline_frac": roofline_of(mm)["frac"]})
+                         "pass_ms": {k: round(v, 4) for k, v in mm["pass_ms"].items()},
+                         "roofline": {k: roofline_of(mm)[k] for k in ("bound", "kernel", "achieved", "unit", "frac")}})
     out = {
         "metric": "time steps/sec, filter+smoother+loglik(+grad), FP32 vs FP64, d=2..8, 1 GPU",
         "value": round(m["steps_per_s"], 1),
@@ -206,6 +265,7 @@ def main():
         "roofline": roofline_of(m),
         "filter_ms": round(m["filter_ms"], 4),
         "smoother_ms": round(m["smoother_ms"], 4),
+        "pass_ms": {k: round(v, 4) for k, v in m["pass_ms"].items()},
         "loglik": m["loglik"],
         "status": list(m["status"]),
     }

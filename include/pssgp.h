@@ -90,9 +90,17 @@ typedef enum { PSSGP_F32 = 0, PSSGP_F64 = 1 } pssgp_dtype;
 
 typedef struct pssgp_options {
     uint32_t chunk;          /* steps per lane, 0 = default (16); 1..64 */
-    uint32_t deterministic;  /* 1: every tile waits for its predecessor's inclusive
-                                prefix, making results bitwise reproducible */
-    uint32_t reserved[6];
+    uint32_t deterministic;  /* accepted for compatibility; every scan combines its
+                                partial results in a fixed order, so results are
+                                always bitwise reproducible for a given chunk */
+    uint32_t reserved[6];    /* zero */
+    void *pass_events[4];    /* optional hipEvent_t handles (NULL entries are skipped),
+                                recorded on the stream before the fold pass, before
+                                the carry pass, before the finish pass and after the
+                                finish pass of the call's filter scan (pssgp_filter,
+                                pssgp_loglik, pssgp_loglik_grad, batched filter) or
+                                smoother scan (pssgp_smooth, batched smoother); for
+                                timing the passes. Owned by the caller. */
 } pssgp_options;
 
 typedef enum {

@@ -50,7 +50,7 @@ class BatchGroup(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("chunk", ctypes.c_uint32), ("deterministic", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32 * 6)]
+                ("reserved", ctypes.c_uint32 * 6), ("pass_events", ctypes.c_void_p * 4)]
 
 
 _lib = None
@@ -138,6 +138,22 @@ def make_options(chunk=0, deterministic=False) -> Options:
     o = Options()
     o.chunk = int(chunk)
     o.deterministic = 1 if deterministic else 0
+    return o
+
+
+def event_handle(ev) -> int:
+    """Raw hipEvent_t of a torch.cuda.Event (recorded once if not yet created)."""
+    if not ev.cuda_event:
+        ev.record()
+    return int(ev.cuda_event)
+
+
+def _with_events(options, events) -> Options:
+    o = Options()
+    if options is not None:
+        ctypes.memmove(ctypes.byref(o), ctypes.byref(options), ctypes.sizeof(Options))
+    for i, ev in enumerate(events):
+        o.pass_events[i] = event_handle(ev) if ev is not None else None
     return o
 
 
@@ -455,21 +471,27 @@ class Pipeline:
         self.Ps = torch.empty((ns, n), dtype=self.tdt, device=device) if full_state else None
         self.device = device
 
-    def run(self, t, y, mask=None, events=None):
+    def run(self, t, y, mask=None, events=None, pass_events=None):
         """events: optional list of 3 torch.cuda.Event recorded before the
-        filter, between filter and smoother, and after the smoother."""
+        filter, between filter and smoother, and after the smoother.
+        pass_events: optional (filter, smoother) pair of lists of 4 recorded
+        torch.cuda.Event (see pssgp_options.pass_events), for the duration
+        of every pass."""
         L = lib()
         mp = ctypes.byref(self.model)
-        op = ctypes.byref(self.options) if self.options is not None else None
+        op_f = op_s = ctypes.byref(self.options) if self.options is not None else None
+        if pass_events is not None:
+            op_f = ctypes.byref(_with_events(self.options, pass_events[0]))
+            op_s = ctypes.byref(_with_events(self.options, pass_events[1]))
         st = _stream()
         if events:
             events[0].record()
         _check(L.pssgp_filter(mp, _p(t), _p(y), _p(mask), None, self.n, self.code, _p(self.m), _p(self.P),
-                              _p(self.loglik), _p(self.ws_f), self.ws_f.numel(), op, st))
+                              _p(self.loglik), _p(self.ws_f), self.ws_f.numel(), op_f, st))
         if events:
             events[1].record()
         _check(L.pssgp_smooth(mp, _p(t), _p(self.m), _p(self.P), self.n, self.code, _p(self.f_mean),
-                              _p(self.f_var), _p(self.ms), _p(self.Ps), _p(self.ws_s), self.ws_s.numel(), op,
+                              _p(self.f_var), _p(self.ms), _p(self.Ps), _p(self.ws_s), self.ws_s.numel(), op_s,
                               st))
         if events:
             events[2].record()

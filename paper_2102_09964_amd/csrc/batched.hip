@@ -58,7 +58,9 @@ __device__ __forceinline__ int group_of(const BatchLaunch &a, int slot)
 template <class LA, class LB, typename T, bool FINISH>
 __global__ __launch_bounds__(PSSGP_WAVE) void batched_filter_kernel(FilterParams<T> p, BatchLaunch a)
 {
+    constexpr int NSN = SNSize<LA, T>::value > SNSize<LB, T>::value ? SNSize<LA, T>::value : SNSize<LB, T>::value;
     __shared__ DevModel mdl;
+    __shared__ double sN[NSN];
     const int slot = (int)blockIdx.x;
     const int gi = group_of(a, slot);
     if (gi == 0)
@@ -66,6 +68,12 @@ __global__ __launch_bounds__(PSSGP_WAVE) void batched_filter_kernel(FilterParams
     else
         unpack_batch_model<LB>(a.bm[1], mdl);
     __syncthreads();
+    if constexpr (sizeof(T) == 4) {
+        if (gi == 0)
+            qpairs_build<LA>(mdl, sN);
+        else
+            qpairs_build<LB>(mdl, sN);
+    }
     const BatchGroup &g = a.g[gi];
     const int tile = slot - g.slot_base;
     TileRange tr{g.k_begin, g.k_end, g.ntiles, g.slot_base};
@@ -74,21 +82,23 @@ __global__ __launch_bounds__(PSSGP_WAVE) void batched_filter_kernel(FilterParams
     if constexpr (FINISH) {
         double ll = 0.0;
         if (gi == 0)
-            filter_tile_finish<LA, T, T, F_MOMENTS, ManySeries>(p, mdl, sv, tr, tile, ll);
+            filter_tile_finish<LA, T, typename CombineType<T>::type, F_MOMENTS, ManySeries>(p, mdl, sN, sv, tr, tile, ll);
         else
-            filter_tile_finish<LB, T, T, F_MOMENTS, ManySeries>(p, mdl, sv, tr, tile, ll);
+            filter_tile_finish<LB, T, typename CombineType<T>::type, F_MOMENTS, ManySeries>(p, mdl, sN, sv, tr, tile, ll);
     } else {
         if (gi == 0)
-            filter_tile_fold<LA, T, T, ManySeries>(p, mdl, sv, tr, tile);
+            filter_tile_fold<LA, T, typename CombineType<T>::type, ManySeries>(p, mdl, sN, sv, tr, tile);
         else
-            filter_tile_fold<LB, T, T, ManySeries>(p, mdl, sv, tr, tile);
+            filter_tile_fold<LB, T, typename CombineType<T>::type, ManySeries>(p, mdl, sN, sv, tr, tile);
     }
 }
 
 template <class LA, class LB, typename T, bool FINISH>
 __global__ __launch_bounds__(PSSGP_WAVE) void batched_smoother_kernel(SmoothParams<T> p, BatchLaunch a)
 {
+    constexpr int NSN = SNSize<LA, T>::value > SNSize<LB, T>::value ? SNSize<LA, T>::value : SNSize<LB, T>::value;
     __shared__ DevModel mdl;
+    __shared__ double sN[NSN];
     const int slot = (int)blockIdx.x;
     const int gi = group_of(a, slot);
     if (gi == 0)
@@ -96,6 +106,12 @@ __global__ __launch_bounds__(PSSGP_WAVE) void batched_smoother_kernel(SmoothPara
     else
         unpack_batch_model<LB>(a.bm[1], mdl);
     __syncthreads();
+    if constexpr (sizeof(T) == 4) {
+        if (gi == 0)
+            qpairs_build<LA>(mdl, sN);
+        else
+            qpairs_build<LB>(mdl, sN);
+    }
     const BatchGroup &g = a.g[gi];
     const int tile = slot - g.slot_base;
     STileRange tr{g.k_begin, g.k_end, g.ntiles, g.slot_base};
@@ -103,14 +119,14 @@ __global__ __launch_bounds__(PSSGP_WAVE) void batched_smoother_kernel(SmoothPara
     series_view(sv, a, g, g.k_begin + ((int64_t)tile * PSSGP_WAVE + lane_id()) * p.chunk);
     if constexpr (FINISH) {
         if (gi == 0)
-            smoother_tile_finish<LA, T, false, ManySeries>(p, mdl, sv, tr, tile);
+            smoother_tile_finish<LA, T, false, ManySeries>(p, mdl, sN, sv, tr, tile);
         else
-            smoother_tile_finish<LB, T, false, ManySeries>(p, mdl, sv, tr, tile);
+            smoother_tile_finish<LB, T, false, ManySeries>(p, mdl, sN, sv, tr, tile);
     } else {
         if (gi == 0)
-            smoother_tile_fold<LA, T, ManySeries>(p, mdl, sv, tr, tile);
+            smoother_tile_fold<LA, T, ManySeries>(p, mdl, sN, sv, tr, tile);
         else
-            smoother_tile_fold<LB, T, ManySeries>(p, mdl, sv, tr, tile);
+            smoother_tile_fold<LB, T, ManySeries>(p, mdl, sN, sv, tr, tile);
     }
 }
 
@@ -150,9 +166,11 @@ int launch_bf(const BatchLaunch &a, hipStream_t s)
     p.lanep = (T *)a.ws.lanep;
     p.partials = a.ws.partials;
     const dim3 grid(a.total_tiles), block(PSSGP_WAVE);
+    pass_event(a.ev, 0, s);
     hipLaunchKernelGGL((batched_filter_kernel<LA, LB, T, false>), grid, block, 0, s, p, a);
     int rc = (int)hipGetLastError();
     if (rc) return rc;
+    pass_event(a.ev, 1, s);
     rc = launch_tile_scan<FilterScanOps<LA::D, T>>(a.ws.lanep, PSSGP_WAVE - 1, a.g[0].slot_base, a.g[0].ntiles, false,
                                                    a.ws.inclp, s);
     if (rc) return rc;
@@ -161,6 +179,7 @@ int launch_bf(const BatchLaunch &a, hipStream_t s)
                                                        false, a.ws.inclp, s);
         if (rc) return rc;
     }
+    pass_event(a.ev, 2, s);
     hipLaunchKernelGGL((batched_filter_kernel<LA, LB, T, true>), grid, block, 0, s, p, a);
     rc = (int)hipGetLastError();
     if (rc) return rc;
@@ -168,7 +187,9 @@ int launch_bf(const BatchLaunch &a, hipStream_t s)
     const dim3 lgrid((unsigned)((a.n_series + per_block - 1) / per_block));
     hipLaunchKernelGGL((series_loglik_kernel<T>), lgrid, dim3(256), 0, s, (const T *)a.ll_terms, a.offsets,
                        a.n_series, a.loglik);
-    return (int)hipGetLastError();
+    rc = (int)hipGetLastError();
+    pass_event(a.ev, 3, s);
+    return rc;
 }
 
 template <class LA, class LB, typename T>
@@ -189,9 +210,11 @@ int launch_bs(const BatchLaunch &a, hipStream_t s)
     p.inclp = (T *)a.ws.inclp;
     p.lanep = (T *)a.ws.lanep;
     const dim3 grid(a.total_tiles), block(PSSGP_WAVE);
+    pass_event(a.ev, 0, s);
     hipLaunchKernelGGL((batched_smoother_kernel<LA, LB, T, false>), grid, block, 0, s, p, a);
     int rc = (int)hipGetLastError();
     if (rc) return rc;
+    pass_event(a.ev, 1, s);
     rc = launch_tile_scan<SmootherScanOps<LA::D, T>>(a.ws.lanep, 0, a.g[0].slot_base, a.g[0].ntiles, true,
                                                      a.ws.inclp, s);
     if (rc) return rc;
@@ -200,8 +223,11 @@ int launch_bs(const BatchLaunch &a, hipStream_t s)
                                                          a.ws.inclp, s);
         if (rc) return rc;
     }
+    pass_event(a.ev, 2, s);
     hipLaunchKernelGGL((batched_smoother_kernel<LA, LB, T, true>), grid, block, 0, s, p, a);
-    return (int)hipGetLastError();
+    rc = (int)hipGetLastError();
+    pass_event(a.ev, 3, s);
+    return rc;
 }
 
 // (d0, d1) with d1 = d0 for a single group

@@ -190,6 +190,7 @@ int run_filter(const pssgp_model *model, const double *t, const void *y, const u
     if ((rc = hip_err((hipError_t)rc, "workspace init"))) return rc;
     if (n == 0) return PSSGP_OK;
     FilterLaunch a;
+    a.ev = opts ? opts->pass_events : nullptr;
     a.t = t;
     a.y = y;
     a.mask = mask;
@@ -346,6 +347,7 @@ int run_batched(const pssgp_batch_group *groups, int ngroups, int64_t n_series, 
     char *b = (char *)ws;
     BatchLaunch a;
     std::memset(&a, 0, sizeof(a));
+    a.ev = opts ? opts->pass_events : nullptr;
     a.ngroups = bp.ngroups;
     for (int i = 0; i < 2; i++) { a.g[i] = bp.g[i]; a.bm[i] = bp.bm[i]; }
     a.total_tiles = bp.total_tiles;
@@ -529,6 +531,7 @@ int pssgp_smooth(const pssgp_model *model, const double *t, const void *m, const
     if ((rc = hip_err((hipError_t)rc, "workspace init"))) return rc;
     if (n == 0) return PSSGP_OK;
     SmoothLaunch a;
+    a.ev = opts ? opts->pass_events : nullptr;
     a.t = t;
     a.m = m;
     a.P = P;
@@ -569,6 +572,7 @@ int pssgp_loglik_grad(const pssgp_model *model, const double *t, const void *y, 
         return hip_err((hipError_t)rc, "workspace init");
     }
     FilterLaunch a;
+    a.ev = opts ? opts->pass_events : nullptr;
     a.t = t;
     a.y = y;
     a.mask = mask;

@@ -2,6 +2,7 @@
 // layout of the state, FP64 discretisation, fixed-size register linear
 // algebra, wave-level shuffles and the workspace control block.
 #pragma once
+#include <type_traits>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -10,6 +11,29 @@
 #include "model.h"
 
 #define PSSGP_WAVE 64
+
+// Minimum waves per SIMD requested from the compiler for the FP32 fold and
+// finish kernels (register budget 512 / waves per lane).
+#ifndef PSSGP_FILTER_MINW
+#define PSSGP_FILTER_MINW 2
+#endif
+#ifndef PSSGP_SMOOTHER_MINW
+#define PSSGP_SMOOTHER_MINW 2
+#endif
+
+// Arithmetic type of the general filtering operator (the lane, tile and
+// lane-start combinations) for scan type T.
+#ifndef PSSGP_COMBINE_F64
+#define PSSGP_COMBINE_F64 0
+#endif
+template <typename T>
+struct CombineType {
+    using type = T;
+};
+template <>
+struct CombineType<float> {
+    using type = typename std::conditional<PSSGP_COMBINE_F64 != 0, double, float>::type;
+};
 
 // ------------------------------------------------------------------ layout
 
@@ -218,6 +242,156 @@ __device__ __forceinline__ void discretize(const DevModel &mdl, const StepScale 
             F[i][j] = first ? 0.0 : (zero ? fid : F[i][j]);
             Q[i][j] = first ? mdl.Pinf[i * D + j] * sc.var_mult : (zero ? 0.0 : Q[i][j]);
         }
+}
+
+// ------------------------------------------------------------------ transition for the FP32 scans
+//
+// With F(s) = sum_r phi_r(s) M_r (the expansion above), the process noise of
+// a block is
+//   Q = Pinf - F Pinf F^T = Pinf - sum_{r <= r'} phi_r phi_r' N_rr',
+//   N_rr = M_r Pinf M_r^T,  N_rr' = M_r Pinf M_r'^T + M_r' Pinf M_r^T (r < r').
+// The N are built once per workgroup into LDS (qpairs_build), so a step
+// needs the phi in FP64 and one FP64 accumulation per entry of F - I and of
+// Q, without FP64 matrix temporaries. The scan receives Dl = F - I and Q,
+// rounded to the scan type.
+
+// (i, j), i <= j, of the row-major packed upper index e of an n x n matrix
+__device__ __forceinline__ void unpack_upper(int e, int n, int &i, int &j)
+{
+    i = 0;
+    while (e >= n - i) {
+        e -= n - i;
+        i++;
+    }
+    j = i + e;
+}
+
+template <class LY>
+struct QPairs {
+    __host__ __device__ static constexpr int np(int b) { return LY::bdim(b) * (LY::bdim(b) + 1) / 2; }
+    __host__ __device__ static constexpr int size(int b) { return np(b) * np(b); }
+    __host__ __device__ static constexpr int off(int b) { return b == 0 ? 0 : size(0); }
+    static constexpr int TOTAL = size(0) + (LY::NB > 1 ? size(1) : 0);
+};
+
+// All threads of the workgroup; sN has QPairs<LY>::TOTAL doubles. Ends with
+// a workgroup barrier.
+template <class LY>
+__device__ void qpairs_build(const DevModel &mdl, double *sN)
+{
+#pragma unroll
+    for (int b = 0; b < LY::NB; b++) {
+        const int dc = LY::bdim(b), o = LY::boff(b), np = QPairs<LY>::np(b);
+        const double *M = mdl.fcoef + mdl.blk[b].fc_off;
+        for (int e = (int)threadIdx.x; e < np * np; e += (int)blockDim.x) {
+            const int pr = e / np, en = e - pr * np;
+            int r, r2, i, j;
+            unpack_upper(pr, dc, r, r2);
+            unpack_upper(en, dc, i, j);
+            double acc = 0.0;
+            for (int k = 0; k < dc; k++)
+                for (int l = 0; l < dc; l++) {
+                    const double pk = mdl.Pinf[(o + k) * LY::D + o + l];
+                    acc = fma(M[r * dc * dc + i * dc + k] * pk, M[r2 * dc * dc + j * dc + l], acc);
+                    if (r != r2) acc = fma(M[r2 * dc * dc + i * dc + k] * pk, M[r * dc * dc + j * dc + l], acc);
+                }
+            sN[QPairs<LY>::off(b) + e] = acc;
+        }
+    }
+    __syncthreads();
+}
+
+template <class LY, int b, typename T>
+__device__ __forceinline__ void disc_fast_block(const DevModel &mdl, const double *sN, const StepScale &sc,
+                                                double dt, bool first, T (&Dl)[LY::D][LY::D],
+                                                T (&Q)[LY::D][LY::D])
+{
+    constexpr int D = LY::D;
+    constexpr int dc = LY::bdim(b);
+    constexpr int o = LY::boff(b);
+    constexpr int np = dc * (dc + 1) / 2;
+    const DevBlock &bk = mdl.blk[b];
+    const double s = dt * sc.inv_ell[b];
+    double phi[dc];
+    if (bk.kind == BLK_MATERN) {
+        double pw = exp(-bk.lam * s);
+#pragma unroll
+        for (int j = 0; j < dc; j++) {
+            phi[j] = pw;
+            pw *= s;
+        }
+    } else {
+#pragma unroll
+        for (int p = 0; p < dc / 2; p++) {
+            const double e = exp(bk.alpha[p] * s);
+            double sn, cs;
+            sincos(bk.beta[p] * s, &sn, &cs);
+            phi[2 * p] = e * cs;
+            phi[2 * p + 1] = e * sn;
+        }
+        if (dc % 2) phi[dc - 1] = exp(bk.alpha[dc / 2] * s);
+    }
+    // series start: F = 0 (every phi zero), which gives Dl = -I and Q = Pinf
+    // exactly; the special case is applied to the phi only, so that the
+    // entries below stay straight-line code
+#pragma unroll
+    for (int r = 0; r < dc; r++) phi[r] = first ? 0.0 : phi[r];
+    const double *M = mdl.fcoef + bk.fc_off;
+#pragma unroll
+    for (int i = 0; i < dc; i++) {
+#pragma unroll
+        for (int j = 0; j < dc; j++) {
+            double acc = (i == j) ? -1.0 : 0.0;
+#pragma unroll
+            for (int r = 0; r < dc; r++) acc = fma(phi[r], M[r * dc * dc + i * dc + j], acc);
+            Dl[o + i][o + j] = T(acc);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    double pp[np];
+#pragma unroll
+    for (int r = 0, e = 0; r < dc; r++)
+#pragma unroll
+        for (int r2 = r; r2 < dc; r2++, e++) pp[e] = phi[r] * phi[r2];
+    const double *N = sN + QPairs<LY>::off(b);
+    double qa[np];
+#pragma unroll
+    for (int i = 0, x = 0; i < dc; i++)
+#pragma unroll
+        for (int j = i; j < dc; j++, x++) qa[x] = mdl.Pinf[(o + i) * D + o + j];
+    // one pair at a time; the scheduling barriers keep the LDS reads of a
+    // pair from being hoisted over the others (register pressure)
+#pragma unroll
+    for (int e = 0; e < np; e++) {
+#pragma unroll
+        for (int x = 0; x < np; x++) qa[x] = fma(-pp[e], N[e * np + x], qa[x]);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int i = 0, x = 0; i < dc; i++)
+#pragma unroll
+        for (int j = i; j < dc; j++, x++) {
+            const T q = T(qa[x] * sc.var_mult);
+            Q[o + i][o + j] = q;
+            Q[o + j][o + i] = q;
+        }
+}
+
+// Dl = F - I and Q of a step in the scan type T (first: series start, the
+// prior, Dl = -I and Q = Pinf). A zero step gives Dl and Q of the order of
+// the FP64 rounding of the expansion, below the resolution of T.
+template <class LY, typename T>
+__device__ __forceinline__ void discretize_fast(const DevModel &mdl, const double *sN, const StepScale &sc,
+                                                double dt, bool first, T (&Dl)[LY::D][LY::D],
+                                                T (&Q)[LY::D][LY::D])
+{
+    constexpr int D = LY::D;
+#pragma unroll
+    for (int i = 0; i < D; i++)
+#pragma unroll
+        for (int j = 0; j < D; j++) { Dl[i][j] = T(0); Q[i][j] = T(0); }
+    disc_fast_block<LY, 0, T>(mdl, sN, sc, dt, first, Dl, Q);
+    if constexpr (LY::NB > 1) disc_fast_block<LY, 1, T>(mdl, sN, sc, dt, first, Dl, Q);
 }
 
 // ------------------------------------------------------------------ register linear algebra

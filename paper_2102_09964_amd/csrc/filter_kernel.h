@@ -56,35 +56,64 @@ struct TileRange {
     int slot_base;
 };
 
-// Transition of step k in the scan type: Dl = F - I (F = 0 at a series
-// start, so Dl = -I there) and Q, both from the FP64 discretisation.
-template <class LY, typename T, class SV>
-__device__ __forceinline__ void step_transition(const DevModel &mdl, const SV &sv, const double *t, int64_t k,
-                                                T (&Dl)[LY::D][LY::D], T (&Q)[LY::D][LY::D],
-                                                uint32_t &bad)
+// Transition of a step in the scan type: Dl = F - I (F = 0 at a series
+// start, so Dl = -I there) and Q. FP32 scans use the pair expansion of Q
+// with the constants in LDS (sN); FP64 scans the FP64 discretisation.
+template <class LY, typename T>
+__device__ __forceinline__ void step_transition(const DevModel &mdl, const double *sN, const StepScale &sc,
+                                                double dt, bool first, T (&Dl)[LY::D][LY::D],
+                                                T (&Q)[LY::D][LY::D])
 {
     constexpr int D = LY::D;
-    double F64[D][D], Q64[D][D];
-    const bool first = sv.first(k);
-    const double tk = t[k];
-    const double dt = tk - t[first ? k : k - 1];  // 0 at a series start (never reads before it)
-    if (!(dt >= 0.0)) bad |= (dt < 0.0) ? PSSGP_STATUS_UNSORTED : PSSGP_STATUS_NONFINITE;
-    discretize<LY, sizeof(T) == 8>(mdl, sv.sc, dt, first, F64, Q64);
+    if constexpr (sizeof(T) == 8) {
+        double F64[D][D], Q64[D][D];
+        discretize<LY, true>(mdl, sc, dt, first, F64, Q64);
 #pragma unroll
-    for (int i = 0; i < D; i++)
+        for (int i = 0; i < D; i++)
 #pragma unroll
-        for (int j = 0; j < D; j++) {
-            Dl[i][j] = T(F64[i][j] - (i == j ? 1.0 : 0.0));
-            Q[i][j] = T(Q64[i][j]);
-        }
+            for (int j = 0; j < D; j++) {
+                Dl[i][j] = T(F64[i][j] - (i == j ? 1.0 : 0.0));
+                Q[i][j] = T(Q64[i][j]);
+            }
+    } else {
+        discretize_fast<LY, T>(mdl, sN, sc, dt, first, Dl, Q);
+    }
 }
+
+// LDS for the pair constants of the FP32 transition (one double for FP64).
+template <class LY, typename T>
+struct SNSize {
+    static constexpr int value = sizeof(T) == 8 ? 1 : QPairs<LY>::TOTAL;
+};
+
+// Per-lane view of the step inputs with the next step's values loaded one
+// iteration ahead.
+template <typename T>
+struct StepInputs {
+    double tc, tp;
+    T yc;
+    bool oc;
+    __device__ __forceinline__ void start(const double *t, const T *y, const uint8_t *mask, int64_t k0, int64_t k1,
+                                          int64_t k_begin)
+    {
+        tc = tp = 0.0;
+        yc = T(0);
+        oc = false;
+        if (k0 < k1) {
+            tc = t[k0];
+            tp = (k0 > k_begin) ? t[k0 - 1] : tc;
+            yc = y ? y[k0] : T(0);
+            oc = mask ? (mask[k0] != 0) : true;
+        }
+    }
+};
 
 // Fold pass of one tile: each lane folds its chunk into an aggregate, the
 // wave scans the 64 chunk aggregates (inclusive, time order) and stores them
 // at lanep; lane 63 then holds the tile aggregate.
 template <class LY, typename T, typename CT, class SV>
-__device__ __forceinline__ void filter_tile_fold(const FilterParams<T> &p, const DevModel &mdl, SV &sv,
-                                                 const TileRange &tr, int tile)
+__device__ __forceinline__ void filter_tile_fold(const FilterParams<T> &p, const DevModel &mdl, const double *sN,
+                                                 SV &sv, const TileRange &tr, int tile)
 {
     constexpr int D = LY::D;
     constexpr int AGG = AggLayout<D>::SIZE;
@@ -96,18 +125,28 @@ __device__ __forceinline__ void filter_tile_fold(const FilterParams<T> &p, const
     T h[D];
 #pragma unroll
     for (int i = 0; i < D; i++) h[i] = T(mdl.H[i]);
-    uint32_t bad = 0;  // reported by the finish pass, which sees the same steps
     FAgg<D, T> agg;
     agg_identity<D, T>(agg);
+    StepInputs<T> in;
+    in.start(p.t, p.y, p.mask, k0, k1, tr.k_begin);
     for (int64_t k = k0; k < k1; k++) {
+        const int64_t kn = (k + 1 < k1) ? k + 1 : k;
+        const double tn = p.t[kn];
+        const T yn = p.y[kn];
+        const bool on = p.mask ? (p.mask[kn] != 0) : true;
+        const T R = p.noise_k ? T(p.noise_k[k]) : T(0);
         PSSGP_RELOAD_CONSTANTS();
         sv.seek(k);
+        const bool first = sv.first(k);
+        const double dt = first ? 0.0 : in.tc - in.tp;
         T Dl[D][D], Q[D][D];
-        step_transition<LY, T, SV>(mdl, sv, p.t, k, Dl, Q, bad);
-        const bool obs = p.mask ? (p.mask[k] != 0) : true;
-        const T yk = obs ? p.y[k] : T(0);
-        const T R = p.noise_k ? T(p.noise_k[k]) : T(sv.R);
-        agg_fold<D, T>(agg, Dl, Q, h, R, yk, obs);
+        step_transition<LY, T>(mdl, sN, sv.sc, dt, first, Dl, Q);
+        const T yk = in.oc ? in.yc : T(0);
+        agg_fold<D, T>(agg, Dl, Q, h, p.noise_k ? R : T(sv.R), yk, in.oc);
+        in.tp = in.tc;
+        in.tc = tn;
+        in.yc = yn;
+        in.oc = on;
     }
     for (int o = 1; o < PSSGP_WAVE; o <<= 1) {
         FAgg<D, T> other;
@@ -124,8 +163,9 @@ __device__ __forceinline__ void filter_tile_fold(const FilterParams<T> &p, const
 // log-likelihood terms with compensated summation. ll_out receives this
 // lane's partial.
 template <class LY, typename T, typename CT, int MODE, class SV>
-__device__ __forceinline__ void filter_tile_finish(const FilterParams<T> &p, const DevModel &mdl, SV &sv,
-                                                   const TileRange &tr, int tile, double &ll_out)
+__device__ __forceinline__ void filter_tile_finish(const FilterParams<T> &p, const DevModel &mdl,
+                                                   const double *sN, SV &sv, const TileRange &tr, int tile,
+                                                   double &ll_out)
 {
     constexpr int D = LY::D;
     constexpr int AGG = AggLayout<D>::SIZE;
@@ -152,14 +192,28 @@ __device__ __forceinline__ void filter_tile_finish(const FilterParams<T> &p, con
     }
 
     T ls = T(0), lc = T(0);
+    StepInputs<T> in;
+    in.start(p.t, p.y, p.mask, k0, k1, tr.k_begin);
     for (int64_t k = k0; k < k1; k++) {
+        const int64_t kn = (k + 1 < k1) ? k + 1 : k;
+        const double tn = p.t[kn];
+        const T yn = p.y[kn];
+        const bool on = p.mask ? (p.mask[kn] != 0) : true;
+        const T Rk = p.noise_k ? T(p.noise_k[k]) : T(0);
         PSSGP_RELOAD_CONSTANTS();
         sv.seek(k);
+        const bool first = sv.first(k);
+        const double dt = first ? 0.0 : in.tc - in.tp;
+        if (!(dt >= 0.0)) bad |= (dt < 0.0) ? PSSGP_STATUS_UNSORTED : PSSGP_STATUS_NONFINITE;
         T Dl[D][D], Q[D][D];
-        step_transition<LY, T, SV>(mdl, sv, p.t, k, Dl, Q, bad);
-        const bool obs = p.mask ? (p.mask[k] != 0) : true;
-        const T yk = obs ? p.y[k] : T(0);
-        const T R = p.noise_k ? T(p.noise_k[k]) : T(sv.R);
+        step_transition<LY, T>(mdl, sN, sv.sc, dt, first, Dl, Q);
+        const bool obs = in.oc;
+        const T yk = obs ? in.yc : T(0);
+        const T R = p.noise_k ? Rk : T(sv.R);
+        in.tp = in.tc;
+        in.tc = tn;
+        in.yc = yn;
+        in.oc = on;
         // predict with Dl = F - I: mp = m + Dl m, Pp = P + X + X^T + X Dl^T + Q
         T mp[D], X[D][D], Pp[D][D], Ph[D];
 #pragma unroll
@@ -219,28 +273,32 @@ __device__ __forceinline__ void filter_tile_finish(const FilterParams<T> &p, con
 }
 
 template <class LY, typename T, typename CT>
-__global__ __launch_bounds__(PSSGP_WAVE) void filter_fold_kernel(FilterParams<T> p, DevModel mdl_arg)
+__global__ __launch_bounds__(PSSGP_WAVE, sizeof(T) == 4 ? PSSGP_FILTER_MINW : 1) void filter_fold_kernel(FilterParams<T> p, DevModel mdl_arg)
 {
     __shared__ DevModel mdl;
+    __shared__ double sN[SNSize<LY, T>::value];
     model_to_lds(mdl_arg, mdl);
+    if constexpr (sizeof(T) == 4) qpairs_build<LY>(mdl, sN);
     OneSeries sv;
     sv.init(mdl, p.n);
     TileRange tr{0, p.n, p.ntiles, 0};
-    filter_tile_fold<LY, T, CT, OneSeries>(p, mdl, sv, tr, (int)blockIdx.x);
+    filter_tile_fold<LY, T, CT, OneSeries>(p, mdl, sN, sv, tr, (int)blockIdx.x);
 }
 
 template <class LY, typename T, typename CT, int MODE>
-__global__ __launch_bounds__(PSSGP_WAVE) void filter_finish_kernel(FilterParams<T> p, DevModel mdl_arg)
+__global__ __launch_bounds__(PSSGP_WAVE, sizeof(T) == 4 ? PSSGP_FILTER_MINW : 1) void filter_finish_kernel(FilterParams<T> p, DevModel mdl_arg)
 {
     __shared__ DevModel mdl;
+    __shared__ double sN[SNSize<LY, T>::value];
     const int lane = lane_id();
     const int tile = (int)blockIdx.x;
     model_to_lds(mdl_arg, mdl);
+    if constexpr (sizeof(T) == 4) qpairs_build<LY>(mdl, sN);
     OneSeries sv;
     sv.init(mdl, p.n);
     TileRange tr{0, p.n, p.ntiles, 0};
     double ll = 0.0;
-    filter_tile_finish<LY, T, CT, MODE, OneSeries>(p, mdl, sv, tr, tile, ll);
+    filter_tile_finish<LY, T, CT, MODE, OneSeries>(p, mdl, sN, sv, tr, tile, ll);
 
     // log-likelihood: deterministic wave sum, tile partial, the last tile to
     // finish reduces the partials in a fixed order (no waiting involved)
@@ -311,25 +369,30 @@ int launch_filter_t(const DevModel &mdl, const FilterLaunch &a, hipStream_t s)
 {
     FilterParams<T> p = filter_params<LY, T>(a);
     const dim3 grid(a.ntiles), block(PSSGP_WAVE);
+    pass_event(a.ev, 0, s);
     hipLaunchKernelGGL((filter_fold_kernel<LY, T, CT>), grid, block, 0, s, p, mdl);
     int rc = (int)hipGetLastError();
     if (rc) return rc;
+    pass_event(a.ev, 1, s);
     rc = launch_tile_scan<FilterScanOps<LY::D, T>>(a.ws.lanep, PSSGP_WAVE - 1, 0, a.ntiles, false, a.ws.inclp, s);
     if (rc) return rc;
+    pass_event(a.ev, 2, s);
     if (a.m)
         hipLaunchKernelGGL((filter_finish_kernel<LY, T, CT, F_MOMENTS>), grid, block, 0, s, p, mdl);
     else if (a.ck)
         hipLaunchKernelGGL((filter_finish_kernel<LY, T, CT, F_CKPT>), grid, block, 0, s, p, mdl);
     else
         hipLaunchKernelGGL((filter_finish_kernel<LY, T, CT, 0>), grid, block, 0, s, p, mdl);
-    return (int)hipGetLastError();
+    rc = (int)hipGetLastError();
+    pass_event(a.ev, 3, s);
+    return rc;
 }
 
 template <int B0, int B1>
 int launch_filter_layout(const DevModel &mdl, bool f64, const FilterLaunch &a, hipStream_t s)
 {
     return f64 ? launch_filter_t<Layout<B0, B1>, double, double>(mdl, a, s)
-               : launch_filter_t<Layout<B0, B1>, float, float>(mdl, a, s);
+               : launch_filter_t<Layout<B0, B1>, float, typename CombineType<float>::type>(mdl, a, s);
 }
 
 template <int B0, int B1>

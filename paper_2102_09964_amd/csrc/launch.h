@@ -27,6 +27,7 @@ struct ScanWs {
 };
 
 struct FilterLaunch {
+    void *const *ev;  // nullable: 4 events around the passes
     const double *t;
     const void *y;
     const uint8_t *mask;
@@ -42,6 +43,7 @@ struct FilterLaunch {
 };
 
 struct SmoothLaunch {
+    void *const *ev;  // nullable: 4 events around the passes
     const double *t;
     const void *m;
     const void *P;
@@ -89,6 +91,7 @@ struct BatchGroup {
 };
 
 struct BatchLaunch {
+    void *const *ev;  // nullable: 4 events around the passes
     int ngroups;
     BatchGroup g[2];
     BatchModel bm[2];
@@ -150,6 +153,12 @@ int launch_discretize(const DevModel &mdl, int b0, int b1, const double *t, int6
                       double *Q, WsCtl *ctl, hipStream_t s);
 int launch_grad(const DevModel &mdl, int b0, int b1, bool f64, const GradLaunch &a, hipStream_t s);
 int launch_plain(const DevModel &mdl, int b0, int b1, const PlainLaunch &a, hipStream_t s);
+// Records pass event i (when given) on stream s.
+inline void pass_event(void *const *ev, int i, hipStream_t s)
+{
+    if (ev && ev[i]) (void)hipEventRecord((hipEvent_t)ev[i], s);
+}
+
 // Zeroes the control block (keep_status: only the tile counter, so that a
 // second pass of the same call keeps the first one's status bits) and
 // zero_out[0, nzero).

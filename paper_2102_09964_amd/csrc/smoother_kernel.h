@@ -54,8 +54,8 @@ struct STileRange {
 // reverse time order) and stores them at lanep; lane 0 then holds the tile
 // aggregate.
 template <class LY, typename T, class SV>
-__device__ __forceinline__ void smoother_tile_fold(const SmoothParams<T> &p, const DevModel &mdl, SV &sv,
-                                                   const STileRange &tr, int tile)
+__device__ __forceinline__ void smoother_tile_fold(const SmoothParams<T> &p, const DevModel &mdl,
+                                                   const double *sN, SV &sv, const STileRange &tr, int tile)
 {
     constexpr int D = LY::D;
     constexpr int AGG = SAggLayout<D>::SIZE;
@@ -71,7 +71,7 @@ __device__ __forceinline__ void smoother_tile_fold(const SmoothParams<T> &p, con
         PSSGP_RELOAD_CONSTANTS();
         sv.seek(k);
         SAgg<D, T> e;
-        smoother_element<LY, T, SV>(mdl, sv, p.t, p.m, p.P, p.n, k, e, bad);
+        smoother_element<LY, T, SV>(mdl, sN, sv, p.t, p.m, p.P, p.n, k, e, bad);
         sagg_combine<D, T>(e, agg, agg);
     }
     for (int o = 1; o < PSSGP_WAVE; o <<= 1) {
@@ -86,8 +86,8 @@ __device__ __forceinline__ void smoother_tile_fold(const SmoothParams<T> &p, con
 // the tile from the right (carry pass), applies its exclusive lane suffix
 // and runs the backward RTS recursion over its chunk.
 template <class LY, typename T, bool FULL, class SV>
-__device__ __forceinline__ void smoother_tile_finish(const SmoothParams<T> &p, const DevModel &mdl, SV &sv,
-                                                     const STileRange &tr, int tile)
+__device__ __forceinline__ void smoother_tile_finish(const SmoothParams<T> &p, const DevModel &mdl,
+                                                     const double *sN, SV &sv, const STileRange &tr, int tile)
 {
     constexpr int D = LY::D;
     constexpr int AGG = SAggLayout<D>::SIZE;
@@ -113,7 +113,7 @@ __device__ __forceinline__ void smoother_tile_finish(const SmoothParams<T> &p, c
         PSSGP_RELOAD_CONSTANTS();
         sv.seek(k);
         SAgg<D, T> e;
-        smoother_element<LY, T, SV>(mdl, sv, p.t, p.m, p.P, p.n, k, e, bad);
+        smoother_element<LY, T, SV>(mdl, sN, sv, p.t, p.m, p.P, p.n, k, e, bad);
         sagg_apply<D, T>(e, ms, Ps, ms, Ps);
         T Ph[D];
         mat_vec<D, T>(Ps, h, Ph);
@@ -131,26 +131,38 @@ __device__ __forceinline__ void smoother_tile_finish(const SmoothParams<T> &p, c
     if (bad) status_or(&p.ctl->status, bad);
 }
 
+// LDS for the pair constants of the FP32 transition (one double for FP64).
 template <class LY, typename T>
-__global__ __launch_bounds__(PSSGP_WAVE) void smoother_fold_kernel(SmoothParams<T> p, DevModel mdl_arg)
+struct SmootherSN {
+    static constexpr int value = sizeof(T) == 8 ? 1 : QPairs<LY>::TOTAL;
+};
+
+template <class LY, typename T>
+__global__ __launch_bounds__(PSSGP_WAVE, sizeof(T) == 4 ? PSSGP_SMOOTHER_MINW : 1) void smoother_fold_kernel(SmoothParams<T> p,
+                                                                                           DevModel mdl_arg)
 {
     __shared__ DevModel mdl;
+    __shared__ double sN[SmootherSN<LY, T>::value];
     model_to_lds(mdl_arg, mdl);
+    if constexpr (sizeof(T) == 4) qpairs_build<LY>(mdl, sN);
     OneSeries sv;
     sv.init(mdl, p.n);
     STileRange tr{0, p.n, p.ntiles, 0};
-    smoother_tile_fold<LY, T, OneSeries>(p, mdl, sv, tr, (int)blockIdx.x);
+    smoother_tile_fold<LY, T, OneSeries>(p, mdl, sN, sv, tr, (int)blockIdx.x);
 }
 
 template <class LY, typename T, bool FULL>
-__global__ __launch_bounds__(PSSGP_WAVE) void smoother_finish_kernel(SmoothParams<T> p, DevModel mdl_arg)
+__global__ __launch_bounds__(PSSGP_WAVE, sizeof(T) == 4 ? PSSGP_SMOOTHER_MINW : 1) void smoother_finish_kernel(SmoothParams<T> p,
+                                                                                             DevModel mdl_arg)
 {
     __shared__ DevModel mdl;
+    __shared__ double sN[SmootherSN<LY, T>::value];
     model_to_lds(mdl_arg, mdl);
+    if constexpr (sizeof(T) == 4) qpairs_build<LY>(mdl, sN);
     OneSeries sv;
     sv.init(mdl, p.n);
     STileRange tr{0, p.n, p.ntiles, 0};
-    smoother_tile_finish<LY, T, FULL, OneSeries>(p, mdl, sv, tr, (int)blockIdx.x);
+    smoother_tile_finish<LY, T, FULL, OneSeries>(p, mdl, sN, sv, tr, (int)blockIdx.x);
 }
 
 template <class LY, typename T>
@@ -171,16 +183,21 @@ int launch_smoother_t(const DevModel &mdl, const SmoothLaunch &a, hipStream_t s)
     p.inclp = (T *)a.ws.inclp;
     p.lanep = (T *)a.ws.lanep;
     const dim3 grid(a.ntiles), block(PSSGP_WAVE);
+    pass_event(a.ev, 0, s);
     hipLaunchKernelGGL((smoother_fold_kernel<LY, T>), grid, block, 0, s, p, mdl);
     int rc = (int)hipGetLastError();
     if (rc) return rc;
+    pass_event(a.ev, 1, s);
     rc = launch_tile_scan<SmootherScanOps<LY::D, T>>(a.ws.lanep, 0, 0, a.ntiles, true, a.ws.inclp, s);
     if (rc) return rc;
+    pass_event(a.ev, 2, s);
     if (a.ms && a.Ps)
         hipLaunchKernelGGL((smoother_finish_kernel<LY, T, true>), grid, block, 0, s, p, mdl);
     else
         hipLaunchKernelGGL((smoother_finish_kernel<LY, T, false>), grid, block, 0, s, p, mdl);
-    return (int)hipGetLastError();
+    rc = (int)hipGetLastError();
+    pass_event(a.ev, 3, s);
+    return rc;
 }
 
 template <int B0, int B1>

@@ -142,16 +142,32 @@ __device__ __forceinline__ void gl_load(const T *p, T (&g)[D], T (&L)[D][D])
         for (int j = i; j < D; j++) { L[i][j] = p[D + sidx<D>(i, j)]; L[j][i] = L[i][j]; }
 }
 
-// Smoother element of step k, computed in FP64 and rounded to T. The last
-// step's element (0, m, P) is formed without branching: its transition is
-// evaluated for a zero step (F = I, Q = 0) and the result replaced by
-// selects, so that every lane runs the same instruction stream.
+// Smoother element of step k, computed in FP64 and rounded to T:
+//   FP = F P_k, Pp = FP F^T + Q = C C^T (Cholesky), Y = C^-1 FP,
+//   E = (C^-T Y)^T = P_k F^T Pp^-1, g = m_k - E F m_k, L = P_k - Y^T Y,
+// so that L is formed as P minus a Gram matrix (no explicit E F P). The
+// transition comes as Dl = F - I. The last step of a series takes the
+// transition F = 0, Q = Pinf, for which the same formulas give exactly its
+// element (0, m, P); every lane runs the same instruction stream. FP32
+// scans use the pair expansion of the transition (constants sN in LDS),
+// FP64 scans the FP64 discretisation.
 template <class LY, typename T, class SV>
-__device__ __forceinline__ void smoother_element(const DevModel &mdl, const SV &sv, const double *t, const T *mf,
-                                                 const T *Pf, int64_t n, int64_t k,
+__device__ __forceinline__ void smoother_element(const DevModel &mdl, const double *sN, const SV &sv,
+                                                 const double *t, const T *mf, const T *Pf, int64_t n, int64_t k,
                                                  SAgg<LY::D, T> &e, uint32_t &bad)
 {
     constexpr int D = LY::D;
+    const bool is_last = sv.last(k);
+    const int64_t kn = is_last ? k : k + 1;  // never reads past the series
+    const double dt = t[kn] - t[k];
+    double Dl[D][D], Q[D][D];
+    if constexpr (sizeof(T) == 8) {
+        discretize<LY, true>(mdl, sv.sc, dt, is_last, Dl, Q);
+#pragma unroll
+        for (int i = 0; i < D; i++) Dl[i][i] -= 1.0;
+    } else {
+        discretize_fast<LY, double>(mdl, sN, sv.sc, dt, is_last, Dl, Q);
+    }
     double m[D], P[D][D];
 #pragma unroll
     for (int i = 0; i < D; i++) m[i] = (double)mf[(size_t)i * n + k];
@@ -162,38 +178,74 @@ __device__ __forceinline__ void smoother_element(const DevModel &mdl, const SV &
             P[i][j] = (double)Pf[(size_t)sidx<D>(i, j) * n + k];
             P[j][i] = P[i][j];
         }
-    const bool is_last = sv.last(k);
-    const int64_t kn = is_last ? k : k + 1;  // never reads past the series
-    const double dt = t[kn] - t[k];
-    double F[D][D], Q[D][D];
-    discretize<LY, sizeof(T) == 8>(mdl, sv.sc, dt, false, F, Q);
-    double FP[D][D], Pp[D][D], X[D][D];
-    mat_mul<D, double>(F, P, FP);
-    mat_mul_nt_sym_add<D, double>(FP, F, Q, Pp);
-    if (!cholesky<D, double>(Pp) && !is_last) bad |= PSSGP_STATUS_CHOLESKY;
-    chol_solve<D, double>(Pp, FP, X);  // X = Pp^-1 F P = E^T
-    double Fm[D];
-    mat_vec<D, double>(F, m, Fm);
+    double Fm[D], Y[D][D], C[D][D];
 #pragma unroll
     for (int i = 0; i < D; i++) {
         double acc = m[i];
 #pragma unroll
-        for (int k2 = 0; k2 < D; k2++) acc = fma(-X[k2][i], Fm[k2], acc);
-        e.g[i] = T(is_last ? m[i] : acc);
-#pragma unroll
-        for (int j = 0; j < D; j++) e.E[i][j] = T(is_last ? 0.0 : X[j][i]);
+        for (int q = 0; q < D; q++) acc = fma(Dl[i][q], m[q], acc);
+        Fm[i] = acc;
     }
-    // L = P - E F P (symmetric in exact arithmetic; upper triangle mirrored)
+    // Y = F P = P + Dl P
+#pragma unroll
+    for (int i = 0; i < D; i++)
+#pragma unroll
+        for (int j = 0; j < D; j++) {
+            double acc = P[i][j];
+#pragma unroll
+            for (int q = 0; q < D; q++) acc = fma(Dl[i][q], P[q][j], acc);
+            Y[i][j] = acc;
+        }
+    // lower triangle of Pp = Y F^T + Q = Y + Y Dl^T + Q
+#pragma unroll
+    for (int i = 0; i < D; i++)
+#pragma unroll
+        for (int j = 0; j <= i; j++) {
+            double acc = Y[i][j] + Q[i][j];
+#pragma unroll
+            for (int q = 0; q < D; q++) acc = fma(Y[i][q], Dl[j][q], acc);
+            C[i][j] = acc;
+        }
+    if (!cholesky<D, double>(C)) bad |= PSSGP_STATUS_CHOLESKY;
+    // Y <- C^-1 Y (forward substitution, column by column)
+#pragma unroll
+    for (int j = 0; j < D; j++)
+#pragma unroll
+        for (int i = 0; i < D; i++) {
+            double s = Y[i][j];
+#pragma unroll
+            for (int q = 0; q < i; q++) s = fma(-C[i][q], Y[q][j], s);
+            Y[i][j] = s / C[i][i];
+        }
+    // L = P - Y^T Y
 #pragma unroll
     for (int i = 0; i < D; i++)
 #pragma unroll
         for (int j = i; j < D; j++) {
             double acc = P[i][j];
 #pragma unroll
-            for (int k2 = 0; k2 < D; k2++) acc = fma(-X[k2][i], FP[k2][j], acc);
-            const T l = T(is_last ? P[i][j] : acc);
+            for (int q = 0; q < D; q++) acc = fma(-Y[q][i], Y[q][j], acc);
+            const T l = T(acc);
             e.L[i][j] = l;
             e.L[j][i] = l;
         }
+    // Y <- C^-T Y (back substitution): Y = Pp^-1 F P = E^T
+#pragma unroll
+    for (int j = 0; j < D; j++)
+#pragma unroll
+        for (int i = D - 1; i >= 0; i--) {
+            double s = Y[i][j];
+#pragma unroll
+            for (int q = i + 1; q < D; q++) s = fma(-C[q][i], Y[q][j], s);
+            Y[i][j] = s / C[i][i];
+        }
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+        double acc = m[i];
+#pragma unroll
+        for (int q = 0; q < D; q++) acc = fma(-Y[q][i], Fm[q], acc);
+        e.g[i] = T(acc);
+#pragma unroll
+        for (int j = 0; j < D; j++) e.E[i][j] = T(Y[j][i]);
+    }
 }
-

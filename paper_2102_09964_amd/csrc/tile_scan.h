@@ -40,11 +40,11 @@ struct FilterScanOps {
     static __device__ __forceinline__ void load(const T *p, Agg &a) { agg_load<D, T>(p, a); }
     static __device__ __forceinline__ void extend(const Agg &acc, const Agg &nx, Agg &out)
     {
-        agg_combine<D, T, T>(acc, nx, out);
+        agg_combine<D, T, typename CombineType<T>::type>(acc, nx, out);
     }
     static __device__ __forceinline__ void apply(T (&v)[D], T (&M)[D][D], const Agg &x)
     {
-        moments_apply<D, T, T>(v, M, x, v, M);
+        moments_apply<D, T, typename CombineType<T>::type>(v, M, x, v, M);
     }
     static __device__ __forceinline__ void mom_store(T *p, const T (&v)[D], const T (&M)[D][D])
     {
