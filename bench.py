@@ -191,6 +191,71 @@ def roofline_of(m):
     return out
 
 
+def measure_batched(steps, warmup, chunk=0):
+    """Batched workload (4096 series, Matern-3/2 and -5/2) in FP32: filter +
+    smoother over all series captured once in a HIP graph and replayed."""
+    import torch
+    import workloads
+    import paper_2102_09964_amd as P
+    from paper_2102_09964_amd import tune
+    w = workloads.batched_matern()
+    t = torch.as_tensor(w["t"], dtype=torch.float64, device="cuda")
+    y = torch.as_tensor(np.nan_to_num(w["y"]), dtype=torch.float32, device="cuda")
+    mask = torch.as_tensor(w["mask"], dtype=torch.uint8, device="cuda")
+    if not chunk:
+        chunk, _ = tune.tune_batched_chunk(w["kinds"], w["offsets"], w["params"], t, y, mask)
+    pipe = P.BatchedPipeline(w["kinds"], w["offsets"], w["params"], dtype="float32",
+                             options=P.make_options(chunk=chunk))
+    for _ in range(warmup):
+        pipe.run(t, y, mask)
+    torch.cuda.synchronize()
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(stream):
+        with torch.cuda.graph(graph, stream=stream):
+            pipe.run(t, y, mask)
+    torch.cuda.current_stream().wait_stream(stream)
+    graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    n = int(w["offsets"][-1])
+    return {"workload": "batched_matern", "dtype": "float32", "n": n, "n_series": int(len(w["kinds"])),
+            "chunk": int(chunk), "graph": True, "steps_per_s": round(n / (ms / 1e3), 1), "ms_per_step": round(ms, 4),
+            "status": [P.status(pipe.ws_f), P.status(pipe.ws_s)]}
+
+
+def measure_grad(steps, warmup, chunk=0):
+    """Log-likelihood and its gradient (hand-written adjoint with checkpoint
+    recompute) for the sum kernel Matern-3/2 + RBF-6 (d = 8), N = 2^20, FP32."""
+    import torch
+    import workloads
+    import paper_2102_09964_amd as P
+    w = workloads.sum_m32_rbf6()
+    model = P.make_model(w["model"]["components"], w["model"]["noise_var"])
+    n = w["t"].shape[0]
+    t = torch.as_tensor(w["t"], dtype=torch.float64, device="cuda")
+    y = torch.as_tensor(np.nan_to_num(w["y"]), dtype=torch.float32, device="cuda")
+    mask = torch.as_tensor(w["mask"], dtype=torch.uint8, device="cuda")
+    opts = P.make_options(chunk=chunk) if chunk else None
+    ws = P.alloc_workspace(model, n, P.F32, P.OP_LOGLIK_GRAD, opts)
+    for _ in range(warmup):
+        P.loglik_grad(model, t, y, mask, dtype="float32", options=opts, ws=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ll, g = P.loglik_grad(model, t, y, mask, dtype="float32", options=opts, ws=ws)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    return {"workload": "sum_m32_rbf6_loglik_grad", "dtype": "float32", "n": n, "d": P.state_dim(model),
+            "steps_per_s": round(n / (ms / 1e3), 1), "ms_per_step": round(ms, 4),
+            "grad": [round(float(v), 6) for v in g.cpu().numpy()]}
+
+
 def cpu_baseline(w, target_s=12.0):
     """Sequential FP64 oracle (filter + smoother + log-likelihood) on a
     prefix of the workload sized for about target_s seconds of one core."""
@@ -217,7 +282,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="rbf6_lognormal", choices=sorted(WORKLOADS))
     ap.add_argument("--dtype", default="float32", choices=["float32", "float64"])
-    ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--chunk", type=int, default=0, help="steps per lane; 0 = autotuned")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-also", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
@@ -231,7 +296,17 @@ def main():
         print("bench.py: no HIP device", file=sys.stderr)
         sys.exit(1)
     w = WORKLOADS[args.workload]()
-    m = measure(w, args.dtype, args.steps, args.warmup, args.chunk)
+    chunk = args.chunk
+    if not chunk:
+        import torch as _t
+        import paper_2102_09964_amd as P
+        from paper_2102_09964_amd import tune
+        model = P.make_model(w["model"]["components"], w["model"]["noise_var"])
+        tdt = getattr(_t, args.dtype)
+        chunk, _ = tune.tune_chunk(model, _t.as_tensor(w["t"], dtype=_t.float64, device="cuda"),
+                                   _t.as_tensor(np.nan_to_num(w["y"]), dtype=tdt, device="cuda"),
+                                   _t.as_tensor(w["mask"], dtype=_t.uint8, device="cuda"), dtype=args.dtype)
+    m = measure(w, args.dtype, args.steps, args.warmup, chunk)
     also = []
     if not args.no_also:
         other = "float64" if args.dtype == "float32" else "float32"
@@ -241,11 +316,14 @@ def main():
                 continue
             ww = w if name == args.workload else WORKLOADS[name]()
             mm = measure(ww, dt, max(3, args.steps // 2), 2)
-            also.append({"workload": name, "dtype": dt, "n": mm["n"], "d": mm["d"],
+            also.append({"workload": name, "dtype": dt, "n": mm["n"], "d": mm["d"], "chunk": mm["chunk"],
                          "steps_per_s": round(mm["steps_per_s"], 1), "ms_per_step": round(mm["ms_per_step"], 4),
                          "filter_ms": round(mm["filter_ms"], 4), "smoother_ms": round(mm["smoother_ms"], 4),
                          "pass_ms": {k: round(v, 4) for k, v in mm["pass_ms"].items()},
                          "roofline": {k: roofline_of(mm)[k] for k in ("bound", "kernel", "achieved", "unit", "frac")}})
+    if not args.no_also:
+        also.append(measure_batched(max(3, args.steps // 2), 2))
+        also.append(measure_grad(max(3, args.steps // 2), 2))
     out = {
         "metric": "time steps/sec, filter+smoother+loglik(+grad), FP32 vs FP64, d=2..8, 1 GPU",
         "value": round(m["steps_per_s"], 1),
@@ -259,7 +337,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if args.dtype == "float32" else "f64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "n_steps": m["n"], "state_dim": m["d"],
+        "config": {"workload": args.workload, "n_steps": m["n"], "state_dim": m["d"], "chunk": m["chunk"],
                    "kernel": "RBF Taylor order 6" if args.workload == "rbf6_lognormal" else args.workload,
                    "scan_dtype": args.dtype, "discretisation": "f64"},
         "roofline": roofline_of(m),

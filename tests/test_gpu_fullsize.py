@@ -1,0 +1,113 @@
+"""GPU parity at the full workload sizes, in the launch configuration the
+benchmark times (default chunk, Pipeline / BatchedPipeline): the HIP path's
+outputs at sampled steps, its log-likelihood (per series when batched) and
+its gradient against oracle values stored by tests/golden/make_golden.py
+(which calls only the oracle). Tolerances as in the other parity tests:
+normwise relative over the sampled steps.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import workloads
+from tests.conftest import gpu_available
+from tests.parity import TOL, rel
+
+pytestmark = pytest.mark.gpu
+
+if not gpu_available():
+    pytest.skip("needs a HIP device", allow_module_level=True)
+
+import torch  # noqa: E402
+
+import paper_2102_09964_amd as P  # noqa: E402
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _gold(name):
+    path = os.path.join(GOLD, name + ".npz")
+    if not os.path.exists(path):
+        pytest.skip("golden file %s not generated" % name)
+    return dict(np.load(path))
+
+
+def _checksums(w, dtype):
+    y = np.nan_to_num(np.asarray(w["y"], np.float64))
+    if dtype == "float32":
+        y = y.astype(np.float32).astype(np.float64)
+    return np.array([np.sum(w["t"]), np.sum(y), float(np.sum(w["mask"]))])
+
+
+def _single(w, dtype):
+    model = P.make_model(w["model"]["components"], w["model"]["noise_var"])
+    n = w["t"].shape[0]
+    pipe = P.Pipeline(model, n, dtype)
+    t = torch.as_tensor(w["t"], dtype=torch.float64, device="cuda")
+    y = torch.as_tensor(np.nan_to_num(w["y"]), dtype=getattr(torch, dtype), device="cuda")
+    mask = torch.as_tensor(w["mask"], dtype=torch.uint8, device="cuda")
+    fm, fv, ll = pipe.run(t, y, mask)
+    torch.cuda.synchronize()
+    return fm.double().cpu().numpy(), fv.double().cpu().numpy(), float(ll.cpu()[0]), \
+        (P.status(pipe.ws_f), P.status(pipe.ws_s))
+
+
+@pytest.mark.parametrize("name,gen,dtype", [
+    ("full_matern52_exp_f64", workloads.matern52_exp, "float64"),
+    ("full_matern52_exp_f32", workloads.matern52_exp, "float32"),
+    ("full_rbf6_lognormal_f32", workloads.rbf6_lognormal, "float32"),
+])
+def test_full_size_single_series(name, gen, dtype):
+    g = _gold(name)
+    w = gen()
+    assert np.allclose(_checksums(w, dtype), g["checksums"], rtol=1e-12, atol=0), "input generator changed"
+    print(name, "n =", w["t"].shape[0], flush=True)
+    fm, fv, ll, status = _single(w, dtype)
+    idx = g["idx"]
+    errs = {"f_mean": rel(fm[idx], g["f_mean"]), "f_var": rel(fv[idx], g["f_var"]),
+            "loglik": abs(ll - g["loglik"][0]) / abs(g["loglik"][0])}
+    print(name, {k: "%.2e" % v for k, v in errs.items()}, flush=True)
+    tol = TOL[dtype]
+    assert status == (0, 0)
+    assert errs["f_mean"] <= tol["mean"] and errs["f_var"] <= tol["var"] and errs["loglik"] <= tol["loglik"], errs
+
+
+def test_full_size_gradient():
+    g = _gold("full_sum_m32_rbf6_grad_f32")
+    w = workloads.sum_m32_rbf6()
+    assert np.allclose(_checksums(w, "float32"), g["checksums"], rtol=1e-12, atol=0), "input generator changed"
+    model = P.make_model(w["model"]["components"], w["model"]["noise_var"])
+    ll, grad = P.loglik_grad(model, w["t"], np.nan_to_num(w["y"]), w["mask"], dtype="float32")
+    torch.cuda.synchronize()
+    ll = float(ll.cpu()[0])
+    grad = grad.cpu().numpy()
+    el = abs(ll - g["loglik"][0]) / abs(g["loglik"][0])
+    eg = np.abs(grad - g["grad"]) / np.maximum(np.abs(g["grad"]), 1e-3 * np.max(np.abs(g["grad"])))
+    print("grad", grad, "oracle", g["grad"], "loglik err %.2e grad err %s" % (el, np.array2string(eg, precision=2)),
+          flush=True)
+    assert el <= TOL["float32"]["loglik"]
+    assert np.all(eg <= 1e-3), eg
+
+
+def test_full_size_batched():
+    g = _gold("full_batched_matern_f32")
+    w = workloads.batched_matern()
+    assert np.allclose(_checksums(w, "float32"), g["checksums"], rtol=1e-12, atol=0), "input generator changed"
+    pipe = P.BatchedPipeline(w["kinds"], w["offsets"], w["params"], dtype="float32")
+    t = torch.as_tensor(w["t"], dtype=torch.float64, device="cuda")
+    y = torch.as_tensor(np.nan_to_num(w["y"]), dtype=torch.float32, device="cuda")
+    mask = torch.as_tensor(w["mask"], dtype=torch.uint8, device="cuda")
+    fm, fv, ll = pipe.run(t, y, mask)
+    torch.cuda.synchronize()
+    idx = g["idx"]
+    fm = fm.double().cpu().numpy()[idx]
+    fv = fv.double().cpu().numpy()[idx]
+    ll = ll.cpu().numpy()
+    el = np.abs(ll - g["loglik"]) / np.abs(g["loglik"])
+    errs = {"f_mean": rel(fm, g["f_mean"]), "f_var": rel(fv, g["f_var"]), "loglik_max": float(np.max(el)),
+            "loglik_median": float(np.median(el))}
+    print("batched", {k: "%.2e" % v for k, v in errs.items()}, flush=True)
+    assert (P.status(pipe.ws_f), P.status(pipe.ws_s)) == (0, 0)
+    tol = TOL["float32"]
+    assert errs["f_mean"] <= tol["mean"] and errs["f_var"] <= tol["var"] and errs["loglik_max"] <= tol["loglik"], errs
