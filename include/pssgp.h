@@ -26,9 +26,11 @@
  *  - Time stamps t are FP64 and non-decreasing (equal times are allowed:
  *    a zero step has F = I, Q = 0). Test points are steps with mask 0
  *    (missing measurement, section 3); y there is ignored and may be NaN.
- *  - dtype selects the scan precision: PSSGP_F32 keeps the discretisation
- *    and element construction in FP64 and runs the scans in FP32 with a
- *    compensated FP32 log-likelihood sum reduced across tiles in FP64;
+ *  - dtype selects the scan precision: PSSGP_F32 keeps the discretisation,
+ *    the smoother elements, the conditioning on each measurement (the
+ *    covariance update, whose subtraction cancels when the noise is small)
+ *    and the log-likelihood terms and sums in FP64, and runs the scan
+ *    algebra (predictions, combinations, stored moments) in FP32;
  *    PSSGP_F64 runs everything in FP64. y, m, P, f_mean, f_var use dtype.
  *  - State moments are in the library's state coordinates:
  *    x_canonical = diag(T) z with T from pssgp_state_basis(), where the

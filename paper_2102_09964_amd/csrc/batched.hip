@@ -160,7 +160,7 @@ int launch_bf(const BatchLaunch &a, hipStream_t s)
     p.P = (T *)a.P;
     p.loglik = nullptr;
     p.ck = nullptr;
-    p.ll_terms = (T *)a.ll_terms;
+    p.ll_terms = (double *)a.ll_terms;
     p.ctl = a.ws.ctl;
     p.inclp = (T *)a.ws.inclp;
     p.lanep = (T *)a.ws.lanep;
@@ -185,7 +185,7 @@ int launch_bf(const BatchLaunch &a, hipStream_t s)
     if (rc) return rc;
     const int per_block = 256 / PSSGP_WAVE;
     const dim3 lgrid((unsigned)((a.n_series + per_block - 1) / per_block));
-    hipLaunchKernelGGL((series_loglik_kernel<T>), lgrid, dim3(256), 0, s, (const T *)a.ll_terms, a.offsets,
+    hipLaunchKernelGGL((series_loglik_kernel<double>), lgrid, dim3(256), 0, s, (const double *)a.ll_terms, a.offsets,
                        a.n_series, a.loglik);
     rc = (int)hipGetLastError();
     pass_event(a.ev, 3, s);

@@ -310,7 +310,7 @@ int make_batch_plan(const pssgp_batch_group *groups, int ngroups, int64_t n_seri
     bp.off_incl = take(nt * incl * bp.tsize);
     bp.off_lane = take(nt * 64 * agg * bp.tsize);
     bp.off_part = take(nt * sizeof(double) * 3);
-    if (op != PSSGP_OP_SMOOTH) bp.off_terms = take((size_t)(n > 0 ? n : 1) * bp.tsize);
+    if (op != PSSGP_OP_SMOOTH) bp.off_terms = take((size_t)(n > 0 ? n : 1) * sizeof(double));
     bp.total = o;
     return PSSGP_OK;
 }

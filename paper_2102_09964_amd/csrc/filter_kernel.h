@@ -41,7 +41,7 @@ struct FilterParams {
     T *P;
     double *loglik;
     T *ck;
-    T *ll_terms;  // batched: per-step log-likelihood terms
+    double *ll_terms;  // batched: per-step log-likelihood terms
     WsCtl *ctl;
     T *inclp;
     T *lanep;
@@ -191,7 +191,7 @@ __device__ __forceinline__ void filter_tile_finish(const FilterParams<T> &p, con
         if (k0 < tr.k_end) moments_store<D, T>(p.ck + (size_t)chunk_id * INCL, m, P);
     }
 
-    T ls = T(0), lc = T(0);
+    double ll = 0.0;  // FP64 per-lane sum of the log-likelihood terms
     StepInputs<T> in;
     in.start(p.t, p.y, p.mask, k0, k1, tr.k_begin);
     for (int64_t k = k0; k < k1; k++) {
@@ -215,7 +215,7 @@ __device__ __forceinline__ void filter_tile_finish(const FilterParams<T> &p, con
         in.yc = yn;
         in.oc = on;
         // predict with Dl = F - I: mp = m + Dl m, Pp = P + X + X^T + X Dl^T + Q
-        T mp[D], X[D][D], Pp[D][D], Ph[D];
+        T mp[D], X[D][D], Pp[D][D];
 #pragma unroll
         for (int i = 0; i < D; i++) {
             T acc = m[i];
@@ -235,27 +235,38 @@ __device__ __forceinline__ void filter_tile_finish(const FilterParams<T> &p, con
                 Pp[i][j] = c;
                 Pp[j][i] = c;
             }
-        mat_vec<D, T>(Pp, h, Ph);
-        const T S = dot<D, T>(h, Ph) + R;
-        const T v = yk - dot<D, T>(h, mp);
-        const T w = obs ? T(1) / S : T(0);
+        // conditioning on y_k in FP64 (symmetric form), from the predicted
+        // moments in T: the subtraction that cancels when the noise is
+        // small against the predicted variance is done in FP64
+        double Ph[D], S = (double)R, hm = 0.0;
+#pragma unroll
+        for (int i = 0; i < D; i++) {
+            double acc = 0.0;
+#pragma unroll
+            for (int j = 0; j < D; j++) acc = fma((double)Pp[i][j], (double)h[j], acc);
+            Ph[i] = acc;
+            hm = fma((double)h[i], (double)mp[i], hm);
+        }
+#pragma unroll
+        for (int i = 0; i < D; i++) S = fma((double)h[i], Ph[i], S);
+        const double v = (double)yk - hm;
+        const double w = obs ? 1.0 / S : 0.0;
         // branch-free: missing steps add an exact zero
-        bad |= (obs && (!(S > T(0)) || !isfinite(S))) ? PSSGP_STATUS_BAD_S : 0u;
+        bad |= (obs && (!(S > 0.0) || !isfinite(S))) ? PSSGP_STATUS_BAD_S : 0u;
         bad |= (obs && !isfinite(yk)) ? PSSGP_STATUS_NONFINITE : 0u;
-        const T term = obs ? T(-0.5) * (log(T(6.283185307179586) * S) + v * v * w) : T(0);
+        const double term = obs ? -0.5 * (log(6.283185307179586 * S) + v * v * w) : 0.0;
         if (p.ll_terms) p.ll_terms[k] = term;
-        kahan_add<T>(ls, lc, term);
-        // update, symmetric (Joseph) form: P = Pp - K c^T - c K^T + S K K^T
-        T K[D];
+        ll += term;
+        double K[D];
 #pragma unroll
         for (int i = 0; i < D; i++) K[i] = Ph[i] * w;
 #pragma unroll
-        for (int i = 0; i < D; i++) m[i] = fma(K[i], v, mp[i]);
+        for (int i = 0; i < D; i++) m[i] = T(fma(K[i], v, (double)mp[i]));
 #pragma unroll
         for (int i = 0; i < D; i++)
 #pragma unroll
             for (int j = i; j < D; j++) {
-                const T c = fma(S * K[i], K[j], fma(-Ph[i], K[j], fma(-K[i], Ph[j], Pp[i][j])));
+                const T c = T(fma(S * K[i], K[j], fma(-Ph[i], K[j], fma(-K[i], Ph[j], (double)Pp[i][j]))));
                 P[i][j] = c;
                 P[j][i] = c;
             }
@@ -269,7 +280,7 @@ __device__ __forceinline__ void filter_tile_finish(const FilterParams<T> &p, con
         }
     }
     if (bad) status_or(&p.ctl->status, bad);
-    ll_out = (double)ls + (double)lc;
+    ll_out = ll;
 }
 
 template <class LY, typename T, typename CT>

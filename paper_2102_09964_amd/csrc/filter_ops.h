@@ -73,36 +73,47 @@ __device__ __forceinline__ void agg_fold(FAgg<D, T> &a, const T (&Dl)[D][D], con
             C1[i][j] = c;
             C1[j][i] = c;
         }
-    T Ch[D], v[D];
-    mat_vec<D, T>(C1, h, Ch);
+    // conditioning on y_k in FP64: when the measurement noise is small
+    // against the predicted variance, C' - K c^T - ... cancels, and the
+    // FP64 arithmetic keeps the result accurate to the precision of T
+    double Ch[D], v[D];
 #pragma unroll
-    for (int j = 0; j < D; j++) {
-        T acc = T(0);
+    for (int i = 0; i < D; i++) {
+        double acc = 0.0, av = 0.0;
 #pragma unroll
-        for (int i = 0; i < D; i++) acc = fma(h[i], A1[i][j], acc);
-        v[j] = acc;
+        for (int j = 0; j < D; j++) {
+            acc = fma((double)C1[i][j], (double)h[j], acc);
+            av = fma((double)h[j], (double)A1[j][i], av);
+        }
+        Ch[i] = acc;
+        v[i] = av;
     }
-    const T S = dot<D, T>(h, Ch) + R;
-    const T w = obs ? T(1) / S : T(0);
-    const T r = obs ? (y - dot<D, T>(h, b1)) : T(0);
-    T K[D];
+    double S = (double)R, hb = 0.0;
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+        S = fma((double)h[i], Ch[i], S);
+        hb = fma((double)h[i], (double)b1[i], hb);
+    }
+    const double w = obs ? 1.0 / S : 0.0;
+    const double r = obs ? ((double)y - hb) : 0.0;
+    double K[D];
 #pragma unroll
     for (int i = 0; i < D; i++) K[i] = Ch[i] * w;
 #pragma unroll
     for (int i = 0; i < D; i++) {
-        a.b[i] = fma(K[i], r, b1[i]);
-        a.eta[i] = fma(v[i], r * w, a.eta[i]);
+        a.b[i] = T(fma(K[i], r, (double)b1[i]));
+        a.eta[i] = T(fma(v[i], r * w, (double)a.eta[i]));
 #pragma unroll
-        for (int j = 0; j < D; j++) a.A[i][j] = fma(-K[i], v[j], A1[i][j]);
+        for (int j = 0; j < D; j++) a.A[i][j] = T(fma(-K[i], v[j], (double)A1[i][j]));
     }
 #pragma unroll
     for (int i = 0; i < D; i++)
 #pragma unroll
         for (int j = i; j < D; j++) {
-            const T c = fma(S * K[i], K[j], fma(-Ch[i], K[j], fma(-K[i], Ch[j], C1[i][j])));
+            const T c = T(fma(S * K[i], K[j], fma(-Ch[i], K[j], fma(-K[i], Ch[j], (double)C1[i][j]))));
             a.C[i][j] = c;
             a.C[j][i] = c;
-            const T jj = fma(v[i] * w, v[j], a.J[i][j]);
+            const T jj = T(fma(v[i] * w, v[j], (double)a.J[i][j]));
             a.J[i][j] = jj;
             a.J[j][i] = jj;
         }

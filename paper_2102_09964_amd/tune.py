@@ -7,8 +7,9 @@ to fill the chip; the best value depends on the state layout, the scan
 precision, the problem size and the device. ``tune_chunk`` times the whole
 filter + smoother (or the batched pipeline) for each candidate on the
 caller's data and keeps the fastest; results are cached in a JSON file
-keyed by device, layout, precision and size bucket (``PSSGP_TUNE_CACHE``,
-default ``~/.cache/pssgp_tune.json``), so a process tunes each key once.
+keyed by layout, precision and size bucket (``PSSGP_TUNE_CACHE``, default
+``~/.cache/pssgp_tune.json``, one file per machine), so each key is tuned
+once.
 """
 from __future__ import annotations
 
@@ -44,11 +45,6 @@ def _store(cache: dict) -> None:
         pass  # a read-only home only loses the cache
 
 
-def _device_name() -> str:
-    import torch
-    return torch.cuda.get_device_name(torch.cuda.current_device())
-
-
 def _time(run, reps: int) -> float:
     import torch
     run()
@@ -69,7 +65,7 @@ def tune_chunk(model, t, y, mask=None, dtype="float32", candidates=CANDIDATES, r
     m = _as_model(model)
     n = int(t.shape[0])
     comps = tuple((int(m.comp[i].kind), int(m.comp[i].order)) for i in range(m.n_comp))
-    key = "single|%s|%s|%s|%d" % (_device_name(), comps, dtype, max(0, math.ceil(math.log2(max(n, 1)))))
+    key = "single|%s|%s|%d" % (comps, dtype, max(0, math.ceil(math.log2(max(n, 1)))))
     cache = _load() if use_cache else {}
     if key in cache:
         return int(cache[key]["chunk"]), {int(k): v for k, v in cache[key]["times"].items()}
@@ -95,8 +91,8 @@ def tune_batched_chunk(kinds, offsets, params, t, y, mask=None, dtype="float32",
     n = int(off[-1])
     ns = off.shape[0] - 1
     kset = tuple(sorted(set(int(k) for k in kinds)))
-    key = "batched|%s|%s|%s|%d|%d" % (_device_name(), kset, dtype, max(0, math.ceil(math.log2(max(n, 1)))),
-                                      max(0, math.ceil(math.log2(max(ns, 1)))))
+    key = "batched|%s|%s|%d|%d" % (kset, dtype, max(0, math.ceil(math.log2(max(n, 1)))),
+                                   max(0, math.ceil(math.log2(max(ns, 1)))))
     cache = _load() if use_cache else {}
     if key in cache:
         return int(cache[key]["chunk"]), {int(k): v for k, v in cache[key]["times"].items()}
