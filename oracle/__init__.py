@@ -67,6 +67,8 @@ def _load():
             lib = ctypes.CDLL(_LIB)
             lib.ssgp_run.restype = ctypes.c_int
             lib.ssgp_run.argtypes = [ctypes.POINTER(_Model), ctypes.c_int64] + [ctypes.c_void_p] * 12
+            lib.ssgp_loglik_terms.restype = ctypes.c_int
+            lib.ssgp_loglik_terms.argtypes = [ctypes.POINTER(_Model), ctypes.c_int64] + [ctypes.c_void_p] * 5
             lib.ssgp_discretize.restype = ctypes.c_int
             lib.ssgp_discretize.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                             ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]
@@ -162,21 +164,45 @@ def run(model: OracleModel, t, y, mask=None, noise_k=None, filter_moments=True,
     return out
 
 
-def run_batched(models, offsets, t, y, mask=None, threads=None, smoother=True):
+def loglik_terms(model: OracleModel, t, y, mask=None, noise_k=None) -> np.ndarray:
+    """Per-step log-likelihood terms of the sequential filter (0 at missing
+    steps); their sum is run()'s loglik, their absolute sum the condition
+    number of that sum."""
+    lib = _load()
+    t = _c(t)
+    y = _c(y)
+    n = t.shape[0]
+    mask_a = None if mask is None else _c(mask, np.uint8)
+    nk = _c(noise_k)
+    Gb, Wb, Pb, Hb = _c(model.Gb), _c(model.Wb), _c(model.Pinfb), _c(model.Hb)
+    cm = _Model(model.d, _ptr(Gb), _ptr(Wb), _ptr(Pb), _ptr(Hb), model.noise_var, 0, None, None, None, None)
+    out = np.empty(max(n, 1))
+    rc = lib.ssgp_loglik_terms(ctypes.byref(cm), n, _ptr(t), _ptr(y), _ptr(mask_a), _ptr(nk), _ptr(out))
+    if rc:
+        raise RuntimeError("ssgp_loglik_terms failed: %d" % rc)
+    return out[:n]
+
+
+def run_batched(models, offsets, t, y, mask=None, threads=None, smoother=True, abs_terms=False):
     """Independent series (CSR offsets) spread over host threads; returns
-    per-series loglik and concatenated f_mean / f_var."""
+    per-series loglik and concatenated f_mean / f_var (abs_terms: also the
+    per-series sum of absolute log-likelihood terms)."""
     offsets = np.asarray(offsets, dtype=np.int64)
     ns = offsets.shape[0] - 1
     total = int(offsets[-1])
     f_mean = np.empty(total) if smoother else None
     f_var = np.empty(total) if smoother else None
     ll = np.empty(ns)
+    lla = np.empty(ns) if abs_terms else None
 
     def one(s):
         a, b = int(offsets[s]), int(offsets[s + 1])
         r = run(models[s], t[a:b], y[a:b], None if mask is None else mask[a:b],
                 filter_moments=False, smoother=smoother)
         ll[s] = r["loglik"]
+        if abs_terms:
+            lla[s] = float(np.sum(np.abs(loglik_terms(models[s], t[a:b], y[a:b],
+                                                       None if mask is None else mask[a:b]))))
         if smoother:
             f_mean[a:b] = r["f_mean"]
             f_var[a:b] = r["f_var"]
@@ -188,4 +214,7 @@ def run_batched(models, offsets, t, y, mask=None, threads=None, smoother=True):
     else:
         with ThreadPoolExecutor(max_workers=threads) as ex:
             list(ex.map(one, range(ns)))
-    return {"loglik": ll, "f_mean": f_mean, "f_var": f_var}
+    out = {"loglik": ll, "f_mean": f_mean, "f_var": f_var}
+    if abs_terms:
+        out["loglik_abs_terms"] = lla
+    return out

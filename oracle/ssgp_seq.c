@@ -640,3 +640,31 @@ int ssgp_run_batched(const ssgp_model *mdls, int64_t n_series, const int64_t *of
     }
     return 0;
 }
+
+/* Per-step log-likelihood terms of the sequential filter:
+ * terms[k] = -1/2 (log 2 pi S_k + v_k^2 / S_k) for an observed step, 0 for
+ * a missing one (prediction-error decomposition, as summed by ssgp_run).
+ * Their absolute sum is the condition number of the log-likelihood as a
+ * sum, used to state its error. Same arguments as ssgp_run. */
+int ssgp_loglik_terms(const ssgp_model *mdl, int64_t n, const double *t, const double *y,
+                      const uint8_t *mask, const double *noise_k, double *terms)
+{
+    if (!mdl || n < 0 || mdl->d < 1 || mdl->d > MAXD || (n > 0 && !terms)) return -1;
+    const int d = mdl->d, dd = d * d;
+    double m[MAXD] = {0}, P[MAXD * MAXD] = {0};
+    double F[MAXD * MAXD], Q[MAXD * MAXD];
+    for (int64_t k = 0; k < n; k++) {
+        const int obs = mask ? (mask[k] != 0) : 1;
+        const double R = noise_k ? noise_k[k] : mdl->R;
+        kf_step_info info;
+        if (k == 0) {
+            memset(F, 0, sizeof(F));
+            memcpy(Q, mdl->Pinf, sizeof(double) * dd);
+        } else {
+            int rc = ssgp_discretize(d, mdl->G, mdl->W, t[k] - t[k - 1], F, Q);
+            if (rc) return rc;
+        }
+        terms[k] = kf_step(d, mdl->H, R, obs, y[k], F, Q, m, P, &info);
+    }
+    return 0;
+}

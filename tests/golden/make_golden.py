@@ -69,11 +69,12 @@ def batched(name, prec):
     y = y_for(w, prec)
     models = [OracleModel(mm["components"], mm["noise_var"]) for mm in w["models"]]
     t0 = time.perf_counter()
-    r = oracle.run_batched(models, w["offsets"], w["t"], y, w["mask"], threads=os.cpu_count())
+    r = oracle.run_batched(models, w["offsets"], w["t"], y, w["mask"], threads=os.cpu_count(), abs_terms=True)
     n = int(w["offsets"][-1])
     idx = sample_idx(n)
     np.savez(os.path.join(HERE, name + ".npz"), idx=idx, f_mean=r["f_mean"][idx], f_var=r["f_var"][idx],
-             loglik=r["loglik"], n=np.array([n]), checksums=checksums(w, y))
+             loglik=r["loglik"], loglik_abs_terms=r["loglik_abs_terms"], n=np.array([n]),
+             checksums=checksums(w, y))
     print("%s: n=%d  %.1f s" % (name, n, time.perf_counter() - t0), flush=True)
 
 

@@ -7,7 +7,8 @@ Error measures (the tolerance is on the first, the rest are reported):
   component's magnitude and its posterior standard deviation), covariances:
   max |dP_ij| / sqrt(max P_ii max P_jj), after mapping the library's
   coordinates to the canonical ones;
-* log-likelihood: |a - b| / |b|.
+* log-likelihood: |a - b| / |b| (per batched series: |a - b| / sum_k |l_k|,
+  the condition number of the sum, since short series can cancel).
 FP32 runs are compared with the oracle run on the FP32-rounded observations.
 """
 from __future__ import annotations

@@ -152,3 +152,16 @@ def test_smoothed_equals_filtered_at_last_step():
     r = oracle.run(OracleModel(comps, 0.01), w["t"], w["y"], w["mask"])
     assert np.array_equal(r["ms"][-1], r["mf"][-1])
     assert np.array_equal(r["Ps"][-1], r["Pf"][-1])
+
+
+def test_loglik_terms_sum_to_loglik():
+    """The per-step terms (prediction-error decomposition) sum to the
+    filter's log-likelihood and vanish at missing steps."""
+    w = workloads.random_series(700, [(MATERN52, 0, 0.8, 1.3)], 0.02, missing=0.3, seed=11)
+    m = OracleModel(w["model"]["components"], w["model"]["noise_var"])
+    y = np.nan_to_num(w["y"])
+    r = oracle.run(m, w["t"], y, w["mask"], filter_moments=False, smoother=False)
+    terms = oracle.loglik_terms(m, w["t"], y, w["mask"])
+    assert abs(np.sum(terms) - r["loglik"]) <= 1e-12 * np.sum(np.abs(terms))
+    assert np.all(terms[w["mask"] == 0] == 0.0)
+    assert np.all(terms[w["mask"] == 1] != 0.0)
