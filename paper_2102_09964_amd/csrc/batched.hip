@@ -49,6 +49,24 @@ __device__ __forceinline__ void series_view(ManySeries &sv, const BatchLaunch &a
     sv.locate(k0 < g.k_end ? k0 : g.k_end - 1);
 }
 
+// Constants of the FP32 transition of every group (workgroup g: group g).
+template <class LA, class LB>
+__global__ __launch_bounds__(256) void batched_consts_kernel(BatchLaunch a)
+{
+    __shared__ DevModel mdl;
+    const int gi = (int)blockIdx.x;
+    if (gi == 0)
+        unpack_batch_model<LA>(a.bm[0], mdl);
+    else
+        unpack_batch_model<LB>(a.bm[1], mdl);
+    __syncthreads();
+    double *out = a.ws.cst + (size_t)gi * PSSGP_CONST_DOUBLES;
+    if (gi == 0)
+        consts_build<LA>(mdl, out);
+    else
+        consts_build<LB>(mdl, out);
+}
+
 // Group of a tile slot (slots of group 1 follow those of group 0).
 __device__ __forceinline__ int group_of(const BatchLaunch &a, int slot)
 {
@@ -58,9 +76,7 @@ __device__ __forceinline__ int group_of(const BatchLaunch &a, int slot)
 template <class LA, class LB, typename T, bool FINISH>
 __global__ __launch_bounds__(PSSGP_WAVE) void batched_filter_kernel(FilterParams<T> p, BatchLaunch a)
 {
-    constexpr int NSN = SNSize<LA, T>::value > SNSize<LB, T>::value ? SNSize<LA, T>::value : SNSize<LB, T>::value;
     __shared__ DevModel mdl;
-    __shared__ double sN[NSN];
     const int slot = (int)blockIdx.x;
     const int gi = group_of(a, slot);
     if (gi == 0)
@@ -68,12 +84,7 @@ __global__ __launch_bounds__(PSSGP_WAVE) void batched_filter_kernel(FilterParams
     else
         unpack_batch_model<LB>(a.bm[1], mdl);
     __syncthreads();
-    if constexpr (sizeof(T) == 4) {
-        if (gi == 0)
-            qpairs_build<LA>(mdl, sN);
-        else
-            qpairs_build<LB>(mdl, sN);
-    }
+    cdouble *cst = (cdouble *)(a.ws.cst + (size_t)gi * PSSGP_CONST_DOUBLES);
     const BatchGroup &g = a.g[gi];
     const int tile = slot - g.slot_base;
     TileRange tr{g.k_begin, g.k_end, g.ntiles, g.slot_base};
@@ -82,23 +93,21 @@ __global__ __launch_bounds__(PSSGP_WAVE) void batched_filter_kernel(FilterParams
     if constexpr (FINISH) {
         double ll = 0.0;
         if (gi == 0)
-            filter_tile_finish<LA, T, typename CombineType<T>::type, F_MOMENTS, ManySeries>(p, mdl, sN, sv, tr, tile, ll);
+            filter_tile_finish<LA, T, typename CombineType<T>::type, F_MOMENTS, ManySeries>(p, mdl, cst, sv, tr, tile, ll);
         else
-            filter_tile_finish<LB, T, typename CombineType<T>::type, F_MOMENTS, ManySeries>(p, mdl, sN, sv, tr, tile, ll);
+            filter_tile_finish<LB, T, typename CombineType<T>::type, F_MOMENTS, ManySeries>(p, mdl, cst, sv, tr, tile, ll);
     } else {
         if (gi == 0)
-            filter_tile_fold<LA, T, typename CombineType<T>::type, ManySeries>(p, mdl, sN, sv, tr, tile);
+            filter_tile_fold<LA, T, typename CombineType<T>::type, ManySeries>(p, mdl, cst, sv, tr, tile);
         else
-            filter_tile_fold<LB, T, typename CombineType<T>::type, ManySeries>(p, mdl, sN, sv, tr, tile);
+            filter_tile_fold<LB, T, typename CombineType<T>::type, ManySeries>(p, mdl, cst, sv, tr, tile);
     }
 }
 
 template <class LA, class LB, typename T, bool FINISH>
 __global__ __launch_bounds__(PSSGP_WAVE) void batched_smoother_kernel(SmoothParams<T> p, BatchLaunch a)
 {
-    constexpr int NSN = SNSize<LA, T>::value > SNSize<LB, T>::value ? SNSize<LA, T>::value : SNSize<LB, T>::value;
     __shared__ DevModel mdl;
-    __shared__ double sN[NSN];
     const int slot = (int)blockIdx.x;
     const int gi = group_of(a, slot);
     if (gi == 0)
@@ -106,12 +115,7 @@ __global__ __launch_bounds__(PSSGP_WAVE) void batched_smoother_kernel(SmoothPara
     else
         unpack_batch_model<LB>(a.bm[1], mdl);
     __syncthreads();
-    if constexpr (sizeof(T) == 4) {
-        if (gi == 0)
-            qpairs_build<LA>(mdl, sN);
-        else
-            qpairs_build<LB>(mdl, sN);
-    }
+    cdouble *cst = (cdouble *)(a.ws.cst + (size_t)gi * PSSGP_CONST_DOUBLES);
     const BatchGroup &g = a.g[gi];
     const int tile = slot - g.slot_base;
     STileRange tr{g.k_begin, g.k_end, g.ntiles, g.slot_base};
@@ -119,14 +123,14 @@ __global__ __launch_bounds__(PSSGP_WAVE) void batched_smoother_kernel(SmoothPara
     series_view(sv, a, g, g.k_begin + ((int64_t)tile * PSSGP_WAVE + lane_id()) * p.chunk);
     if constexpr (FINISH) {
         if (gi == 0)
-            smoother_tile_finish<LA, T, false, ManySeries>(p, mdl, sN, sv, tr, tile);
+            smoother_tile_finish<LA, T, false, ManySeries>(p, mdl, cst, sv, tr, tile);
         else
-            smoother_tile_finish<LB, T, false, ManySeries>(p, mdl, sN, sv, tr, tile);
+            smoother_tile_finish<LB, T, false, ManySeries>(p, mdl, cst, sv, tr, tile);
     } else {
         if (gi == 0)
-            smoother_tile_fold<LA, T, ManySeries>(p, mdl, sN, sv, tr, tile);
+            smoother_tile_fold<LA, T, ManySeries>(p, mdl, cst, sv, tr, tile);
         else
-            smoother_tile_fold<LB, T, ManySeries>(p, mdl, sN, sv, tr, tile);
+            smoother_tile_fold<LB, T, ManySeries>(p, mdl, cst, sv, tr, tile);
     }
 }
 
@@ -167,6 +171,8 @@ int launch_bf(const BatchLaunch &a, hipStream_t s)
     p.partials = a.ws.partials;
     const dim3 grid(a.total_tiles), block(PSSGP_WAVE);
     pass_event(a.ev, 0, s);
+    if constexpr (sizeof(T) == 4)
+        hipLaunchKernelGGL((batched_consts_kernel<LA, LB>), dim3(a.ngroups), dim3(256), 0, s, a);
     hipLaunchKernelGGL((batched_filter_kernel<LA, LB, T, false>), grid, block, 0, s, p, a);
     int rc = (int)hipGetLastError();
     if (rc) return rc;
@@ -211,6 +217,8 @@ int launch_bs(const BatchLaunch &a, hipStream_t s)
     p.lanep = (T *)a.ws.lanep;
     const dim3 grid(a.total_tiles), block(PSSGP_WAVE);
     pass_event(a.ev, 0, s);
+    if constexpr (sizeof(T) == 4)
+        hipLaunchKernelGGL((batched_consts_kernel<LA, LB>), dim3(a.ngroups), dim3(256), 0, s, a);
     hipLaunchKernelGGL((batched_smoother_kernel<LA, LB, T, false>), grid, block, 0, s, p, a);
     int rc = (int)hipGetLastError();
     if (rc) return rc;

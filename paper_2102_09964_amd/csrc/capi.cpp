@@ -22,7 +22,7 @@ size_t ctl_bytes() { return 256; }
 struct Plan {
     int d = 0, ns = 0, chunk = kDefaultChunk, ntiles = 0;
     size_t tsize = 4;
-    size_t off_incl = 0, off_lane = 0, off_part = 0, off_ck = 0, off_rec = 0;
+    size_t off_incl = 0, off_lane = 0, off_part = 0, off_ck = 0, off_rec = 0, off_cst = 0;
     size_t off_incl2 = 0, off_lane2 = 0, off_part2 = 0;
     size_t off_x = 0, off_xraw = 0;  // plain baseline element arrays
     size_t total = 0;
@@ -73,6 +73,7 @@ Plan make_plan(int d, int ncomp, int64_t n, pssgp_dtype dtype, int op, const pss
         p.total = off;
         return p;
     }
+    p.off_cst = take(PSSGP_CONST_DOUBLES * sizeof(double));
     if (op == PSSGP_OP_SMOOTH) {
         p.off_incl = take(nt * smooth_incl_elems(d) * p.tsize);
         p.off_lane = take(nt * 64 * smooth_agg_elems(d) * p.tsize);
@@ -158,6 +159,7 @@ ScanWs scan_ws(void *ws, const Plan &p, bool second = false)
     s.inclp = b + (second ? p.off_incl2 : p.off_incl);
     s.lanep = b + (second ? p.off_lane2 : p.off_lane);
     s.partials = (double *)(b + (second ? p.off_part2 : p.off_part));
+    s.cst = (double *)(b + p.off_cst);
     return s;
 }
 
@@ -213,7 +215,7 @@ struct BatchPlan {
     size_t tsize = 4;
     BatchGroup g[2];
     BatchModel bm[2];
-    size_t off_incl = 0, off_lane = 0, off_part = 0, off_terms = 0, total = 0;
+    size_t off_incl = 0, off_lane = 0, off_part = 0, off_terms = 0, off_cst = 0, total = 0;
 };
 
 int make_batch_plan(const pssgp_batch_group *groups, int ngroups, int64_t n_series, const int64_t *off,
@@ -310,6 +312,7 @@ int make_batch_plan(const pssgp_batch_group *groups, int ngroups, int64_t n_seri
     bp.off_incl = take(nt * incl * bp.tsize);
     bp.off_lane = take(nt * 64 * agg * bp.tsize);
     bp.off_part = take(nt * sizeof(double) * 3);
+    bp.off_cst = take(2 * PSSGP_CONST_DOUBLES * sizeof(double));
     if (op != PSSGP_OP_SMOOTH) bp.off_terms = take((size_t)(n > 0 ? n : 1) * sizeof(double));
     bp.total = o;
     return PSSGP_OK;
@@ -369,6 +372,7 @@ int run_batched(const pssgp_batch_group *groups, int ngroups, int64_t n_series, 
     a.ws.inclp = b + bp.off_incl;
     a.ws.lanep = b + bp.off_lane;
     a.ws.partials = (double *)(b + bp.off_part);
+    a.ws.cst = (double *)(b + bp.off_cst);
     const bool zero_ll = (op == PSSGP_OP_FILTER && a.n == 0);
     rc = launch_ws_init(a.ws.ctl, zero_ll ? loglik : nullptr,
                         zero_ll ? (int)n_series : 0, s);

@@ -250,10 +250,11 @@ __device__ __forceinline__ void discretize(const DevModel &mdl, const StepScale 
 // a block is
 //   Q = Pinf - F Pinf F^T = Pinf - sum_{r <= r'} phi_r phi_r' N_rr',
 //   N_rr = M_r Pinf M_r^T,  N_rr' = M_r Pinf M_r'^T + M_r' Pinf M_r^T (r < r').
-// The N are built once per workgroup into LDS (qpairs_build), so a step
-// needs the phi in FP64 and one FP64 accumulation per entry of F - I and of
-// Q, without FP64 matrix temporaries. The scan receives Dl = F - I and Q,
-// rounded to the scan type.
+// The N are built once per call into device memory (consts_build) and read
+// as scalar operands, so a step needs the phi in FP64 and one FP64
+// accumulation per entry of F - I and of Q, without FP64 matrix
+// temporaries. The scan receives Dl = F - I and Q, rounded to the scan
+// type.
 
 // (i, j), i <= j, of the row-major packed upper index e of an n x n matrix
 __device__ __forceinline__ void unpack_upper(int e, int n, int &i, int &j)
@@ -266,23 +267,44 @@ __device__ __forceinline__ void unpack_upper(int e, int n, int &i, int &j)
     j = i + e;
 }
 
+// Read-only model constants in device memory, read through the constant
+// address space: uniform loads of these become scalar loads into SGPRs,
+// which the FP64 multiply-adds take as operands (no LDS or VGPR traffic).
+typedef const __attribute__((address_space(4))) double cdouble;
+
+// Hides the value of a constant pointer from the optimiser at the top of a
+// step loop, so that the loads through it are issued inside every
+// iteration instead of being hoisted (and held in registers) across it.
+#define PSSGP_LAUNDER(ptr) asm volatile("" : "+s"(ptr))
+
+// Layout of the constants of the FP32 transition: per block the expansion
+// matrices M_r (dc^3) and the pair matrices N_rr' (np^2, packed upper
+// entries of each pair), then Pinf (D^2, row-major).
 template <class LY>
-struct QPairs {
+struct ConstLayout {
     __host__ __device__ static constexpr int np(int b) { return LY::bdim(b) * (LY::bdim(b) + 1) / 2; }
-    __host__ __device__ static constexpr int size(int b) { return np(b) * np(b); }
-    __host__ __device__ static constexpr int off(int b) { return b == 0 ? 0 : size(0); }
-    static constexpr int TOTAL = size(0) + (LY::NB > 1 ? size(1) : 0);
+    __host__ __device__ static constexpr int size(int b)
+    {
+        return LY::bdim(b) * LY::bdim(b) * LY::bdim(b) + np(b) * np(b);
+    }
+    __host__ __device__ static constexpr int m_off(int b) { return b == 0 ? 0 : size(0); }
+    __host__ __device__ static constexpr int n_off(int b)
+    {
+        return m_off(b) + LY::bdim(b) * LY::bdim(b) * LY::bdim(b);
+    }
+    static constexpr int PINF = size(0) + (LY::NB > 1 ? size(1) : 0);
+    static constexpr int TOTAL = PINF + LY::D * LY::D;
 };
 
-// All threads of the workgroup; sN has QPairs<LY>::TOTAL doubles. Ends with
-// a workgroup barrier.
+// Fills the constants of one model (all threads of one workgroup).
 template <class LY>
-__device__ void qpairs_build(const DevModel &mdl, double *sN)
+__device__ void consts_build(const DevModel &mdl, double *out)
 {
-#pragma unroll
+    static_assert(ConstLayout<LY>::TOTAL <= PSSGP_CONST_DOUBLES, "constants exceed their workspace room");
     for (int b = 0; b < LY::NB; b++) {
-        const int dc = LY::bdim(b), o = LY::boff(b), np = QPairs<LY>::np(b);
+        const int dc = LY::bdim(b), o = LY::boff(b), np = ConstLayout<LY>::np(b);
         const double *M = mdl.fcoef + mdl.blk[b].fc_off;
+        for (int e = (int)threadIdx.x; e < dc * dc * dc; e += (int)blockDim.x) out[ConstLayout<LY>::m_off(b) + e] = M[e];
         for (int e = (int)threadIdx.x; e < np * np; e += (int)blockDim.x) {
             const int pr = e / np, en = e - pr * np;
             int r, r2, i, j;
@@ -295,16 +317,21 @@ __device__ void qpairs_build(const DevModel &mdl, double *sN)
                     acc = fma(M[r * dc * dc + i * dc + k] * pk, M[r2 * dc * dc + j * dc + l], acc);
                     if (r != r2) acc = fma(M[r2 * dc * dc + i * dc + k] * pk, M[r * dc * dc + j * dc + l], acc);
                 }
-            sN[QPairs<LY>::off(b) + e] = acc;
+            out[ConstLayout<LY>::n_off(b) + e] = acc;
         }
     }
-    __syncthreads();
+    for (int e = (int)threadIdx.x; e < LY::D * LY::D; e += (int)blockDim.x) out[ConstLayout<LY>::PINF + e] = mdl.Pinf[e];
+}
+
+template <class LY>
+__global__ __launch_bounds__(256) void consts_kernel(DevModel mdl, double *out)
+{
+    consts_build<LY>(mdl, out);
 }
 
 template <class LY, int b, typename T>
-__device__ __forceinline__ void disc_fast_block(const DevModel &mdl, const double *sN, const StepScale &sc,
-                                                double dt, bool first, T (&Dl)[LY::D][LY::D],
-                                                T (&Q)[LY::D][LY::D])
+__device__ __forceinline__ void disc_fast_block(const DevModel &mdl, cdouble *cst, const StepScale &sc, double dt,
+                                                bool first, T (&Dl)[LY::D][LY::D], T (&Q)[LY::D][LY::D])
 {
     constexpr int D = LY::D;
     constexpr int dc = LY::bdim(b);
@@ -336,7 +363,7 @@ __device__ __forceinline__ void disc_fast_block(const DevModel &mdl, const doubl
     // entries below stay straight-line code
 #pragma unroll
     for (int r = 0; r < dc; r++) phi[r] = first ? 0.0 : phi[r];
-    const double *M = mdl.fcoef + bk.fc_off;
+    cdouble *M = cst + ConstLayout<LY>::m_off(b);
 #pragma unroll
     for (int i = 0; i < dc; i++) {
 #pragma unroll
@@ -353,12 +380,12 @@ __device__ __forceinline__ void disc_fast_block(const DevModel &mdl, const doubl
     for (int r = 0, e = 0; r < dc; r++)
 #pragma unroll
         for (int r2 = r; r2 < dc; r2++, e++) pp[e] = phi[r] * phi[r2];
-    const double *N = sN + QPairs<LY>::off(b);
+    cdouble *N = cst + ConstLayout<LY>::n_off(b);
     double qa[np];
 #pragma unroll
     for (int i = 0, x = 0; i < dc; i++)
 #pragma unroll
-        for (int j = i; j < dc; j++, x++) qa[x] = mdl.Pinf[(o + i) * D + o + j];
+        for (int j = i; j < dc; j++, x++) qa[x] = cst[ConstLayout<LY>::PINF + (o + i) * D + o + j];
     // one pair at a time; the scheduling barriers keep the LDS reads of a
     // pair from being hoisted over the others (register pressure)
 #pragma unroll
@@ -381,17 +408,16 @@ __device__ __forceinline__ void disc_fast_block(const DevModel &mdl, const doubl
 // prior, Dl = -I and Q = Pinf). A zero step gives Dl and Q of the order of
 // the FP64 rounding of the expansion, below the resolution of T.
 template <class LY, typename T>
-__device__ __forceinline__ void discretize_fast(const DevModel &mdl, const double *sN, const StepScale &sc,
-                                                double dt, bool first, T (&Dl)[LY::D][LY::D],
-                                                T (&Q)[LY::D][LY::D])
+__device__ __forceinline__ void discretize_fast(const DevModel &mdl, cdouble *cst, const StepScale &sc, double dt,
+                                                bool first, T (&Dl)[LY::D][LY::D], T (&Q)[LY::D][LY::D])
 {
     constexpr int D = LY::D;
 #pragma unroll
     for (int i = 0; i < D; i++)
 #pragma unroll
         for (int j = 0; j < D; j++) { Dl[i][j] = T(0); Q[i][j] = T(0); }
-    disc_fast_block<LY, 0, T>(mdl, sN, sc, dt, first, Dl, Q);
-    if constexpr (LY::NB > 1) disc_fast_block<LY, 1, T>(mdl, sN, sc, dt, first, Dl, Q);
+    disc_fast_block<LY, 0, T>(mdl, cst, sc, dt, first, Dl, Q);
+    if constexpr (LY::NB > 1) disc_fast_block<LY, 1, T>(mdl, cst, sc, dt, first, Dl, Q);
 }
 
 // ------------------------------------------------------------------ register linear algebra

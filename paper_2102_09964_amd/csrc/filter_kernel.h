@@ -42,6 +42,7 @@ struct FilterParams {
     double *loglik;
     T *ck;
     double *ll_terms;  // batched: per-step log-likelihood terms
+    const double *cst;  // model constants of the FP32 transition (ConstLayout)
     WsCtl *ctl;
     T *inclp;
     T *lanep;
@@ -58,9 +59,9 @@ struct TileRange {
 
 // Transition of a step in the scan type: Dl = F - I (F = 0 at a series
 // start, so Dl = -I there) and Q. FP32 scans use the pair expansion of Q
-// with the constants in LDS (sN); FP64 scans the FP64 discretisation.
+// with the constants at cst; FP64 scans the FP64 discretisation.
 template <class LY, typename T>
-__device__ __forceinline__ void step_transition(const DevModel &mdl, const double *sN, const StepScale &sc,
+__device__ __forceinline__ void step_transition(const DevModel &mdl, cdouble *cst, const StepScale &sc,
                                                 double dt, bool first, T (&Dl)[LY::D][LY::D],
                                                 T (&Q)[LY::D][LY::D])
 {
@@ -76,15 +77,9 @@ __device__ __forceinline__ void step_transition(const DevModel &mdl, const doubl
                 Q[i][j] = T(Q64[i][j]);
             }
     } else {
-        discretize_fast<LY, T>(mdl, sN, sc, dt, first, Dl, Q);
+        discretize_fast<LY, T>(mdl, cst, sc, dt, first, Dl, Q);
     }
 }
-
-// LDS for the pair constants of the FP32 transition (one double for FP64).
-template <class LY, typename T>
-struct SNSize {
-    static constexpr int value = sizeof(T) == 8 ? 1 : QPairs<LY>::TOTAL;
-};
 
 // Per-lane view of the step inputs with the next step's values loaded one
 // iteration ahead.
@@ -112,7 +107,7 @@ struct StepInputs {
 // wave scans the 64 chunk aggregates (inclusive, time order) and stores them
 // at lanep; lane 63 then holds the tile aggregate.
 template <class LY, typename T, typename CT, class SV>
-__device__ __forceinline__ void filter_tile_fold(const FilterParams<T> &p, const DevModel &mdl, const double *sN,
+__device__ __forceinline__ void filter_tile_fold(const FilterParams<T> &p, const DevModel &mdl, cdouble *cst,
                                                  SV &sv, const TileRange &tr, int tile)
 {
     constexpr int D = LY::D;
@@ -139,8 +134,10 @@ __device__ __forceinline__ void filter_tile_fold(const FilterParams<T> &p, const
         sv.seek(k);
         const bool first = sv.first(k);
         const double dt = first ? 0.0 : in.tc - in.tp;
+        cdouble *c = cst;
+        PSSGP_LAUNDER(c);
         T Dl[D][D], Q[D][D];
-        step_transition<LY, T>(mdl, sN, sv.sc, dt, first, Dl, Q);
+        step_transition<LY, T>(mdl, c, sv.sc, dt, first, Dl, Q);
         const T yk = in.oc ? in.yc : T(0);
         agg_fold<D, T>(agg, Dl, Q, h, p.noise_k ? R : T(sv.R), yk, in.oc);
         in.tp = in.tc;
@@ -164,7 +161,7 @@ __device__ __forceinline__ void filter_tile_fold(const FilterParams<T> &p, const
 // lane's partial.
 template <class LY, typename T, typename CT, int MODE, class SV>
 __device__ __forceinline__ void filter_tile_finish(const FilterParams<T> &p, const DevModel &mdl,
-                                                   const double *sN, SV &sv, const TileRange &tr, int tile,
+                                                   cdouble *cst, SV &sv, const TileRange &tr, int tile,
                                                    double &ll_out)
 {
     constexpr int D = LY::D;
@@ -205,8 +202,10 @@ __device__ __forceinline__ void filter_tile_finish(const FilterParams<T> &p, con
         const bool first = sv.first(k);
         const double dt = first ? 0.0 : in.tc - in.tp;
         if (!(dt >= 0.0)) bad |= (dt < 0.0) ? PSSGP_STATUS_UNSORTED : PSSGP_STATUS_NONFINITE;
+        cdouble *c = cst;
+        PSSGP_LAUNDER(c);
         T Dl[D][D], Q[D][D];
-        step_transition<LY, T>(mdl, sN, sv.sc, dt, first, Dl, Q);
+        step_transition<LY, T>(mdl, c, sv.sc, dt, first, Dl, Q);
         const bool obs = in.oc;
         const T yk = obs ? in.yc : T(0);
         const T R = p.noise_k ? Rk : T(sv.R);
@@ -287,29 +286,25 @@ template <class LY, typename T, typename CT>
 __global__ __launch_bounds__(PSSGP_WAVE, sizeof(T) == 4 ? PSSGP_FILTER_MINW : 1) void filter_fold_kernel(FilterParams<T> p, DevModel mdl_arg)
 {
     __shared__ DevModel mdl;
-    __shared__ double sN[SNSize<LY, T>::value];
     model_to_lds(mdl_arg, mdl);
-    if constexpr (sizeof(T) == 4) qpairs_build<LY>(mdl, sN);
     OneSeries sv;
     sv.init(mdl, p.n);
     TileRange tr{0, p.n, p.ntiles, 0};
-    filter_tile_fold<LY, T, CT, OneSeries>(p, mdl, sN, sv, tr, (int)blockIdx.x);
+    filter_tile_fold<LY, T, CT, OneSeries>(p, mdl, (cdouble *)p.cst, sv, tr, (int)blockIdx.x);
 }
 
 template <class LY, typename T, typename CT, int MODE>
 __global__ __launch_bounds__(PSSGP_WAVE, sizeof(T) == 4 ? PSSGP_FILTER_MINW : 1) void filter_finish_kernel(FilterParams<T> p, DevModel mdl_arg)
 {
     __shared__ DevModel mdl;
-    __shared__ double sN[SNSize<LY, T>::value];
     const int lane = lane_id();
     const int tile = (int)blockIdx.x;
     model_to_lds(mdl_arg, mdl);
-    if constexpr (sizeof(T) == 4) qpairs_build<LY>(mdl, sN);
     OneSeries sv;
     sv.init(mdl, p.n);
     TileRange tr{0, p.n, p.ntiles, 0};
     double ll = 0.0;
-    filter_tile_finish<LY, T, CT, MODE, OneSeries>(p, mdl, sN, sv, tr, tile, ll);
+    filter_tile_finish<LY, T, CT, MODE, OneSeries>(p, mdl, (cdouble *)p.cst, sv, tr, tile, ll);
 
     // log-likelihood: deterministic wave sum, tile partial, the last tile to
     // finish reduces the partials in a fixed order (no waiting involved)
@@ -368,6 +363,7 @@ FilterParams<T> filter_params(const FilterLaunch &a)
     p.loglik = a.loglik;
     p.ck = (T *)a.ck;
     p.ll_terms = nullptr;
+    p.cst = a.ws.cst;
     p.ctl = a.ws.ctl;
     p.inclp = (T *)a.ws.inclp;
     p.lanep = (T *)a.ws.lanep;
@@ -381,6 +377,7 @@ int launch_filter_t(const DevModel &mdl, const FilterLaunch &a, hipStream_t s)
     FilterParams<T> p = filter_params<LY, T>(a);
     const dim3 grid(a.ntiles), block(PSSGP_WAVE);
     pass_event(a.ev, 0, s);
+    if constexpr (sizeof(T) == 4) hipLaunchKernelGGL((consts_kernel<LY>), dim3(1), dim3(256), 0, s, mdl, a.ws.cst);
     hipLaunchKernelGGL((filter_fold_kernel<LY, T, CT>), grid, block, 0, s, p, mdl);
     int rc = (int)hipGetLastError();
     if (rc) return rc;

@@ -18,12 +18,17 @@ struct WsCtl {
 #define PSSGP_LAYOUTS(X) X(1, 0) X(2, 0) X(3, 0) X(4, 0) X(6, 0) X(2, 6) X(1, 2)
 #endif
 
+// Room for the constants of the FP32 transition of one model in the
+// workspace, in doubles (8 KB).
+#define PSSGP_CONST_DOUBLES 1024
+
 // Workspace pieces of one scan launch (all device pointers).
 struct ScanWs {
     WsCtl *ctl;
     void *inclp;     // per-tile carries (moments entering the tile)
     void *lanep;     // per-lane inclusive aggregates within the tile
     double *partials;  // per-tile partial sums (loglik, gradient)
+    double *cst;       // model constants of the FP32 transition (8 KB per model)
 };
 
 struct FilterLaunch {

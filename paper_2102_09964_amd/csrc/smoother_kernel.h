@@ -41,6 +41,7 @@ struct SmoothParams {
     WsCtl *ctl;
     T *inclp;
     T *lanep;
+    const double *cst;  // model constants of the FP32 transition (ConstLayout)
 };
 
 struct STileRange {
@@ -55,7 +56,7 @@ struct STileRange {
 // aggregate.
 template <class LY, typename T, class SV>
 __device__ __forceinline__ void smoother_tile_fold(const SmoothParams<T> &p, const DevModel &mdl,
-                                                   const double *sN, SV &sv, const STileRange &tr, int tile)
+                                                   cdouble *cst, SV &sv, const STileRange &tr, int tile)
 {
     constexpr int D = LY::D;
     constexpr int AGG = SAggLayout<D>::SIZE;
@@ -70,8 +71,10 @@ __device__ __forceinline__ void smoother_tile_fold(const SmoothParams<T> &p, con
     for (int64_t k = k1 - 1; k >= k0; k--) {
         PSSGP_RELOAD_CONSTANTS();
         sv.seek(k);
+        cdouble *c = cst;
+        PSSGP_LAUNDER(c);
         SAgg<D, T> e;
-        smoother_element<LY, T, SV>(mdl, sN, sv, p.t, p.m, p.P, p.n, k, e, bad);
+        smoother_element<LY, T, SV>(mdl, c, sv, p.t, p.m, p.P, p.n, k, e, bad);
         sagg_combine<D, T>(e, agg, agg);
     }
     for (int o = 1; o < PSSGP_WAVE; o <<= 1) {
@@ -87,7 +90,7 @@ __device__ __forceinline__ void smoother_tile_fold(const SmoothParams<T> &p, con
 // and runs the backward RTS recursion over its chunk.
 template <class LY, typename T, bool FULL, class SV>
 __device__ __forceinline__ void smoother_tile_finish(const SmoothParams<T> &p, const DevModel &mdl,
-                                                     const double *sN, SV &sv, const STileRange &tr, int tile)
+                                                     cdouble *cst, SV &sv, const STileRange &tr, int tile)
 {
     constexpr int D = LY::D;
     constexpr int AGG = SAggLayout<D>::SIZE;
@@ -112,8 +115,10 @@ __device__ __forceinline__ void smoother_tile_finish(const SmoothParams<T> &p, c
     for (int64_t k = k1 - 1; k >= k0; k--) {
         PSSGP_RELOAD_CONSTANTS();
         sv.seek(k);
+        cdouble *c = cst;
+        PSSGP_LAUNDER(c);
         SAgg<D, T> e;
-        smoother_element<LY, T, SV>(mdl, sN, sv, p.t, p.m, p.P, p.n, k, e, bad);
+        smoother_element<LY, T, SV>(mdl, c, sv, p.t, p.m, p.P, p.n, k, e, bad);
         sagg_apply<D, T>(e, ms, Ps, ms, Ps);
         T Ph[D];
         mat_vec<D, T>(Ps, h, Ph);
@@ -131,24 +136,16 @@ __device__ __forceinline__ void smoother_tile_finish(const SmoothParams<T> &p, c
     if (bad) status_or(&p.ctl->status, bad);
 }
 
-// LDS for the pair constants of the FP32 transition (one double for FP64).
-template <class LY, typename T>
-struct SmootherSN {
-    static constexpr int value = sizeof(T) == 8 ? 1 : QPairs<LY>::TOTAL;
-};
-
 template <class LY, typename T>
 __global__ __launch_bounds__(PSSGP_WAVE, sizeof(T) == 4 ? PSSGP_SMOOTHER_MINW : 1) void smoother_fold_kernel(SmoothParams<T> p,
                                                                                            DevModel mdl_arg)
 {
     __shared__ DevModel mdl;
-    __shared__ double sN[SmootherSN<LY, T>::value];
     model_to_lds(mdl_arg, mdl);
-    if constexpr (sizeof(T) == 4) qpairs_build<LY>(mdl, sN);
     OneSeries sv;
     sv.init(mdl, p.n);
     STileRange tr{0, p.n, p.ntiles, 0};
-    smoother_tile_fold<LY, T, OneSeries>(p, mdl, sN, sv, tr, (int)blockIdx.x);
+    smoother_tile_fold<LY, T, OneSeries>(p, mdl, (cdouble *)p.cst, sv, tr, (int)blockIdx.x);
 }
 
 template <class LY, typename T, bool FULL>
@@ -156,13 +153,11 @@ __global__ __launch_bounds__(PSSGP_WAVE, sizeof(T) == 4 ? PSSGP_SMOOTHER_MINW : 
                                                                                              DevModel mdl_arg)
 {
     __shared__ DevModel mdl;
-    __shared__ double sN[SmootherSN<LY, T>::value];
     model_to_lds(mdl_arg, mdl);
-    if constexpr (sizeof(T) == 4) qpairs_build<LY>(mdl, sN);
     OneSeries sv;
     sv.init(mdl, p.n);
     STileRange tr{0, p.n, p.ntiles, 0};
-    smoother_tile_finish<LY, T, FULL, OneSeries>(p, mdl, sN, sv, tr, (int)blockIdx.x);
+    smoother_tile_finish<LY, T, FULL, OneSeries>(p, mdl, (cdouble *)p.cst, sv, tr, (int)blockIdx.x);
 }
 
 template <class LY, typename T>
@@ -182,8 +177,10 @@ int launch_smoother_t(const DevModel &mdl, const SmoothLaunch &a, hipStream_t s)
     p.ctl = a.ws.ctl;
     p.inclp = (T *)a.ws.inclp;
     p.lanep = (T *)a.ws.lanep;
+    p.cst = a.ws.cst;
     const dim3 grid(a.ntiles), block(PSSGP_WAVE);
     pass_event(a.ev, 0, s);
+    if constexpr (sizeof(T) == 4) hipLaunchKernelGGL((consts_kernel<LY>), dim3(1), dim3(256), 0, s, mdl, a.ws.cst);
     hipLaunchKernelGGL((smoother_fold_kernel<LY, T>), grid, block, 0, s, p, mdl);
     int rc = (int)hipGetLastError();
     if (rc) return rc;

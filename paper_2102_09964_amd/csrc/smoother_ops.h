@@ -149,10 +149,10 @@ __device__ __forceinline__ void gl_load(const T *p, T (&g)[D], T (&L)[D][D])
 // transition comes as Dl = F - I. The last step of a series takes the
 // transition F = 0, Q = Pinf, for which the same formulas give exactly its
 // element (0, m, P); every lane runs the same instruction stream. FP32
-// scans use the pair expansion of the transition (constants sN in LDS),
-// FP64 scans the FP64 discretisation.
+// scans use the pair expansion of the transition (constants at cst), FP64
+// scans the FP64 discretisation.
 template <class LY, typename T, class SV>
-__device__ __forceinline__ void smoother_element(const DevModel &mdl, const double *sN, const SV &sv,
+__device__ __forceinline__ void smoother_element(const DevModel &mdl, cdouble *cst, const SV &sv,
                                                  const double *t, const T *mf, const T *Pf, int64_t n, int64_t k,
                                                  SAgg<LY::D, T> &e, uint32_t &bad)
 {
@@ -166,7 +166,7 @@ __device__ __forceinline__ void smoother_element(const DevModel &mdl, const doub
 #pragma unroll
         for (int i = 0; i < D; i++) Dl[i][i] -= 1.0;
     } else {
-        discretize_fast<LY, double>(mdl, sN, sv.sc, dt, is_last, Dl, Q);
+        discretize_fast<LY, double>(mdl, cst, sv.sc, dt, is_last, Dl, Q);
     }
     double m[D], P[D][D];
 #pragma unroll
