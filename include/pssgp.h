@@ -96,13 +96,15 @@ typedef struct pssgp_options {
                                 partial results in a fixed order, so results are
                                 always bitwise reproducible for a given chunk */
     uint32_t reserved[6];    /* zero */
-    void *pass_events[4];    /* optional hipEvent_t handles (NULL entries are skipped),
+    void *pass_events[8];    /* optional hipEvent_t handles (NULL entries are skipped),
                                 recorded on the stream before the fold pass, before
                                 the carry pass, before the finish pass and after the
-                                finish pass of the call's filter scan (pssgp_filter,
-                                pssgp_loglik, pssgp_loglik_grad, batched filter) or
-                                smoother scan (pssgp_smooth, batched smoother); for
-                                timing the passes. Owned by the caller. */
+                                finish pass of the call's filter scan (entries 0-3:
+                                pssgp_filter, pssgp_loglik, pssgp_loglik_grad,
+                                pssgp_predict, batched filter) and smoother scan
+                                (entries 0-3 for pssgp_smooth and the batched
+                                smoother, entries 4-7 for pssgp_predict); for timing
+                                the passes. Owned by the caller. */
 } pssgp_options;
 
 typedef enum {
@@ -111,7 +113,8 @@ typedef enum {
     PSSGP_OP_LOGLIK = 3,
     PSSGP_OP_LOGLIK_GRAD = 4,
     PSSGP_OP_DISCRETIZE = 5,
-    PSSGP_OP_PLAIN = 6
+    PSSGP_OP_PLAIN = 6,
+    PSSGP_OP_PREDICT = 7
 } pssgp_op;
 
 /* Status word bits set on the device. */
@@ -207,6 +210,19 @@ int pssgp_smooth(const pssgp_model *model, const double *t, const void *m, const
 int pssgp_plain_predict(const pssgp_model *model, const double *t, const double *y,
                         const uint8_t *mask, int64_t n, double *m, double *P, double *f_mean,
                         double *f_var, double *loglik, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Filter, log-likelihood and smoother in one call (section 3 and
+ * supplement, Lemma 1; test points are missing steps): f_mean, f_var
+ * dtype[n] and loglik double[1] as from pssgp_filter + pssgp_smooth, with
+ * the filter moments handed to the smoother inside the workspace (in a
+ * layout where every access of a wave is contiguous) instead of through
+ * m and P. Workspace: pssgp_workspace_bytes(..., PSSGP_OP_PREDICT, opts);
+ * the same opts (chunk) must be passed. Errors as pssgp_filter.
+ */
+int pssgp_predict(const pssgp_model *model, const double *t, const void *y, const uint8_t *mask, int64_t n,
+                  pssgp_dtype dtype, void *f_mean, void *f_var, double *loglik, void *ws, size_t ws_bytes,
+                  const pssgp_options *opts, void *stream);
 
 /* Log-likelihood only: pssgp_filter without state outputs. */
 int pssgp_loglik(const pssgp_model *model, const double *t, const void *y, const uint8_t *mask,

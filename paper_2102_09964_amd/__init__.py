@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libpssgp.so")
 
 MATERN12, MATERN32, MATERN52, RBF = 1, 2, 3, 4
 F32, F64 = 0, 1
-OP_FILTER, OP_SMOOTH, OP_LOGLIK, OP_LOGLIK_GRAD, OP_DISCRETIZE, OP_PLAIN = 1, 2, 3, 4, 5, 6
+OP_FILTER, OP_SMOOTH, OP_LOGLIK, OP_LOGLIK_GRAD, OP_DISCRETIZE, OP_PLAIN, OP_PREDICT = 1, 2, 3, 4, 5, 6, 7
 STATUS_UNSORTED, STATUS_NONFINITE, STATUS_BAD_S, STATUS_CHOLESKY = 1, 2, 4, 8
 
 _ERRORS = {-1: "EINVAL", -2: "EUNSUPPORTED", -3: "EWORKSPACE", -4: "EDEVICE", -5: "ENODEVICE",
@@ -50,7 +50,7 @@ class BatchGroup(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("chunk", ctypes.c_uint32), ("deterministic", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32 * 6), ("pass_events", ctypes.c_void_p * 4)]
+                ("reserved", ctypes.c_uint32 * 6), ("pass_events", ctypes.c_void_p * 8)]
 
 
 _lib = None
@@ -82,6 +82,7 @@ SIGNATURES = [
     ("pssgp_batched_smooth", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _I64, _VP, _VP, _VP, _VP, _VP, _VP,
                                             ctypes.c_int, _VP, _VP, _VP, _SZ, _OP, _VP]),
     ("pssgp_status", ctypes.c_int, [_VP, _VP, ctypes.POINTER(ctypes.c_uint32)]),
+    ("pssgp_predict", ctypes.c_int, [_MP, _VP, _VP, _VP, _I64, ctypes.c_int, _VP, _VP, _VP, _VP, _SZ, _OP, _VP]),
     ("pssgp_plain_predict", ctypes.c_int, [_MP, _VP, _VP, _VP, _I64, _VP, _VP, _VP, _VP, _VP, _VP, _SZ, _VP]),
 ]
 
@@ -315,9 +316,26 @@ def smooth(model, t, m_f, P_f, dtype="float32", full_state=False, options=None, 
     return out
 
 
-def predict(model, t, y, mask=None, dtype="float32", options=None, device="cuda"):
+def predict(model, t, y, mask=None, dtype="float32", options=None, device="cuda", fused=True):
     """Filter + smoother on a merged grid (test points: mask 0). Returns
-    dict with 'f_mean', 'f_var', 'loglik'."""
+    dict with 'f_mean', 'f_var', 'loglik' (and the filter moments 'm', 'P'
+    when fused=False)."""
+    if fused:
+        _require_gpu()
+        torch = _torch()
+        m = _as_model(model)
+        code, tdt = _dt(dtype)
+        t = _dev(t, torch.float64, device)
+        n = t.shape[0]
+        y = _dev(y, tdt, device)
+        mask = _dev(mask, torch.uint8, device)
+        ws = alloc_workspace(m, n, code, OP_PREDICT, options, device)
+        fm = torch.empty(n, dtype=tdt, device=device)
+        fv = torch.empty(n, dtype=tdt, device=device)
+        ll = torch.empty(1, dtype=torch.float64, device=device)
+        _check(lib().pssgp_predict(ctypes.byref(m), _p(t), _p(y), _p(mask), n, code, _p(fm), _p(fv), _p(ll), _p(ws),
+                                   ws.numel(), ctypes.byref(options) if options is not None else None, _stream()))
+        return {"f_mean": fm, "f_var": fv, "loglik": ll, "ws": ws}
     f = filter(model, t, y, mask, dtype=dtype, options=options, device=device)
     s = smooth(model, t, f["m"], f["P"], dtype=dtype, options=options, device=device)
     return {"f_mean": s["f_mean"], "f_var": s["f_var"], "loglik": f["loglik"], "m": f["m"], "P": f["P"]}
@@ -447,11 +465,14 @@ class Pipeline:
     length and dtype: workspaces and outputs are allocated once, so that
     ``run()`` only launches kernels (stream-ordered, no synchronisation).
 
-    Events bracketing the two scan launches are recorded on the current
-    stream when ``events`` is true, for per-kernel timing.
+    By default both scans run in one ``pssgp_predict`` call, which hands the
+    filter moments to the smoother inside its workspace; with
+    ``full_state`` (smoothed state moments wanted) or ``fused=False`` the
+    filter moments are written to ``m``, ``P`` and read back by
+    ``pssgp_smooth``.
     """
 
-    def __init__(self, model, n, dtype="float32", options=None, full_state=False, device="cuda"):
+    def __init__(self, model, n, dtype="float32", options=None, full_state=False, fused=True, device="cuda"):
         _require_gpu()
         torch = _torch()
         self.model = _as_model(model)
@@ -459,11 +480,17 @@ class Pipeline:
         self.n = int(n)
         self.d = state_dim(self.model)
         self.options = options
+        self.fused = fused and not full_state
         ns = self.d * (self.d + 1) // 2
-        self.ws_f = alloc_workspace(self.model, n, self.code, OP_FILTER, options, device)
-        self.ws_s = alloc_workspace(self.model, n, self.code, OP_SMOOTH, options, device)
-        self.m = torch.empty((self.d, n), dtype=self.tdt, device=device)
-        self.P = torch.empty((ns, n), dtype=self.tdt, device=device)
+        if self.fused:
+            self.ws_p = alloc_workspace(self.model, n, self.code, OP_PREDICT, options, device)
+            self.ws_f = self.ws_s = self.ws_p
+            self.m = self.P = None
+        else:
+            self.ws_f = alloc_workspace(self.model, n, self.code, OP_FILTER, options, device)
+            self.ws_s = alloc_workspace(self.model, n, self.code, OP_SMOOTH, options, device)
+            self.m = torch.empty((self.d, n), dtype=self.tdt, device=device)
+            self.P = torch.empty((ns, n), dtype=self.tdt, device=device)
         self.loglik = torch.empty(1, dtype=torch.float64, device=device)
         self.f_mean = torch.empty(n, dtype=self.tdt, device=device)
         self.f_var = torch.empty(n, dtype=self.tdt, device=device)
@@ -479,11 +506,23 @@ class Pipeline:
         of every pass."""
         L = lib()
         mp = ctypes.byref(self.model)
-        op_f = op_s = ctypes.byref(self.options) if self.options is not None else None
+        st = _stream()
+        op = ctypes.byref(self.options) if self.options is not None else None
+        if self.fused:
+            if pass_events is not None:
+                op = ctypes.byref(_with_events(self.options, list(pass_events[0]) + list(pass_events[1])))
+            if events:
+                events[0].record()
+            _check(L.pssgp_predict(mp, _p(t), _p(y), _p(mask), self.n, self.code, _p(self.f_mean), _p(self.f_var),
+                                   _p(self.loglik), _p(self.ws_p), self.ws_p.numel(), op, st))
+            if events:
+                events[1].record()
+                events[2].record()
+            return self.f_mean, self.f_var, self.loglik
+        op_f = op_s = op
         if pass_events is not None:
             op_f = ctypes.byref(_with_events(self.options, pass_events[0]))
             op_s = ctypes.byref(_with_events(self.options, pass_events[1]))
-        st = _stream()
         if events:
             events[0].record()
         _check(L.pssgp_filter(mp, _p(t), _p(y), _p(mask), None, self.n, self.code, _p(self.m), _p(self.P),

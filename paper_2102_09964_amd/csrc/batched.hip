@@ -122,10 +122,12 @@ __global__ __launch_bounds__(PSSGP_WAVE) void batched_smoother_kernel(SmoothPara
     ManySeries sv;
     series_view(sv, a, g, g.k_begin + ((int64_t)tile * PSSGP_WAVE + lane_id()) * p.chunk);
     if constexpr (FINISH) {
+        extern __shared__ __align__(16) unsigned char pssgp_dyn_smem[];
+        T *s_out = reinterpret_cast<T *>(pssgp_dyn_smem);
         if (gi == 0)
-            smoother_tile_finish<LA, T, false, ManySeries>(p, mdl, cst, sv, tr, tile);
+            smoother_tile_finish<LA, T, false, ManySeries>(p, mdl, cst, sv, tr, tile, s_out);
         else
-            smoother_tile_finish<LB, T, false, ManySeries>(p, mdl, cst, sv, tr, tile);
+            smoother_tile_finish<LB, T, false, ManySeries>(p, mdl, cst, sv, tr, tile, s_out);
     } else {
         if (gi == 0)
             smoother_tile_fold<LA, T, ManySeries>(p, mdl, cst, sv, tr, tile);
@@ -215,6 +217,8 @@ int launch_bs(const BatchLaunch &a, hipStream_t s)
     p.ctl = a.ws.ctl;
     p.inclp = (T *)a.ws.inclp;
     p.lanep = (T *)a.ws.lanep;
+    p.cst = a.ws.cst;
+    p.tiled = 0;
     const dim3 grid(a.total_tiles), block(PSSGP_WAVE);
     pass_event(a.ev, 0, s);
     if constexpr (sizeof(T) == 4)
@@ -232,7 +236,8 @@ int launch_bs(const BatchLaunch &a, hipStream_t s)
         if (rc) return rc;
     }
     pass_event(a.ev, 2, s);
-    hipLaunchKernelGGL((batched_smoother_kernel<LA, LB, T, true>), grid, block, 0, s, p, a);
+    const size_t smem = (size_t)2 * PSSGP_WAVE * a.chunk * sizeof(T);
+    hipLaunchKernelGGL((batched_smoother_kernel<LA, LB, T, true>), grid, block, smem, s, p, a);
     rc = (int)hipGetLastError();
     pass_event(a.ev, 3, s);
     return rc;

@@ -25,6 +25,7 @@ struct Plan {
     size_t off_incl = 0, off_lane = 0, off_part = 0, off_ck = 0, off_rec = 0, off_cst = 0;
     size_t off_incl2 = 0, off_lane2 = 0, off_part2 = 0;
     size_t off_x = 0, off_xraw = 0;  // plain baseline element arrays
+    size_t off_hand = 0;             // predict: filter-to-smoother handover
     size_t total = 0;
 };
 
@@ -74,6 +75,17 @@ Plan make_plan(int d, int ncomp, int64_t n, pssgp_dtype dtype, int op, const pss
         return p;
     }
     p.off_cst = take(PSSGP_CONST_DOUBLES * sizeof(double));
+    if (op == PSSGP_OP_PREDICT) {
+        // filter then smoother on one stream: the scans share their regions
+        // (the filter's are the larger); the handover holds the filter
+        // moments of every lane chunk in the tile layout
+        p.off_incl = take(nt * filter_incl_elems(d) * p.tsize);
+        p.off_lane = take(nt * 64 * filter_agg_elems(d) * p.tsize);
+        p.off_part = take(nt * sizeof(double) * n_params(ncomp));
+        p.off_hand = take(nt * 64 * (size_t)p.chunk * (d + d * (d + 1) / 2) * p.tsize);
+        p.total = off;
+        return p;
+    }
     if (op == PSSGP_OP_SMOOTH) {
         p.off_incl = take(nt * smooth_incl_elems(d) * p.tsize);
         p.off_lane = take(nt * 64 * smooth_agg_elems(d) * p.tsize);
@@ -191,7 +203,7 @@ int run_filter(const pssgp_model *model, const double *t, const void *y, const u
     rc = launch_ws_init(sw.ctl, n == 0 ? loglik : nullptr, n == 0 && loglik ? 1 : 0, s);
     if ((rc = hip_err((hipError_t)rc, "workspace init"))) return rc;
     if (n == 0) return PSSGP_OK;
-    FilterLaunch a;
+    FilterLaunch a{};
     a.ev = opts ? opts->pass_events : nullptr;
     a.t = t;
     a.y = y;
@@ -428,7 +440,7 @@ size_t pssgp_workspace_bytes(const pssgp_model *model, int64_t n, pssgp_dtype dt
                              const pssgp_options *opts)
 {
     int d = pssgp_build_devmodel(model, nullptr, nullptr);
-    if (d < 0 || n < 0 || op < PSSGP_OP_FILTER || op > PSSGP_OP_PLAIN) return 0;
+    if (d < 0 || n < 0 || op < PSSGP_OP_FILTER || op > PSSGP_OP_PREDICT) return 0;
     return make_plan(d, model->n_comp, n, dtype, op, opts).total;
 }
 
@@ -534,7 +546,7 @@ int pssgp_smooth(const pssgp_model *model, const double *t, const void *m, const
     rc = launch_ws_init(sw.ctl, nullptr, 0, s);
     if ((rc = hip_err((hipError_t)rc, "workspace init"))) return rc;
     if (n == 0) return PSSGP_OK;
-    SmoothLaunch a;
+    SmoothLaunch a{};
     a.ev = opts ? opts->pass_events : nullptr;
     a.t = t;
     a.m = m;
@@ -548,6 +560,60 @@ int pssgp_smooth(const pssgp_model *model, const double *t, const void *m, const
     a.Ps = Ps;
     a.ws = sw;
     return check_launch(launch_smoother(dm, b0, b1, dtype == PSSGP_F64, a, s), "smoother launch");
+}
+
+int pssgp_predict(const pssgp_model *model, const double *t, const void *y, const uint8_t *mask, int64_t n,
+                  pssgp_dtype dtype, void *f_mean, void *f_var, double *loglik, void *ws, size_t ws_bytes,
+                  const pssgp_options *opts, void *stream)
+{
+    DevModel dm;
+    int b0, b1;
+    int rc = prepare(model, n, dtype, dm, b0, b1);
+    if (rc) return rc;
+    if ((rc = check_opts(opts))) return rc;
+    if (!loglik || (n > 0 && (!t || !y || !f_mean || !f_var))) {
+        pssgp_set_error("t, y, f_mean, f_var and loglik must be device pointers");
+        return PSSGP_EINVAL;
+    }
+    Plan p = make_plan(dm.d, dm.nblk, n, dtype, PSSGP_OP_PREDICT, opts);
+    if ((rc = check_ws(ws, ws_bytes, p))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    char *b = (char *)ws;
+    ScanWs sw = scan_ws(ws, p);
+    rc = launch_ws_init(sw.ctl, n == 0 ? loglik : nullptr, n == 0 ? 1 : 0, s);
+    if ((rc = hip_err((hipError_t)rc, "workspace init"))) return rc;
+    if (n == 0) return PSSGP_OK;
+    void *hand = b + p.off_hand;
+    FilterLaunch a{};
+    a.ev = opts ? opts->pass_events : nullptr;
+    a.t = t;
+    a.y = y;
+    a.mask = mask;
+    a.noise_k = nullptr;
+    a.n = n;
+    a.chunk = p.chunk;
+    a.ntiles = p.ntiles;
+    a.m = hand;
+    a.P = nullptr;
+    a.loglik = loglik;
+    a.ck = nullptr;
+    a.tiled = 1;
+    a.ws = sw;
+    rc = check_launch(launch_filter(dm, b0, b1, dtype == PSSGP_F64, a, s), "filter launch");
+    if (rc) return rc;
+    SmoothLaunch sm{};
+    sm.ev = opts ? opts->pass_events + 4 : nullptr;
+    sm.t = t;
+    sm.m = hand;
+    sm.P = nullptr;
+    sm.n = n;
+    sm.chunk = p.chunk;
+    sm.ntiles = p.ntiles;
+    sm.f_mean = f_mean;
+    sm.f_var = f_var;
+    sm.tiled = 1;
+    sm.ws = sw;
+    return check_launch(launch_smoother(dm, b0, b1, dtype == PSSGP_F64, sm, s), "smoother launch");
 }
 
 int pssgp_loglik_grad(const pssgp_model *model, const double *t, const void *y, const uint8_t *mask,
@@ -575,7 +641,7 @@ int pssgp_loglik_grad(const pssgp_model *model, const double *t, const void *y, 
         rc = launch_ws_init(sw.ctl, grad, np, s);
         return hip_err((hipError_t)rc, "workspace init");
     }
-    FilterLaunch a;
+    FilterLaunch a{};
     a.ev = opts ? opts->pass_events : nullptr;
     a.t = t;
     a.y = y;
@@ -594,7 +660,7 @@ int pssgp_loglik_grad(const pssgp_model *model, const double *t, const void *y, 
     ScanWs sw2 = scan_ws(ws, p, true);
     rc = launch_ws_init(sw2.ctl, nullptr, 0, s, /*keep_status=*/true);
     if ((rc = hip_err((hipError_t)rc, "workspace init"))) return rc;
-    GradLaunch g;
+    GradLaunch g{};
     g.t = t;
     g.y = y;
     g.mask = mask;

@@ -651,6 +651,16 @@ __device__ __forceinline__ double wave_sum(double v)
     return __shfl(v, 0, PSSGP_WAVE);
 }
 
+// Per-lane records of a tile are stored lane-interleaved: field f of the
+// record of lane l of tile slot s is at base[(s * size + f) * 64 + l], so
+// that the 64 lanes of a wave access 64 consecutive elements; the record
+// helpers take the field stride 64.
+template <typename T>
+__device__ __forceinline__ T *lane_rec(T *base, int64_t slot, int size, int lane)
+{
+    return base + ((size_t)slot * size) * PSSGP_WAVE + lane;
+}
+
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (PSSGP_WAVE - 1)); }
 
 // The model constants (up to ~3.5 KB, mostly the expansion matrices of the

@@ -24,9 +24,13 @@
 #include "device_common.h"
 #include "filter_ops.h"
 #include "launch.h"
+#include "smoother_ops.h"
 #include "tile_scan.h"
 
-enum : int { F_MOMENTS = 1, F_CKPT = 2 };
+// Finish-pass outputs: filter moments in the [entry][n] layout, per-chunk
+// checkpoints for the adjoint, filter moments in the tile layout for the
+// smoother of the same call.
+enum : int { F_MOMENTS = 1, F_CKPT = 2, F_TILED = 4 };
 
 template <typename T>
 struct FilterParams {
@@ -150,7 +154,7 @@ __device__ __forceinline__ void filter_tile_fold(const FilterParams<T> &p, const
         agg_shfl_up<D, T>(agg, other, o);
         if (lane >= o) agg_combine<D, T, CT>(other, agg, agg);
     }
-    agg_store<D, T>(p.lanep + (size_t)chunk_id * AGG, agg);
+    agg_store<D, T>(lane_rec(p.lanep, slot, AGG, lane), agg, PSSGP_WAVE);
 }
 
 // Finish pass of one tile: each lane takes the moments entering the tile
@@ -181,11 +185,11 @@ __device__ __forceinline__ void filter_tile_finish(const FilterParams<T> &p, con
     moments_load<D, T>(p.inclp + (size_t)slot * INCL, m, P);
     if (lane > 0) {
         FAgg<D, T> excl;
-        agg_load<D, T>(p.lanep + (size_t)(chunk_id - 1) * AGG, excl);
+        agg_load<D, T>(lane_rec(p.lanep, slot, AGG, lane - 1), excl, PSSGP_WAVE);
         moments_apply<D, T, CT>(m, P, excl, m, P);
     }
     if constexpr ((MODE & F_CKPT) != 0) {
-        if (k0 < tr.k_end) moments_store<D, T>(p.ck + (size_t)chunk_id * INCL, m, P);
+        if (k0 < tr.k_end) moments_store<D, T>(lane_rec(p.ck, slot, INCL, lane), m, P, PSSGP_WAVE);
     }
 
     double ll = 0.0;  // FP64 per-lane sum of the log-likelihood terms
@@ -269,6 +273,15 @@ __device__ __forceinline__ void filter_tile_finish(const FilterParams<T> &p, con
                 P[i][j] = c;
                 P[j][i] = c;
             }
+        if constexpr ((MODE & F_TILED) != 0) {
+            T *b = p.m + tiled_index<D>(slot, p.chunk, (int)(k - k0), 0, lane);
+#pragma unroll
+            for (int i = 0; i < D; i++) b[(size_t)i * PSSGP_WAVE] = m[i];
+#pragma unroll
+            for (int i = 0; i < D; i++)
+#pragma unroll
+                for (int j = i; j < D; j++) b[(size_t)(D + sidx<D>(i, j)) * PSSGP_WAVE] = P[i][j];
+        }
         if constexpr ((MODE & F_MOMENTS) != 0) {
 #pragma unroll
             for (int i = 0; i < D; i++) p.m[(size_t)i * p.n + k] = m[i];
@@ -385,7 +398,9 @@ int launch_filter_t(const DevModel &mdl, const FilterLaunch &a, hipStream_t s)
     rc = launch_tile_scan<FilterScanOps<LY::D, T>>(a.ws.lanep, PSSGP_WAVE - 1, 0, a.ntiles, false, a.ws.inclp, s);
     if (rc) return rc;
     pass_event(a.ev, 2, s);
-    if (a.m)
+    if (a.m && a.tiled)
+        hipLaunchKernelGGL((filter_finish_kernel<LY, T, CT, F_TILED>), grid, block, 0, s, p, mdl);
+    else if (a.m)
         hipLaunchKernelGGL((filter_finish_kernel<LY, T, CT, F_MOMENTS>), grid, block, 0, s, p, mdl);
     else if (a.ck)
         hipLaunchKernelGGL((filter_finish_kernel<LY, T, CT, F_CKPT>), grid, block, 0, s, p, mdl);

@@ -346,73 +346,73 @@ struct AggLayout {
 };
 
 template <int D, typename T>
-__device__ __forceinline__ void agg_store(T *p, const FAgg<D, T> &a)
+__device__ __forceinline__ void agg_store(T *p, const FAgg<D, T> &a, size_t st = 1)
 {
 #pragma unroll
     for (int i = 0; i < D; i++)
 #pragma unroll
-        for (int j = 0; j < D; j++) p[i * D + j] = a.A[i][j];
-    p += D * D;
+        for (int j = 0; j < D; j++) p[(size_t)(i * D + j) * st] = a.A[i][j];
+    p += (size_t)(D * D) * st;
 #pragma unroll
-    for (int i = 0; i < D; i++) p[i] = a.b[i];
-    p += D;
-#pragma unroll
-    for (int i = 0; i < D; i++)
-#pragma unroll
-        for (int j = i; j < D; j++) p[sidx<D>(i, j)] = a.C[i][j];
-    p += AggLayout<D>::NS;
-#pragma unroll
-    for (int i = 0; i < D; i++) p[i] = a.eta[i];
-    p += D;
+    for (int i = 0; i < D; i++) p[(size_t)(i) * st] = a.b[i];
+    p += (size_t)(D) * st;
 #pragma unroll
     for (int i = 0; i < D; i++)
 #pragma unroll
-        for (int j = i; j < D; j++) p[sidx<D>(i, j)] = a.J[i][j];
+        for (int j = i; j < D; j++) p[(size_t)(sidx<D>(i, j)) * st] = a.C[i][j];
+    p += (size_t)(AggLayout<D>::NS) * st;
+#pragma unroll
+    for (int i = 0; i < D; i++) p[(size_t)(i) * st] = a.eta[i];
+    p += (size_t)(D) * st;
+#pragma unroll
+    for (int i = 0; i < D; i++)
+#pragma unroll
+        for (int j = i; j < D; j++) p[(size_t)(sidx<D>(i, j)) * st] = a.J[i][j];
 }
 
 template <int D, typename T>
-__device__ __forceinline__ void agg_load(const T *p, FAgg<D, T> &a)
+__device__ __forceinline__ void agg_load(const T *p, FAgg<D, T> &a, size_t st = 1)
 {
 #pragma unroll
     for (int i = 0; i < D; i++)
 #pragma unroll
-        for (int j = 0; j < D; j++) a.A[i][j] = p[i * D + j];
-    p += D * D;
+        for (int j = 0; j < D; j++) a.A[i][j] = p[(size_t)(i * D + j) * st];
+    p += (size_t)(D * D) * st;
 #pragma unroll
-    for (int i = 0; i < D; i++) a.b[i] = p[i];
-    p += D;
-#pragma unroll
-    for (int i = 0; i < D; i++)
-#pragma unroll
-        for (int j = i; j < D; j++) { a.C[i][j] = p[sidx<D>(i, j)]; a.C[j][i] = a.C[i][j]; }
-    p += AggLayout<D>::NS;
-#pragma unroll
-    for (int i = 0; i < D; i++) a.eta[i] = p[i];
-    p += D;
+    for (int i = 0; i < D; i++) a.b[i] = p[(size_t)(i) * st];
+    p += (size_t)(D) * st;
 #pragma unroll
     for (int i = 0; i < D; i++)
 #pragma unroll
-        for (int j = i; j < D; j++) { a.J[i][j] = p[sidx<D>(i, j)]; a.J[j][i] = a.J[i][j]; }
+        for (int j = i; j < D; j++) { a.C[i][j] = p[(size_t)(sidx<D>(i, j)) * st]; a.C[j][i] = a.C[i][j]; }
+    p += (size_t)(AggLayout<D>::NS) * st;
+#pragma unroll
+    for (int i = 0; i < D; i++) a.eta[i] = p[(size_t)(i) * st];
+    p += (size_t)(D) * st;
+#pragma unroll
+    for (int i = 0; i < D; i++)
+#pragma unroll
+        for (int j = i; j < D; j++) { a.J[i][j] = p[(size_t)(sidx<D>(i, j)) * st]; a.J[j][i] = a.J[i][j]; }
 }
 
 template <int D, typename T>
-__device__ __forceinline__ void moments_store(T *p, const T (&b)[D], const T (&C)[D][D])
+__device__ __forceinline__ void moments_store(T *p, const T (&b)[D], const T (&C)[D][D], size_t st = 1)
 {
 #pragma unroll
-    for (int i = 0; i < D; i++) p[i] = b[i];
+    for (int i = 0; i < D; i++) p[(size_t)(i) * st] = b[i];
 #pragma unroll
     for (int i = 0; i < D; i++)
 #pragma unroll
-        for (int j = i; j < D; j++) p[D + sidx<D>(i, j)] = C[i][j];
+        for (int j = i; j < D; j++) p[(size_t)(D + sidx<D>(i, j)) * st] = C[i][j];
 }
 
 template <int D, typename T>
-__device__ __forceinline__ void moments_load(const T *p, T (&b)[D], T (&C)[D][D])
+__device__ __forceinline__ void moments_load(const T *p, T (&b)[D], T (&C)[D][D], size_t st = 1)
 {
 #pragma unroll
-    for (int i = 0; i < D; i++) b[i] = p[i];
+    for (int i = 0; i < D; i++) b[i] = p[(size_t)(i) * st];
 #pragma unroll
     for (int i = 0; i < D; i++)
 #pragma unroll
-        for (int j = i; j < D; j++) { C[i][j] = p[D + sidx<D>(i, j)]; C[j][i] = C[i][j]; }
+        for (int j = i; j < D; j++) { C[i][j] = p[(size_t)(D + sidx<D>(i, j)) * st]; C[j][i] = C[i][j]; }
 }

@@ -112,7 +112,7 @@ struct AdjointScanOps {
     static constexpr int AGG = SAggLayout<D>::SIZE;
     static constexpr int MOM = SAggLayout<D>::INCL;
     static __device__ __forceinline__ void identity(Agg &a) { sagg_identity<D, T>(a); }
-    static __device__ __forceinline__ void load(const T *p, Agg &a) { sagg_load<D, T>(p, a); }
+    static __device__ __forceinline__ void load(const T *p, Agg &a) { sagg_load<D, T>(p, a, PSSGP_WAVE); }
     static __device__ __forceinline__ void extend(const Agg &acc, const Agg &nx, Agg &out)
     {
         adj_combine<D, T>(nx, acc, out);
@@ -181,7 +181,7 @@ __global__ __launch_bounds__(PSSGP_WAVE) void grad_fold_kernel(GradParams<T> p, 
 #pragma unroll
             for (int j = 0; j < D; j++) P[i][j] = T(0);
         }
-        if (k0 < p.n) moments_load<D, T>(p.ck + (size_t)chunk_id * INCL, m, P);
+        if (k0 < p.n) moments_load<D, T>(lane_rec(p.ck, tile, INCL, lane), m, P, PSSGP_WAVE);
         for (int64_t k = k0; k < k1; k++) {
             PSSGP_RELOAD_CONSTANTS();
             T F[D][D], Q[D][D];
@@ -269,7 +269,7 @@ __global__ __launch_bounds__(PSSGP_WAVE) void grad_fold_kernel(GradParams<T> p, 
             sagg_shfl_down<D, T>(agg, other, o);
             if (lane + o < PSSGP_WAVE) adj_combine<D, T>(agg, other, agg);
         }
-        sagg_store<D, T>(p.lanep + (size_t)chunk_id * AGG, agg);
+        sagg_store<D, T>(lane_rec(p.lanep, tile, AGG, lane), agg, PSSGP_WAVE);
     }
     (void)bad;
 }
@@ -301,7 +301,7 @@ __global__ __launch_bounds__(PSSGP_WAVE) void grad_finish_kernel(GradParams<T> p
     gl_load<D, T>(p.inclp + (size_t)tile * INCL, mb, Pb);
     if (lane < PSSGP_WAVE - 1) {
         SAgg<D, T> excl;
-        sagg_load<D, T>(p.lanep + (size_t)(chunk_id + 1) * AGG, excl);
+        sagg_load<D, T>(lane_rec(p.lanep, tile, AGG, lane + 1), excl, PSSGP_WAVE);
         adj_apply<D, T>(excl, mb, Pb);
     }
     double gacc[NP];

@@ -44,6 +44,7 @@ struct FilterLaunch {
     void *P;         // nullable
     double *loglik;  // nullable
     void *ck;        // nullable: per-chunk checkpoints of the start moments
+    int tiled;       // write m (P unused) in the tile layout of the handover
     ScanWs ws;
 };
 
@@ -59,6 +60,7 @@ struct SmoothLaunch {
     void *f_var;
     void *ms;  // nullable
     void *Ps;  // nullable
+    int tiled; // m holds the filter moments in the tile layout (P unused)
     ScanWs ws;
 };
 

@@ -141,7 +141,8 @@ __global__ __launch_bounds__(128) void plain_smoother_elements(DevModel mdl, con
         OneSeries sv;
         sv.init(mdl, n);
         uint32_t bad = 0;
-        smoother_element<LY, double, OneSeries>(mdl, (cdouble *)nullptr, sv, t, m, P, n, n - 1 - j, e, bad);
+        smoother_element<LY, double, OneSeries>(mdl, (cdouble *)nullptr, sv, t, m + (n - 1 - j), P + (n - 1 - j), (size_t)n,
+                                                 n - 1 - j, e, bad);
     }
     Y[j] = e;
     Yraw[j] = e;

@@ -42,6 +42,7 @@ struct SmoothParams {
     T *inclp;
     T *lanep;
     const double *cst;  // model constants of the FP32 transition (ConstLayout)
+    int tiled;          // m holds the filter moments in the tile layout (P unused)
 };
 
 struct STileRange {
@@ -73,8 +74,19 @@ __device__ __forceinline__ void smoother_tile_fold(const SmoothParams<T> &p, con
         sv.seek(k);
         cdouble *c = cst;
         PSSGP_LAUNDER(c);
+        const T *mk, *pk;
+        size_t st;
+        if (p.tiled) {
+            mk = p.m + tiled_index<D>(slot, p.chunk, (int)(k - k0), 0, lane);
+            pk = mk + (size_t)D * PSSGP_WAVE;
+            st = PSSGP_WAVE;
+        } else {
+            mk = p.m + k;
+            pk = p.P + k;
+            st = (size_t)p.n;
+        }
         SAgg<D, T> e;
-        smoother_element<LY, T, SV>(mdl, c, sv, p.t, p.m, p.P, p.n, k, e, bad);
+        smoother_element<LY, T, SV>(mdl, c, sv, p.t, mk, pk, st, k, e, bad);
         sagg_combine<D, T>(e, agg, agg);
     }
     for (int o = 1; o < PSSGP_WAVE; o <<= 1) {
@@ -82,7 +94,7 @@ __device__ __forceinline__ void smoother_tile_fold(const SmoothParams<T> &p, con
         sagg_shfl_down<D, T>(agg, other, o);
         if (lane + o < PSSGP_WAVE) sagg_combine<D, T>(agg, other, agg);
     }
-    sagg_store<D, T>(p.lanep + (size_t)chunk_id * AGG, agg);
+    sagg_store<D, T>(lane_rec(p.lanep, slot, AGG, lane), agg, PSSGP_WAVE);
 }
 
 // Finish pass of one tile: each lane takes the smoothed moments entering
@@ -90,7 +102,8 @@ __device__ __forceinline__ void smoother_tile_fold(const SmoothParams<T> &p, con
 // and runs the backward RTS recursion over its chunk.
 template <class LY, typename T, bool FULL, class SV>
 __device__ __forceinline__ void smoother_tile_finish(const SmoothParams<T> &p, const DevModel &mdl,
-                                                     cdouble *cst, SV &sv, const STileRange &tr, int tile)
+                                                     cdouble *cst, SV &sv, const STileRange &tr, int tile,
+                                                     T *s_out)
 {
     constexpr int D = LY::D;
     constexpr int AGG = SAggLayout<D>::SIZE;
@@ -104,12 +117,14 @@ __device__ __forceinline__ void smoother_tile_finish(const SmoothParams<T> &p, c
     T h[D];
 #pragma unroll
     for (int i = 0; i < D; i++) h[i] = T(mdl.H[i]);
+    const int64_t tile_start = tr.k_begin + (int64_t)tile * PSSGP_WAVE * p.chunk;
+    const int tile_len = PSSGP_WAVE * p.chunk;
 
     T ms[D], Ps[D][D];
     gl_load<D, T>(p.inclp + (size_t)slot * INCL, ms, Ps);
     if (lane < PSSGP_WAVE - 1) {
         SAgg<D, T> excl;
-        sagg_load<D, T>(p.lanep + (size_t)(chunk_id + 1) * AGG, excl);
+        sagg_load<D, T>(lane_rec(p.lanep, slot, AGG, lane + 1), excl, PSSGP_WAVE);
         sagg_apply<D, T>(excl, ms, Ps, ms, Ps);
     }
     for (int64_t k = k1 - 1; k >= k0; k--) {
@@ -117,13 +132,25 @@ __device__ __forceinline__ void smoother_tile_finish(const SmoothParams<T> &p, c
         sv.seek(k);
         cdouble *c = cst;
         PSSGP_LAUNDER(c);
+        const T *mk, *pk;
+        size_t st;
+        if (p.tiled) {
+            mk = p.m + tiled_index<D>(slot, p.chunk, (int)(k - k0), 0, lane);
+            pk = mk + (size_t)D * PSSGP_WAVE;
+            st = PSSGP_WAVE;
+        } else {
+            mk = p.m + k;
+            pk = p.P + k;
+            st = (size_t)p.n;
+        }
         SAgg<D, T> e;
-        smoother_element<LY, T, SV>(mdl, c, sv, p.t, p.m, p.P, p.n, k, e, bad);
+        smoother_element<LY, T, SV>(mdl, c, sv, p.t, mk, pk, st, k, e, bad);
         sagg_apply<D, T>(e, ms, Ps, ms, Ps);
         T Ph[D];
         mat_vec<D, T>(Ps, h, Ph);
-        p.f_mean[k] = dot<D, T>(h, ms);
-        p.f_var[k] = dot<D, T>(h, Ph);
+        // f outputs staged in LDS (index k - tile start) for coalesced stores
+        s_out[k - tile_start] = dot<D, T>(h, ms);
+        s_out[tile_len + (k - tile_start)] = dot<D, T>(h, Ph);
         if constexpr (FULL) {
 #pragma unroll
             for (int i = 0; i < D; i++) p.ms[(size_t)i * p.n + k] = ms[i];
@@ -131,6 +158,14 @@ __device__ __forceinline__ void smoother_tile_finish(const SmoothParams<T> &p, c
             for (int i = 0; i < D; i++)
 #pragma unroll
                 for (int j = i; j < D; j++) p.Ps[(size_t)sidx<D>(i, j) * p.n + k] = Ps[i][j];
+        }
+    }
+    __syncthreads();
+    for (int i = lane; i < tile_len; i += PSSGP_WAVE) {
+        const int64_t k = tile_start + i;
+        if (k < tr.k_end) {
+            p.f_mean[k] = s_out[i];
+            p.f_var[k] = s_out[tile_len + i];
         }
     }
     if (bad) status_or(&p.ctl->status, bad);
@@ -157,7 +192,9 @@ __global__ __launch_bounds__(PSSGP_WAVE, sizeof(T) == 4 ? PSSGP_SMOOTHER_MINW : 
     OneSeries sv;
     sv.init(mdl, p.n);
     STileRange tr{0, p.n, p.ntiles, 0};
-    smoother_tile_finish<LY, T, FULL, OneSeries>(p, mdl, (cdouble *)p.cst, sv, tr, (int)blockIdx.x);
+    extern __shared__ __align__(16) unsigned char pssgp_dyn_smem[];
+    smoother_tile_finish<LY, T, FULL, OneSeries>(p, mdl, (cdouble *)p.cst, sv, tr, (int)blockIdx.x,
+                                                 reinterpret_cast<T *>(pssgp_dyn_smem));
 }
 
 template <class LY, typename T>
@@ -178,6 +215,7 @@ int launch_smoother_t(const DevModel &mdl, const SmoothLaunch &a, hipStream_t s)
     p.inclp = (T *)a.ws.inclp;
     p.lanep = (T *)a.ws.lanep;
     p.cst = a.ws.cst;
+    p.tiled = a.tiled;
     const dim3 grid(a.ntiles), block(PSSGP_WAVE);
     pass_event(a.ev, 0, s);
     if constexpr (sizeof(T) == 4) hipLaunchKernelGGL((consts_kernel<LY>), dim3(1), dim3(256), 0, s, mdl, a.ws.cst);
@@ -188,10 +226,11 @@ int launch_smoother_t(const DevModel &mdl, const SmoothLaunch &a, hipStream_t s)
     rc = launch_tile_scan<SmootherScanOps<LY::D, T>>(a.ws.lanep, 0, 0, a.ntiles, true, a.ws.inclp, s);
     if (rc) return rc;
     pass_event(a.ev, 2, s);
+    const size_t smem = (size_t)2 * PSSGP_WAVE * a.chunk * sizeof(T);
     if (a.ms && a.Ps)
-        hipLaunchKernelGGL((smoother_finish_kernel<LY, T, true>), grid, block, 0, s, p, mdl);
+        hipLaunchKernelGGL((smoother_finish_kernel<LY, T, true>), grid, block, smem, s, p, mdl);
     else
-        hipLaunchKernelGGL((smoother_finish_kernel<LY, T, false>), grid, block, 0, s, p, mdl);
+        hipLaunchKernelGGL((smoother_finish_kernel<LY, T, false>), grid, block, smem, s, p, mdl);
     rc = (int)hipGetLastError();
     pass_event(a.ev, 3, s);
     return rc;

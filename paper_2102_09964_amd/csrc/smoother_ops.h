@@ -91,58 +91,71 @@ struct SAggLayout {
 };
 
 template <int D, typename T>
-__device__ __forceinline__ void sagg_store(T *p, const SAgg<D, T> &a)
+__device__ __forceinline__ void sagg_store(T *p, const SAgg<D, T> &a, size_t st = 1)
 {
 #pragma unroll
     for (int i = 0; i < D; i++)
 #pragma unroll
-        for (int j = 0; j < D; j++) p[i * D + j] = a.E[i][j];
+        for (int j = 0; j < D; j++) p[(size_t)(i * D + j) * st] = a.E[i][j];
 #pragma unroll
-    for (int i = 0; i < D; i++) p[D * D + i] = a.g[i];
+    for (int i = 0; i < D; i++) p[(size_t)(D * D + i) * st] = a.g[i];
 #pragma unroll
     for (int i = 0; i < D; i++)
 #pragma unroll
-        for (int j = i; j < D; j++) p[D * D + D + sidx<D>(i, j)] = a.L[i][j];
+        for (int j = i; j < D; j++) p[(size_t)(D * D + D + sidx<D>(i, j)) * st] = a.L[i][j];
 }
 
 template <int D, typename T>
-__device__ __forceinline__ void sagg_load(const T *p, SAgg<D, T> &a)
+__device__ __forceinline__ void sagg_load(const T *p, SAgg<D, T> &a, size_t st = 1)
 {
 #pragma unroll
     for (int i = 0; i < D; i++)
 #pragma unroll
-        for (int j = 0; j < D; j++) a.E[i][j] = p[i * D + j];
+        for (int j = 0; j < D; j++) a.E[i][j] = p[(size_t)(i * D + j) * st];
 #pragma unroll
-    for (int i = 0; i < D; i++) a.g[i] = p[D * D + i];
+    for (int i = 0; i < D; i++) a.g[i] = p[(size_t)(D * D + i) * st];
 #pragma unroll
     for (int i = 0; i < D; i++)
 #pragma unroll
-        for (int j = i; j < D; j++) { a.L[i][j] = p[D * D + D + sidx<D>(i, j)]; a.L[j][i] = a.L[i][j]; }
+        for (int j = i; j < D; j++) { a.L[i][j] = p[(size_t)(D * D + D + sidx<D>(i, j)) * st]; a.L[j][i] = a.L[i][j]; }
 }
 
 template <int D, typename T>
-__device__ __forceinline__ void gl_store(T *p, const T (&g)[D], const T (&L)[D][D])
+__device__ __forceinline__ void gl_store(T *p, const T (&g)[D], const T (&L)[D][D], size_t st = 1)
 {
 #pragma unroll
-    for (int i = 0; i < D; i++) p[i] = g[i];
+    for (int i = 0; i < D; i++) p[(size_t)(i) * st] = g[i];
 #pragma unroll
     for (int i = 0; i < D; i++)
 #pragma unroll
-        for (int j = i; j < D; j++) p[D + sidx<D>(i, j)] = L[i][j];
+        for (int j = i; j < D; j++) p[(size_t)(D + sidx<D>(i, j)) * st] = L[i][j];
 }
 
 template <int D, typename T>
-__device__ __forceinline__ void gl_load(const T *p, T (&g)[D], T (&L)[D][D])
+__device__ __forceinline__ void gl_load(const T *p, T (&g)[D], T (&L)[D][D], size_t st = 1)
 {
 #pragma unroll
-    for (int i = 0; i < D; i++) g[i] = p[i];
+    for (int i = 0; i < D; i++) g[i] = p[(size_t)(i) * st];
 #pragma unroll
     for (int i = 0; i < D; i++)
 #pragma unroll
-        for (int j = i; j < D; j++) { L[i][j] = p[D + sidx<D>(i, j)]; L[j][i] = L[i][j]; }
+        for (int j = i; j < D; j++) { L[i][j] = p[(size_t)(D + sidx<D>(i, j)) * st]; L[j][i] = L[i][j]; }
 }
 
-// Smoother element of step k, computed in FP64 and rounded to T:
+// Handover of the filter moments to the smoother in the tile layout (used
+// when both scans run in one call): entry e (m: 0..D-1, packed P: D..) of
+// step k0 + j of lane l of tile slot s is at
+// base[((s * chunk + j) * (D + NS) + e) * 64 + l], so that every access of a
+// wave covers 64 consecutive elements.
+template <int D>
+__device__ __forceinline__ size_t tiled_index(int slot, int chunk, int j, int e, int lane)
+{
+    return (((size_t)slot * chunk + j) * (D + D * (D + 1) / 2) + e) * 64 + lane;
+}
+
+// Smoother element of step k, computed in FP64 and rounded to T. The
+// filter moments of step k are read at mk[i * st] (m) and pk[s * st]
+// (packed P):
 //   FP = F P_k, Pp = FP F^T + Q = C C^T (Cholesky), Y = C^-1 FP,
 //   E = (C^-T Y)^T = P_k F^T Pp^-1, g = m_k - E F m_k, L = P_k - Y^T Y,
 // so that L is formed as P minus a Gram matrix (no explicit E F P). The
@@ -153,7 +166,7 @@ __device__ __forceinline__ void gl_load(const T *p, T (&g)[D], T (&L)[D][D])
 // scans the FP64 discretisation.
 template <class LY, typename T, class SV>
 __device__ __forceinline__ void smoother_element(const DevModel &mdl, cdouble *cst, const SV &sv,
-                                                 const double *t, const T *mf, const T *Pf, int64_t n, int64_t k,
+                                                 const double *t, const T *mk, const T *pk, size_t st, int64_t k,
                                                  SAgg<LY::D, T> &e, uint32_t &bad)
 {
     constexpr int D = LY::D;
@@ -170,12 +183,12 @@ __device__ __forceinline__ void smoother_element(const DevModel &mdl, cdouble *c
     }
     double m[D], P[D][D];
 #pragma unroll
-    for (int i = 0; i < D; i++) m[i] = (double)mf[(size_t)i * n + k];
+    for (int i = 0; i < D; i++) m[i] = (double)mk[(size_t)i * st];
 #pragma unroll
     for (int i = 0; i < D; i++)
 #pragma unroll
         for (int j = i; j < D; j++) {
-            P[i][j] = (double)Pf[(size_t)sidx<D>(i, j) * n + k];
+            P[i][j] = (double)pk[(size_t)sidx<D>(i, j) * st];
             P[j][i] = P[i][j];
         }
     double Fm[D], Y[D][D], C[D][D];

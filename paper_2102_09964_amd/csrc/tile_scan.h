@@ -37,7 +37,7 @@ struct FilterScanOps {
     static constexpr int AGG = AggLayout<D>::SIZE;
     static constexpr int MOM = AggLayout<D>::INCL;
     static __device__ __forceinline__ void identity(Agg &a) { agg_identity<D, T>(a); }
-    static __device__ __forceinline__ void load(const T *p, Agg &a) { agg_load<D, T>(p, a); }
+    static __device__ __forceinline__ void load(const T *p, Agg &a) { agg_load<D, T>(p, a, PSSGP_WAVE); }
     static __device__ __forceinline__ void extend(const Agg &acc, const Agg &nx, Agg &out)
     {
         agg_combine<D, T, typename CombineType<T>::type>(acc, nx, out);
@@ -60,7 +60,7 @@ struct SmootherScanOps {
     static constexpr int AGG = SAggLayout<D>::SIZE;
     static constexpr int MOM = SAggLayout<D>::INCL;
     static __device__ __forceinline__ void identity(Agg &a) { sagg_identity<D, T>(a); }
-    static __device__ __forceinline__ void load(const T *p, Agg &a) { sagg_load<D, T>(p, a); }
+    static __device__ __forceinline__ void load(const T *p, Agg &a) { sagg_load<D, T>(p, a, PSSGP_WAVE); }
     // processing order is reverse time: the next aggregate is earlier in time
     static __device__ __forceinline__ void extend(const Agg &acc, const Agg &nx, Agg &out)
     {
@@ -107,7 +107,7 @@ __global__ __launch_bounds__(PSSGP_TS_THREADS) void tile_scan_kernel(const typen
     const int per = (ntiles + PSSGP_TS_THREADS - 1) / PSSGP_TS_THREADS;
     const int i0 = min(tid * per, ntiles), i1 = min(i0 + per, ntiles);
     auto slot_of = [&](int i) { return slot_base + (reverse ? ntiles - 1 - i : i); };
-    auto agg_at = [&](int i) { return lanep + ((size_t)slot_of(i) * PSSGP_WAVE + edge_lane) * Ops::AGG; };
+    auto agg_at = [&](int i) { return lanep + ((size_t)slot_of(i) * Ops::AGG) * PSSGP_WAVE + edge_lane; };
 
     // fold of this thread's tiles, then inclusive scan over the wave
     Agg acc;

@@ -12,7 +12,7 @@ import pytest
 import workloads
 from oracle.model import MATERN12, MATERN32, MATERN52, RBF
 from tests.conftest import gpu_available
-from tests.parity import check, compare, rel, run_gpu, run_oracle
+from tests.parity import TOL, check, compare, rel, run_gpu, run_oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -167,3 +167,41 @@ def test_plain_baseline_vs_oracle(layout, n):
            "mf": g["m"].cpu().numpy().T * T[None, :],
            "Pf": P.unpack_sym(g["P"].cpu().numpy(), d) * T[None, :, None] * T[None, None, :]}
     check(compare(out, o, "float64"), "float64", "plain %s n=%d" % (layout, n))
+
+
+@pytest.mark.parametrize("layout", ["m12", "m32", "m52", "rbf6", "m32+rbf6"])
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+def test_fused_predict_vs_oracle(layout, dtype):
+    """pssgp_predict (filter and smoother in one call, moments handed over
+    in the workspace's tile layout) against the oracle, over several tiles
+    with a ragged tail and lane chunks of several lengths."""
+    comps = {"m12": [(MATERN12, 0, 0.9, 1.1)], "m32": [(MATERN32, 0, 0.7, 1.3)], "m52": [(MATERN52, 0, 1.1, 0.8)],
+             "rbf6": [(RBF, 6, 1.0, 1.0)], "m32+rbf6": [(MATERN32, 0, 2.0, 0.5), (RBF, 6, 0.5, 0.5)]}[layout]
+    n = 9000 + 37
+    w = workloads.random_series(n, comps, 0.01, missing=0.2, span=n / 200.0, gap="exponential", seed=21)
+    o = run_oracle(w, dtype, filter_moments=False)
+    model = P.make_model(comps, 0.01)
+    tol = TOL[dtype]
+    for chunk in (1, 5, 16):
+        print("fused", layout, dtype, "chunk", chunk, flush=True)
+        r = P.predict(model, w["t"], np.nan_to_num(w["y"]), w["mask"], dtype=dtype,
+                      options=P.make_options(chunk=chunk))
+        torch.cuda.synchronize()
+        errs = {"f_mean": rel(r["f_mean"].double().cpu().numpy(), o["f_mean"]),
+                "f_var": rel(r["f_var"].double().cpu().numpy(), o["f_var"]),
+                "loglik": abs(float(r["loglik"].cpu()[0]) - o["loglik"]) / abs(o["loglik"])}
+        print("  ", {k: "%.2e" % v for k, v in errs.items()}, flush=True)
+        assert P.status(r["ws"]) == 0
+        assert errs["f_mean"] <= tol["mean"] and errs["f_var"] <= tol["var"] and errs["loglik"] <= tol["loglik"], errs
+
+
+def test_fused_matches_separate_calls():
+    """The fused call and pssgp_filter + pssgp_smooth compute the same
+    arithmetic (only the layout of the handover differs): bitwise equal."""
+    w = workloads.random_series(20000, [(RBF, 6, 1.0, 1.0)], 0.01, missing=0.2, span=100.0, seed=5)
+    model = P.make_model(w["model"]["components"], 0.01)
+    a = P.predict(model, w["t"], np.nan_to_num(w["y"]), w["mask"], dtype="float32")
+    b = P.predict(model, w["t"], np.nan_to_num(w["y"]), w["mask"], dtype="float32", fused=False)
+    torch.cuda.synchronize()
+    assert torch.equal(a["f_mean"], b["f_mean"]) and torch.equal(a["f_var"], b["f_var"])
+    assert torch.equal(a["loglik"], b["loglik"])
