@@ -169,6 +169,7 @@ int launch_bf(const BatchLaunch &a, hipStream_t s)
     p.ll_terms = (double *)a.ll_terms;
     p.ctl = a.ws.ctl;
     p.inclp = (T *)a.ws.inclp;
+    p.aggp = (T *)a.ws.aggp;
     p.lanep = (T *)a.ws.lanep;
     p.partials = a.ws.partials;
     const dim3 grid(a.total_tiles), block(PSSGP_WAVE);
@@ -179,11 +180,11 @@ int launch_bf(const BatchLaunch &a, hipStream_t s)
     int rc = (int)hipGetLastError();
     if (rc) return rc;
     pass_event(a.ev, 1, s);
-    rc = launch_tile_scan<FilterScanOps<LA::D, T>>(a.ws.lanep, PSSGP_WAVE - 1, a.g[0].slot_base, a.g[0].ntiles, false,
+    rc = launch_tile_scan<FilterScanOps<LA::D, T>>(a.ws.aggp, a.g[0].slot_base, a.g[0].ntiles, false,
                                                    a.ws.inclp, s);
     if (rc) return rc;
     if (a.ngroups > 1) {
-        rc = launch_tile_scan<FilterScanOps<LB::D, T>>(a.ws.lanep, PSSGP_WAVE - 1, a.g[1].slot_base, a.g[1].ntiles,
+        rc = launch_tile_scan<FilterScanOps<LB::D, T>>(a.ws.aggp, a.g[1].slot_base, a.g[1].ntiles,
                                                        false, a.ws.inclp, s);
         if (rc) return rc;
     }
@@ -216,6 +217,7 @@ int launch_bs(const BatchLaunch &a, hipStream_t s)
     p.Ps = nullptr;
     p.ctl = a.ws.ctl;
     p.inclp = (T *)a.ws.inclp;
+    p.aggp = (T *)a.ws.aggp;
     p.lanep = (T *)a.ws.lanep;
     p.cst = a.ws.cst;
     p.tiled = 0;
@@ -227,11 +229,11 @@ int launch_bs(const BatchLaunch &a, hipStream_t s)
     int rc = (int)hipGetLastError();
     if (rc) return rc;
     pass_event(a.ev, 1, s);
-    rc = launch_tile_scan<SmootherScanOps<LA::D, T>>(a.ws.lanep, 0, a.g[0].slot_base, a.g[0].ntiles, true,
+    rc = launch_tile_scan<SmootherScanOps<LA::D, T>>(a.ws.aggp, a.g[0].slot_base, a.g[0].ntiles, true,
                                                      a.ws.inclp, s);
     if (rc) return rc;
     if (a.ngroups > 1) {
-        rc = launch_tile_scan<SmootherScanOps<LB::D, T>>(a.ws.lanep, 0, a.g[1].slot_base, a.g[1].ntiles, true,
+        rc = launch_tile_scan<SmootherScanOps<LB::D, T>>(a.ws.aggp, a.g[1].slot_base, a.g[1].ntiles, true,
                                                          a.ws.inclp, s);
         if (rc) return rc;
     }

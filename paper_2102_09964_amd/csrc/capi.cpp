@@ -22,8 +22,8 @@ size_t ctl_bytes() { return 256; }
 struct Plan {
     int d = 0, ns = 0, chunk = kDefaultChunk, ntiles = 0;
     size_t tsize = 4;
-    size_t off_incl = 0, off_lane = 0, off_part = 0, off_ck = 0, off_rec = 0, off_cst = 0;
-    size_t off_incl2 = 0, off_lane2 = 0, off_part2 = 0;
+    size_t off_incl = 0, off_lane = 0, off_part = 0, off_ck = 0, off_rec = 0, off_cst = 0, off_agg = 0;
+    size_t off_incl2 = 0, off_lane2 = 0, off_part2 = 0, off_agg2 = 0;
     size_t off_x = 0, off_xraw = 0;  // plain baseline element arrays
     size_t off_hand = 0;             // predict: filter-to-smoother handover
     size_t total = 0;
@@ -80,6 +80,7 @@ Plan make_plan(int d, int ncomp, int64_t n, pssgp_dtype dtype, int op, const pss
         // (the filter's are the larger); the handover holds the filter
         // moments of every lane chunk in the tile layout
         p.off_incl = take(nt * filter_incl_elems(d) * p.tsize);
+        p.off_agg = take(nt * filter_agg_elems(d) * p.tsize);
         p.off_lane = take(nt * 64 * filter_agg_elems(d) * p.tsize);
         p.off_part = take(nt * sizeof(double) * n_params(ncomp));
         p.off_hand = take(nt * 64 * (size_t)p.chunk * (d + d * (d + 1) / 2) * p.tsize);
@@ -88,9 +89,11 @@ Plan make_plan(int d, int ncomp, int64_t n, pssgp_dtype dtype, int op, const pss
     }
     if (op == PSSGP_OP_SMOOTH) {
         p.off_incl = take(nt * smooth_incl_elems(d) * p.tsize);
+        p.off_agg = take(nt * smooth_agg_elems(d) * p.tsize);
         p.off_lane = take(nt * 64 * smooth_agg_elems(d) * p.tsize);
     } else {
         p.off_incl = take(nt * filter_incl_elems(d) * p.tsize);
+        p.off_agg = take(nt * filter_agg_elems(d) * p.tsize);
         p.off_lane = take(nt * 64 * filter_agg_elems(d) * p.tsize);
     }
     p.off_part = take(nt * sizeof(double) * n_params(ncomp));
@@ -98,6 +101,7 @@ Plan make_plan(int d, int ncomp, int64_t n, pssgp_dtype dtype, int op, const pss
         p.off_ck = take(nt * 64 * filter_incl_elems(d) * p.tsize);
         p.off_rec = take((size_t)(n > 0 ? n : 1) * grad_rec_elems(d) * p.tsize);
         p.off_incl2 = take(nt * (d + d * (d + 1) / 2) * p.tsize);
+        p.off_agg2 = take(nt * grad_agg_elems(d) * p.tsize);
         p.off_lane2 = take(nt * 64 * grad_agg_elems(d) * p.tsize);
         p.off_part2 = take(nt * sizeof(double) * n_params(ncomp));
     }
@@ -169,6 +173,7 @@ ScanWs scan_ws(void *ws, const Plan &p, bool second = false)
     ScanWs s;
     s.ctl = (WsCtl *)b;
     s.inclp = b + (second ? p.off_incl2 : p.off_incl);
+    s.aggp = b + (second ? p.off_agg2 : p.off_agg);
     s.lanep = b + (second ? p.off_lane2 : p.off_lane);
     s.partials = (double *)(b + (second ? p.off_part2 : p.off_part));
     s.cst = (double *)(b + p.off_cst);
@@ -227,7 +232,7 @@ struct BatchPlan {
     size_t tsize = 4;
     BatchGroup g[2];
     BatchModel bm[2];
-    size_t off_incl = 0, off_lane = 0, off_part = 0, off_terms = 0, off_cst = 0, total = 0;
+    size_t off_incl = 0, off_lane = 0, off_part = 0, off_terms = 0, off_cst = 0, off_agg = 0, total = 0;
 };
 
 int make_batch_plan(const pssgp_batch_group *groups, int ngroups, int64_t n_series, const int64_t *off,
@@ -322,6 +327,7 @@ int make_batch_plan(const pssgp_batch_group *groups, int ngroups, int64_t n_seri
     const int agg = (op == PSSGP_OP_SMOOTH) ? smooth_agg_elems(d) : filter_agg_elems(d);
     const int incl = (op == PSSGP_OP_SMOOTH) ? smooth_incl_elems(d) : filter_incl_elems(d);
     bp.off_incl = take(nt * incl * bp.tsize);
+    bp.off_agg = take(nt * agg * bp.tsize);
     bp.off_lane = take(nt * 64 * agg * bp.tsize);
     bp.off_part = take(nt * sizeof(double) * 3);
     bp.off_cst = take(2 * PSSGP_CONST_DOUBLES * sizeof(double));
@@ -382,6 +388,7 @@ int run_batched(const pssgp_batch_group *groups, int ngroups, int64_t n_series, 
     a.ll_terms = bp.off_terms ? b + bp.off_terms : nullptr;
     a.ws.ctl = (WsCtl *)b;
     a.ws.inclp = b + bp.off_incl;
+    a.ws.aggp = b + bp.off_agg;
     a.ws.lanep = b + bp.off_lane;
     a.ws.partials = (double *)(b + bp.off_part);
     a.ws.cst = (double *)(b + bp.off_cst);

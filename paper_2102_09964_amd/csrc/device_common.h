@@ -22,9 +22,11 @@
 #endif
 
 // Arithmetic type of the general filtering operator (the lane, tile and
-// lane-start combinations) for scan type T.
+// lane-start combinations) for scan type T: FP64 for FP32 scans, because
+// the operator conditions one aggregate on the information of another,
+// which cancels like the covariance update when the noise is small.
 #ifndef PSSGP_COMBINE_F64
-#define PSSGP_COMBINE_F64 0
+#define PSSGP_COMBINE_F64 1
 #endif
 template <typename T>
 struct CombineType {

@@ -48,6 +48,7 @@ struct FilterParams {
     double *ll_terms;  // batched: per-step log-likelihood terms
     const double *cst;  // model constants of the FP32 transition (ConstLayout)
     WsCtl *ctl;
+    T *aggp;
     T *inclp;
     T *lanep;
     double *partials;
@@ -155,6 +156,7 @@ __device__ __forceinline__ void filter_tile_fold(const FilterParams<T> &p, const
         if (lane >= o) agg_combine<D, T, CT>(other, agg, agg);
     }
     agg_store<D, T>(lane_rec(p.lanep, slot, AGG, lane), agg, PSSGP_WAVE);
+    if (lane == PSSGP_WAVE - 1) agg_store<D, T>(p.aggp + (size_t)slot * AGG, agg);  // tile aggregate
 }
 
 // Finish pass of one tile: each lane takes the moments entering the tile
@@ -379,6 +381,7 @@ FilterParams<T> filter_params(const FilterLaunch &a)
     p.cst = a.ws.cst;
     p.ctl = a.ws.ctl;
     p.inclp = (T *)a.ws.inclp;
+    p.aggp = (T *)a.ws.aggp;
     p.lanep = (T *)a.ws.lanep;
     p.partials = a.ws.partials;
     return p;
@@ -395,7 +398,7 @@ int launch_filter_t(const DevModel &mdl, const FilterLaunch &a, hipStream_t s)
     int rc = (int)hipGetLastError();
     if (rc) return rc;
     pass_event(a.ev, 1, s);
-    rc = launch_tile_scan<FilterScanOps<LY::D, T>>(a.ws.lanep, PSSGP_WAVE - 1, 0, a.ntiles, false, a.ws.inclp, s);
+    rc = launch_tile_scan<FilterScanOps<LY::D, T>>(a.ws.aggp, 0, a.ntiles, false, a.ws.inclp, s);
     if (rc) return rc;
     pass_event(a.ev, 2, s);
     if (a.m && a.tiled)

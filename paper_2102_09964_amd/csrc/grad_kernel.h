@@ -112,7 +112,7 @@ struct AdjointScanOps {
     static constexpr int AGG = SAggLayout<D>::SIZE;
     static constexpr int MOM = SAggLayout<D>::INCL;
     static __device__ __forceinline__ void identity(Agg &a) { sagg_identity<D, T>(a); }
-    static __device__ __forceinline__ void load(const T *p, Agg &a) { sagg_load<D, T>(p, a, PSSGP_WAVE); }
+    static __device__ __forceinline__ void load(const T *p, Agg &a) { sagg_load<D, T>(p, a); }
     static __device__ __forceinline__ void extend(const Agg &acc, const Agg &nx, Agg &out)
     {
         adj_combine<D, T>(nx, acc, out);
@@ -136,6 +136,7 @@ struct GradParams {
     T *rec;
     double *grad;
     WsCtl *ctl;
+    T *aggp;
     T *inclp;
     T *lanep;
     double *partials;
@@ -270,6 +271,7 @@ __global__ __launch_bounds__(PSSGP_WAVE) void grad_fold_kernel(GradParams<T> p, 
             if (lane + o < PSSGP_WAVE) adj_combine<D, T>(agg, other, agg);
         }
         sagg_store<D, T>(lane_rec(p.lanep, tile, AGG, lane), agg, PSSGP_WAVE);
+        if (lane == 0) sagg_store<D, T>(p.aggp + (size_t)tile * AGG, agg);  // tile aggregate
     }
     (void)bad;
 }
@@ -461,13 +463,14 @@ int launch_grad_t(const DevModel &mdl, const GradLaunch &a, hipStream_t s)
     p.grad = a.grad;
     p.ctl = a.ws.ctl;
     p.inclp = (T *)a.ws.inclp;
+    p.aggp = (T *)a.ws.aggp;
     p.lanep = (T *)a.ws.lanep;
     p.partials = a.ws.partials;
     const dim3 grid(a.ntiles), block(PSSGP_WAVE);
     hipLaunchKernelGGL((grad_fold_kernel<LY, T>), grid, block, 0, s, p, mdl);
     int rc = (int)hipGetLastError();
     if (rc) return rc;
-    rc = launch_tile_scan<AdjointScanOps<LY::D, T>>(a.ws.lanep, 0, 0, a.ntiles, true, a.ws.inclp, s);
+    rc = launch_tile_scan<AdjointScanOps<LY::D, T>>(a.ws.aggp, 0, a.ntiles, true, a.ws.inclp, s);
     if (rc) return rc;
     hipLaunchKernelGGL((grad_finish_kernel<LY, T>), grid, block, 0, s, p, mdl);
     return (int)hipGetLastError();

@@ -25,6 +25,7 @@ struct WsCtl {
 // Workspace pieces of one scan launch (all device pointers).
 struct ScanWs {
     WsCtl *ctl;
+    void *aggp;      // per-tile aggregates, contiguous (read by the carry pass)
     void *inclp;     // per-tile carries (moments entering the tile)
     void *lanep;     // per-lane inclusive aggregates within the tile
     double *partials;  // per-tile partial sums (loglik, gradient)

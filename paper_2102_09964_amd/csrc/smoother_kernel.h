@@ -39,6 +39,7 @@ struct SmoothParams {
     T *ms;
     T *Ps;
     WsCtl *ctl;
+    T *aggp;
     T *inclp;
     T *lanep;
     const double *cst;  // model constants of the FP32 transition (ConstLayout)
@@ -95,6 +96,7 @@ __device__ __forceinline__ void smoother_tile_fold(const SmoothParams<T> &p, con
         if (lane + o < PSSGP_WAVE) sagg_combine<D, T>(agg, other, agg);
     }
     sagg_store<D, T>(lane_rec(p.lanep, slot, AGG, lane), agg, PSSGP_WAVE);
+    if (lane == 0) sagg_store<D, T>(p.aggp + (size_t)slot * AGG, agg);  // tile aggregate
 }
 
 // Finish pass of one tile: each lane takes the smoothed moments entering
@@ -213,6 +215,7 @@ int launch_smoother_t(const DevModel &mdl, const SmoothLaunch &a, hipStream_t s)
     p.Ps = (T *)a.Ps;
     p.ctl = a.ws.ctl;
     p.inclp = (T *)a.ws.inclp;
+    p.aggp = (T *)a.ws.aggp;
     p.lanep = (T *)a.ws.lanep;
     p.cst = a.ws.cst;
     p.tiled = a.tiled;
@@ -223,7 +226,7 @@ int launch_smoother_t(const DevModel &mdl, const SmoothLaunch &a, hipStream_t s)
     int rc = (int)hipGetLastError();
     if (rc) return rc;
     pass_event(a.ev, 1, s);
-    rc = launch_tile_scan<SmootherScanOps<LY::D, T>>(a.ws.lanep, 0, 0, a.ntiles, true, a.ws.inclp, s);
+    rc = launch_tile_scan<SmootherScanOps<LY::D, T>>(a.ws.aggp, 0, a.ntiles, true, a.ws.inclp, s);
     if (rc) return rc;
     pass_event(a.ev, 2, s);
     const size_t smem = (size_t)2 * PSSGP_WAVE * a.chunk * sizeof(T);

@@ -37,7 +37,7 @@ struct FilterScanOps {
     static constexpr int AGG = AggLayout<D>::SIZE;
     static constexpr int MOM = AggLayout<D>::INCL;
     static __device__ __forceinline__ void identity(Agg &a) { agg_identity<D, T>(a); }
-    static __device__ __forceinline__ void load(const T *p, Agg &a) { agg_load<D, T>(p, a, PSSGP_WAVE); }
+    static __device__ __forceinline__ void load(const T *p, Agg &a) { agg_load<D, T>(p, a); }
     static __device__ __forceinline__ void extend(const Agg &acc, const Agg &nx, Agg &out)
     {
         agg_combine<D, T, typename CombineType<T>::type>(acc, nx, out);
@@ -60,7 +60,7 @@ struct SmootherScanOps {
     static constexpr int AGG = SAggLayout<D>::SIZE;
     static constexpr int MOM = SAggLayout<D>::INCL;
     static __device__ __forceinline__ void identity(Agg &a) { sagg_identity<D, T>(a); }
-    static __device__ __forceinline__ void load(const T *p, Agg &a) { sagg_load<D, T>(p, a, PSSGP_WAVE); }
+    static __device__ __forceinline__ void load(const T *p, Agg &a) { sagg_load<D, T>(p, a); }
     // processing order is reverse time: the next aggregate is earlier in time
     static __device__ __forceinline__ void extend(const Agg &acc, const Agg &nx, Agg &out)
     {
@@ -88,13 +88,12 @@ __device__ __forceinline__ void agg_shfl_up_raw(const Agg &in, Agg &out, int o)
 }
 
 // Carries of tiles [slot_base, slot_base + ntiles): carry[slot] receives the
-// moments entering the tile in processing order. The aggregate of a tile is
-// the inclusive lane aggregate of lane `edge_lane` stored by the fold pass
-// (lane 63 for a prefix scan, lane 0 for a suffix scan).
+// moments entering the tile in processing order. aggp[slot] holds the tile
+// aggregate (the inclusive aggregate of its edge lane: lane 63 for a prefix
+// scan, lane 0 for a suffix scan), stored contiguously by the fold pass.
 template <class Ops>
-__global__ __launch_bounds__(PSSGP_TS_THREADS) void tile_scan_kernel(const typename Ops::T *lanep, int edge_lane,
-                                                                    int slot_base, int ntiles, int reverse,
-                                                                    typename Ops::T *carry)
+__global__ __launch_bounds__(PSSGP_TS_THREADS) void tile_scan_kernel(const typename Ops::T *aggp, int slot_base,
+                                                                    int ntiles, int reverse, typename Ops::T *carry)
 {
     using T = typename Ops::T;
     using Agg = typename Ops::Agg;
@@ -107,7 +106,7 @@ __global__ __launch_bounds__(PSSGP_TS_THREADS) void tile_scan_kernel(const typen
     const int per = (ntiles + PSSGP_TS_THREADS - 1) / PSSGP_TS_THREADS;
     const int i0 = min(tid * per, ntiles), i1 = min(i0 + per, ntiles);
     auto slot_of = [&](int i) { return slot_base + (reverse ? ntiles - 1 - i : i); };
-    auto agg_at = [&](int i) { return lanep + ((size_t)slot_of(i) * Ops::AGG) * PSSGP_WAVE + edge_lane; };
+    auto agg_at = [&](int i) { return aggp + (size_t)slot_of(i) * Ops::AGG; };
 
     // fold of this thread's tiles, then inclusive scan over the wave
     Agg acc;
@@ -154,12 +153,11 @@ __global__ __launch_bounds__(PSSGP_TS_THREADS) void tile_scan_kernel(const typen
 }
 
 template <class Ops>
-int launch_tile_scan(const void *lanep, int edge_lane, int slot_base, int ntiles, bool reverse, void *carry,
-                     hipStream_t s)
+int launch_tile_scan(const void *aggp, int slot_base, int ntiles, bool reverse, void *carry, hipStream_t s)
 {
     using T = typename Ops::T;
     if (ntiles <= 0) return 0;
-    hipLaunchKernelGGL((tile_scan_kernel<Ops>), dim3(1), dim3(PSSGP_TS_THREADS), 0, s, (const T *)lanep, edge_lane,
-                       slot_base, ntiles, reverse ? 1 : 0, (T *)carry);
+    hipLaunchKernelGGL((tile_scan_kernel<Ops>), dim3(1), dim3(PSSGP_TS_THREADS), 0, s, (const T *)aggp, slot_base,
+                       ntiles, reverse ? 1 : 0, (T *)carry);
     return (int)hipGetLastError();
 }
