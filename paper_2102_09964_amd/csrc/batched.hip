@@ -98,9 +98,9 @@ __global__ __launch_bounds__(PSSGP_WAVE) void batched_filter_kernel(FilterParams
             filter_tile_finish<LB, T, typename CombineType<T>::type, F_MOMENTS, ManySeries>(p, mdl, cst, sv, tr, tile, ll);
     } else {
         if (gi == 0)
-            filter_tile_fold<LA, T, typename CombineType<T>::type, ManySeries>(p, mdl, cst, sv, tr, tile);
+            filter_tile_fold<LA, T, T, ManySeries>(p, mdl, cst, sv, tr, tile);
         else
-            filter_tile_fold<LB, T, typename CombineType<T>::type, ManySeries>(p, mdl, cst, sv, tr, tile);
+            filter_tile_fold<LB, T, T, ManySeries>(p, mdl, cst, sv, tr, tile);
     }
 }
 
@@ -125,14 +125,14 @@ __global__ __launch_bounds__(PSSGP_WAVE) void batched_smoother_kernel(SmoothPara
         extern __shared__ __align__(16) unsigned char pssgp_dyn_smem[];
         T *s_out = reinterpret_cast<T *>(pssgp_dyn_smem);
         if (gi == 0)
-            smoother_tile_finish<LA, T, false, ManySeries>(p, mdl, cst, sv, tr, tile, s_out);
+            smoother_tile_finish<LA, T, false, false, ManySeries>(p, mdl, cst, sv, tr, tile, s_out);
         else
-            smoother_tile_finish<LB, T, false, ManySeries>(p, mdl, cst, sv, tr, tile, s_out);
+            smoother_tile_finish<LB, T, false, false, ManySeries>(p, mdl, cst, sv, tr, tile, s_out);
     } else {
         if (gi == 0)
-            smoother_tile_fold<LA, T, ManySeries>(p, mdl, cst, sv, tr, tile);
+            smoother_tile_fold<LA, T, false, ManySeries>(p, mdl, cst, sv, tr, tile);
         else
-            smoother_tile_fold<LB, T, ManySeries>(p, mdl, cst, sv, tr, tile);
+            smoother_tile_fold<LB, T, false, ManySeries>(p, mdl, cst, sv, tr, tile);
     }
 }
 
@@ -220,7 +220,6 @@ int launch_bs(const BatchLaunch &a, hipStream_t s)
     p.aggp = (T *)a.ws.aggp;
     p.lanep = (T *)a.ws.lanep;
     p.cst = a.ws.cst;
-    p.tiled = 0;
     const dim3 grid(a.total_tiles), block(PSSGP_WAVE);
     pass_event(a.ev, 0, s);
     if constexpr (sizeof(T) == 4)

@@ -77,13 +77,13 @@ Plan make_plan(int d, int ncomp, int64_t n, pssgp_dtype dtype, int op, const pss
     p.off_cst = take(PSSGP_CONST_DOUBLES * sizeof(double));
     if (op == PSSGP_OP_PREDICT) {
         // filter then smoother on one stream: the scans share their regions
-        // (the filter's are the larger); the handover holds the filter
-        // moments of every lane chunk in the tile layout
+        // (the filter's are the larger); the handover holds the smoother
+        // elements of every step, written by the filter in the tile layout
         p.off_incl = take(nt * filter_incl_elems(d) * p.tsize);
         p.off_agg = take(nt * filter_agg_elems(d) * p.tsize);
         p.off_lane = take(nt * 64 * filter_agg_elems(d) * p.tsize);
         p.off_part = take(nt * sizeof(double) * n_params(ncomp));
-        p.off_hand = take(nt * 64 * (size_t)p.chunk * (d + d * (d + 1) / 2) * p.tsize);
+        p.off_hand = take(nt * 64 * (size_t)p.chunk * (d * d + d + d * (d + 1) / 2) * p.tsize);
         p.total = off;
         return p;
     }

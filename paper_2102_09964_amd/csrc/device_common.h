@@ -21,10 +21,12 @@
 #define PSSGP_SMOOTHER_MINW 2
 #endif
 
-// Arithmetic type of the general filtering operator (the lane, tile and
-// lane-start combinations) for scan type T: FP64 for FP32 scans, because
-// the operator conditions one aggregate on the information of another,
-// which cancels like the covariance update when the noise is small.
+// Arithmetic type of the general filtering operator where it is applied
+// once per lane or tile (the carry scan and the lane-start moments): FP64
+// for FP32 scans, because the operator conditions one aggregate on the
+// information of another, which cancels like the covariance update when
+// the noise is small. The lane scan of the fold pass (six combinations per
+// lane) runs in the scan type.
 #ifndef PSSGP_COMBINE_F64
 #define PSSGP_COMBINE_F64 1
 #endif

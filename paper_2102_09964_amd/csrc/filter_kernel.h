@@ -28,9 +28,9 @@
 #include "tile_scan.h"
 
 // Finish-pass outputs: filter moments in the [entry][n] layout, per-chunk
-// checkpoints for the adjoint, filter moments in the tile layout for the
+// checkpoints for the adjoint, smoother elements in the tile layout for the
 // smoother of the same call.
-enum : int { F_MOMENTS = 1, F_CKPT = 2, F_TILED = 4 };
+enum : int { F_MOMENTS = 1, F_CKPT = 2, F_ELEMS = 4 };
 
 template <typename T>
 struct FilterParams {
@@ -107,6 +107,96 @@ struct StepInputs {
         }
     }
 };
+
+// Smoother element of step k (supplement, Proposition 2), emitted by the
+// filter right after predicting step k + 1, from what that prediction
+// already holds: the filtered moments (m, P) of step k, X = (F - I) P,
+// mp = F m and Pp = F P F^T + Q of step k + 1. In FP64:
+//   Pp = C C^T (Cholesky), Y = C^-1 F P, L = P - Y^T Y,
+//   E = (C^-T Y)^T = P F^T Pp^-1, g = m - E mp.
+// At the last step of a series the caller passes the prior transition
+// (F = 0, Q = Pinf), for which these give exactly the element (0, m, P).
+// The element is stored as (E row-major, g, L packed) with field stride st.
+template <int D, typename T>
+__device__ __forceinline__ void emit_smoother_element(const T (&m)[D], const T (&P)[D][D], const T (&X)[D][D],
+                                                      const T (&mp)[D], const T (&Pp)[D][D], T *out, size_t st,
+                                                      uint32_t &bad)
+{
+    double C[D][D], Y[D][D];
+#pragma unroll
+    for (int i = 0; i < D; i++)
+#pragma unroll
+        for (int j = 0; j < D; j++) {
+            C[i][j] = (double)Pp[i][j];
+            Y[i][j] = (double)P[i][j] + (double)X[i][j];
+        }
+    if (!cholesky<D, double>(C)) bad |= PSSGP_STATUS_CHOLESKY;
+#pragma unroll
+    for (int j = 0; j < D; j++)
+#pragma unroll
+        for (int i = 0; i < D; i++) {
+            double acc = Y[i][j];
+#pragma unroll
+            for (int q = 0; q < i; q++) acc = fma(-C[i][q], Y[q][j], acc);
+            Y[i][j] = acc / C[i][i];
+        }
+    constexpr int NS = D * (D + 1) / 2;
+#pragma unroll
+    for (int i = 0; i < D; i++)
+#pragma unroll
+        for (int j = i; j < D; j++) {
+            double acc = (double)P[i][j];
+#pragma unroll
+            for (int q = 0; q < D; q++) acc = fma(-Y[q][i], Y[q][j], acc);
+            out[(size_t)(D * D + D + sidx<D>(i, j)) * st] = T(acc);
+        }
+#pragma unroll
+    for (int j = 0; j < D; j++)
+#pragma unroll
+        for (int i = D - 1; i >= 0; i--) {
+            double acc = Y[i][j];
+#pragma unroll
+            for (int q = i + 1; q < D; q++) acc = fma(-C[q][i], Y[q][j], acc);
+            Y[i][j] = acc / C[i][i];
+        }
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+        double acc = (double)m[i];
+#pragma unroll
+        for (int q = 0; q < D; q++) acc = fma(-Y[q][i], (double)mp[q], acc);
+        out[(size_t)(D * D + i) * st] = T(acc);
+#pragma unroll
+        for (int j = 0; j < D; j++) out[(size_t)(i * D + j) * st] = T(Y[j][i]);
+    }
+    (void)NS;
+}
+
+// Predicted moments of one step from (m, P) with Dl = F - I:
+// mp = m + Dl m, X = Dl P, Pp = P + X + X^T + X Dl^T + Q.
+template <int D, typename T>
+__device__ __forceinline__ void predict_step(const T (&m)[D], const T (&P)[D][D], const T (&Dl)[D][D],
+                                             const T (&Q)[D][D], T (&mp)[D], T (&X)[D][D], T (&Pp)[D][D])
+{
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+        T acc = m[i];
+#pragma unroll
+        for (int k2 = 0; k2 < D; k2++) acc = fma(Dl[i][k2], m[k2], acc);
+        mp[i] = acc;
+    }
+    mat_mul<D, T>(Dl, P, X);
+#pragma unroll
+    for (int i = 0; i < D; i++)
+#pragma unroll
+        for (int j = i; j < D; j++) {
+            T acc = T(0);
+#pragma unroll
+            for (int k2 = 0; k2 < D; k2++) acc = fma(X[i][k2], Dl[j][k2], acc);
+            const T c = P[i][j] + ((X[i][j] + X[j][i]) + acc) + Q[i][j];
+            Pp[i][j] = c;
+            Pp[j][i] = c;
+        }
+}
 
 // Fold pass of one tile: each lane folds its chunk into an aggregate, the
 // wave scans the 64 chunk aggregates (inclusive, time order) and stores them
@@ -221,25 +311,14 @@ __device__ __forceinline__ void filter_tile_finish(const FilterParams<T> &p, con
         in.oc = on;
         // predict with Dl = F - I: mp = m + Dl m, Pp = P + X + X^T + X Dl^T + Q
         T mp[D], X[D][D], Pp[D][D];
-#pragma unroll
-        for (int i = 0; i < D; i++) {
-            T acc = m[i];
-#pragma unroll
-            for (int k2 = 0; k2 < D; k2++) acc = fma(Dl[i][k2], m[k2], acc);
-            mp[i] = acc;
+        predict_step<D, T>(m, P, Dl, Q, mp, X, Pp);
+        if constexpr ((MODE & F_ELEMS) != 0) {
+            // smoother element of the previous step of this lane
+            if (k > k0)
+                emit_smoother_element<D, T>(m, P, X, mp, Pp,
+                                            p.m + elem_index<D>(slot, p.chunk, (int)(k - 1 - k0), lane),
+                                            PSSGP_WAVE, bad);
         }
-        mat_mul<D, T>(Dl, P, X);
-#pragma unroll
-        for (int i = 0; i < D; i++)
-#pragma unroll
-            for (int j = i; j < D; j++) {
-                T acc = T(0);
-#pragma unroll
-                for (int k2 = 0; k2 < D; k2++) acc = fma(X[i][k2], Dl[j][k2], acc);
-                const T c = P[i][j] + ((X[i][j] + X[j][i]) + acc) + Q[i][j];
-                Pp[i][j] = c;
-                Pp[j][i] = c;
-            }
         // conditioning on y_k in FP64 (symmetric form), from the predicted
         // moments in T: the subtraction that cancels when the noise is
         // small against the predicted variance is done in FP64
@@ -275,15 +354,6 @@ __device__ __forceinline__ void filter_tile_finish(const FilterParams<T> &p, con
                 P[i][j] = c;
                 P[j][i] = c;
             }
-        if constexpr ((MODE & F_TILED) != 0) {
-            T *b = p.m + tiled_index<D>(slot, p.chunk, (int)(k - k0), 0, lane);
-#pragma unroll
-            for (int i = 0; i < D; i++) b[(size_t)i * PSSGP_WAVE] = m[i];
-#pragma unroll
-            for (int i = 0; i < D; i++)
-#pragma unroll
-                for (int j = i; j < D; j++) b[(size_t)(D + sidx<D>(i, j)) * PSSGP_WAVE] = P[i][j];
-        }
         if constexpr ((MODE & F_MOMENTS) != 0) {
 #pragma unroll
             for (int i = 0; i < D; i++) p.m[(size_t)i * p.n + k] = m[i];
@@ -293,10 +363,28 @@ __device__ __forceinline__ void filter_tile_finish(const FilterParams<T> &p, con
                 for (int j = i; j < D; j++) p.P[(size_t)sidx<D>(i, j) * p.n + k] = P[i][j];
         }
     }
+    if constexpr ((MODE & F_ELEMS) != 0) {
+        // element of the lane's last step: predict the next step (the first of
+        // the next lane), or take the prior transition at a series end
+        if (k1 > k0) {
+            sv.seek(k1 - 1);
+            const bool end = (k1 >= tr.k_end) || sv.last(k1 - 1);
+            const double dt = end ? 0.0 : p.t[k1] - p.t[k1 - 1];
+            cdouble *c = cst;
+            PSSGP_LAUNDER(c);
+            T Dl[D][D], Q[D][D], mp[D], X[D][D], Pp[D][D];
+            step_transition<LY, T>(mdl, c, sv.sc, dt, end, Dl, Q);
+            predict_step<D, T>(m, P, Dl, Q, mp, X, Pp);
+            emit_smoother_element<D, T>(m, P, X, mp, Pp,
+                                        p.m + elem_index<D>(slot, p.chunk, (int)(k1 - 1 - k0), lane), PSSGP_WAVE,
+                                        bad);
+        }
+    }
     if (bad) status_or(&p.ctl->status, bad);
     ll_out = ll;
 }
 
+// CT: arithmetic type of the lane scan's combinations
 template <class LY, typename T, typename CT>
 __global__ __launch_bounds__(PSSGP_WAVE, sizeof(T) == 4 ? PSSGP_FILTER_MINW : 1) void filter_fold_kernel(FilterParams<T> p, DevModel mdl_arg)
 {
@@ -394,7 +482,7 @@ int launch_filter_t(const DevModel &mdl, const FilterLaunch &a, hipStream_t s)
     const dim3 grid(a.ntiles), block(PSSGP_WAVE);
     pass_event(a.ev, 0, s);
     if constexpr (sizeof(T) == 4) hipLaunchKernelGGL((consts_kernel<LY>), dim3(1), dim3(256), 0, s, mdl, a.ws.cst);
-    hipLaunchKernelGGL((filter_fold_kernel<LY, T, CT>), grid, block, 0, s, p, mdl);
+    hipLaunchKernelGGL((filter_fold_kernel<LY, T, T>), grid, block, 0, s, p, mdl);
     int rc = (int)hipGetLastError();
     if (rc) return rc;
     pass_event(a.ev, 1, s);
@@ -402,7 +490,7 @@ int launch_filter_t(const DevModel &mdl, const FilterLaunch &a, hipStream_t s)
     if (rc) return rc;
     pass_event(a.ev, 2, s);
     if (a.m && a.tiled)
-        hipLaunchKernelGGL((filter_finish_kernel<LY, T, CT, F_TILED>), grid, block, 0, s, p, mdl);
+        hipLaunchKernelGGL((filter_finish_kernel<LY, T, CT, F_ELEMS>), grid, block, 0, s, p, mdl);
     else if (a.m)
         hipLaunchKernelGGL((filter_finish_kernel<LY, T, CT, F_MOMENTS>), grid, block, 0, s, p, mdl);
     else if (a.ck)

@@ -45,7 +45,7 @@ struct FilterLaunch {
     void *P;         // nullable
     double *loglik;  // nullable
     void *ck;        // nullable: per-chunk checkpoints of the start moments
-    int tiled;       // write m (P unused) in the tile layout of the handover
+    int tiled;       // write smoother elements to m (P unused) in the tile layout of the handover
     ScanWs ws;
 };
 
@@ -61,7 +61,7 @@ struct SmoothLaunch {
     void *f_var;
     void *ms;  // nullable
     void *Ps;  // nullable
-    int tiled; // m holds the filter moments in the tile layout (P unused)
+    int tiled; // m holds the smoother elements in the tile layout (P unused)
     ScanWs ws;
 };
 

@@ -43,7 +43,6 @@ struct SmoothParams {
     T *inclp;
     T *lanep;
     const double *cst;  // model constants of the FP32 transition (ConstLayout)
-    int tiled;          // m holds the filter moments in the tile layout (P unused)
 };
 
 struct STileRange {
@@ -56,7 +55,7 @@ struct STileRange {
 // right, the wave scans the 64 chunk aggregates as suffixes (inclusive,
 // reverse time order) and stores them at lanep; lane 0 then holds the tile
 // aggregate.
-template <class LY, typename T, class SV>
+template <class LY, typename T, bool ELEMS, class SV>
 __device__ __forceinline__ void smoother_tile_fold(const SmoothParams<T> &p, const DevModel &mdl,
                                                    cdouble *cst, SV &sv, const STileRange &tr, int tile)
 {
@@ -73,21 +72,14 @@ __device__ __forceinline__ void smoother_tile_fold(const SmoothParams<T> &p, con
     for (int64_t k = k1 - 1; k >= k0; k--) {
         PSSGP_RELOAD_CONSTANTS();
         sv.seek(k);
-        cdouble *c = cst;
-        PSSGP_LAUNDER(c);
-        const T *mk, *pk;
-        size_t st;
-        if (p.tiled) {
-            mk = p.m + tiled_index<D>(slot, p.chunk, (int)(k - k0), 0, lane);
-            pk = mk + (size_t)D * PSSGP_WAVE;
-            st = PSSGP_WAVE;
-        } else {
-            mk = p.m + k;
-            pk = p.P + k;
-            st = (size_t)p.n;
-        }
         SAgg<D, T> e;
-        smoother_element<LY, T, SV>(mdl, c, sv, p.t, mk, pk, st, k, e, bad);
+        if constexpr (ELEMS) {
+            sagg_load<D, T>(p.m + elem_index<D>(slot, p.chunk, (int)(k - k0), lane), e, PSSGP_WAVE);
+        } else {
+            cdouble *c = cst;
+            PSSGP_LAUNDER(c);
+            smoother_element<LY, T, SV>(mdl, c, sv, p.t, p.m + k, p.P + k, (size_t)p.n, k, e, bad);
+        }
         sagg_combine<D, T>(e, agg, agg);
     }
     for (int o = 1; o < PSSGP_WAVE; o <<= 1) {
@@ -102,7 +94,7 @@ __device__ __forceinline__ void smoother_tile_fold(const SmoothParams<T> &p, con
 // Finish pass of one tile: each lane takes the smoothed moments entering
 // the tile from the right (carry pass), applies its exclusive lane suffix
 // and runs the backward RTS recursion over its chunk.
-template <class LY, typename T, bool FULL, class SV>
+template <class LY, typename T, bool FULL, bool ELEMS, class SV>
 __device__ __forceinline__ void smoother_tile_finish(const SmoothParams<T> &p, const DevModel &mdl,
                                                      cdouble *cst, SV &sv, const STileRange &tr, int tile,
                                                      T *s_out)
@@ -132,21 +124,14 @@ __device__ __forceinline__ void smoother_tile_finish(const SmoothParams<T> &p, c
     for (int64_t k = k1 - 1; k >= k0; k--) {
         PSSGP_RELOAD_CONSTANTS();
         sv.seek(k);
-        cdouble *c = cst;
-        PSSGP_LAUNDER(c);
-        const T *mk, *pk;
-        size_t st;
-        if (p.tiled) {
-            mk = p.m + tiled_index<D>(slot, p.chunk, (int)(k - k0), 0, lane);
-            pk = mk + (size_t)D * PSSGP_WAVE;
-            st = PSSGP_WAVE;
-        } else {
-            mk = p.m + k;
-            pk = p.P + k;
-            st = (size_t)p.n;
-        }
         SAgg<D, T> e;
-        smoother_element<LY, T, SV>(mdl, c, sv, p.t, mk, pk, st, k, e, bad);
+        if constexpr (ELEMS) {
+            sagg_load<D, T>(p.m + elem_index<D>(slot, p.chunk, (int)(k - k0), lane), e, PSSGP_WAVE);
+        } else {
+            cdouble *c = cst;
+            PSSGP_LAUNDER(c);
+            smoother_element<LY, T, SV>(mdl, c, sv, p.t, p.m + k, p.P + k, (size_t)p.n, k, e, bad);
+        }
         sagg_apply<D, T>(e, ms, Ps, ms, Ps);
         T Ph[D];
         mat_vec<D, T>(Ps, h, Ph);
@@ -173,7 +158,9 @@ __device__ __forceinline__ void smoother_tile_finish(const SmoothParams<T> &p, c
     if (bad) status_or(&p.ctl->status, bad);
 }
 
-template <class LY, typename T>
+// ELEMS: the smoother elements come from the filter of the same call (tile
+// layout at p.m) instead of being built from the filter moments.
+template <class LY, typename T, bool ELEMS>
 __global__ __launch_bounds__(PSSGP_WAVE, sizeof(T) == 4 ? PSSGP_SMOOTHER_MINW : 1) void smoother_fold_kernel(SmoothParams<T> p,
                                                                                            DevModel mdl_arg)
 {
@@ -182,10 +169,10 @@ __global__ __launch_bounds__(PSSGP_WAVE, sizeof(T) == 4 ? PSSGP_SMOOTHER_MINW : 
     OneSeries sv;
     sv.init(mdl, p.n);
     STileRange tr{0, p.n, p.ntiles, 0};
-    smoother_tile_fold<LY, T, OneSeries>(p, mdl, (cdouble *)p.cst, sv, tr, (int)blockIdx.x);
+    smoother_tile_fold<LY, T, ELEMS, OneSeries>(p, mdl, (cdouble *)p.cst, sv, tr, (int)blockIdx.x);
 }
 
-template <class LY, typename T, bool FULL>
+template <class LY, typename T, bool FULL, bool ELEMS>
 __global__ __launch_bounds__(PSSGP_WAVE, sizeof(T) == 4 ? PSSGP_SMOOTHER_MINW : 1) void smoother_finish_kernel(SmoothParams<T> p,
                                                                                              DevModel mdl_arg)
 {
@@ -195,8 +182,8 @@ __global__ __launch_bounds__(PSSGP_WAVE, sizeof(T) == 4 ? PSSGP_SMOOTHER_MINW : 
     sv.init(mdl, p.n);
     STileRange tr{0, p.n, p.ntiles, 0};
     extern __shared__ __align__(16) unsigned char pssgp_dyn_smem[];
-    smoother_tile_finish<LY, T, FULL, OneSeries>(p, mdl, (cdouble *)p.cst, sv, tr, (int)blockIdx.x,
-                                                 reinterpret_cast<T *>(pssgp_dyn_smem));
+    smoother_tile_finish<LY, T, FULL, ELEMS, OneSeries>(p, mdl, (cdouble *)p.cst, sv, tr, (int)blockIdx.x,
+                                                        reinterpret_cast<T *>(pssgp_dyn_smem));
 }
 
 template <class LY, typename T>
@@ -218,11 +205,15 @@ int launch_smoother_t(const DevModel &mdl, const SmoothLaunch &a, hipStream_t s)
     p.aggp = (T *)a.ws.aggp;
     p.lanep = (T *)a.ws.lanep;
     p.cst = a.ws.cst;
-    p.tiled = a.tiled;
     const dim3 grid(a.ntiles), block(PSSGP_WAVE);
     pass_event(a.ev, 0, s);
-    if constexpr (sizeof(T) == 4) hipLaunchKernelGGL((consts_kernel<LY>), dim3(1), dim3(256), 0, s, mdl, a.ws.cst);
-    hipLaunchKernelGGL((smoother_fold_kernel<LY, T>), grid, block, 0, s, p, mdl);
+    if (a.tiled) {
+        // elements from the filter of the same call: no transition needed
+        hipLaunchKernelGGL((smoother_fold_kernel<LY, T, true>), grid, block, 0, s, p, mdl);
+    } else {
+        if constexpr (sizeof(T) == 4) hipLaunchKernelGGL((consts_kernel<LY>), dim3(1), dim3(256), 0, s, mdl, a.ws.cst);
+        hipLaunchKernelGGL((smoother_fold_kernel<LY, T, false>), grid, block, 0, s, p, mdl);
+    }
     int rc = (int)hipGetLastError();
     if (rc) return rc;
     pass_event(a.ev, 1, s);
@@ -230,10 +221,12 @@ int launch_smoother_t(const DevModel &mdl, const SmoothLaunch &a, hipStream_t s)
     if (rc) return rc;
     pass_event(a.ev, 2, s);
     const size_t smem = (size_t)2 * PSSGP_WAVE * a.chunk * sizeof(T);
-    if (a.ms && a.Ps)
-        hipLaunchKernelGGL((smoother_finish_kernel<LY, T, true>), grid, block, smem, s, p, mdl);
+    if (a.tiled)
+        hipLaunchKernelGGL((smoother_finish_kernel<LY, T, false, true>), grid, block, smem, s, p, mdl);
+    else if (a.ms && a.Ps)
+        hipLaunchKernelGGL((smoother_finish_kernel<LY, T, true, false>), grid, block, smem, s, p, mdl);
     else
-        hipLaunchKernelGGL((smoother_finish_kernel<LY, T, false>), grid, block, smem, s, p, mdl);
+        hipLaunchKernelGGL((smoother_finish_kernel<LY, T, false, false>), grid, block, smem, s, p, mdl);
     rc = (int)hipGetLastError();
     pass_event(a.ev, 3, s);
     return rc;

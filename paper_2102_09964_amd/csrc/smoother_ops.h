@@ -142,15 +142,15 @@ __device__ __forceinline__ void gl_load(const T *p, T (&g)[D], T (&L)[D][D], siz
         for (int j = i; j < D; j++) { L[i][j] = p[(size_t)(D + sidx<D>(i, j)) * st]; L[j][i] = L[i][j]; }
 }
 
-// Handover of the filter moments to the smoother in the tile layout (used
-// when both scans run in one call): entry e (m: 0..D-1, packed P: D..) of
-// step k0 + j of lane l of tile slot s is at
-// base[((s * chunk + j) * (D + NS) + e) * 64 + l], so that every access of a
-// wave covers 64 consecutive elements.
+// Handover from the filter to the smoother when both scans run in one
+// call: the smoother elements of step k0 + j of lane l of tile slot s are
+// stored at base[((s * chunk + j) * SIZE + field) * 64 + l] (SIZE = D^2 +
+// D + NS fields: E row-major, g, packed L), so that every access of a wave
+// covers 64 consecutive elements.
 template <int D>
-__device__ __forceinline__ size_t tiled_index(int slot, int chunk, int j, int e, int lane)
+__device__ __forceinline__ size_t elem_index(int slot, int chunk, int j, int lane)
 {
-    return (((size_t)slot * chunk + j) * (D + D * (D + 1) / 2) + e) * 64 + lane;
+    return ((size_t)slot * chunk + j) * (D * D + D + D * (D + 1) / 2) * 64 + lane;
 }
 
 // Smoother element of step k, computed in FP64 and rounded to T. The
