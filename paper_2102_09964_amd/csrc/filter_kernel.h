@@ -62,13 +62,13 @@ struct TileRange {
     int slot_base;
 };
 
-// Transition of a step in the scan type: Dl = F - I (F = 0 at a series
-// start, so Dl = -I there) and Q. FP32 scans use the pair expansion of Q
-// with the constants at cst; FP64 scans the FP64 discretisation.
-template <class LY, typename T>
+// Transition of a step, Dl = F - I (F = 0 at a series start, so Dl = -I
+// there) and Q, rounded to U: for FP32 scans (T) by the pair expansion of
+// Q with the constants at cst, for FP64 scans by the FP64 discretisation.
+template <class LY, typename U, typename T = U>
 __device__ __forceinline__ void step_transition(const DevModel &mdl, cdouble *cst, const StepScale &sc,
-                                                double dt, bool first, T (&Dl)[LY::D][LY::D],
-                                                T (&Q)[LY::D][LY::D])
+                                                double dt, bool first, U (&Dl)[LY::D][LY::D],
+                                                U (&Q)[LY::D][LY::D])
 {
     constexpr int D = LY::D;
     if constexpr (sizeof(T) == 8) {
@@ -78,11 +78,11 @@ __device__ __forceinline__ void step_transition(const DevModel &mdl, cdouble *cs
         for (int i = 0; i < D; i++)
 #pragma unroll
             for (int j = 0; j < D; j++) {
-                Dl[i][j] = T(F64[i][j] - (i == j ? 1.0 : 0.0));
-                Q[i][j] = T(Q64[i][j]);
+                Dl[i][j] = U(F64[i][j] - (i == j ? 1.0 : 0.0));
+                Q[i][j] = U(Q64[i][j]);
             }
     } else {
-        discretize_fast<LY, T>(mdl, cst, sc, dt, first, Dl, Q);
+        discretize_fast<LY, U>(mdl, cst, sc, dt, first, Dl, Q);
     }
 }
 
@@ -110,26 +110,24 @@ struct StepInputs {
 
 // Smoother element of step k (supplement, Proposition 2), emitted by the
 // filter right after predicting step k + 1, from what that prediction
-// already holds: the filtered moments (m, P) of step k, X = (F - I) P,
-// mp = F m and Pp = F P F^T + Q of step k + 1. In FP64:
+// already holds: the filtered moments (m, P) of step k and, in FP64,
+// Y = F P, mp = F m and Pp = F P F^T + Q of step k + 1:
 //   Pp = C C^T (Cholesky), Y = C^-1 F P, L = P - Y^T Y,
 //   E = (C^-T Y)^T = P F^T Pp^-1, g = m - E mp.
 // At the last step of a series the caller passes the prior transition
 // (F = 0, Q = Pinf), for which these give exactly the element (0, m, P).
 // The element is stored as (E row-major, g, L packed) with field stride st.
 template <int D, typename T>
-__device__ __forceinline__ void emit_smoother_element(const T (&m)[D], const T (&P)[D][D], const T (&X)[D][D],
-                                                      const T (&mp)[D], const T (&Pp)[D][D], T *out, size_t st,
-                                                      uint32_t &bad)
+__device__ __forceinline__ void emit_smoother_element(const T (&m)[D], const T (&P)[D][D], double (&Y)[D][D],
+                                                      const double (&mp)[D], const double (&Pp)[D][D], T *out,
+                                                      size_t st, uint32_t &bad)
 {
-    double C[D][D], Y[D][D];
+    // Y holds F P on entry and is overwritten
+    double C[D][D];
 #pragma unroll
     for (int i = 0; i < D; i++)
 #pragma unroll
-        for (int j = 0; j < D; j++) {
-            C[i][j] = (double)Pp[i][j];
-            Y[i][j] = (double)P[i][j] + (double)X[i][j];
-        }
+        for (int j = 0; j <= i; j++) C[i][j] = Pp[i][j];
     if (!cholesky<D, double>(C)) bad |= PSSGP_STATUS_CHOLESKY;
 #pragma unroll
     for (int j = 0; j < D; j++)
@@ -140,7 +138,6 @@ __device__ __forceinline__ void emit_smoother_element(const T (&m)[D], const T (
             for (int q = 0; q < i; q++) acc = fma(-C[i][q], Y[q][j], acc);
             Y[i][j] = acc / C[i][i];
         }
-    constexpr int NS = D * (D + 1) / 2;
 #pragma unroll
     for (int i = 0; i < D; i++)
 #pragma unroll
@@ -163,38 +160,46 @@ __device__ __forceinline__ void emit_smoother_element(const T (&m)[D], const T (
     for (int i = 0; i < D; i++) {
         double acc = (double)m[i];
 #pragma unroll
-        for (int q = 0; q < D; q++) acc = fma(-Y[q][i], (double)mp[q], acc);
+        for (int q = 0; q < D; q++) acc = fma(-Y[q][i], mp[q], acc);
         out[(size_t)(D * D + i) * st] = T(acc);
 #pragma unroll
         for (int j = 0; j < D; j++) out[(size_t)(i * D + j) * st] = T(Y[j][i]);
     }
-    (void)NS;
 }
 
-// Predicted moments of one step from (m, P) with Dl = F - I:
-// mp = m + Dl m, X = Dl P, Pp = P + X + X^T + X Dl^T + Q.
+// Predicted moments of one step in FP64 from (m, P) in T and the FP64
+// transition Dl = F - I, Q: mp = m + Dl m, Y = F P = P + Dl P,
+// Pp = Y F^T + Q = Y + Y Dl^T + Q. FP64 keeps Pp consistent with P to
+// the precision the smoother element needs (its L is P minus a Gram matrix
+// that nearly equals P when Q is small).
 template <int D, typename T>
-__device__ __forceinline__ void predict_step(const T (&m)[D], const T (&P)[D][D], const T (&Dl)[D][D],
-                                             const T (&Q)[D][D], T (&mp)[D], T (&X)[D][D], T (&Pp)[D][D])
+__device__ __forceinline__ void predict_step(const T (&m)[D], const T (&P)[D][D], const double (&Dl)[D][D],
+                                             const double (&Q)[D][D], double (&mp)[D], double (&Y)[D][D],
+                                             double (&Pp)[D][D])
 {
 #pragma unroll
     for (int i = 0; i < D; i++) {
-        T acc = m[i];
+        double acc = (double)m[i];
 #pragma unroll
-        for (int k2 = 0; k2 < D; k2++) acc = fma(Dl[i][k2], m[k2], acc);
+        for (int k2 = 0; k2 < D; k2++) acc = fma(Dl[i][k2], (double)m[k2], acc);
         mp[i] = acc;
+#pragma unroll
+        for (int j = 0; j < D; j++) {
+            double y = (double)P[i][j];
+#pragma unroll
+            for (int k2 = 0; k2 < D; k2++) y = fma(Dl[i][k2], (double)P[k2][j], y);
+            Y[i][j] = y;
+        }
     }
-    mat_mul<D, T>(Dl, P, X);
 #pragma unroll
     for (int i = 0; i < D; i++)
 #pragma unroll
         for (int j = i; j < D; j++) {
-            T acc = T(0);
+            double acc = Y[i][j] + Q[i][j];
 #pragma unroll
-            for (int k2 = 0; k2 < D; k2++) acc = fma(X[i][k2], Dl[j][k2], acc);
-            const T c = P[i][j] + ((X[i][j] + X[j][i]) + acc) + Q[i][j];
-            Pp[i][j] = c;
-            Pp[j][i] = c;
+            for (int k2 = 0; k2 < D; k2++) acc = fma(Y[i][k2], Dl[j][k2], acc);
+            Pp[i][j] = acc;
+            Pp[j][i] = acc;
         }
 }
 
@@ -232,7 +237,7 @@ __device__ __forceinline__ void filter_tile_fold(const FilterParams<T> &p, const
         cdouble *c = cst;
         PSSGP_LAUNDER(c);
         T Dl[D][D], Q[D][D];
-        step_transition<LY, T>(mdl, c, sv.sc, dt, first, Dl, Q);
+        step_transition<LY, T, T>(mdl, c, sv.sc, dt, first, Dl, Q);
         const T yk = in.oc ? in.yc : T(0);
         agg_fold<D, T>(agg, Dl, Q, h, p.noise_k ? R : T(sv.R), yk, in.oc);
         in.tp = in.tc;
@@ -300,8 +305,8 @@ __device__ __forceinline__ void filter_tile_finish(const FilterParams<T> &p, con
         if (!(dt >= 0.0)) bad |= (dt < 0.0) ? PSSGP_STATUS_UNSORTED : PSSGP_STATUS_NONFINITE;
         cdouble *c = cst;
         PSSGP_LAUNDER(c);
-        T Dl[D][D], Q[D][D];
-        step_transition<LY, T>(mdl, c, sv.sc, dt, first, Dl, Q);
+        double Dl[D][D], Q[D][D];
+        step_transition<LY, double, T>(mdl, c, sv.sc, dt, first, Dl, Q);
         const bool obs = in.oc;
         const T yk = obs ? in.yc : T(0);
         const T R = p.noise_k ? Rk : T(sv.R);
@@ -309,13 +314,13 @@ __device__ __forceinline__ void filter_tile_finish(const FilterParams<T> &p, con
         in.tc = tn;
         in.yc = yn;
         in.oc = on;
-        // predict with Dl = F - I: mp = m + Dl m, Pp = P + X + X^T + X Dl^T + Q
-        T mp[D], X[D][D], Pp[D][D];
-        predict_step<D, T>(m, P, Dl, Q, mp, X, Pp);
+        // predict in FP64 (mp = F m, Y = F P, Pp = F P F^T + Q)
+        double mp[D], Y[D][D], Pp[D][D];
+        predict_step<D, T>(m, P, Dl, Q, mp, Y, Pp);
         if constexpr ((MODE & F_ELEMS) != 0) {
             // smoother element of the previous step of this lane
             if (k > k0)
-                emit_smoother_element<D, T>(m, P, X, mp, Pp,
+                emit_smoother_element<D, T>(m, P, Y, mp, Pp,
                                             p.m + elem_index<D>(slot, p.chunk, (int)(k - 1 - k0), lane),
                                             PSSGP_WAVE, bad);
         }
@@ -327,9 +332,9 @@ __device__ __forceinline__ void filter_tile_finish(const FilterParams<T> &p, con
         for (int i = 0; i < D; i++) {
             double acc = 0.0;
 #pragma unroll
-            for (int j = 0; j < D; j++) acc = fma((double)Pp[i][j], (double)h[j], acc);
+            for (int j = 0; j < D; j++) acc = fma(Pp[i][j], (double)h[j], acc);
             Ph[i] = acc;
-            hm = fma((double)h[i], (double)mp[i], hm);
+            hm = fma((double)h[i], mp[i], hm);
         }
 #pragma unroll
         for (int i = 0; i < D; i++) S = fma((double)h[i], Ph[i], S);
@@ -345,12 +350,12 @@ __device__ __forceinline__ void filter_tile_finish(const FilterParams<T> &p, con
 #pragma unroll
         for (int i = 0; i < D; i++) K[i] = Ph[i] * w;
 #pragma unroll
-        for (int i = 0; i < D; i++) m[i] = T(fma(K[i], v, (double)mp[i]));
+        for (int i = 0; i < D; i++) m[i] = T(fma(K[i], v, mp[i]));
 #pragma unroll
         for (int i = 0; i < D; i++)
 #pragma unroll
             for (int j = i; j < D; j++) {
-                const T c = T(fma(S * K[i], K[j], fma(-Ph[i], K[j], fma(-K[i], Ph[j], (double)Pp[i][j]))));
+                const T c = T(fma(S * K[i], K[j], fma(-Ph[i], K[j], fma(-K[i], Ph[j], Pp[i][j]))));
                 P[i][j] = c;
                 P[j][i] = c;
             }
@@ -372,10 +377,10 @@ __device__ __forceinline__ void filter_tile_finish(const FilterParams<T> &p, con
             const double dt = end ? 0.0 : p.t[k1] - p.t[k1 - 1];
             cdouble *c = cst;
             PSSGP_LAUNDER(c);
-            T Dl[D][D], Q[D][D], mp[D], X[D][D], Pp[D][D];
-            step_transition<LY, T>(mdl, c, sv.sc, dt, end, Dl, Q);
-            predict_step<D, T>(m, P, Dl, Q, mp, X, Pp);
-            emit_smoother_element<D, T>(m, P, X, mp, Pp,
+            double Dl[D][D], Q[D][D], mp[D], Y[D][D], Pp[D][D];
+            step_transition<LY, double, T>(mdl, c, sv.sc, dt, end, Dl, Q);
+            predict_step<D, T>(m, P, Dl, Q, mp, Y, Pp);
+            emit_smoother_element<D, T>(m, P, Y, mp, Pp,
                                         p.m + elem_index<D>(slot, p.chunk, (int)(k1 - 1 - k0), lane), PSSGP_WAVE,
                                         bad);
         }
