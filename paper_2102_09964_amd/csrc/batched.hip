@@ -181,11 +181,11 @@ int launch_bf(const BatchLaunch &a, hipStream_t s)
     if (rc) return rc;
     pass_event(a.ev, 1, s);
     rc = launch_tile_scan<FilterScanOps<LA::D, T>>(a.ws.aggp, a.g[0].slot_base, a.g[0].ntiles, false,
-                                                   a.ws.inclp, s);
+                                                   a.ws.inclp, a.ws.gagg, a.ws.gcarry, s);
     if (rc) return rc;
     if (a.ngroups > 1) {
         rc = launch_tile_scan<FilterScanOps<LB::D, T>>(a.ws.aggp, a.g[1].slot_base, a.g[1].ntiles,
-                                                       false, a.ws.inclp, s);
+                                                       false, a.ws.inclp, a.ws.gagg, a.ws.gcarry, s);
         if (rc) return rc;
     }
     pass_event(a.ev, 2, s);
@@ -229,11 +229,11 @@ int launch_bs(const BatchLaunch &a, hipStream_t s)
     if (rc) return rc;
     pass_event(a.ev, 1, s);
     rc = launch_tile_scan<SmootherScanOps<LA::D, T>>(a.ws.aggp, a.g[0].slot_base, a.g[0].ntiles, true,
-                                                     a.ws.inclp, s);
+                                                     a.ws.inclp, a.ws.gagg, a.ws.gcarry, s);
     if (rc) return rc;
     if (a.ngroups > 1) {
         rc = launch_tile_scan<SmootherScanOps<LB::D, T>>(a.ws.aggp, a.g[1].slot_base, a.g[1].ntiles, true,
-                                                         a.ws.inclp, s);
+                                                         a.ws.inclp, a.ws.gagg, a.ws.gcarry, s);
         if (rc) return rc;
     }
     pass_event(a.ev, 2, s);

@@ -25,6 +25,7 @@ struct Plan {
     size_t off_incl = 0, off_lane = 0, off_part = 0, off_ck = 0, off_rec = 0, off_cst = 0, off_agg = 0;
     size_t off_incl2 = 0, off_lane2 = 0, off_part2 = 0, off_agg2 = 0;
     size_t off_x = 0, off_xraw = 0;  // plain baseline element arrays
+    size_t off_gagg = 0, off_gcarry = 0;  // carry pass group scratch
     size_t off_hand = 0;             // predict: filter-to-smoother handover
     size_t total = 0;
 };
@@ -75,6 +76,12 @@ Plan make_plan(int d, int ncomp, int64_t n, pssgp_dtype dtype, int op, const pss
         return p;
     }
     p.off_cst = take(PSSGP_CONST_DOUBLES * sizeof(double));
+    {
+        const size_t ng = (nt + 63) / 64 + 1;
+        const size_t agg_max = (size_t)(filter_agg_elems(d) > grad_agg_elems(d) ? filter_agg_elems(d) : grad_agg_elems(d));
+        p.off_gagg = take(ng * agg_max * p.tsize);
+        p.off_gcarry = take(ng * (size_t)filter_incl_elems(d) * p.tsize);
+    }
     if (op == PSSGP_OP_PREDICT) {
         // filter then smoother on one stream: the scans share their regions
         // (the filter's are the larger); the handover holds the smoother
@@ -174,6 +181,8 @@ ScanWs scan_ws(void *ws, const Plan &p, bool second = false)
     s.ctl = (WsCtl *)b;
     s.inclp = b + (second ? p.off_incl2 : p.off_incl);
     s.aggp = b + (second ? p.off_agg2 : p.off_agg);
+    s.gagg = b + p.off_gagg;
+    s.gcarry = b + p.off_gcarry;
     s.lanep = b + (second ? p.off_lane2 : p.off_lane);
     s.partials = (double *)(b + (second ? p.off_part2 : p.off_part));
     s.cst = (double *)(b + p.off_cst);
@@ -233,6 +242,7 @@ struct BatchPlan {
     BatchGroup g[2];
     BatchModel bm[2];
     size_t off_incl = 0, off_lane = 0, off_part = 0, off_terms = 0, off_cst = 0, off_agg = 0, total = 0;
+    size_t off_gagg = 0, off_gcarry = 0;
 };
 
 int make_batch_plan(const pssgp_batch_group *groups, int ngroups, int64_t n_series, const int64_t *off,
@@ -328,6 +338,8 @@ int make_batch_plan(const pssgp_batch_group *groups, int ngroups, int64_t n_seri
     const int incl = (op == PSSGP_OP_SMOOTH) ? smooth_incl_elems(d) : filter_incl_elems(d);
     bp.off_incl = take(nt * incl * bp.tsize);
     bp.off_agg = take(nt * agg * bp.tsize);
+    bp.off_gagg = take(((nt + 63) / 64 + 1) * agg * bp.tsize);
+    bp.off_gcarry = take(((nt + 63) / 64 + 1) * incl * bp.tsize);
     bp.off_lane = take(nt * 64 * agg * bp.tsize);
     bp.off_part = take(nt * sizeof(double) * 3);
     bp.off_cst = take(2 * PSSGP_CONST_DOUBLES * sizeof(double));
@@ -389,6 +401,8 @@ int run_batched(const pssgp_batch_group *groups, int ngroups, int64_t n_series, 
     a.ws.ctl = (WsCtl *)b;
     a.ws.inclp = b + bp.off_incl;
     a.ws.aggp = b + bp.off_agg;
+    a.ws.gagg = b + bp.off_gagg;
+    a.ws.gcarry = b + bp.off_gcarry;
     a.ws.lanep = b + bp.off_lane;
     a.ws.partials = (double *)(b + bp.off_part);
     a.ws.cst = (double *)(b + bp.off_cst);

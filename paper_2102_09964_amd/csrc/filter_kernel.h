@@ -491,7 +491,7 @@ int launch_filter_t(const DevModel &mdl, const FilterLaunch &a, hipStream_t s)
     int rc = (int)hipGetLastError();
     if (rc) return rc;
     pass_event(a.ev, 1, s);
-    rc = launch_tile_scan<FilterScanOps<LY::D, T>>(a.ws.aggp, 0, a.ntiles, false, a.ws.inclp, s);
+    rc = launch_tile_scan<FilterScanOps<LY::D, T>>(a.ws.aggp, 0, a.ntiles, false, a.ws.inclp, a.ws.gagg, a.ws.gcarry, s);
     if (rc) return rc;
     pass_event(a.ev, 2, s);
     if (a.m && a.tiled)

@@ -113,6 +113,8 @@ struct AdjointScanOps {
     static constexpr int MOM = SAggLayout<D>::INCL;
     static __device__ __forceinline__ void identity(Agg &a) { sagg_identity<D, T>(a); }
     static __device__ __forceinline__ void load(const T *p, Agg &a) { sagg_load<D, T>(p, a); }
+    static __device__ __forceinline__ void store(T *p, const Agg &a) { sagg_store<D, T>(p, a); }
+    static __device__ __forceinline__ void mom_load(const T *p, T (&v)[D], T (&M)[D][D]) { gl_load<D, T>(p, v, M); }
     static __device__ __forceinline__ void extend(const Agg &acc, const Agg &nx, Agg &out)
     {
         adj_combine<D, T>(nx, acc, out);
@@ -470,7 +472,7 @@ int launch_grad_t(const DevModel &mdl, const GradLaunch &a, hipStream_t s)
     hipLaunchKernelGGL((grad_fold_kernel<LY, T>), grid, block, 0, s, p, mdl);
     int rc = (int)hipGetLastError();
     if (rc) return rc;
-    rc = launch_tile_scan<AdjointScanOps<LY::D, T>>(a.ws.aggp, 0, a.ntiles, true, a.ws.inclp, s);
+    rc = launch_tile_scan<AdjointScanOps<LY::D, T>>(a.ws.aggp, 0, a.ntiles, true, a.ws.inclp, a.ws.gagg, a.ws.gcarry, s);
     if (rc) return rc;
     hipLaunchKernelGGL((grad_finish_kernel<LY, T>), grid, block, 0, s, p, mdl);
     return (int)hipGetLastError();

@@ -26,6 +26,8 @@ struct WsCtl {
 struct ScanWs {
     WsCtl *ctl;
     void *aggp;      // per-tile aggregates, contiguous (read by the carry pass)
+    void *gagg;      // carry pass scratch: aggregates of groups of 64 tiles
+    void *gcarry;    // carry pass scratch: moments entering each group
     void *inclp;     // per-tile carries (moments entering the tile)
     void *lanep;     // per-lane inclusive aggregates within the tile
     double *partials;  // per-tile partial sums (loglik, gradient)

@@ -20,8 +20,9 @@
 // (g, L) or the adjoint (mbar, Pbar).
 //
 // Ops provides: D, T, Agg, AGG (stored size), MOM (stored moment size),
-// identity, load, extend(acc, next, out) (acc followed by next in processing
-// order), apply(v, M, x) (moments advanced over x) and mom_store.
+// identity, load, store, extend(acc, next, out) (acc followed by next in
+// processing order), apply(v, M, x) (moments advanced over x), mom_load and
+// mom_store.
 #pragma once
 #include "device_common.h"
 #include "filter_ops.h"
@@ -38,6 +39,8 @@ struct FilterScanOps {
     static constexpr int MOM = AggLayout<D>::INCL;
     static __device__ __forceinline__ void identity(Agg &a) { agg_identity<D, T>(a); }
     static __device__ __forceinline__ void load(const T *p, Agg &a) { agg_load<D, T>(p, a); }
+    static __device__ __forceinline__ void store(T *p, const Agg &a) { agg_store<D, T>(p, a); }
+    static __device__ __forceinline__ void mom_load(const T *p, T (&v)[D], T (&M)[D][D]) { moments_load<D, T>(p, v, M); }
     static __device__ __forceinline__ void extend(const Agg &acc, const Agg &nx, Agg &out)
     {
         agg_combine<D, T, typename CombineType<T>::type>(acc, nx, out);
@@ -61,6 +64,8 @@ struct SmootherScanOps {
     static constexpr int MOM = SAggLayout<D>::INCL;
     static __device__ __forceinline__ void identity(Agg &a) { sagg_identity<D, T>(a); }
     static __device__ __forceinline__ void load(const T *p, Agg &a) { sagg_load<D, T>(p, a); }
+    static __device__ __forceinline__ void store(T *p, const Agg &a) { sagg_store<D, T>(p, a); }
+    static __device__ __forceinline__ void mom_load(const T *p, T (&v)[D], T (&M)[D][D]) { gl_load<D, T>(p, v, M); }
     // processing order is reverse time: the next aggregate is earlier in time
     static __device__ __forceinline__ void extend(const Agg &acc, const Agg &nx, Agg &out)
     {
@@ -152,12 +157,83 @@ __global__ __launch_bounds__(PSSGP_TS_THREADS) void tile_scan_kernel(const typen
     }
 }
 
+// Hierarchical form for many tiles, in groups of 64 consecutive tiles (in
+// processing order):
+//   A  one wave per group scans its 64 tile aggregates (Kogge-Stone) and
+//      overwrites each with its inclusive aggregate within the group; the
+//      last one is the group total (gagg)
+//   B  tile_scan_kernel over the group totals gives the moments entering
+//      every group (gcarry)
+//   C  one thread per tile applies the inclusive aggregate of its
+//      predecessor in the group to the group's carry.
+// The serial depth is 6 + (depth of B) + 1 combinations instead of a
+// sequential run per thread, and A and C spread over the whole chip.
 template <class Ops>
-int launch_tile_scan(const void *aggp, int slot_base, int ntiles, bool reverse, void *carry, hipStream_t s)
+__global__ __launch_bounds__(PSSGP_WAVE) void group_reduce_kernel(typename Ops::T *aggp, int slot_base, int ntiles,
+                                                                 int reverse, typename Ops::T *gagg)
+{
+    using T = typename Ops::T;
+    using Agg = typename Ops::Agg;
+    const int lane = lane_id();
+    const int i = (int)blockIdx.x * PSSGP_WAVE + lane;
+    const int slot = slot_base + (reverse ? ntiles - 1 - i : i);
+    Agg acc;
+    if (i < ntiles)
+        Ops::load(aggp + (size_t)slot * Ops::AGG, acc);
+    else
+        Ops::identity(acc);
+    for (int o = 1; o < PSSGP_WAVE; o <<= 1) {
+        Agg other;
+        agg_shfl_up_raw<Agg, T>(acc, other, o);
+        if (lane >= o) Ops::extend(other, acc, acc);
+    }
+    if (i < ntiles) Ops::store(aggp + (size_t)slot * Ops::AGG, acc);
+    if (lane == PSSGP_WAVE - 1) Ops::store(gagg + (size_t)blockIdx.x * Ops::AGG, acc);
+}
+
+template <class Ops>
+__global__ __launch_bounds__(256) void tile_carry_kernel(const typename Ops::T *aggp, const typename Ops::T *gcarry,
+                                                        int slot_base, int ntiles, int reverse,
+                                                        typename Ops::T *carry)
+{
+    using T = typename Ops::T;
+    using Agg = typename Ops::Agg;
+    constexpr int D = Ops::D;
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= ntiles) return;
+    const int g = i / PSSGP_WAVE, j = i - g * PSSGP_WAVE;
+    T v[D], M[D][D];
+    Ops::mom_load(gcarry + (size_t)g * Ops::MOM, v, M);
+    if (j > 0) {
+        const int prev = slot_base + (reverse ? ntiles - i : i - 1);
+        Agg x;
+        Ops::load(aggp + (size_t)prev * Ops::AGG, x);
+        Ops::apply(v, M, x);
+    }
+    const int slot = slot_base + (reverse ? ntiles - 1 - i : i);
+    Ops::mom_store(carry + (size_t)slot * Ops::MOM, v, M);
+}
+
+// Carries of tiles [slot_base, slot_base + ntiles). gagg and gcarry are
+// scratch for ceil(ntiles / 64) group aggregates and carries; aggp is
+// overwritten.
+template <class Ops>
+int launch_tile_scan(void *aggp, int slot_base, int ntiles, bool reverse, void *carry, void *gagg, void *gcarry,
+                     hipStream_t s)
 {
     using T = typename Ops::T;
     if (ntiles <= 0) return 0;
-    hipLaunchKernelGGL((tile_scan_kernel<Ops>), dim3(1), dim3(PSSGP_TS_THREADS), 0, s, (const T *)aggp, slot_base,
-                       ntiles, reverse ? 1 : 0, (T *)carry);
+    if (ntiles <= 2 * PSSGP_WAVE) {
+        hipLaunchKernelGGL((tile_scan_kernel<Ops>), dim3(1), dim3(PSSGP_TS_THREADS), 0, s, (const T *)aggp,
+                           slot_base, ntiles, reverse ? 1 : 0, (T *)carry);
+        return (int)hipGetLastError();
+    }
+    const int ng = (ntiles + PSSGP_WAVE - 1) / PSSGP_WAVE;
+    hipLaunchKernelGGL((group_reduce_kernel<Ops>), dim3(ng), dim3(PSSGP_WAVE), 0, s, (T *)aggp, slot_base, ntiles,
+                       reverse ? 1 : 0, (T *)gagg);
+    hipLaunchKernelGGL((tile_scan_kernel<Ops>), dim3(1), dim3(PSSGP_TS_THREADS), 0, s, (const T *)gagg, 0, ng, 0,
+                       (T *)gcarry);
+    hipLaunchKernelGGL((tile_carry_kernel<Ops>), dim3((ntiles + 255) / 256), dim3(256), 0, s, (const T *)aggp,
+                       (const T *)gcarry, slot_base, ntiles, reverse ? 1 : 0, (T *)carry);
     return (int)hipGetLastError();
 }
