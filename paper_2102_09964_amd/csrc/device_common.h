@@ -22,13 +22,14 @@
 #endif
 
 // Arithmetic type of the general filtering operator where it is applied
-// once per lane or tile (the carry scan and the lane-start moments): FP64
-// for FP32 scans, because the operator conditions one aggregate on the
-// information of another, which cancels like the covariance update when
-// the noise is small. The lane scan of the fold pass (six combinations per
-// lane) runs in the scan type.
+// once per lane or tile (the carry scan and the lane-start moments). The
+// scan type by default: in FP64 at d = 6 the operator's working set (two
+// aggregates, the LU factors) exceeds the register file and each
+// combination costs ~25 us; FP64 helps only when every step's moments come
+// from combinations (one step per lane), which the tuned chunks avoid.
+// Compile with -DPSSGP_COMBINE_F64=1 for FP64.
 #ifndef PSSGP_COMBINE_F64
-#define PSSGP_COMBINE_F64 1
+#define PSSGP_COMBINE_F64 0
 #endif
 template <typename T>
 struct CombineType {
