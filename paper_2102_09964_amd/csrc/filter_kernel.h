@@ -491,17 +491,26 @@ int launch_filter_t(const DevModel &mdl, const FilterLaunch &a, hipStream_t s)
     int rc = (int)hipGetLastError();
     if (rc) return rc;
     pass_event(a.ev, 1, s);
-    rc = launch_tile_scan<FilterScanOps<LY::D, T>>(a.ws.aggp, 0, a.ntiles, false, a.ws.inclp, a.ws.gagg, a.ws.gcarry, s);
-    if (rc) return rc;
-    pass_event(a.ev, 2, s);
-    if (a.m && a.tiled)
-        hipLaunchKernelGGL((filter_finish_kernel<LY, T, CT, F_ELEMS>), grid, block, 0, s, p, mdl);
-    else if (a.m)
-        hipLaunchKernelGGL((filter_finish_kernel<LY, T, CT, F_MOMENTS>), grid, block, 0, s, p, mdl);
-    else if (a.ck)
-        hipLaunchKernelGGL((filter_finish_kernel<LY, T, CT, F_CKPT>), grid, block, 0, s, p, mdl);
-    else
-        hipLaunchKernelGGL((filter_finish_kernel<LY, T, CT, 0>), grid, block, 0, s, p, mdl);
+    if (a.ck) {
+        // forward pass of the gradient: the carries and lane-start moments in
+        // FP64, because the noise-variance derivative is sensitive to them
+        rc = launch_tile_scan<FilterScanOps<LY::D, T, double>>(a.ws.aggp, 0, a.ntiles, false, a.ws.inclp, a.ws.gagg,
+                                                                a.ws.gcarry, s);
+        if (rc) return rc;
+        pass_event(a.ev, 2, s);
+        hipLaunchKernelGGL((filter_finish_kernel<LY, T, double, F_CKPT>), grid, block, 0, s, p, mdl);
+    } else {
+        rc = launch_tile_scan<FilterScanOps<LY::D, T, CT>>(a.ws.aggp, 0, a.ntiles, false, a.ws.inclp, a.ws.gagg,
+                                                            a.ws.gcarry, s);
+        if (rc) return rc;
+        pass_event(a.ev, 2, s);
+        if (a.m && a.tiled)
+            hipLaunchKernelGGL((filter_finish_kernel<LY, T, CT, F_ELEMS>), grid, block, 0, s, p, mdl);
+        else if (a.m)
+            hipLaunchKernelGGL((filter_finish_kernel<LY, T, CT, F_MOMENTS>), grid, block, 0, s, p, mdl);
+        else
+            hipLaunchKernelGGL((filter_finish_kernel<LY, T, CT, 0>), grid, block, 0, s, p, mdl);
+    }
     rc = (int)hipGetLastError();
     pass_event(a.ev, 3, s);
     return rc;

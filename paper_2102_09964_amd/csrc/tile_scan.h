@@ -30,10 +30,11 @@
 
 #define PSSGP_TS_THREADS 256
 
-template <int D_, typename T_>
+template <int D_, typename T_, typename CT_ = typename CombineType<T_>::type>
 struct FilterScanOps {
     static constexpr int D = D_;
     using T = T_;
+    using CT = CT_;  // arithmetic type of the operator
     using Agg = FAgg<D, T>;
     static constexpr int AGG = AggLayout<D>::SIZE;
     static constexpr int MOM = AggLayout<D>::INCL;
@@ -43,11 +44,11 @@ struct FilterScanOps {
     static __device__ __forceinline__ void mom_load(const T *p, T (&v)[D], T (&M)[D][D]) { moments_load<D, T>(p, v, M); }
     static __device__ __forceinline__ void extend(const Agg &acc, const Agg &nx, Agg &out)
     {
-        agg_combine<D, T, typename CombineType<T>::type>(acc, nx, out);
+        agg_combine<D, T, CT>(acc, nx, out);
     }
     static __device__ __forceinline__ void apply(T (&v)[D], T (&M)[D][D], const Agg &x)
     {
-        moments_apply<D, T, typename CombineType<T>::type>(v, M, x, v, M);
+        moments_apply<D, T, CT>(v, M, x, v, M);
     }
     static __device__ __forceinline__ void mom_store(T *p, const T (&v)[D], const T (&M)[D][D])
     {
