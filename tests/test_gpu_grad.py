@@ -93,7 +93,8 @@ def test_loglik_grad_loglik_matches_filter():
     ll_g, _ = _gpu(w, comps, noise, "float32", chunk=16)
     m = P.make_model(comps, noise)
     ll_f = float(P.loglik(m, w["t"], np.nan_to_num(w["y"]), w["mask"], dtype="float32").cpu()[0])
-    assert ll_g == ll_f
+    # same filter; the gradient's forward pass combines its carries in FP64
+    assert abs(ll_g - ll_f) <= 1e-7 * abs(ll_f), (ll_g, ll_f)
 
 
 def test_autograd_function():
