@@ -12,10 +12,11 @@ noisy three-tone sinusoid, 20 % missing, FP32 scans with FP64
 discretisation and a compensated log-likelihood.
 
 The JSON line carries, besides the contract fields:
-* roofline: the dominant scan kernel's algorithmic HBM bytes per launch
-  divided by its mean duration (HIP events on the launch stream) against
-  the 8 TB/s HBM3E peak, plus its arithmetic rate against the FP32 vector
-  peak;
+* roofline: the dominant scan kernel's algorithmic flops (or HBM bytes) per
+  launch divided by its mean duration (HIP events on the launch stream),
+  against the vector ALU peak (78.6 TFLOP/s without packed FP32) or the
+  8 TB/s HBM3E peak, whichever its arithmetic intensity puts it under, and
+  its measured HBM traffic per launch from the committed counter summary;
 * cpu_baseline: the sequential FP64 oracle on a bounded prefix of the same
   workload, on one host core;
 * also: the same measurement for the other precision and the other
@@ -51,41 +52,90 @@ PASSES = ("filter_fold", "filter_carry", "filter_finish", "smoother_fold", "smoo
 
 
 def pass_costs(d, tsize, chunk):
-    """Algorithmic HBM bytes and flops per time step of every pass (2 flops
-    per multiply-add; the FP64 transition and smoother elements and the FP32
-    scan algebra both count, since with packed FP32 disabled both run at the
-    same vector rate). Bytes: inputs read once, the filter-to-smoother
-    handover (m, P) written then read, outputs written, and the per-lane
-    aggregates of the fold passes (one per chunk of steps)."""
+    """Algorithmic HBM bytes and flops per time step of every pass of the
+    fused filter + smoother call (2 flops per multiply-add; FP64 and FP32
+    vector operations count alike, since with packed FP32 disabled both run
+    at the same vector rate).
+
+    Bytes are each kernel's own inputs and outputs: the step inputs
+    (t, y, mask), the smoother element of every step that the filter's
+    finish pass hands to the smoother (E, g, packed L: d^2 + d + d(d+1)/2
+    values), the per-lane aggregates of the fold passes (one per chunk of
+    steps, read back by the finish passes) and the outputs f_mean, f_var.
+    Flops: the FP64 discretisation from the pair constants (F - I: d^3,
+    Q: (d(d+1)/2)^2), the filter fold (element of one step folded into the
+    lane aggregate), the FP64 prediction (F m, F P, F P F^T + Q), the FP64
+    conditioning, the smoother element from the prediction (Cholesky of the
+    predicted covariance, two triangular solves, the Gram matrix), the
+    smoother operator and its application, and the lane scans (6 operator
+    applications per lane and tile, i.e. per chunk of steps)."""
     ns = d * (d + 1) // 2
-    mom = tsize * (d + ns)
-    fagg = tsize * (d * d + 2 * d + 2 * ns) / chunk
-    sagg = tsize * (d * d + d + ns) / chunk
-    disc = d ** 3 + ns * ns + ns                     # F - I by the expansion, Q by the pair sums
-    kf = d ** 3 + ns * d + 2 * d * d + 4 * ns        # predict in F - I form, Joseph update
-    fold = 2 * d ** 3 + ns * d + 3 * d * d + 4 * ns  # unknown-start fold of one step
-    combine = 5 * d ** 3                             # general operator (lane scan, per chunk)
-    selem = 3 * d ** 3 + 2 * ns * d + 2 * d * d      # smoother element (Cholesky form)
-    scomb = 2 * d ** 3 + ns * d
-    sapply = d ** 3 + ns * d + 2 * d * d
-    out = {
-        "filter_fold": (9 + tsize + fagg, 2 * (disc + fold + 6 * combine / chunk)),
+    elem = tsize * (d * d + d + ns)                  # smoother element in the handover
+    fagg = tsize * (d * d + 2 * d + 2 * ns) / chunk  # filter lane aggregate (A, b, C, eta, J)
+    sagg = tsize * (d * d + d + ns) / chunk          # smoother lane aggregate (E, g, L)
+    inputs = 8 + tsize + 1                           # t (FP64), y, mask
+    disc = d ** 3 + ns * ns + ns
+    fold = 2 * d ** 3 + ns * d + 3 * d * d + 4 * ns
+    combine = 5 * d ** 3                             # general filtering operator
+    predict = d ** 3 + d * d + ns * d + ns
+    cond = d * d + 3 * d + 3 * ns
+    selem = d ** 3 // 6 + d * d * (d - 1) + ns * d + d * d
+    scomb = 2 * d ** 3 + ns * d + d * d
+    sapply = d ** 3 + ns * d + 2 * d * d + 2 * d
+    return {
+        "filter_fold": (inputs + fagg, 2 * (disc + fold + 6 * combine / chunk)),
         "filter_carry": (0.0, 0.0),
-        "filter_finish": (9 + tsize + fagg + mom, 2 * (disc + kf)),
-        "smoother_fold": (8 + mom + sagg, 2 * (disc + selem + scomb + 6 * scomb / chunk)),
+        "filter_finish": (inputs + fagg + elem, 2 * (disc + predict + cond + selem + combine / chunk)),
+        "smoother_fold": (elem + sagg, 2 * (scomb + 6 * scomb / chunk)),
         "smoother_carry": (0.0, 0.0),
-        "smoother_finish": (8 + mom + sagg + 2 * tsize, 2 * (disc + selem + sapply)),
+        "smoother_finish": (elem + sagg + 2 * tsize, 2 * (sapply + sapply / chunk)),
     }
-    return out
 
 
-def algorithmic_bytes(d, tsize, n):
-    """HBM bytes the path must move per step pass (inputs read once, the
-    filter to smoother handover (m, P) written then read, outputs written)."""
-    mom = tsize * d * (d + 3) // 2
-    filt = n * (8 + tsize + 1 + mom)          # t, y, mask in; m, P out
-    smooth = n * (8 + mom + 2 * tsize)        # t, m, P in; f_mean, f_var out
-    return filt, smooth
+def algorithmic_bytes(tsize, n):
+    """HBM bytes the whole path must move: the step inputs (t, y, mask) read
+    once and f_mean, f_var written once."""
+    return n * (8 + tsize + 1 + 2 * tsize)
+
+
+def sources_digest():
+    """SHA-256 of the kernel sources (the traffic figures of a profile
+    summary hold only for the sources they were taken with)."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2102_09964_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".h", ".hip", ".cpp")):
+            h.update(name.encode())
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel, workload, dtype, chunk):
+    """HBM bytes per launch of a kernel from the committed counter summaries
+    (profiles/traffic_*.txt, lines 'traffic: kernel=... workload=... dtype=...
+    chunk=... bytes=... sources=...'), or None when no line matches or the
+    kernel sources changed since the counters were taken."""
+    pdir = os.path.join(ROOT, "profiles")
+    if not os.path.isdir(pdir):
+        return None
+    digest = None
+    for name in sorted(os.listdir(pdir)):
+        if not (name.startswith("traffic_") and name.endswith(".txt")):
+            continue
+        with open(os.path.join(pdir, name)) as f:
+            for line in f:
+                if not line.startswith("traffic:"):
+                    continue
+                kv = dict(x.split("=", 1) for x in line.split()[1:])
+                if (kv.get("kernel"), kv.get("workload"), kv.get("dtype"), kv.get("chunk")) != \
+                        (kernel, workload, dtype, str(chunk)):
+                    continue
+                digest = digest or sources_digest()
+                if kv.get("sources") == digest:
+                    return float(kv["bytes"])
+    return None
 
 
 def measure(w, dtype, steps, warmup, chunk=0):
@@ -129,12 +179,11 @@ def measure(w, dtype, steps, warmup, chunk=0):
     ll = float(pipe.loglik.cpu()[0])
     status = (P.status(pipe.ws_f), P.status(pipe.ws_s))
     tsize = 4 if dtype == "float32" else 8
-    fb, sb = algorithmic_bytes(d, tsize, n)
     return {"n": n, "d": d, "tsize": tsize, "chunk": chunk or 16, "ms_per_step": ms_step,
             "filter_ms": sum(v for k, v in pass_ms.items() if k.startswith("filter")),
             "smoother_ms": sum(v for k, v in pass_ms.items() if k.startswith("smoother")),
             "pass_ms": pass_ms, "steps_per_s": n / (ms_step / 1e3), "loglik": ll, "status": status,
-            "filter_bytes": fb, "smoother_bytes": sb}
+            "path_bytes": algorithmic_bytes(tsize, n)}
 
 
 def measure_plain(w, steps, warmup):
@@ -162,11 +211,13 @@ def measure_plain(w, steps, warmup):
     return {"steps_per_s": round(n / (ms / 1e3), 1), "ms_per_step": round(ms, 4), "loglik": ll}
 
 
-def roofline_of(m):
+def roofline_of(m, workload=None, dtype=None):
     """Roofline of the dominant pass (longest mean duration): its
     algorithmic flops and bytes per launch over that duration, against the
     vector ALU peak and the HBM peak; `bound` is the roofline the pass's
-    arithmetic intensity puts it under."""
+    arithmetic intensity puts it under. `traffic` is the kernel's measured
+    HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated on a copy),
+    when a counter summary for these sources, workload and chunk exists."""
     costs = pass_costs(m["d"], m["tsize"], m["chunk"])
     dom = max(m["pass_ms"], key=lambda k: m["pass_ms"][k])
     ms = m["pass_ms"][dom]
@@ -176,18 +227,21 @@ def roofline_of(m):
     intensity = fpstep / bpstep if bpstep else float("inf")
     ridge = FP32_UNPACKED_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
     alu = intensity >= ridge
+    traffic = measured_traffic(dom, workload, dtype, m["chunk"]) if workload else None
     out = {"bound": "alu" if alu else "hbm",
            "achieved": round(tfl if alu else gbs, 3),
            "peak": FP32_UNPACKED_PEAK_TFLOPS if alu else HBM_PEAK_GBS,
            "unit": "TFLOP/s" if alu else "GB/s",
            "frac": round(tfl / FP32_UNPACKED_PEAK_TFLOPS if alu else gbs / HBM_PEAK_GBS, 5),
-           "traffic": None,
+           "traffic": traffic,
            "kernel": dom, "kernel_ms": round(ms, 4),
            "flops_per_step": round(fpstep, 1), "bytes_per_step": round(bpstep, 1),
+           "algorithmic_bytes_per_launch": round(bpstep * m["n"]),
            "achieved_gbs": round(gbs, 2), "hbm_frac": round(gbs / HBM_PEAK_GBS, 5),
            "achieved_tflops": round(tfl, 3),
-           "path_hbm_frac": round((m["filter_bytes"] + m["smoother_bytes"]) / (m["ms_per_step"] / 1e3) / 1e9
-                                  / HBM_PEAK_GBS, 5)}
+           "path_hbm_frac": round(m["path_bytes"] / (m["ms_per_step"] / 1e3) / 1e9 / HBM_PEAK_GBS, 5)}
+    if traffic:
+        out["traffic_over_algorithmic"] = round(traffic / (bpstep * m["n"]), 3)
     return out
 
 
@@ -275,6 +329,20 @@ def cpu_baseline(w, target_s=12.0):
             "sample": "first %d of %d steps, filter+smoother+loglik, FP64 sequential C, %.1f s" % (n, n_all, dt)}
 
 
+def copy_probe():
+    """A plain device copy of known size (1 GiB, three times): the counter
+    values FETCH_SIZE and WRITE_SIZE read for it give the factors that turn
+    the counters of the scan kernels into bytes."""
+    import torch
+    n = 1 << 28
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": n * 4, "copies": 3}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -286,7 +354,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-also", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy 1 GiB three times (calibration of the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe()
+        return
     if args.gpus != 1:
         print("bench.py: runs on one GPU only; sharding the time axis over several GPUs is designed "
               "but not implemented. Use --gpus 1.", file=sys.stderr)
@@ -340,7 +413,7 @@ def main():
         "config": {"workload": args.workload, "n_steps": m["n"], "state_dim": m["d"], "chunk": m["chunk"],
                    "kernel": "RBF Taylor order 6" if args.workload == "rbf6_lognormal" else args.workload,
                    "scan_dtype": args.dtype, "discretisation": "f64"},
-        "roofline": roofline_of(m),
+        "roofline": roofline_of(m, args.workload, args.dtype),
         "filter_ms": round(m["filter_ms"], 4),
         "smoother_ms": round(m["smoother_ms"], 4),
         "pass_ms": {k: round(v, 4) for k, v in m["pass_ms"].items()},

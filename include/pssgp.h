@@ -101,9 +101,10 @@ typedef struct pssgp_options {
                                 the carry pass, before the finish pass and after the
                                 finish pass of the call's filter scan (entries 0-3:
                                 pssgp_filter, pssgp_loglik, pssgp_loglik_grad,
-                                pssgp_predict, batched filter) and smoother scan
-                                (entries 0-3 for pssgp_smooth and the batched
-                                smoother, entries 4-7 for pssgp_predict); for timing
+                                pssgp_predict, the batched filter and batched
+                                predict) and smoother scan (entries 0-3 for
+                                pssgp_smooth and the batched smoother, entries 4-7
+                                for pssgp_predict and the batched predict); for timing
                                 the passes. Owned by the caller. */
 } pssgp_options;
 
@@ -256,8 +257,8 @@ int pssgp_loglik_grad(const pssgp_model *model, const double *t, const void *y,
  * ignored) and the series range [series_begin, series_end) of group g;
  * n_groups is 1 or 2, the groups are contiguous, cover all series and have
  * ascending state sizes. params: device double[n_series][3], per series
- * (lengthscale, variance, noise_var). One persistent launch scans all
- * series: a series start is a filter element with A = 0 (section 3) and a
+ * (lengthscale, variance, noise_var). One set of scan launches (fold,
+ * carry, finish) covers all series: a series start is a filter element with A = 0 (section 3) and a
  * series end a smoother element with E = 0, so both scans restart at series
  * boundaries without segment flags. m: device dtype[d_max][n_total], P:
  * device dtype[NS_max][n_total] (d_max, NS_max of the largest group); a
@@ -285,6 +286,23 @@ int pssgp_batched_smooth(const pssgp_batch_group *groups_host, int n_groups, int
                          const double *t, const void *m, const void *P, pssgp_dtype dtype,
                          void *f_mean, void *f_var, void *ws, size_t ws_bytes,
                          const pssgp_options *opts, void *stream);
+
+/*
+ * Batched filter and smoother in one call (the batched form of
+ * pssgp_predict; sections 3 and 4 with the series boundaries above): the
+ * filter's finish pass writes the smoother element of every step into the
+ * workspace and the smoother scans those elements, so no moments go to
+ * caller memory. y, mask as for pssgp_batched_filter; f_mean, f_var: device
+ * dtype[n_total]; loglik: device double[n_series]. Workspace size:
+ * pssgp_batched_workspace_bytes(..., PSSGP_OP_PREDICT, opts).
+ * opts->pass_events, when set, holds 8 events: the filter's 4, then the
+ * smoother's 4. Errors as for pssgp_batched_filter.
+ */
+int pssgp_batched_predict(const pssgp_batch_group *groups_host, int n_groups, int64_t n_series,
+                          const int64_t *offsets, const int64_t *offsets_host, const double *params,
+                          const double *t, const void *y, const uint8_t *mask, pssgp_dtype dtype,
+                          void *f_mean, void *f_var, double *loglik, void *ws, size_t ws_bytes,
+                          const pssgp_options *opts, void *stream);
 
 /* Status word of the most recent call that used workspace ws (read after
  * synchronising stream); bits: PSSGP_STATUS_*. */

@@ -81,6 +81,8 @@ SIGNATURES = [
                                             ctypes.c_int, _VP, _VP, _VP, _VP, _SZ, _OP, _VP]),
     ("pssgp_batched_smooth", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _I64, _VP, _VP, _VP, _VP, _VP, _VP,
                                             ctypes.c_int, _VP, _VP, _VP, _SZ, _OP, _VP]),
+    ("pssgp_batched_predict", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _I64, _VP, _VP, _VP, _VP, _VP, _VP,
+                                             ctypes.c_int, _VP, _VP, _VP, _VP, _SZ, _OP, _VP]),
     ("pssgp_status", ctypes.c_int, [_VP, _VP, ctypes.POINTER(ctypes.c_uint32)]),
     ("pssgp_predict", ctypes.c_int, [_MP, _VP, _VP, _VP, _I64, ctypes.c_int, _VP, _VP, _VP, _VP, _SZ, _OP, _VP]),
     ("pssgp_plain_predict", ctypes.c_int, [_MP, _VP, _VP, _VP, _I64, _VP, _VP, _VP, _VP, _VP, _VP, _SZ, _VP]),
@@ -563,10 +565,13 @@ class BatchedPipeline:
 
     kinds: per-series Matern kind (sorted by state size, at most two kinds);
     offsets: int64 [n_series + 1]; params: float64 [n_series, 3] with
-    (lengthscale, variance, noise_var) per series.
+    (lengthscale, variance, noise_var) per series. fused=True runs both scans
+    in one pssgp_batched_predict call (smoother elements handed over in the
+    workspace, no filter moments in memory); fused=False runs
+    pssgp_batched_filter, keeps m and P, then pssgp_batched_smooth.
     """
 
-    def __init__(self, kinds, offsets, params, dtype="float32", options=None, device="cuda"):
+    def __init__(self, kinds, offsets, params, dtype="float32", options=None, device="cuda", fused=True):
         _require_gpu()
         torch = _torch()
         self.groups = batch_groups(kinds)
@@ -582,35 +587,59 @@ class BatchedPipeline:
         self.dmax = dmax
         L = lib()
         op = ctypes.byref(options) if options is not None else None
-        nb_f = L.pssgp_batched_workspace_bytes(self.groups, self.ng, self.ns, self.offsets_host.ctypes.data,
-                                               self.code, OP_FILTER, op)
-        nb_s = L.pssgp_batched_workspace_bytes(self.groups, self.ng, self.ns, self.offsets_host.ctypes.data,
-                                               self.code, OP_SMOOTH, op)
-        if nb_f == 0 or nb_s == 0:
+        self.fused = bool(fused)
+        ops = (OP_PREDICT,) if self.fused else (OP_FILTER, OP_SMOOTH)
+        nbs = [L.pssgp_batched_workspace_bytes(self.groups, self.ng, self.ns, self.offsets_host.ctypes.data,
+                                               self.code, o, op) for o in ops]
+        if min(nbs) == 0:
             raise PssgpError(-1, L.pssgp_last_error().decode())
-        self.ws_f = torch.empty(nb_f, dtype=torch.uint8, device=device)
-        self.ws_s = torch.empty(nb_s, dtype=torch.uint8, device=device)
-        self.m = torch.empty((dmax, self.n), dtype=self.tdt, device=device)
-        self.P = torch.empty((dmax * (dmax + 1) // 2, self.n), dtype=self.tdt, device=device)
+        if self.fused:
+            self.ws_p = torch.empty(nbs[0], dtype=torch.uint8, device=device)
+            self.ws_f = self.ws_s = self.ws_p
+            self.m = self.P = None
+        else:
+            self.ws_f = torch.empty(nbs[0], dtype=torch.uint8, device=device)
+            self.ws_s = torch.empty(nbs[1], dtype=torch.uint8, device=device)
+            self.m = torch.empty((dmax, self.n), dtype=self.tdt, device=device)
+            self.P = torch.empty((dmax * (dmax + 1) // 2, self.n), dtype=self.tdt, device=device)
         self.loglik = torch.empty(self.ns, dtype=torch.float64, device=device)
         self.f_mean = torch.empty(self.n, dtype=self.tdt, device=device)
         self.f_var = torch.empty(self.n, dtype=self.tdt, device=device)
 
-    def run(self, t, y, mask=None, events=None):
+    def run(self, t, y, mask=None, events=None, pass_events=None):
+        """events: optional 3 torch.cuda.Event (before, between, after the
+        two scans; the middle one coincides with the last when fused);
+        pass_events: optional (filter, smoother) pair of lists of 4 events."""
         L = lib()
         op = ctypes.byref(self.options) if self.options is not None else None
         st = _stream()
         oh = self.offsets_host.ctypes.data
+        if self.fused:
+            if pass_events is not None:
+                op = ctypes.byref(_with_events(self.options, list(pass_events[0]) + list(pass_events[1])))
+            if events:
+                events[0].record()
+            _check(L.pssgp_batched_predict(self.groups, self.ng, self.ns, _p(self.offsets), oh, _p(self.params),
+                                           _p(t), _p(y), _p(mask), self.code, _p(self.f_mean), _p(self.f_var),
+                                           _p(self.loglik), _p(self.ws_p), self.ws_p.numel(), op, st))
+            if events:
+                events[1].record()
+                events[2].record()
+            return self.f_mean, self.f_var, self.loglik
+        op_f = op_s = op
+        if pass_events is not None:
+            op_f = ctypes.byref(_with_events(self.options, pass_events[0]))
+            op_s = ctypes.byref(_with_events(self.options, pass_events[1]))
         if events:
             events[0].record()
         _check(L.pssgp_batched_filter(self.groups, self.ng, self.ns, _p(self.offsets), oh, _p(self.params), _p(t),
                                       _p(y), _p(mask), self.code, _p(self.m), _p(self.P), _p(self.loglik),
-                                      _p(self.ws_f), self.ws_f.numel(), op, st))
+                                      _p(self.ws_f), self.ws_f.numel(), op_f, st))
         if events:
             events[1].record()
         _check(L.pssgp_batched_smooth(self.groups, self.ng, self.ns, _p(self.offsets), oh, _p(self.params), _p(t),
                                       _p(self.m), _p(self.P), self.code, _p(self.f_mean), _p(self.f_var),
-                                      _p(self.ws_s), self.ws_s.numel(), op, st))
+                                      _p(self.ws_s), self.ws_s.numel(), op_s, st))
         if events:
             events[2].record()
         return self.f_mean, self.f_var, self.loglik

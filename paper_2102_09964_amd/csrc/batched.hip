@@ -73,7 +73,9 @@ __device__ __forceinline__ int group_of(const BatchLaunch &a, int slot)
     return (a.ngroups > 1 && slot >= a.g[1].slot_base) ? 1 : 0;
 }
 
-template <class LA, class LB, typename T, bool FINISH>
+// ELEMS: the finish pass writes smoother elements to the handover (p.m)
+// instead of the filter moments
+template <class LA, class LB, typename T, bool FINISH, bool ELEMS>
 __global__ __launch_bounds__(PSSGP_WAVE) void batched_filter_kernel(FilterParams<T> p, BatchLaunch a)
 {
     __shared__ DevModel mdl;
@@ -91,11 +93,12 @@ __global__ __launch_bounds__(PSSGP_WAVE) void batched_filter_kernel(FilterParams
     ManySeries sv;
     series_view(sv, a, g, g.k_begin + ((int64_t)tile * PSSGP_WAVE + lane_id()) * p.chunk);
     if constexpr (FINISH) {
+        constexpr int MODE = ELEMS ? F_ELEMS : F_MOMENTS;
         double ll = 0.0;
         if (gi == 0)
-            filter_tile_finish<LA, T, typename CombineType<T>::type, F_MOMENTS, ManySeries>(p, mdl, cst, sv, tr, tile, ll);
+            filter_tile_finish<LA, T, typename CombineType<T>::type, MODE, ManySeries>(p, mdl, cst, sv, tr, tile, ll);
         else
-            filter_tile_finish<LB, T, typename CombineType<T>::type, F_MOMENTS, ManySeries>(p, mdl, cst, sv, tr, tile, ll);
+            filter_tile_finish<LB, T, typename CombineType<T>::type, MODE, ManySeries>(p, mdl, cst, sv, tr, tile, ll);
     } else {
         if (gi == 0)
             filter_tile_fold<LA, T, T, ManySeries>(p, mdl, cst, sv, tr, tile);
@@ -104,7 +107,9 @@ __global__ __launch_bounds__(PSSGP_WAVE) void batched_filter_kernel(FilterParams
     }
 }
 
-template <class LA, class LB, typename T, bool FINISH>
+// ELEMS: the smoother elements come from the handover (p.m) written by the
+// filter of the same call
+template <class LA, class LB, typename T, bool FINISH, bool ELEMS>
 __global__ __launch_bounds__(PSSGP_WAVE) void batched_smoother_kernel(SmoothParams<T> p, BatchLaunch a)
 {
     __shared__ DevModel mdl;
@@ -125,14 +130,14 @@ __global__ __launch_bounds__(PSSGP_WAVE) void batched_smoother_kernel(SmoothPara
         extern __shared__ __align__(16) unsigned char pssgp_dyn_smem[];
         T *s_out = reinterpret_cast<T *>(pssgp_dyn_smem);
         if (gi == 0)
-            smoother_tile_finish<LA, T, false, false, ManySeries>(p, mdl, cst, sv, tr, tile, s_out);
+            smoother_tile_finish<LA, T, false, ELEMS, ManySeries>(p, mdl, cst, sv, tr, tile, s_out);
         else
-            smoother_tile_finish<LB, T, false, false, ManySeries>(p, mdl, cst, sv, tr, tile, s_out);
+            smoother_tile_finish<LB, T, false, ELEMS, ManySeries>(p, mdl, cst, sv, tr, tile, s_out);
     } else {
         if (gi == 0)
-            smoother_tile_fold<LA, T, false, ManySeries>(p, mdl, cst, sv, tr, tile);
+            smoother_tile_fold<LA, T, ELEMS, ManySeries>(p, mdl, cst, sv, tr, tile);
         else
-            smoother_tile_fold<LB, T, false, ManySeries>(p, mdl, cst, sv, tr, tile);
+            smoother_tile_fold<LB, T, ELEMS, ManySeries>(p, mdl, cst, sv, tr, tile);
     }
 }
 
@@ -151,7 +156,7 @@ __global__ __launch_bounds__(256) void series_loglik_kernel(const T *terms, cons
     if (s < n_series && lane == 0) out[s] = acc;
 }
 
-template <class LA, class LB, typename T>
+template <class LA, class LB, typename T, bool ELEMS>
 int launch_bf(const BatchLaunch &a, hipStream_t s)
 {
     FilterParams<T> p;
@@ -176,7 +181,7 @@ int launch_bf(const BatchLaunch &a, hipStream_t s)
     pass_event(a.ev, 0, s);
     if constexpr (sizeof(T) == 4)
         hipLaunchKernelGGL((batched_consts_kernel<LA, LB>), dim3(a.ngroups), dim3(256), 0, s, a);
-    hipLaunchKernelGGL((batched_filter_kernel<LA, LB, T, false>), grid, block, 0, s, p, a);
+    hipLaunchKernelGGL((batched_filter_kernel<LA, LB, T, false, false>), grid, block, 0, s, p, a);
     int rc = (int)hipGetLastError();
     if (rc) return rc;
     pass_event(a.ev, 1, s);
@@ -189,7 +194,7 @@ int launch_bf(const BatchLaunch &a, hipStream_t s)
         if (rc) return rc;
     }
     pass_event(a.ev, 2, s);
-    hipLaunchKernelGGL((batched_filter_kernel<LA, LB, T, true>), grid, block, 0, s, p, a);
+    hipLaunchKernelGGL((batched_filter_kernel<LA, LB, T, true, ELEMS>), grid, block, 0, s, p, a);
     rc = (int)hipGetLastError();
     if (rc) return rc;
     const int per_block = 256 / PSSGP_WAVE;
@@ -201,8 +206,8 @@ int launch_bf(const BatchLaunch &a, hipStream_t s)
     return rc;
 }
 
-template <class LA, class LB, typename T>
-int launch_bs(const BatchLaunch &a, hipStream_t s)
+template <class LA, class LB, typename T, bool ELEMS>
+int launch_bs(const BatchLaunch &a, void *const *ev, hipStream_t s)
 {
     SmoothParams<T> p;
     p.t = a.t;
@@ -221,13 +226,13 @@ int launch_bs(const BatchLaunch &a, hipStream_t s)
     p.lanep = (T *)a.ws.lanep;
     p.cst = a.ws.cst;
     const dim3 grid(a.total_tiles), block(PSSGP_WAVE);
-    pass_event(a.ev, 0, s);
-    if constexpr (sizeof(T) == 4)
+    pass_event(ev, 0, s);
+    if constexpr (sizeof(T) == 4 && !ELEMS)
         hipLaunchKernelGGL((batched_consts_kernel<LA, LB>), dim3(a.ngroups), dim3(256), 0, s, a);
-    hipLaunchKernelGGL((batched_smoother_kernel<LA, LB, T, false>), grid, block, 0, s, p, a);
+    hipLaunchKernelGGL((batched_smoother_kernel<LA, LB, T, false, ELEMS>), grid, block, 0, s, p, a);
     int rc = (int)hipGetLastError();
     if (rc) return rc;
-    pass_event(a.ev, 1, s);
+    pass_event(ev, 1, s);
     rc = launch_tile_scan<SmootherScanOps<LA::D, T>>(a.ws.aggp, a.g[0].slot_base, a.g[0].ntiles, true,
                                                      a.ws.inclp, a.ws.gagg, a.ws.gcarry, s);
     if (rc) return rc;
@@ -236,12 +241,20 @@ int launch_bs(const BatchLaunch &a, hipStream_t s)
                                                          a.ws.inclp, a.ws.gagg, a.ws.gcarry, s);
         if (rc) return rc;
     }
-    pass_event(a.ev, 2, s);
+    pass_event(ev, 2, s);
     const size_t smem = (size_t)2 * PSSGP_WAVE * a.chunk * sizeof(T);
-    hipLaunchKernelGGL((batched_smoother_kernel<LA, LB, T, true>), grid, block, smem, s, p, a);
+    hipLaunchKernelGGL((batched_smoother_kernel<LA, LB, T, true, ELEMS>), grid, block, smem, s, p, a);
     rc = (int)hipGetLastError();
-    pass_event(a.ev, 3, s);
+    pass_event(ev, 3, s);
     return rc;
+}
+
+template <class LA, class LB, typename T>
+int launch_bp(const BatchLaunch &a, hipStream_t s)
+{
+    int rc = launch_bf<LA, LB, T, true>(a, s);
+    if (rc) return rc;
+    return launch_bs<LA, LB, T, true>(a, a.ev ? a.ev + 4 : nullptr, s);
 }
 
 // (d0, d1) with d1 = d0 for a single group
@@ -254,8 +267,8 @@ int launch_batched_filter(const BatchLaunch &a, bool f64, hipStream_t s)
     const int d0 = a.bm[0].d, d1 = a.ngroups > 1 ? a.bm[1].d : d0;
 #define X(A, B)                                                                                   \
     if (d0 == A && d1 == B)                                                                       \
-        return f64 ? launch_bf<Layout<A, 0>, Layout<B, 0>, double>(a, s)                          \
-                   : launch_bf<Layout<A, 0>, Layout<B, 0>, float>(a, s);
+        return f64 ? launch_bf<Layout<A, 0>, Layout<B, 0>, double, false>(a, s)                   \
+                   : launch_bf<Layout<A, 0>, Layout<B, 0>, float, false>(a, s);
     PSSGP_BATCH_PAIRS(X)
 #undef X
     return -1;
@@ -266,8 +279,20 @@ int launch_batched_smooth(const BatchLaunch &a, bool f64, hipStream_t s)
     const int d0 = a.bm[0].d, d1 = a.ngroups > 1 ? a.bm[1].d : d0;
 #define X(A, B)                                                                                   \
     if (d0 == A && d1 == B)                                                                       \
-        return f64 ? launch_bs<Layout<A, 0>, Layout<B, 0>, double>(a, s)                          \
-                   : launch_bs<Layout<A, 0>, Layout<B, 0>, float>(a, s);
+        return f64 ? launch_bs<Layout<A, 0>, Layout<B, 0>, double, false>(a, a.ev, s)             \
+                   : launch_bs<Layout<A, 0>, Layout<B, 0>, float, false>(a, a.ev, s);
+    PSSGP_BATCH_PAIRS(X)
+#undef X
+    return -1;
+}
+
+int launch_batched_predict(const BatchLaunch &a, bool f64, hipStream_t s)
+{
+    const int d0 = a.bm[0].d, d1 = a.ngroups > 1 ? a.bm[1].d : d0;
+#define X(A, B)                                                                                   \
+    if (d0 == A && d1 == B)                                                                       \
+        return f64 ? launch_bp<Layout<A, 0>, Layout<B, 0>, double>(a, s)                          \
+                   : launch_bp<Layout<A, 0>, Layout<B, 0>, float>(a, s);
     PSSGP_BATCH_PAIRS(X)
 #undef X
     return -1;

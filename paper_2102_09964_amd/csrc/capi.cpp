@@ -242,7 +242,7 @@ struct BatchPlan {
     BatchGroup g[2];
     BatchModel bm[2];
     size_t off_incl = 0, off_lane = 0, off_part = 0, off_terms = 0, off_cst = 0, off_agg = 0, total = 0;
-    size_t off_gagg = 0, off_gcarry = 0;
+    size_t off_gagg = 0, off_gcarry = 0, off_hand = 0;
 };
 
 int make_batch_plan(const pssgp_batch_group *groups, int ngroups, int64_t n_series, const int64_t *off,
@@ -344,6 +344,12 @@ int make_batch_plan(const pssgp_batch_group *groups, int ngroups, int64_t n_seri
     bp.off_part = take(nt * sizeof(double) * 3);
     bp.off_cst = take(2 * PSSGP_CONST_DOUBLES * sizeof(double));
     if (op != PSSGP_OP_SMOOTH) bp.off_terms = take((size_t)(n > 0 ? n : 1) * sizeof(double));
+    if (op == PSSGP_OP_PREDICT) {
+        // smoother elements of every step in the tile layout; the slots of
+        // the second group (larger state) start past the first group's
+        // elements because the groups ascend in state size
+        bp.off_hand = take(nt * 64 * (size_t)bp.chunk * (d * d + d + d * (d + 1) / 2) * bp.tsize);
+    }
     bp.total = o;
     return PSSGP_OK;
 }
@@ -356,15 +362,15 @@ int run_batched(const pssgp_batch_group *groups, int ngroups, int64_t n_series, 
     BatchPlan bp;
     int rc = make_batch_plan(groups, ngroups, n_series, offsets_host, dtype, op, opts, bp);
     if (rc) return rc;
-    if (!offsets || !params || !t || !m || !P) {
+    if (!offsets || !params || !t || (op != PSSGP_OP_PREDICT && (!m || !P))) {
         pssgp_set_error("batched: offsets, params, t, m and P must be device pointers");
         return PSSGP_EINVAL;
     }
-    if (op == PSSGP_OP_FILTER && (!y || !loglik)) {
+    if (op != PSSGP_OP_SMOOTH && (!y || !loglik)) {
         pssgp_set_error("batched filter: y and loglik must be device pointers");
         return PSSGP_EINVAL;
     }
-    if (op == PSSGP_OP_SMOOTH && (!f_mean || !f_var)) {
+    if (op != PSSGP_OP_FILTER && (!f_mean || !f_var)) {
         pssgp_set_error("batched smoother: f_mean and f_var must be device pointers");
         return PSSGP_EINVAL;
     }
@@ -406,13 +412,21 @@ int run_batched(const pssgp_batch_group *groups, int ngroups, int64_t n_series, 
     a.ws.lanep = b + bp.off_lane;
     a.ws.partials = (double *)(b + bp.off_part);
     a.ws.cst = (double *)(b + bp.off_cst);
-    const bool zero_ll = (op == PSSGP_OP_FILTER && a.n == 0);
+    if (op == PSSGP_OP_PREDICT) {
+        a.m = b + bp.off_hand;
+        a.P = nullptr;
+        a.tiled = 1;
+    }
+    const bool zero_ll = (op != PSSGP_OP_SMOOTH && a.n == 0);
     rc = launch_ws_init(a.ws.ctl, zero_ll ? loglik : nullptr,
                         zero_ll ? (int)n_series : 0, s);
     if ((rc = hip_err((hipError_t)rc, "workspace init"))) return rc;
     if (a.n == 0) return PSSGP_OK;
     const bool f64 = dtype == PSSGP_F64;
-    rc = (op == PSSGP_OP_FILTER) ? launch_batched_filter(a, f64, s) : launch_batched_smooth(a, f64, s);
+    if (op == PSSGP_OP_PREDICT)
+        rc = launch_batched_predict(a, f64, s);
+    else
+        rc = (op == PSSGP_OP_FILTER) ? launch_batched_filter(a, f64, s) : launch_batched_smooth(a, f64, s);
     return check_launch(rc, "batched launch");
 }
 
@@ -699,7 +713,7 @@ size_t pssgp_batched_workspace_bytes(const pssgp_batch_group *groups_host, int n
                                      const int64_t *offsets_host, pssgp_dtype dtype, int op,
                                      const pssgp_options *opts)
 {
-    if (op != PSSGP_OP_FILTER && op != PSSGP_OP_SMOOTH) return 0;
+    if (op != PSSGP_OP_FILTER && op != PSSGP_OP_SMOOTH && op != PSSGP_OP_PREDICT) return 0;
     BatchPlan bp;
     if (make_batch_plan(groups_host, n_groups, n_series, offsets_host, dtype, op, opts, bp)) return 0;
     return bp.total;
@@ -723,6 +737,16 @@ int pssgp_batched_smooth(const pssgp_batch_group *groups_host, int n_groups, int
     return run_batched(groups_host, n_groups, n_series, offsets, offsets_host, params, t, nullptr, nullptr,
                        dtype, (void *)m, (void *)P, nullptr, f_mean, f_var, ws, ws_bytes, opts, stream,
                        PSSGP_OP_SMOOTH);
+}
+
+int pssgp_batched_predict(const pssgp_batch_group *groups_host, int n_groups, int64_t n_series,
+                          const int64_t *offsets, const int64_t *offsets_host, const double *params,
+                          const double *t, const void *y, const uint8_t *mask, pssgp_dtype dtype, void *f_mean,
+                          void *f_var, double *loglik, void *ws, size_t ws_bytes, const pssgp_options *opts,
+                          void *stream)
+{
+    return run_batched(groups_host, n_groups, n_series, offsets, offsets_host, params, t, y, mask, dtype, nullptr,
+                       nullptr, loglik, f_mean, f_var, ws, ws_bytes, opts, stream, PSSGP_OP_PREDICT);
 }
 
 int pssgp_status(void *ws, void *stream, uint32_t *bits_host)

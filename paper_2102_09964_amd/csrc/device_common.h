@@ -578,7 +578,9 @@ __device__ __forceinline__ void lu_solve(const T (&LU)[D][D], const int (&piv)[D
         T acc = x[c];
 #pragma unroll
         for (int k = c + 1; k < D; k++) acc = fma(-LU[c][k], x[k], acc);
-        x[c] = acc / LU[c][c];
+        // reciprocal of the pivot, shared by every right-hand side solved
+        // with the same factors (one division per pivot, not per solve)
+        x[c] = acc * (T(1) / LU[c][c]);
     }
 }
 
@@ -612,6 +614,9 @@ __device__ __forceinline__ bool cholesky(T (&A)[D][D])
 template <int D, typename T>
 __device__ __forceinline__ void chol_solve(const T (&Lf)[D][D], const T (&B)[D][D], T (&X)[D][D])
 {
+    T rd[D];  // reciprocals of the diagonal: D divisions instead of 2 D^2
+#pragma unroll
+    for (int i = 0; i < D; i++) rd[i] = T(1) / Lf[i][i];
 #pragma unroll
     for (int j = 0; j < D; j++) {
         T z[D];
@@ -620,14 +625,14 @@ __device__ __forceinline__ void chol_solve(const T (&Lf)[D][D], const T (&B)[D][
             T s = B[i][j];
 #pragma unroll
             for (int k = 0; k < i; k++) s = fma(-Lf[i][k], z[k], s);
-            z[i] = s / Lf[i][i];
+            z[i] = s * rd[i];
         }
 #pragma unroll
         for (int i = D - 1; i >= 0; i--) {
             T s = z[i];
 #pragma unroll
             for (int k = i + 1; k < D; k++) s = fma(-Lf[k][i], X[k][j], s);
-            X[i][j] = s / Lf[i][i];
+            X[i][j] = s * rd[i];
         }
     }
 }

@@ -129,6 +129,9 @@ __device__ __forceinline__ void emit_smoother_element(const T (&m)[D], const T (
 #pragma unroll
         for (int j = 0; j <= i; j++) C[i][j] = Pp[i][j];
     if (!cholesky<D, double>(C)) bad |= PSSGP_STATUS_CHOLESKY;
+    double rd[D];  // reciprocals of the Cholesky diagonal
+#pragma unroll
+    for (int i = 0; i < D; i++) rd[i] = 1.0 / C[i][i];
 #pragma unroll
     for (int j = 0; j < D; j++)
 #pragma unroll
@@ -136,7 +139,7 @@ __device__ __forceinline__ void emit_smoother_element(const T (&m)[D], const T (
             double acc = Y[i][j];
 #pragma unroll
             for (int q = 0; q < i; q++) acc = fma(-C[i][q], Y[q][j], acc);
-            Y[i][j] = acc / C[i][i];
+            Y[i][j] = acc * rd[i];
         }
 #pragma unroll
     for (int i = 0; i < D; i++)
@@ -154,7 +157,7 @@ __device__ __forceinline__ void emit_smoother_element(const T (&m)[D], const T (
             double acc = Y[i][j];
 #pragma unroll
             for (int q = i + 1; q < D; q++) acc = fma(-C[q][i], Y[q][j], acc);
-            Y[i][j] = acc / C[i][i];
+            Y[i][j] = acc * rd[i];
         }
 #pragma unroll
     for (int i = 0; i < D; i++) {

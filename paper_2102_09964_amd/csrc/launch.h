@@ -120,11 +120,15 @@ struct BatchLaunch {
     void *f_var;
     double *loglik;           // device [n_series]
     void *ll_terms;           // workspace: per-step terms
+    int tiled;                // m: smoother-element handover (filter then smoother in one call)
     ScanWs ws;
 };
 
 int launch_batched_filter(const BatchLaunch &a, bool f64, hipStream_t s);
 int launch_batched_smooth(const BatchLaunch &a, bool f64, hipStream_t s);
+// filter writing the handover, then the smoother reading it (a.tiled = 1;
+// a.ev, when set, holds 8 events: filter passes, then smoother passes)
+int launch_batched_predict(const BatchLaunch &a, bool f64, hipStream_t s);
 
 // Per-layout launchers, instantiated in one translation unit per layout.
 template <int B0, int B1>

@@ -220,6 +220,9 @@ __device__ __forceinline__ void smoother_element(const DevModel &mdl, cdouble *c
             C[i][j] = acc;
         }
     if (!cholesky<D, double>(C)) bad |= PSSGP_STATUS_CHOLESKY;
+    double rd[D];  // reciprocals of the Cholesky diagonal
+#pragma unroll
+    for (int i = 0; i < D; i++) rd[i] = 1.0 / C[i][i];
     // Y <- C^-1 Y (forward substitution, column by column)
 #pragma unroll
     for (int j = 0; j < D; j++)
@@ -228,7 +231,7 @@ __device__ __forceinline__ void smoother_element(const DevModel &mdl, cdouble *c
             double s = Y[i][j];
 #pragma unroll
             for (int q = 0; q < i; q++) s = fma(-C[i][q], Y[q][j], s);
-            Y[i][j] = s / C[i][i];
+            Y[i][j] = s * rd[i];
         }
     // L = P - Y^T Y
 #pragma unroll
@@ -250,7 +253,7 @@ __device__ __forceinline__ void smoother_element(const DevModel &mdl, cdouble *c
             double s = Y[i][j];
 #pragma unroll
             for (int q = i + 1; q < D; q++) s = fma(-C[q][i], Y[q][j], s);
-            Y[i][j] = s / C[i][i];
+            Y[i][j] = s * rd[i];
         }
 #pragma unroll
     for (int i = 0; i < D; i++) {

@@ -1,7 +1,9 @@
 """GPU parity of the batched form (many independent series of uneven
-lengths and hyperparameters, two state layouts, one persistent launch per
-scan) against the oracle run series by series, and replay of the batched
-pipeline captured in a HIP graph.
+lengths and hyperparameters, two state layouts, one set of scan launches for
+all series) against the oracle run series by series, for the fused call
+(filter and smoother in one pssgp_batched_predict, elements handed over in
+the workspace) and the separate filter and smoother calls, and replay of the
+batched pipeline captured in a HIP graph.
 """
 import numpy as np
 import pytest
@@ -35,9 +37,10 @@ def _oracle(w, dtype):
     return oracle.run_batched(models, w["offsets"], w["t"], y, w["mask"], threads=8, abs_terms=True)
 
 
-def _gpu(w, dtype, options=None, pipe=None):
+def _gpu(w, dtype, options=None, pipe=None, fused=True):
     tdt = getattr(torch, dtype)
-    pipe = pipe or P.BatchedPipeline(w["kinds"], w["offsets"], w["params"], dtype=dtype, options=options)
+    pipe = pipe or P.BatchedPipeline(w["kinds"], w["offsets"], w["params"], dtype=dtype, options=options,
+                                     fused=fused)
     t = torch.as_tensor(w["t"], dtype=torch.float64, device="cuda")
     y = torch.as_tensor(np.nan_to_num(w["y"]), dtype=tdt, device="cuda")
     mask = torch.as_tensor(w["mask"], dtype=torch.uint8, device="cuda")
@@ -65,22 +68,33 @@ def _check(g, o, off, dtype):
     assert worst["f_mean"] <= tol[0] and worst["f_var"] <= tol[0] and worst["loglik"] <= tol[1], worst
 
 
+@pytest.mark.parametrize("fused", [True, False])
 @pytest.mark.parametrize("dtype", ["float64", "float32"])
-def test_batched_vs_oracle(dtype):
+def test_batched_vs_oracle(dtype, fused):
     w = _batch()
     assert set(np.unique(w["kinds"])) == {P.MATERN32, P.MATERN52}
     o = _oracle(w, dtype)
-    g, _ = _gpu(w, dtype)
+    g, _ = _gpu(w, dtype, fused=fused)
     assert g["status"] == (0, 0)
     _check(g, o, w["offsets"], dtype)
 
 
+@pytest.mark.parametrize("fused", [True, False])
 @pytest.mark.parametrize("chunk", [1, 5, 64])
-def test_batched_chunks(chunk):
+def test_batched_chunks(chunk, fused):
     w = _batch(n_series=30, min_len=3, max_len=900, seed=chunk)
     o = _oracle(w, "float64")
-    g, _ = _gpu(w, "float64", options=P.make_options(chunk=chunk))
+    g, _ = _gpu(w, "float64", options=P.make_options(chunk=chunk), fused=fused)
     _check(g, o, w["offsets"], "float64")
+
+
+@pytest.mark.parametrize("chunk", [4, 16])
+def test_batched_fused_float32_chunks(chunk):
+    w = _batch(n_series=30, min_len=3, max_len=900, seed=10 + chunk)
+    o = _oracle(w, "float32")
+    g, _ = _gpu(w, "float32", options=P.make_options(chunk=chunk))
+    assert g["status"] == (0, 0)
+    _check(g, o, w["offsets"], "float32")
 
 
 def test_batched_single_kind_and_short_series():
@@ -97,8 +111,9 @@ def test_batched_single_kind_and_short_series():
     w2 = {"t": w["t"][sel], "y": w["y"][sel], "mask": w["mask"][sel], "offsets": np.array(off),
           "kinds": w["kinds"][idx], "params": w["params"][idx], "models": [w["models"][s] for s in idx]}
     o = _oracle(w2, "float64")
-    g, _ = _gpu(w2, "float64")
-    _check(g, o, w2["offsets"], "float64")
+    for fused in (True, False):
+        g, _ = _gpu(w2, "float64", fused=fused)
+        _check(g, o, w2["offsets"], "float64")
 
 
 def test_batched_equals_single_series_path():
