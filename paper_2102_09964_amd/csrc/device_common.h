@@ -12,14 +12,21 @@
 
 #define PSSGP_WAVE 64
 
-// Minimum waves per SIMD requested from the compiler for the FP32 fold and
-// finish kernels (register budget 512 / waves per lane).
-#ifndef PSSGP_FILTER_MINW
-#define PSSGP_FILTER_MINW 2
-#endif
-#ifndef PSSGP_SMOOTHER_MINW
-#define PSSGP_SMOOTHER_MINW 2
-#endif
+// Waves per SIMD that the scan kernels ask the compiler for (launch
+// bounds; a lane's register budget is 512 / waves, accumulation registers
+// included). Two where a lane's working set fits in 256 registers; one
+// where it does not, so that the accumulation registers hold what would
+// otherwise spill to scratch memory, which misses in L2 and goes to HBM
+// (at d = 8 the FP32 filter fold and finish ran 2.6x faster with one wave
+// than with two). FP64 scans always take one.
+template <int D, typename T>
+constexpr int fold_waves() { return sizeof(T) == 8 ? 1 : (D >= 7 ? 1 : 2); }
+template <int D, typename T>
+constexpr int finish_waves() { return sizeof(T) == 8 ? 1 : (D >= 6 ? 1 : 2); }
+// smoother scans that build their elements from the filter moments hold
+// the FP64 element algebra; those reading handed-over elements do not
+template <int D, typename T, bool ELEMS>
+constexpr int smoother_waves() { return sizeof(T) == 8 ? 1 : ((ELEMS || D < 7) ? 2 : 1); }
 
 // Arithmetic type of the general filtering operator where it is applied
 // once per lane or tile (the carry scan and the lane-start moments). The

@@ -394,7 +394,8 @@ __device__ __forceinline__ void filter_tile_finish(const FilterParams<T> &p, con
 
 // CT: arithmetic type of the lane scan's combinations
 template <class LY, typename T, typename CT>
-__global__ __launch_bounds__(PSSGP_WAVE, sizeof(T) == 4 ? PSSGP_FILTER_MINW : 1) void filter_fold_kernel(FilterParams<T> p, DevModel mdl_arg)
+__global__ __launch_bounds__(PSSGP_WAVE, (fold_waves<LY::D, T>())) void filter_fold_kernel(FilterParams<T> p,
+                                                                                        DevModel mdl_arg)
 {
     __shared__ DevModel mdl;
     model_to_lds(mdl_arg, mdl);
@@ -405,7 +406,8 @@ __global__ __launch_bounds__(PSSGP_WAVE, sizeof(T) == 4 ? PSSGP_FILTER_MINW : 1)
 }
 
 template <class LY, typename T, typename CT, int MODE>
-__global__ __launch_bounds__(PSSGP_WAVE, sizeof(T) == 4 ? PSSGP_FILTER_MINW : 1) void filter_finish_kernel(FilterParams<T> p, DevModel mdl_arg)
+__global__ __launch_bounds__(PSSGP_WAVE, (finish_waves<LY::D, T>())) void filter_finish_kernel(FilterParams<T> p,
+                                                                                            DevModel mdl_arg)
 {
     __shared__ DevModel mdl;
     const int lane = lane_id();
