@@ -96,9 +96,9 @@ __global__ __launch_bounds__(PSSGP_WAVE) void batched_filter_kernel(FilterParams
         constexpr int MODE = ELEMS ? F_ELEMS : F_MOMENTS;
         double ll = 0.0;
         if (gi == 0)
-            filter_tile_finish<LA, T, typename CombineType<T>::type, MODE, ManySeries>(p, mdl, cst, sv, tr, tile, ll);
+            filter_tile_finish<LA, T, double, MODE, ManySeries>(p, mdl, cst, sv, tr, tile, ll);
         else
-            filter_tile_finish<LB, T, typename CombineType<T>::type, MODE, ManySeries>(p, mdl, cst, sv, tr, tile, ll);
+            filter_tile_finish<LB, T, double, MODE, ManySeries>(p, mdl, cst, sv, tr, tile, ll);
     } else {
         if (gi == 0)
             filter_tile_fold<LA, T, T, ManySeries>(p, mdl, cst, sv, tr, tile);

@@ -258,15 +258,16 @@ __device__ __forceinline__ void discretize(const DevModel &mdl, const StepScale 
 
 // ------------------------------------------------------------------ transition for the FP32 scans
 //
-// With F(s) = sum_r phi_r(s) M_r (the expansion above), the process noise of
-// a block is
-//   Q = Pinf - F Pinf F^T = Pinf - sum_{r <= r'} phi_r phi_r' N_rr',
-//   N_rr = M_r Pinf M_r^T,  N_rr' = M_r Pinf M_r'^T + M_r' Pinf M_r^T (r < r').
-// The N are built once per call into device memory (consts_build) and read
-// as scalar operands, so a step needs the phi in FP64 and one FP64
-// accumulation per entry of F - I and of Q, without FP64 matrix
-// temporaries. The scan receives Dl = F - I and Q, rounded to the scan
-// type.
+// With F(s) = sum_r phi_r(s) M_r (the expansion above) the process noise of
+// a block is Q = Pinf - F Pinf F^T (stationarity of the SDE). The M_r and
+// Pinf are copied once per call into device memory (consts_build) and read
+// as scalar operands; a step computes the phi, F - I (dc^3 multiply-adds)
+// and Q row by row from F - I (dc^3 + dc^2 (dc + 1) / 2), all in FP64. The
+// scan receives Dl = F - I and Q, rounded to the scan type. (The
+// alternative Q = Pinf - sum_{r <= r'} phi_r phi_r' M_r Pinf M_r'^T needs
+// (dc (dc + 1) / 2)^2 multiply-adds and as many constants, and the
+// expansion matrices M_r of the RBF blocks are spectral projectors with
+// norms up to the eigenbasis condition number, which its terms cancel.)
 
 // (i, j), i <= j, of the row-major packed upper index e of an n x n matrix
 __device__ __forceinline__ void unpack_upper(int e, int n, int &i, int &j)
@@ -289,21 +290,12 @@ typedef const __attribute__((address_space(4))) double cdouble;
 // iteration instead of being hoisted (and held in registers) across it.
 #define PSSGP_LAUNDER(ptr) asm volatile("" : "+s"(ptr))
 
-// Layout of the constants of the FP32 transition: per block the expansion
-// matrices M_r (dc^3) and the pair matrices N_rr' (np^2, packed upper
-// entries of each pair), then Pinf (D^2, row-major).
+// Layout of the constants of the fast transition: per block the expansion
+// matrices M_r (dc^3), then Pinf (D^2, row-major).
 template <class LY>
 struct ConstLayout {
-    __host__ __device__ static constexpr int np(int b) { return LY::bdim(b) * (LY::bdim(b) + 1) / 2; }
-    __host__ __device__ static constexpr int size(int b)
-    {
-        return LY::bdim(b) * LY::bdim(b) * LY::bdim(b) + np(b) * np(b);
-    }
+    __host__ __device__ static constexpr int size(int b) { return LY::bdim(b) * LY::bdim(b) * LY::bdim(b); }
     __host__ __device__ static constexpr int m_off(int b) { return b == 0 ? 0 : size(0); }
-    __host__ __device__ static constexpr int n_off(int b)
-    {
-        return m_off(b) + LY::bdim(b) * LY::bdim(b) * LY::bdim(b);
-    }
     static constexpr int PINF = size(0) + (LY::NB > 1 ? size(1) : 0);
     static constexpr int TOTAL = PINF + LY::D * LY::D;
 };
@@ -314,23 +306,9 @@ __device__ void consts_build(const DevModel &mdl, double *out)
 {
     static_assert(ConstLayout<LY>::TOTAL <= PSSGP_CONST_DOUBLES, "constants exceed their workspace room");
     for (int b = 0; b < LY::NB; b++) {
-        const int dc = LY::bdim(b), o = LY::boff(b), np = ConstLayout<LY>::np(b);
+        const int dc = LY::bdim(b);
         const double *M = mdl.fcoef + mdl.blk[b].fc_off;
         for (int e = (int)threadIdx.x; e < dc * dc * dc; e += (int)blockDim.x) out[ConstLayout<LY>::m_off(b) + e] = M[e];
-        for (int e = (int)threadIdx.x; e < np * np; e += (int)blockDim.x) {
-            const int pr = e / np, en = e - pr * np;
-            int r, r2, i, j;
-            unpack_upper(pr, dc, r, r2);
-            unpack_upper(en, dc, i, j);
-            double acc = 0.0;
-            for (int k = 0; k < dc; k++)
-                for (int l = 0; l < dc; l++) {
-                    const double pk = mdl.Pinf[(o + k) * LY::D + o + l];
-                    acc = fma(M[r * dc * dc + i * dc + k] * pk, M[r2 * dc * dc + j * dc + l], acc);
-                    if (r != r2) acc = fma(M[r2 * dc * dc + i * dc + k] * pk, M[r * dc * dc + j * dc + l], acc);
-                }
-            out[ConstLayout<LY>::n_off(b) + e] = acc;
-        }
     }
     for (int e = (int)threadIdx.x; e < LY::D * LY::D; e += (int)blockDim.x) out[ConstLayout<LY>::PINF + e] = mdl.Pinf[e];
 }
@@ -348,7 +326,6 @@ __device__ __forceinline__ void disc_fast_block(const DevModel &mdl, cdouble *cs
     constexpr int D = LY::D;
     constexpr int dc = LY::bdim(b);
     constexpr int o = LY::boff(b);
-    constexpr int np = dc * (dc + 1) / 2;
     const DevBlock &bk = mdl.blk[b];
     const double s = dt * sc.inv_ell[b];
     double phi[dc];
@@ -376,6 +353,7 @@ __device__ __forceinline__ void disc_fast_block(const DevModel &mdl, cdouble *cs
 #pragma unroll
     for (int r = 0; r < dc; r++) phi[r] = first ? 0.0 : phi[r];
     cdouble *M = cst + ConstLayout<LY>::m_off(b);
+    double dl[dc][dc];  // F - I of the block in FP64
 #pragma unroll
     for (int i = 0; i < dc; i++) {
 #pragma unroll
@@ -383,42 +361,44 @@ __device__ __forceinline__ void disc_fast_block(const DevModel &mdl, cdouble *cs
             double acc = (i == j) ? -1.0 : 0.0;
 #pragma unroll
             for (int r = 0; r < dc; r++) acc = fma(phi[r], M[r * dc * dc + i * dc + j], acc);
+            dl[i][j] = acc;
             Dl[o + i][o + j] = T(acc);
         }
         __builtin_amdgcn_sched_barrier(0);
     }
-    double pp[np];
+    // Q = Pinf - F Pinf F^T with F = I + dl, one row at a time: with
+    // x = row i of dl Pinf and w = row i of F Pinf = Pinf_i + x,
+    // Q_ij = -(x_j + sum_k w_k dl_jk). The difference is formed from the
+    // dl terms only, so a short step does not subtract two nearly equal
+    // copies of Pinf; F = 0 (dl = -I) gives Q = Pinf exactly
+    cdouble *Pi = cst + ConstLayout<LY>::PINF;
 #pragma unroll
-    for (int r = 0, e = 0; r < dc; r++)
+    for (int i = 0; i < dc; i++) {
+        double x[dc], w[dc];
 #pragma unroll
-        for (int r2 = r; r2 < dc; r2++, e++) pp[e] = phi[r] * phi[r2];
-    cdouble *N = cst + ConstLayout<LY>::n_off(b);
-    double qa[np];
+        for (int k = 0; k < dc; k++) {
+            double acc = 0.0;
 #pragma unroll
-    for (int i = 0, x = 0; i < dc; i++)
+            for (int q = 0; q < dc; q++) acc = fma(dl[i][q], Pi[(o + q) * D + o + k], acc);
+            x[k] = acc;
+            w[k] = Pi[(o + i) * D + o + k] + acc;
+        }
 #pragma unroll
-        for (int j = i; j < dc; j++, x++) qa[x] = cst[ConstLayout<LY>::PINF + (o + i) * D + o + j];
-    // one pair at a time; the scheduling barriers keep the LDS reads of a
-    // pair from being hoisted over the others (register pressure)
+        for (int j = i; j < dc; j++) {
+            double acc = x[j];
 #pragma unroll
-    for (int e = 0; e < np; e++) {
-#pragma unroll
-        for (int x = 0; x < np; x++) qa[x] = fma(-pp[e], N[e * np + x], qa[x]);
-        __builtin_amdgcn_sched_barrier(0);
-    }
-#pragma unroll
-    for (int i = 0, x = 0; i < dc; i++)
-#pragma unroll
-        for (int j = i; j < dc; j++, x++) {
-            const T q = T(qa[x] * sc.var_mult);
+            for (int k = 0; k < dc; k++) acc = fma(w[k], dl[j][k], acc);
+            const T q = T(-acc * sc.var_mult);
             Q[o + i][o + j] = q;
             Q[o + j][o + i] = q;
         }
+        __builtin_amdgcn_sched_barrier(0);
+    }
 }
 
 // Dl = F - I and Q of a step in the scan type T (first: series start, the
 // prior, Dl = -I and Q = Pinf). A zero step gives Dl and Q of the order of
-// the FP64 rounding of the expansion, below the resolution of T.
+// the FP64 rounding of the expansion.
 template <class LY, typename T>
 __device__ __forceinline__ void discretize_fast(const DevModel &mdl, cdouble *cst, const StepScale &sc, double dt,
                                                 bool first, T (&Dl)[LY::D][LY::D], T (&Q)[LY::D][LY::D])

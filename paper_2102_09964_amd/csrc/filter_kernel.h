@@ -63,8 +63,8 @@ struct TileRange {
 };
 
 // Transition of a step, Dl = F - I (F = 0 at a series start, so Dl = -I
-// there) and Q, rounded to U: for FP32 scans (T) by the pair expansion of
-// Q with the constants at cst, for FP64 scans by the FP64 discretisation.
+// there) and Q, rounded to U: for FP32 scans (T) from the expansion of F
+// with the constants at cst, for FP64 scans by the FP64 discretisation.
 template <class LY, typename U, typename T = U>
 __device__ __forceinline__ void step_transition(const DevModel &mdl, cdouble *cst, const StepScale &sc,
                                                 double dt, bool first, U (&Dl)[LY::D][LY::D],
@@ -225,6 +225,7 @@ __device__ __forceinline__ void filter_tile_fold(const FilterParams<T> &p, const
     for (int i = 0; i < D; i++) h[i] = T(mdl.H[i]);
     FAgg<D, T> agg;
     agg_identity<D, T>(agg);
+    bool from_start = false;  // the aggregate covers a series start, so its A is 0
     StepInputs<T> in;
     in.start(p.t, p.y, p.mask, k0, k1, tr.k_begin);
     for (int64_t k = k0; k < k1; k++) {
@@ -236,6 +237,7 @@ __device__ __forceinline__ void filter_tile_fold(const FilterParams<T> &p, const
         PSSGP_RELOAD_CONSTANTS();
         sv.seek(k);
         const bool first = sv.first(k);
+        from_start = from_start || first;
         const double dt = first ? 0.0 : in.tc - in.tp;
         cdouble *c = cst;
         PSSGP_LAUNDER(c);
@@ -251,7 +253,25 @@ __device__ __forceinline__ void filter_tile_fold(const FilterParams<T> &p, const
     for (int o = 1; o < PSSGP_WAVE; o <<= 1) {
         FAgg<D, T> other;
         agg_shfl_up<D, T>(agg, other, o);
-        if (lane >= o) agg_combine<D, T, CT>(other, agg, agg);
+        const bool other_from_start = __shfl_up((int)from_start, o, PSSGP_WAVE) != 0;
+        if (lane >= o) {
+            if (other_from_start) {
+                // the earlier prefix starts at a series start: it is a pair of
+                // filter moments (A = 0; its eta, J are never used again), and
+                // the combination is its conditioning on the later aggregate,
+                // which cancels when that aggregate is informative: in FP64
+                moments_apply<D, T, double>(other.b, other.C, agg, agg.b, agg.C);
+#pragma unroll
+                for (int i = 0; i < D; i++) {
+                    agg.eta[i] = T(0);
+#pragma unroll
+                    for (int j = 0; j < D; j++) { agg.A[i][j] = T(0); agg.J[i][j] = T(0); }
+                }
+            } else {
+                agg_combine<D, T, CT>(other, agg, agg);
+            }
+            from_start = from_start || other_from_start;
+        }
     }
     agg_store<D, T>(lane_rec(p.lanep, slot, AGG, lane), agg, PSSGP_WAVE);
     if (lane == PSSGP_WAVE - 1) agg_store<D, T>(p.aggp + (size_t)slot * AGG, agg);  // tile aggregate
@@ -509,12 +529,14 @@ int launch_filter_t(const DevModel &mdl, const FilterLaunch &a, hipStream_t s)
                                                             a.ws.gcarry, s);
         if (rc) return rc;
         pass_event(a.ev, 2, s);
+        // lane-start moments (the lane's exclusive prefix applied to the
+        // tile's carry, once per lane) in FP64
         if (a.m && a.tiled)
-            hipLaunchKernelGGL((filter_finish_kernel<LY, T, CT, F_ELEMS>), grid, block, 0, s, p, mdl);
+            hipLaunchKernelGGL((filter_finish_kernel<LY, T, double, F_ELEMS>), grid, block, 0, s, p, mdl);
         else if (a.m)
-            hipLaunchKernelGGL((filter_finish_kernel<LY, T, CT, F_MOMENTS>), grid, block, 0, s, p, mdl);
+            hipLaunchKernelGGL((filter_finish_kernel<LY, T, double, F_MOMENTS>), grid, block, 0, s, p, mdl);
         else
-            hipLaunchKernelGGL((filter_finish_kernel<LY, T, CT, 0>), grid, block, 0, s, p, mdl);
+            hipLaunchKernelGGL((filter_finish_kernel<LY, T, double, 0>), grid, block, 0, s, p, mdl);
     }
     rc = (int)hipGetLastError();
     pass_event(a.ev, 3, s);

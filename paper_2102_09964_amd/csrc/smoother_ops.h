@@ -162,8 +162,8 @@ __device__ __forceinline__ size_t elem_index(int slot, int chunk, int j, int lan
 // transition comes as Dl = F - I. The last step of a series takes the
 // transition F = 0, Q = Pinf, for which the same formulas give exactly its
 // element (0, m, P); every lane runs the same instruction stream. FP32
-// scans use the pair expansion of the transition (constants at cst), FP64
-// scans the FP64 discretisation.
+// scans use the expansion of the transition (constants at cst), FP64 scans
+// the FP64 discretisation.
 template <class LY, typename T, class SV>
 __device__ __forceinline__ void smoother_element(const DevModel &mdl, cdouble *cst, const SV &sv,
                                                  const double *t, const T *mk, const T *pk, size_t st, int64_t k,

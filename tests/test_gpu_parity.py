@@ -195,12 +195,13 @@ def test_fused_predict_vs_oracle(layout, dtype):
                 "loglik": abs(float(r["loglik"].cpu()[0]) - o["loglik"]) / abs(o["loglik"])}
         print("  ", {k: "%.2e" % v for k, v in errs.items()}, flush=True)
         assert P.status(r["ws"]) == 0
-        # the d = 8 sum kernel in FP32: the smoothed variance near the series
-        # start inherits the FP32 rounding of the filter moments along the
-        # whole series (an emulation with FP32 moment storage and exact
-        # arithmetic gives 5e-5); its FP32 parity is stated for the
-        # log-likelihood (the workload it serves), f_var is held to 1e-3
-        var_tol = 1e-3 if (layout == "m32+rbf6" and dtype == "float32") else tol["var"]
+        # the d = 8 sum kernel in FP32: with the prefixes from the series
+        # start and the lane starts conditioned in FP64, 2-3e-4 of f_var
+        # remain from the FP32 storage of the moments and smoother elements
+        # and the FP32 smoother operator (an emulation with FP32 moment
+        # storage and exact arithmetic gives 5e-5); its FP32 parity is stated
+        # for the log-likelihood (the workload it serves), f_var is held to 5e-4
+        var_tol = 5e-4 if (layout == "m32+rbf6" and dtype == "float32") else tol["var"]
         assert errs["f_mean"] <= tol["mean"] and errs["f_var"] <= var_tol and errs["loglik"] <= tol["loglik"], errs
 
 
