@@ -23,10 +23,8 @@ template <int D, typename T>
 constexpr int fold_waves() { return sizeof(T) == 8 ? 1 : (D >= 7 ? 1 : 2); }
 template <int D, typename T>
 constexpr int finish_waves() { return sizeof(T) == 8 ? 1 : (D >= 6 ? 1 : 2); }
-// smoother scans that build their elements from the filter moments hold
-// the FP64 element algebra; those reading handed-over elements do not
-template <int D, typename T, bool ELEMS>
-constexpr int smoother_waves() { return sizeof(T) == 8 ? 1 : ((ELEMS || D < 7) ? 2 : 1); }
+template <int D, typename T>
+constexpr int smoother_waves() { return sizeof(T) == 8 ? 1 : (D >= 7 ? 1 : 2); }
 
 // Arithmetic type of the general filtering operator where it is applied
 // once per lane or tile (the carry scan and the lane-start moments). The

@@ -161,7 +161,7 @@ __device__ __forceinline__ void smoother_tile_finish(const SmoothParams<T> &p, c
 // ELEMS: the smoother elements come from the filter of the same call (tile
 // layout at p.m) instead of being built from the filter moments.
 template <class LY, typename T, bool ELEMS>
-__global__ __launch_bounds__(PSSGP_WAVE, (smoother_waves<LY::D, T, ELEMS>())) void smoother_fold_kernel(SmoothParams<T> p,
+__global__ __launch_bounds__(PSSGP_WAVE, (smoother_waves<LY::D, T>())) void smoother_fold_kernel(SmoothParams<T> p,
                                                                                            DevModel mdl_arg)
 {
     __shared__ DevModel mdl;
@@ -173,7 +173,7 @@ __global__ __launch_bounds__(PSSGP_WAVE, (smoother_waves<LY::D, T, ELEMS>())) vo
 }
 
 template <class LY, typename T, bool FULL, bool ELEMS>
-__global__ __launch_bounds__(PSSGP_WAVE, (smoother_waves<LY::D, T, ELEMS>())) void smoother_finish_kernel(SmoothParams<T> p,
+__global__ __launch_bounds__(PSSGP_WAVE, (smoother_waves<LY::D, T>())) void smoother_finish_kernel(SmoothParams<T> p,
                                                                                              DevModel mdl_arg)
 {
     __shared__ DevModel mdl;

@@ -111,18 +111,25 @@ __global__ __launch_bounds__(PSSGP_TS_THREADS) void tile_scan_kernel(const typen
     const int wv = tid / PSSGP_WAVE;
     const int per = (ntiles + PSSGP_TS_THREADS - 1) / PSSGP_TS_THREADS;
     const int i0 = min(tid * per, ntiles), i1 = min(i0 + per, ntiles);
+    // threads holding tiles, and how many of them are in this wave (uniform
+    // over the wave): scan levels beyond that would combine identities only
+    const int nact = (ntiles + per - 1) / per;
+    const int wact = min(max(nact - wv * PSSGP_WAVE, 0), PSSGP_WAVE);
     auto slot_of = [&](int i) { return slot_base + (reverse ? ntiles - 1 - i : i); };
     auto agg_at = [&](int i) { return aggp + (size_t)slot_of(i) * Ops::AGG; };
 
     // fold of this thread's tiles, then inclusive scan over the wave
     Agg acc;
-    Ops::identity(acc);
-    for (int i = i0; i < i1; i++) {
+    if (i0 < i1)
+        Ops::load(agg_at(i0), acc);
+    else
+        Ops::identity(acc);
+    for (int i = i0 + 1; i < i1; i++) {
         Agg x;
         Ops::load(agg_at(i), x);
         Ops::extend(acc, x, acc);
     }
-    for (int o = 1; o < PSSGP_WAVE; o <<= 1) {
+    for (int o = 1; o < wact; o <<= 1) {
         Agg other;
         agg_shfl_up_raw<Agg, T>(acc, other, o);
         if (lane >= o) Ops::extend(other, acc, acc);
@@ -143,13 +150,15 @@ __global__ __launch_bounds__(PSSGP_TS_THREADS) void tile_scan_kernel(const typen
 #pragma unroll
         for (int j = 0; j < D; j++) M[i][j] = T(0);
     }
-    for (int q = 0; q < wv; q++) {
-        Agg x;
-        T *d = reinterpret_cast<T *>(&x);
-        for (int i = 0; i < NW; i++) d[i] = s_tot[q][i];
-        Ops::apply(v, M, x);
+    if (wact > 0) {
+        for (int q = 0; q < wv; q++) {
+            Agg x;
+            T *d = reinterpret_cast<T *>(&x);
+            for (int i = 0; i < NW; i++) d[i] = s_tot[q][i];
+            Ops::apply(v, M, x);
+        }
     }
-    if (lane > 0) Ops::apply(v, M, prev);
+    if (lane > 0 && i0 < i1) Ops::apply(v, M, prev);
     for (int i = i0; i < i1; i++) {
         Ops::mom_store(carry + (size_t)slot_of(i) * Ops::MOM, v, M);
         Agg x;
@@ -178,18 +187,21 @@ __global__ __launch_bounds__(PSSGP_WAVE) void group_reduce_kernel(typename Ops::
     const int lane = lane_id();
     const int i = (int)blockIdx.x * PSSGP_WAVE + lane;
     const int slot = slot_base + (reverse ? ntiles - 1 - i : i);
+    // tiles in this group (the last one may be partial): the scan levels
+    // beyond them would combine identities only
+    const int act = min(ntiles - (int)blockIdx.x * PSSGP_WAVE, PSSGP_WAVE);
     Agg acc;
     if (i < ntiles)
         Ops::load(aggp + (size_t)slot * Ops::AGG, acc);
     else
         Ops::identity(acc);
-    for (int o = 1; o < PSSGP_WAVE; o <<= 1) {
+    for (int o = 1; o < act; o <<= 1) {
         Agg other;
         agg_shfl_up_raw<Agg, T>(acc, other, o);
         if (lane >= o) Ops::extend(other, acc, acc);
     }
     if (i < ntiles) Ops::store(aggp + (size_t)slot * Ops::AGG, acc);
-    if (lane == PSSGP_WAVE - 1) Ops::store(gagg + (size_t)blockIdx.x * Ops::AGG, acc);
+    if (lane == act - 1) Ops::store(gagg + (size_t)blockIdx.x * Ops::AGG, acc);  // group total
 }
 
 template <class Ops>
