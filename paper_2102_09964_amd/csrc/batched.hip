@@ -177,6 +177,7 @@ int launch_bf(const BatchLaunch &a, hipStream_t s)
     p.aggp = (T *)a.ws.aggp;
     p.lanep = (T *)a.ws.lanep;
     p.partials = a.ws.partials;
+    p.slane = (T *)a.slane;
     const dim3 grid(a.total_tiles), block(PSSGP_WAVE);
     pass_event(a.ev, 0, s);
     if constexpr (sizeof(T) == 4)
@@ -225,6 +226,7 @@ int launch_bs(const BatchLaunch &a, void *const *ev, hipStream_t s)
     p.aggp = (T *)a.ws.aggp;
     p.lanep = (T *)a.ws.lanep;
     p.cst = a.ws.cst;
+    p.slane = (const T *)a.slane;
     const dim3 grid(a.total_tiles), block(PSSGP_WAVE);
     pass_event(ev, 0, s);
     if constexpr (sizeof(T) == 4 && !ELEMS)

@@ -27,6 +27,7 @@ struct Plan {
     size_t off_x = 0, off_xraw = 0;  // plain baseline element arrays
     size_t off_gagg = 0, off_gcarry = 0;  // carry pass group scratch
     size_t off_hand = 0;             // predict: filter-to-smoother handover
+    size_t off_slane = 0;            // predict: per-lane smoother aggregates
     size_t total = 0;
 };
 
@@ -91,6 +92,7 @@ Plan make_plan(int d, int ncomp, int64_t n, pssgp_dtype dtype, int op, const pss
         p.off_lane = take(nt * 64 * filter_agg_elems(d) * p.tsize);
         p.off_part = take(nt * sizeof(double) * n_params(ncomp));
         p.off_hand = take(nt * 64 * (size_t)p.chunk * (d * d + d + d * (d + 1) / 2) * p.tsize);
+        p.off_slane = take(nt * 64 * (size_t)smooth_agg_elems(d) * p.tsize);
         p.total = off;
         return p;
     }
@@ -242,7 +244,7 @@ struct BatchPlan {
     BatchGroup g[2];
     BatchModel bm[2];
     size_t off_incl = 0, off_lane = 0, off_part = 0, off_terms = 0, off_cst = 0, off_agg = 0, total = 0;
-    size_t off_gagg = 0, off_gcarry = 0, off_hand = 0;
+    size_t off_gagg = 0, off_gcarry = 0, off_hand = 0, off_slane = 0;
 };
 
 int make_batch_plan(const pssgp_batch_group *groups, int ngroups, int64_t n_series, const int64_t *off,
@@ -349,6 +351,7 @@ int make_batch_plan(const pssgp_batch_group *groups, int ngroups, int64_t n_seri
         // the second group (larger state) start past the first group's
         // elements because the groups ascend in state size
         bp.off_hand = take(nt * 64 * (size_t)bp.chunk * (d * d + d + d * (d + 1) / 2) * bp.tsize);
+        bp.off_slane = take(nt * 64 * (size_t)smooth_agg_elems(d) * bp.tsize);
     }
     bp.total = o;
     return PSSGP_OK;
@@ -414,6 +417,7 @@ int run_batched(const pssgp_batch_group *groups, int ngroups, int64_t n_series, 
     a.ws.cst = (double *)(b + bp.off_cst);
     if (op == PSSGP_OP_PREDICT) {
         a.m = b + bp.off_hand;
+        a.slane = b + bp.off_slane;
         a.P = nullptr;
         a.tiled = 1;
     }
@@ -633,6 +637,7 @@ int pssgp_predict(const pssgp_model *model, const double *t, const void *y, cons
     a.loglik = loglik;
     a.ck = nullptr;
     a.tiled = 1;
+    a.slane = b + p.off_slane;
     a.ws = sw;
     rc = check_launch(launch_filter(dm, b0, b1, dtype == PSSGP_F64, a, s), "filter launch");
     if (rc) return rc;
@@ -647,6 +652,7 @@ int pssgp_predict(const pssgp_model *model, const double *t, const void *y, cons
     sm.f_mean = f_mean;
     sm.f_var = f_var;
     sm.tiled = 1;
+    sm.slane = b + p.off_slane;
     sm.ws = sw;
     return check_launch(launch_smoother(dm, b0, b1, dtype == PSSGP_F64, sm, s), "smoother launch");
 }

@@ -52,6 +52,7 @@ struct FilterParams {
     T *inclp;
     T *lanep;
     double *partials;
+    T *slane;  // fused call: per-lane smoother aggregates (lane_aggregate_handover)
 };
 
 // Tile geometry: steps [k_begin, k_end) split into ntiles tiles; workspace
@@ -108,7 +109,7 @@ struct StepInputs {
     }
 };
 
-// Smoother element of step k (supplement, Proposition 2), emitted by the
+// Smoother element of step k (supplement, Proposition 2), built by the
 // filter right after predicting step k + 1, from what that prediction
 // already holds: the filtered moments (m, P) of step k and, in FP64,
 // Y = F P, mp = F m and Pp = F P F^T + Q of step k + 1:
@@ -116,11 +117,12 @@ struct StepInputs {
 //   E = (C^-T Y)^T = P F^T Pp^-1, g = m - E mp.
 // At the last step of a series the caller passes the prior transition
 // (F = 0, Q = Pinf), for which these give exactly the element (0, m, P).
-// The element is stored as (E row-major, g, L packed) with field stride st.
+// e receives the element rounded to T.
 template <int D, typename T>
-__device__ __forceinline__ void emit_smoother_element(const T (&m)[D], const T (&P)[D][D], double (&Y)[D][D],
-                                                      const double (&mp)[D], const double (&Pp)[D][D], T *out,
-                                                      size_t st, uint32_t &bad)
+__device__ __forceinline__ void smoother_element_from_prediction(const T (&m)[D], const T (&P)[D][D],
+                                                                 double (&Y)[D][D], const double (&mp)[D],
+                                                                 const double (&Pp)[D][D], SAgg<D, T> &e,
+                                                                 uint32_t &bad)
 {
     // Y holds F P on entry and is overwritten
     double C[D][D];
@@ -148,7 +150,8 @@ __device__ __forceinline__ void emit_smoother_element(const T (&m)[D], const T (
             double acc = (double)P[i][j];
 #pragma unroll
             for (int q = 0; q < D; q++) acc = fma(-Y[q][i], Y[q][j], acc);
-            out[(size_t)(D * D + D + sidx<D>(i, j)) * st] = T(acc);
+            e.L[i][j] = T(acc);
+            e.L[j][i] = e.L[i][j];
         }
 #pragma unroll
     for (int j = 0; j < D; j++)
@@ -164,10 +167,21 @@ __device__ __forceinline__ void emit_smoother_element(const T (&m)[D], const T (
         double acc = (double)m[i];
 #pragma unroll
         for (int q = 0; q < D; q++) acc = fma(-Y[q][i], mp[q], acc);
-        out[(size_t)(D * D + i) * st] = T(acc);
+        e.g[i] = T(acc);
 #pragma unroll
-        for (int j = 0; j < D; j++) out[(size_t)(i * D + j) * st] = T(Y[j][i]);
+        for (int j = 0; j < D; j++) e.E[i][j] = T(Y[j][i]);
     }
+}
+
+// The smoother element of a step is handed over (stored in the tile layout)
+// and, where the smoother takes lane aggregates from the filter
+// (lane_aggregate_handover), also appended to the lane's running smoother
+// aggregate: acc <- acc (x) e (acc covers the lane's earlier steps).
+template <int D, typename T, bool LANEAGG>
+__device__ __forceinline__ void hand_over_element(const SAgg<D, T> &e, T *out, SAgg<D, T> &acc)
+{
+    sagg_store<D, T>(out, e, PSSGP_WAVE);
+    if constexpr (LANEAGG) sagg_combine<D, T>(acc, e, acc);
 }
 
 // Predicted moments of one step in FP64 from (m, P) in T and the FP64
@@ -301,6 +315,11 @@ __device__ __forceinline__ void filter_tile_finish(const FilterParams<T> &p, con
     for (int i = 0; i < D; i++) h[i] = T(mdl.H[i]);
     uint32_t bad = 0;
 
+    // smoother lane aggregate accumulated from the handed-over elements
+    constexpr bool LANEAGG = (MODE & F_ELEMS) != 0 && lane_aggregate_handover<D>();
+    SAgg<D, T> sacc;
+    if constexpr (LANEAGG) sagg_identity<D, T>(sacc);
+
     T m[D], P[D][D];
     moments_load<D, T>(p.inclp + (size_t)slot * INCL, m, P);
     if (lane > 0) {
@@ -342,10 +361,12 @@ __device__ __forceinline__ void filter_tile_finish(const FilterParams<T> &p, con
         predict_step<D, T>(m, P, Dl, Q, mp, Y, Pp);
         if constexpr ((MODE & F_ELEMS) != 0) {
             // smoother element of the previous step of this lane
-            if (k > k0)
-                emit_smoother_element<D, T>(m, P, Y, mp, Pp,
-                                            p.m + elem_index<D>(slot, p.chunk, (int)(k - 1 - k0), lane),
-                                            PSSGP_WAVE, bad);
+            if (k > k0) {
+                SAgg<D, T> e;
+                smoother_element_from_prediction<D, T>(m, P, Y, mp, Pp, e, bad);
+                hand_over_element<D, T, LANEAGG>(e, p.m + elem_index<D>(slot, p.chunk, (int)(k - 1 - k0), lane),
+                                                 sacc);
+            }
         }
         // conditioning on y_k in FP64 (symmetric form), from the predicted
         // moments in T: the subtraction that cancels when the noise is
@@ -403,10 +424,13 @@ __device__ __forceinline__ void filter_tile_finish(const FilterParams<T> &p, con
             double Dl[D][D], Q[D][D], mp[D], Y[D][D], Pp[D][D];
             step_transition<LY, double, T>(mdl, c, sv.sc, dt, end, Dl, Q);
             predict_step<D, T>(m, P, Dl, Q, mp, Y, Pp);
-            emit_smoother_element<D, T>(m, P, Y, mp, Pp,
-                                        p.m + elem_index<D>(slot, p.chunk, (int)(k1 - 1 - k0), lane), PSSGP_WAVE,
-                                        bad);
+            SAgg<D, T> e;
+            smoother_element_from_prediction<D, T>(m, P, Y, mp, Pp, e, bad);
+            hand_over_element<D, T, LANEAGG>(e, p.m + elem_index<D>(slot, p.chunk, (int)(k1 - 1 - k0), lane),
+                                             sacc);
         }
+        // the lane's smoother aggregate (identity for a lane without steps)
+        if constexpr (LANEAGG) sagg_store<D, T>(lane_rec(p.slane, slot, SAggLayout<D>::SIZE, lane), sacc, PSSGP_WAVE);
     }
     if (bad) status_or(&p.ctl->status, bad);
     ll_out = ll;
@@ -502,6 +526,7 @@ FilterParams<T> filter_params(const FilterLaunch &a)
     p.aggp = (T *)a.ws.aggp;
     p.lanep = (T *)a.ws.lanep;
     p.partials = a.ws.partials;
+    p.slane = (T *)a.slane;
     return p;
 }
 

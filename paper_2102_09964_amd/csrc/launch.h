@@ -48,6 +48,7 @@ struct FilterLaunch {
     double *loglik;  // nullable
     void *ck;        // nullable: per-chunk checkpoints of the start moments
     int tiled;       // write smoother elements to m (P unused) in the tile layout of the handover
+    void *slane;     // tiled: per-lane smoother aggregates (lane_aggregate_handover)
     ScanWs ws;
 };
 
@@ -64,6 +65,7 @@ struct SmoothLaunch {
     void *ms;  // nullable
     void *Ps;  // nullable
     int tiled; // m holds the smoother elements in the tile layout (P unused)
+    const void *slane;  // tiled: per-lane smoother aggregates written by the filter
     ScanWs ws;
 };
 
@@ -121,6 +123,7 @@ struct BatchLaunch {
     double *loglik;           // device [n_series]
     void *ll_terms;           // workspace: per-step terms
     int tiled;                // m: smoother-element handover (filter then smoother in one call)
+    void *slane;              // tiled: per-lane smoother aggregates
     ScanWs ws;
 };
 

@@ -43,6 +43,7 @@ struct SmoothParams {
     T *inclp;
     T *lanep;
     const double *cst;  // model constants of the FP32 transition (ConstLayout)
+    const T *slane;     // fused call: per-lane aggregates from the filter
 };
 
 struct STileRange {
@@ -69,6 +70,10 @@ __device__ __forceinline__ void smoother_tile_fold(const SmoothParams<T> &p, con
     uint32_t bad = 0;  // reported by the finish pass
     SAgg<D, T> agg;
     sagg_identity<D, T>(agg);
+    if constexpr (ELEMS && lane_aggregate_handover<D>()) {
+        // the filter composed this lane's elements while building them
+        sagg_load<D, T>(lane_rec(p.slane, slot, AGG, lane), agg, PSSGP_WAVE);
+    } else {
     for (int64_t k = k1 - 1; k >= k0; k--) {
         PSSGP_RELOAD_CONSTANTS();
         sv.seek(k);
@@ -81,6 +86,7 @@ __device__ __forceinline__ void smoother_tile_fold(const SmoothParams<T> &p, con
             smoother_element<LY, T, SV>(mdl, c, sv, p.t, p.m + k, p.P + k, (size_t)p.n, k, e, bad);
         }
         sagg_combine<D, T>(e, agg, agg);
+    }
     }
     for (int o = 1; o < PSSGP_WAVE; o <<= 1) {
         SAgg<D, T> other;
@@ -205,6 +211,7 @@ int launch_smoother_t(const DevModel &mdl, const SmoothLaunch &a, hipStream_t s)
     p.aggp = (T *)a.ws.aggp;
     p.lanep = (T *)a.ws.lanep;
     p.cst = a.ws.cst;
+    p.slane = (const T *)a.slane;
     const dim3 grid(a.ntiles), block(PSSGP_WAVE);
     pass_event(a.ev, 0, s);
     if (a.tiled) {

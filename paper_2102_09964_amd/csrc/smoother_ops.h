@@ -153,6 +153,15 @@ __device__ __forceinline__ size_t elem_index(int slot, int chunk, int j, int lan
     return ((size_t)slot * chunk + j) * (D * D + D + D * (D + 1) / 2) * 64 + lane;
 }
 
+// Whether the filter of a fused call also hands over, per lane, the
+// smoother aggregate of the lane's elements (accumulated while it builds
+// them), so that the smoother's fold pass reads one aggregate per lane
+// instead of every element. It costs the filter one FP32 smoother
+// combination per step and a working set of SIZE more values per lane,
+// which the register budget allows up to d = 6.
+template <int D>
+constexpr bool lane_aggregate_handover() { return D <= 6; }
+
 // Smoother element of step k, computed in FP64 and rounded to T. The
 // filter moments of step k are read at mk[i * st] (m) and pk[s * st]
 // (packed P):
