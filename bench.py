@@ -3,8 +3,10 @@
 One step = one pass of the whole path over one batch of synthetic input:
 parallel Kalman filter scan (discretisation, element construction, prefix
 scan, log-likelihood) followed by the parallel RTS smoother scan (posterior
-mean and variance of f at every step). The metric is time steps per second:
-series length / time per step, with the inputs resident in HBM.
+mean and variance of f at every step), as one fused library call captured
+in a HIP graph and replayed (the eager per-call time is reported beside
+it). The metric is time steps per second: series length / time per step,
+with the inputs resident in HBM.
 
 Default workload: RBF kernel through its order-6 Taylor state-space model
 (d = 6), 2^22 time stamps with log-normal gaps (median 0.01), the paper's
@@ -68,7 +70,10 @@ def pass_costs(d, tsize, chunk):
     conditioning, the smoother element from the prediction (Cholesky of the
     predicted covariance, two triangular solves, the Gram matrix), the
     smoother operator and its application, and the lane scans (6 operator
-    applications per lane and tile, i.e. per chunk of steps)."""
+    applications per lane and tile, i.e. per chunk of steps). Up to d = 6 the
+    filter's finish pass also composes each lane's smoother elements into a
+    lane aggregate (one smoother operator per step) and the smoother's fold
+    pass reads those aggregates instead of the elements."""
     ns = d * (d + 1) // 2
     elem = tsize * (d * d + d + ns)                  # smoother element in the handover
     fagg = tsize * (d * d + 2 * d + 2 * ns) / chunk  # filter lane aggregate (A, b, C, eta, J)
@@ -82,11 +87,14 @@ def pass_costs(d, tsize, chunk):
     selem = d ** 3 // 6 + d * d * (d - 1) + ns * d + d * d
     scomb = 2 * d ** 3 + ns * d + d * d
     sapply = d ** 3 + ns * d + 2 * d * d + 2 * d
+    lane_agg = d <= 6
     return {
         "filter_fold": (inputs + fagg, 2 * (disc + fold + 6 * combine / chunk)),
         "filter_carry": (0.0, 0.0),
-        "filter_finish": (inputs + fagg + elem, 2 * (disc + predict + cond + selem + combine / chunk)),
-        "smoother_fold": (elem + sagg, 2 * (scomb + 6 * scomb / chunk)),
+        "filter_finish": (inputs + fagg + elem + (sagg if lane_agg else 0.0),
+                          2 * (disc + predict + cond + selem + (scomb if lane_agg else 0) + combine / chunk)),
+        "smoother_fold": ((2 * sagg, 2 * 6 * scomb / chunk) if lane_agg else
+                          (elem + sagg, 2 * (scomb + 6 * scomb / chunk))),
         "smoother_carry": (0.0, 0.0),
         "smoother_finish": (elem + sagg + 2 * tsize, 2 * (sapply + sapply / chunk)),
     }
@@ -153,14 +161,32 @@ def measure(w, dtype, steps, warmup, chunk=0):
     for _ in range(warmup):
         pipe.run(t, y, mask)
     torch.cuda.synchronize()
-    # whole-step timing: wall clock over the timed steps (stream-ordered,
-    # synchronised on both sides)
+    # eager whole-step timing: wall clock over the timed steps, one library
+    # call per step (stream-ordered, synchronised on both sides)
     t0 = time.perf_counter()
     for i in range(steps):
         pipe.run(t, y, mask)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_step = (t1 - t0) * 1e3 / steps
+    ms_eager = (time.perf_counter() - t0) * 1e3 / steps
+    # the step captured once in a HIP graph and replayed: the same kernels
+    # without the host launch gaps between them
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(stream):
+        with torch.cuda.graph(graph, stream=stream):
+            pipe.run(t, y, mask)
+    torch.cuda.current_stream().wait_stream(stream)
+    for _ in range(max(1, warmup)):
+        graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t0) * 1e3 / steps
+    graph_ll = float(pipe.loglik.cpu()[0])
+    del graph
     # per-pass timing: HIP events recorded by the library on the launch
     # stream around every pass, in a second timed run of the same steps
     evs = [[[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(2)] for _ in range(steps)]
@@ -177,9 +203,11 @@ def measure(w, dtype, steps, warmup, chunk=0):
         for j, name in enumerate(("fold", "carry", "finish")):
             pass_ms[scan + "_" + name] = float(np.mean([e[g][j].elapsed_time(e[g][j + 1]) for e in evs]))
     ll = float(pipe.loglik.cpu()[0])
+    if ll != graph_ll:
+        raise RuntimeError("graph replay and eager call disagree: %r vs %r" % (graph_ll, ll))
     status = (P.status(pipe.ws_f), P.status(pipe.ws_s))
     tsize = 4 if dtype == "float32" else 8
-    return {"n": n, "d": d, "tsize": tsize, "chunk": chunk or 16, "ms_per_step": ms_step,
+    return {"n": n, "d": d, "tsize": tsize, "chunk": chunk or 16, "ms_per_step": ms_step, "ms_eager": ms_eager,
             "filter_ms": sum(v for k, v in pass_ms.items() if k.startswith("filter")),
             "smoother_ms": sum(v for k, v in pass_ms.items() if k.startswith("smoother")),
             "pass_ms": pass_ms, "steps_per_s": n / (ms_step / 1e3), "loglik": ll, "status": status,
@@ -405,6 +433,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(m["ms_per_step"], 4),
+        "ms_per_step_eager": round(m["ms_eager"], 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
