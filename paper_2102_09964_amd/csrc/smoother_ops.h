@@ -159,8 +159,11 @@ __device__ __forceinline__ size_t elem_index(int slot, int chunk, int j, int lan
 // instead of every element. It costs the filter one FP32 smoother
 // combination per step and a working set of SIZE more values per lane,
 // which the register budget allows up to d = 6.
+#ifndef PSSGP_LANEAGG_MAXD
+#define PSSGP_LANEAGG_MAXD 6
+#endif
 template <int D>
-constexpr bool lane_aggregate_handover() { return D <= 6; }
+constexpr bool lane_aggregate_handover() { return D <= PSSGP_LANEAGG_MAXD; }
 
 // Smoother element of step k, computed in FP64 and rounded to T. The
 // filter moments of step k are read at mk[i * st] (m) and pk[s * st]
