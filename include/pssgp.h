@@ -263,7 +263,9 @@ int pssgp_loglik_grad(const pssgp_model *model, const double *t, const void *y,
  * boundaries without segment flags. m: device dtype[d_max][n_total], P:
  * device dtype[NS_max][n_total] (d_max, NS_max of the largest group); a
  * series of state size d uses rows [0, d) of m and the first d(d+1)/2 rows
- * of P in its own packing. loglik: device double[n_series].
+ * of P in its own packing. loglik: device double[n_series]; an empty
+ * series (offsets[s] = offsets[s+1]) gets 0. When the batch holds no steps
+ * at all, the per-step arrays (t, y, mask, m, P, f_mean, f_var) may be NULL.
  */
 typedef struct pssgp_batch_group {
     pssgp_component kind;

@@ -365,15 +365,17 @@ int run_batched(const pssgp_batch_group *groups, int ngroups, int64_t n_series, 
     BatchPlan bp;
     int rc = make_batch_plan(groups, ngroups, n_series, offsets_host, dtype, op, opts, bp);
     if (rc) return rc;
-    if (!offsets || !params || !t || (op != PSSGP_OP_PREDICT && (!m || !P))) {
+    // per-step arrays may be NULL when the batch holds no steps
+    const bool steps = offsets_host[n_series] > 0;
+    if (!offsets || !params || (steps && (!t || (op != PSSGP_OP_PREDICT && (!m || !P))))) {
         pssgp_set_error("batched: offsets, params, t, m and P must be device pointers");
         return PSSGP_EINVAL;
     }
-    if (op != PSSGP_OP_SMOOTH && (!y || !loglik)) {
+    if (op != PSSGP_OP_SMOOTH && (!loglik || (steps && !y))) {
         pssgp_set_error("batched filter: y and loglik must be device pointers");
         return PSSGP_EINVAL;
     }
-    if (op != PSSGP_OP_FILTER && (!f_mean || !f_var)) {
+    if (op != PSSGP_OP_FILTER && steps && (!f_mean || !f_var)) {
         pssgp_set_error("batched smoother: f_mean and f_var must be device pointers");
         return PSSGP_EINVAL;
     }

@@ -116,6 +116,66 @@ def test_batched_single_kind_and_short_series():
         _check(g, o, w2["offsets"], "float64")
 
 
+@pytest.mark.parametrize("fused", [True, False])
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+def test_batched_empty_and_single_step_series(dtype, fused):
+    """Series of length 0 (first of each layout group, the last series, and
+    two in a row) and of length 1 among ordinary ones: the empty series get
+    an exact zero log-likelihood, every other series matches the oracle."""
+    w = _batch(n_series=40, min_len=2, max_len=400, seed=11)
+    off, kinds = w["offsets"], w["kinds"]
+    ns = len(off) - 1
+    b = int(np.argmax(kinds == P.MATERN52))
+    empty = {0, 3, 4, b, ns - 1}
+    single = {1, b + 1, ns - 2}
+    sel, new_off = [], [0]
+    for s in range(ns):
+        a = int(off[s])
+        e = a if s in empty else (a + 1 if s in single else int(off[s + 1]))
+        sel.append(np.arange(a, e))
+        new_off.append(new_off[-1] + (e - a))
+    sel = np.concatenate(sel)
+    w2 = {"t": w["t"][sel], "y": w["y"][sel], "mask": w["mask"][sel], "offsets": np.array(new_off),
+          "kinds": kinds, "params": w["params"], "models": w["models"]}
+    o = _oracle(w2, dtype)
+    g, _ = _gpu(w2, dtype, fused=fused)
+    assert g["status"] == (0, 0)
+    tol = {"float64": (1e-9, 1e-9), "float32": (1e-4, 1e-5)}[dtype]
+    off2 = w2["offsets"]
+    for s in range(ns):
+        a, e = off2[s], off2[s + 1]
+        if a == e:
+            assert g["loglik"][s] == 0.0, s
+            continue
+        assert rel(g["f_mean"][a:e], o["f_mean"][a:e]) <= tol[0], s
+        assert rel(g["f_var"][a:e], o["f_var"][a:e]) <= tol[0], s
+        assert abs(g["loglik"][s] - o["loglik"][s]) <= tol[1] * max(o["loglik_abs_terms"][s], 1e-300), s
+
+
+@pytest.mark.parametrize("fused", [True, False])
+def test_batched_empty_groups(fused):
+    """A layout group whose series are all empty, and a batch with no steps
+    at all: zero log-likelihoods, the other group unaffected."""
+    w = _batch(n_series=12, min_len=5, max_len=300, seed=12)
+    off, kinds = w["offsets"], w["kinds"]
+    b = int(np.argmax(kinds == P.MATERN52))
+    sel = np.arange(0, int(off[b]))  # keep the Matern-3/2 group only
+    new_off = np.concatenate([off[:b + 1], np.full(len(off) - b - 1, off[b])])
+    w2 = {"t": w["t"][sel], "y": w["y"][sel], "mask": w["mask"][sel], "offsets": new_off, "kinds": kinds,
+          "params": w["params"], "models": w["models"]}
+    o = _oracle(w2, "float64")
+    g, _ = _gpu(w2, "float64", fused=fused)
+    assert g["status"] == (0, 0)
+    assert np.all(g["loglik"][b:] == 0.0)
+    assert rel(g["f_mean"], o["f_mean"]) <= 1e-9 and rel(g["f_var"], o["f_var"]) <= 1e-9
+    assert np.max(np.abs(g["loglik"][:b] - o["loglik"][:b]) / np.abs(o["loglik"][:b])) <= 1e-9
+    # no steps at all
+    w3 = {"t": w["t"][:0], "y": w["y"][:0], "mask": w["mask"][:0], "offsets": np.zeros_like(off), "kinds": kinds,
+          "params": w["params"], "models": w["models"]}
+    g3, _ = _gpu(w3, "float64", fused=fused)
+    assert np.all(g3["loglik"] == 0.0)
+
+
 def test_batched_equals_single_series_path():
     w = _batch(n_series=6, min_len=2000, max_len=5000, seed=9)
     g, _ = _gpu(w, "float32")
