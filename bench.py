@@ -239,14 +239,15 @@ def measure_plain(w, steps, warmup):
     return {"steps_per_s": round(n / (ms / 1e3), 1), "ms_per_step": round(ms, 4), "loglik": ll}
 
 
-def roofline_of(m, workload=None, dtype=None):
+def roofline_of(m, workload=None, dtype=None, costs=None):
     """Roofline of the dominant pass (longest mean duration): its
     algorithmic flops and bytes per launch over that duration, against the
     vector ALU peak and the HBM peak; `bound` is the roofline the pass's
     arithmetic intensity puts it under. `traffic` is the kernel's measured
     HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated on a copy),
-    when a counter summary for these sources, workload and chunk exists."""
-    costs = pass_costs(m["d"], m["tsize"], m["chunk"])
+    when a counter summary for these sources, workload and chunk exists.
+    costs: per-pass (bytes, flops) per step, default pass_costs of m."""
+    costs = costs or pass_costs(m["d"], m["tsize"], m["chunk"])
     dom = max(m["pass_ms"], key=lambda k: m["pass_ms"][k])
     ms = m["pass_ms"][dom]
     bpstep, fpstep = costs[dom]
@@ -305,9 +306,40 @@ def measure_batched(steps, warmup, chunk=0):
         graph.replay()
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / steps
+    del graph
+    # per-pass durations from the library's HIP events, in eager calls
+    evs = [[[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(2)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    for i in range(steps):
+        pipe.run(t, y, mask, pass_events=evs[i])
+    torch.cuda.synchronize()
+    pass_ms = {}
+    for g, scan in enumerate(("filter", "smoother")):
+        for j, name in enumerate(("fold", "carry", "finish")):
+            pass_ms[scan + "_" + name] = float(np.mean([e[g][j].elapsed_time(e[g][j + 1]) for e in evs]))
     n = int(w["offsets"][-1])
+    # cost per step: the layout groups weighted by their steps; the filter's
+    # finish also writes the per-step log-likelihood terms (FP64) that the
+    # per-series sum reads back
+    off = np.asarray(w["offsets"])
+    costs = {k: [0.0, 0.0] for k in PASSES}
+    for kind, dd in ((P.MATERN32, 2), (P.MATERN52, 3)):
+        idx = np.nonzero(np.asarray(w["kinds"]) == kind)[0]
+        frac = float(np.sum(off[idx + 1] - off[idx])) / n
+        for k, (b, f) in pass_costs(dd, 4, chunk).items():
+            costs[k][0] += frac * b
+            costs[k][1] += frac * f
+    costs["filter_finish"][0] += 16.0
+    m = {"n": n, "chunk": chunk, "pass_ms": pass_ms, "ms_per_step": ms, "path_bytes": algorithmic_bytes(4, n)}
+    rf = roofline_of(m, costs={k: tuple(v) for k, v in costs.items()})
     return {"workload": "batched_matern", "dtype": "float32", "n": n, "n_series": int(len(w["kinds"])),
             "chunk": int(chunk), "graph": True, "steps_per_s": round(n / (ms / 1e3), 1), "ms_per_step": round(ms, 4),
+            "pass_ms": {k: round(v, 4) for k, v in pass_ms.items()},
+            "roofline": {k: rf[k] for k in ("bound", "kernel", "achieved", "unit", "frac", "achieved_gbs", "hbm_frac",
+                                            "path_hbm_frac")},
+            # all passes' algorithmic bytes (inputs, handover, lane records,
+            # outputs) over the whole step
+            "step_gbs": round(sum(v[0] for v in costs.values()) * n / (ms / 1e3) / 1e9, 1),
             "status": [P.status(pipe.ws_f), P.status(pipe.ws_s)]}
 
 

@@ -141,19 +141,31 @@ __global__ __launch_bounds__(PSSGP_WAVE) void batched_smoother_kernel(SmoothPara
     }
 }
 
-// One wave per series: sum of its per-step log-likelihood terms in FP64,
-// lanes strided over the steps, then a fixed-order wave tree.
-template <typename T>
-__global__ __launch_bounds__(256) void series_loglik_kernel(const T *terms, const int64_t *off, int64_t n_series,
-                                                           double *out)
+// One workgroup per series: sum of its per-step log-likelihood terms in
+// FP64. Threads take the steps strided by the workgroup size (coalesced
+// loads, several in flight per thread), then a fixed-order tree: wave sums,
+// then the wave totals in wave order, so the result does not depend on
+// timing. (One wave per series left the longest series, 65 536 steps, as a
+// chain of 1 024 dependent load rounds.)
+#define PSSGP_LL_THREADS 1024
+__global__ __launch_bounds__(PSSGP_LL_THREADS) void series_loglik_kernel(const double *terms, const int64_t *off,
+                                                                       double *out)
 {
-    const int64_t s = (int64_t)blockIdx.x * (blockDim.x / PSSGP_WAVE) + threadIdx.x / PSSGP_WAVE;
-    const int lane = lane_id();
+    __shared__ double s_w[PSSGP_LL_THREADS / PSSGP_WAVE];
+    const int64_t s = blockIdx.x;
+    const int64_t beg = off[s], end = off[s + 1];
+    const int tid = (int)threadIdx.x;
     double acc = 0.0;
-    if (s < n_series)
-        for (int64_t k = off[s] + lane; k < off[s + 1]; k += PSSGP_WAVE) acc += (double)terms[k];
+#pragma unroll 8
+    for (int64_t k = beg + tid; k < end; k += PSSGP_LL_THREADS) acc += terms[k];
     acc = wave_sum(acc);
-    if (s < n_series && lane == 0) out[s] = acc;
+    if (lane_id() == 0) s_w[tid / PSSGP_WAVE] = acc;
+    __syncthreads();
+    if (tid == 0) {
+        double tot = 0.0;
+        for (int w = 0; w < PSSGP_LL_THREADS / PSSGP_WAVE; w++) tot += s_w[w];
+        out[s] = tot;
+    }
 }
 
 template <class LA, class LB, typename T, bool ELEMS>
@@ -198,10 +210,8 @@ int launch_bf(const BatchLaunch &a, hipStream_t s)
     hipLaunchKernelGGL((batched_filter_kernel<LA, LB, T, true, ELEMS>), grid, block, 0, s, p, a);
     rc = (int)hipGetLastError();
     if (rc) return rc;
-    const int per_block = 256 / PSSGP_WAVE;
-    const dim3 lgrid((unsigned)((a.n_series + per_block - 1) / per_block));
-    hipLaunchKernelGGL((series_loglik_kernel<double>), lgrid, dim3(256), 0, s, (const double *)a.ll_terms, a.offsets,
-                       a.n_series, a.loglik);
+    hipLaunchKernelGGL(series_loglik_kernel, dim3((unsigned)a.n_series), dim3(PSSGP_LL_THREADS), 0, s,
+                       (const double *)a.ll_terms, a.offsets, a.loglik);
     rc = (int)hipGetLastError();
     pass_event(a.ev, 3, s);
     return rc;

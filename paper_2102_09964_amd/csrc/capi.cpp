@@ -250,8 +250,8 @@ struct BatchPlan {
 int make_batch_plan(const pssgp_batch_group *groups, int ngroups, int64_t n_series, const int64_t *off,
                     pssgp_dtype dtype, int op, const pssgp_options *opts, BatchPlan &bp)
 {
-    if (!groups || ngroups < 1 || ngroups > 2 || n_series < 1 || !off) {
-        pssgp_set_error("batched: 1 or 2 groups, n_series >= 1 and host offsets are required");
+    if (!groups || ngroups < 1 || ngroups > 2 || n_series < 1 || n_series > INT32_MAX || !off) {
+        pssgp_set_error("batched: 1 or 2 groups, 1 <= n_series <= 2^31 - 1 and host offsets are required");
         return PSSGP_EINVAL;
     }
     if (dtype != PSSGP_F32 && dtype != PSSGP_F64) {
