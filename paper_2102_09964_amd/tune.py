@@ -46,7 +46,9 @@ def _store(cache: dict) -> None:
 
 
 def _time(run, reps: int) -> float:
+    """Best of reps timed calls after two untimed ones (clock ramp-up)."""
     import torch
+    run()
     run()
     torch.cuda.synchronize()
     best = float("inf")
@@ -58,7 +60,7 @@ def _time(run, reps: int) -> float:
     return best
 
 
-def tune_chunk(model, t, y, mask=None, dtype="float32", candidates=CANDIDATES, reps=3, use_cache=True):
+def tune_chunk(model, t, y, mask=None, dtype="float32", candidates=CANDIDATES, reps=5, use_cache=True):
     """Fastest chunk for a single-series filter + smoother on these inputs
     (device tensors). Returns (chunk, {chunk: seconds})."""
     from . import Pipeline, make_options, state_dim, _as_model
@@ -82,7 +84,7 @@ def tune_chunk(model, t, y, mask=None, dtype="float32", candidates=CANDIDATES, r
     return best, times
 
 
-def tune_batched_chunk(kinds, offsets, params, t, y, mask=None, dtype="float32", candidates=CANDIDATES, reps=3,
+def tune_batched_chunk(kinds, offsets, params, t, y, mask=None, dtype="float32", candidates=CANDIDATES, reps=5,
                        use_cache=True):
     """Fastest chunk for the batched filter + smoother on these series."""
     import numpy as np
