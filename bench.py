@@ -389,6 +389,32 @@ def cpu_baseline(w, target_s=12.0):
             "sample": "first %d of %d steps, filter+smoother+loglik, FP64 sequential C, %.1f s" % (n, n_all, dt)}
 
 
+def cpu_baseline_batched(target_s=10.0, max_threads=16):
+    """The oracle on the batched workload: series spread over host threads
+    (the C oracle releases the interpreter lock), on the first series of
+    the batch up to about target_s seconds."""
+    import oracle
+    import workloads
+    from oracle.model import OracleModel
+    w = workloads.batched_matern()
+    off = np.asarray(w["offsets"])
+    threads = max(1, min(max_threads, os.cpu_count() or 1))
+    models = [OracleModel(m["components"], m["noise_var"]) for m in w["models"]]
+    t0 = time.perf_counter()
+    oracle.run(models[0], w["t"][:off[1]], w["y"][:off[1]], w["mask"][:off[1]], filter_moments=False)
+    per = (time.perf_counter() - t0) / max(1, int(off[1]))
+    budget = target_s * threads / per  # steps that fit the time on all threads
+    ns = int(np.searchsorted(off[1:], budget)) + 1
+    ns = max(threads, min(ns, len(models)))
+    t0 = time.perf_counter()
+    oracle.run_batched(models[:ns], off[:ns + 1], w["t"], w["y"], w["mask"], threads=threads)
+    dt = time.perf_counter() - t0
+    n = int(off[ns])
+    return {"value": round(n / dt, 1), "unit": "time steps/s", "cores": threads, "kind": "oracle",
+            "sample": "first %d of %d series (%d steps), filter+smoother+loglik, FP64 C, %d threads, %.1f s"
+                      % (ns, len(models), n, threads, dt)}
+
+
 def copy_probe():
     """A plain device copy of known size (1 GiB, three times): the counter
     values FETCH_SIZE and WRITE_SIZE read for it give the factors that turn
@@ -455,7 +481,10 @@ def main():
                          "pass_ms": {k: round(v, 4) for k, v in mm["pass_ms"].items()},
                          "roofline": {k: roofline_of(mm)[k] for k in ("bound", "kernel", "achieved", "unit", "frac")}})
     if not args.no_also:
-        also.append(measure_batched(max(3, args.steps // 2), 2))
+        mb = measure_batched(max(3, args.steps // 2), 2)
+        if not args.no_cpu_baseline:
+            mb["cpu_baseline"] = cpu_baseline_batched()
+        also.append(mb)
         also.append(measure_grad(max(3, args.steps // 2), 2))
     out = {
         "metric": "time steps/sec, filter+smoother+loglik(+grad), FP32 vs FP64, d=2..8, 1 GPU",
