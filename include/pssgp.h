@@ -215,10 +215,12 @@ int pssgp_plain_predict(const pssgp_model *model, const double *t, const double 
 /*
  * Filter, log-likelihood and smoother in one call (section 3 and
  * supplement, Lemma 1; test points are missing steps): f_mean, f_var
- * dtype[n] and loglik double[1] as from pssgp_filter + pssgp_smooth, with
- * the filter moments handed to the smoother inside the workspace (in a
- * layout where every access of a wave is contiguous) instead of through
- * m and P. Workspace: pssgp_workspace_bytes(..., PSSGP_OP_PREDICT, opts);
+ * dtype[n] and loglik double[1] as from pssgp_filter + pssgp_smooth,
+ * but the filter builds the smoother element of every step from its own
+ * FP64 prediction and hands the elements (and, for d <= 6, each lane's
+ * composed smoother aggregate) to the smoother inside the workspace, in a
+ * layout where every access of a wave is contiguous, instead of writing m
+ * and P. Workspace: pssgp_workspace_bytes(..., PSSGP_OP_PREDICT, opts);
  * the same opts (chunk) must be passed. Errors as pssgp_filter.
  */
 int pssgp_predict(const pssgp_model *model, const double *t, const void *y, const uint8_t *mask, int64_t n,
@@ -288,6 +290,18 @@ int pssgp_batched_smooth(const pssgp_batch_group *groups_host, int n_groups, int
                          const double *t, const void *m, const void *P, pssgp_dtype dtype,
                          void *f_mean, void *f_var, void *ws, size_t ws_bytes,
                          const pssgp_options *opts, void *stream);
+
+/*
+ * Batched log-likelihood only: pssgp_batched_filter without the moment
+ * outputs (m, P not written; they may be NULL). loglik: device
+ * double[n_series]. Workspace: pssgp_batched_workspace_bytes(...,
+ * PSSGP_OP_LOGLIK, opts). Errors as for pssgp_batched_filter.
+ */
+int pssgp_batched_loglik(const pssgp_batch_group *groups_host, int n_groups, int64_t n_series,
+                         const int64_t *offsets, const int64_t *offsets_host, const double *params,
+                         const double *t, const void *y, const uint8_t *mask, pssgp_dtype dtype,
+                         double *loglik, void *ws, size_t ws_bytes, const pssgp_options *opts,
+                         void *stream);
 
 /*
  * Batched filter and smoother in one call (the batched form of

@@ -81,6 +81,8 @@ SIGNATURES = [
                                             ctypes.c_int, _VP, _VP, _VP, _VP, _SZ, _OP, _VP]),
     ("pssgp_batched_smooth", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _I64, _VP, _VP, _VP, _VP, _VP, _VP,
                                             ctypes.c_int, _VP, _VP, _VP, _SZ, _OP, _VP]),
+    ("pssgp_batched_loglik", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _I64, _VP, _VP, _VP, _VP, _VP, _VP,
+                                            ctypes.c_int, _VP, _VP, _SZ, _OP, _VP]),
     ("pssgp_batched_predict", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _I64, _VP, _VP, _VP, _VP, _VP, _VP,
                                              ctypes.c_int, _VP, _VP, _VP, _VP, _SZ, _OP, _VP]),
     ("pssgp_status", ctypes.c_int, [_VP, _VP, ctypes.POINTER(ctypes.c_uint32)]),
@@ -558,6 +560,33 @@ def batch_groups(kinds):
         arr[g].series_begin = a
         arr[g].series_end = b
     return arr
+
+
+def batched_loglik(kinds, offsets, params, t, y, mask=None, dtype="float32", options=None, device="cuda"):
+    """Per-series log-likelihoods of a batch (pssgp_batched_loglik); kinds,
+    offsets, params as for BatchedPipeline. Returns a float64 tensor
+    [n_series]."""
+    _require_gpu()
+    torch = _torch()
+    groups = batch_groups(kinds)
+    off_h = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    ns = off_h.shape[0] - 1
+    code, tdt = _dt(dtype)
+    L = lib()
+    op = ctypes.byref(options) if options is not None else None
+    nb = L.pssgp_batched_workspace_bytes(groups, len(groups), ns, off_h.ctypes.data, code, OP_LOGLIK, op)
+    if nb == 0:
+        raise PssgpError(-1, L.pssgp_last_error().decode())
+    ws = torch.empty(nb, dtype=torch.uint8, device=device)
+    off_d = torch.as_tensor(off_h, device=device)
+    prm = _dev(np.asarray(params, dtype=np.float64).reshape(ns, 3), torch.float64, device)
+    t = _dev(t, torch.float64, device)
+    y = _dev(y, tdt, device)
+    mask = _dev(mask, torch.uint8, device) if mask is not None else None
+    ll = torch.empty(ns, dtype=torch.float64, device=device)
+    _check(L.pssgp_batched_loglik(groups, len(groups), ns, _p(off_d), off_h.ctypes.data, _p(prm), _p(t), _p(y),
+                                  _p(mask), code, _p(ll), _p(ws), ws.numel(), op, _stream()))
+    return ll
 
 
 class BatchedPipeline:

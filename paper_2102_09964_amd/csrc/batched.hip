@@ -73,9 +73,10 @@ __device__ __forceinline__ int group_of(const BatchLaunch &a, int slot)
     return (a.ngroups > 1 && slot >= a.g[1].slot_base) ? 1 : 0;
 }
 
-// ELEMS: the finish pass writes smoother elements to the handover (p.m)
-// instead of the filter moments
-template <class LA, class LB, typename T, bool FINISH, bool ELEMS>
+// FMODE: what the finish pass writes besides the log-likelihood terms:
+// F_MOMENTS (filter moments), F_ELEMS (smoother elements to the handover
+// at p.m) or 0 (nothing)
+template <class LA, class LB, typename T, bool FINISH, int FMODE>
 __global__ __launch_bounds__(PSSGP_WAVE) void batched_filter_kernel(FilterParams<T> p, BatchLaunch a)
 {
     __shared__ DevModel mdl;
@@ -93,7 +94,7 @@ __global__ __launch_bounds__(PSSGP_WAVE) void batched_filter_kernel(FilterParams
     ManySeries sv;
     series_view(sv, a, g, g.k_begin + ((int64_t)tile * PSSGP_WAVE + lane_id()) * p.chunk);
     if constexpr (FINISH) {
-        constexpr int MODE = ELEMS ? F_ELEMS : F_MOMENTS;
+        constexpr int MODE = FMODE;
         double ll = 0.0;
         if (gi == 0)
             filter_tile_finish<LA, T, double, MODE, ManySeries>(p, mdl, cst, sv, tr, tile, ll);
@@ -168,7 +169,7 @@ __global__ __launch_bounds__(PSSGP_LL_THREADS) void series_loglik_kernel(const d
     }
 }
 
-template <class LA, class LB, typename T, bool ELEMS>
+template <class LA, class LB, typename T, int FMODE>
 int launch_bf(const BatchLaunch &a, hipStream_t s)
 {
     FilterParams<T> p;
@@ -194,7 +195,7 @@ int launch_bf(const BatchLaunch &a, hipStream_t s)
     pass_event(a.ev, 0, s);
     if constexpr (sizeof(T) == 4)
         hipLaunchKernelGGL((batched_consts_kernel<LA, LB>), dim3(a.ngroups), dim3(256), 0, s, a);
-    hipLaunchKernelGGL((batched_filter_kernel<LA, LB, T, false, false>), grid, block, 0, s, p, a);
+    hipLaunchKernelGGL((batched_filter_kernel<LA, LB, T, false, 0>), grid, block, 0, s, p, a);
     int rc = (int)hipGetLastError();
     if (rc) return rc;
     pass_event(a.ev, 1, s);
@@ -207,7 +208,7 @@ int launch_bf(const BatchLaunch &a, hipStream_t s)
         if (rc) return rc;
     }
     pass_event(a.ev, 2, s);
-    hipLaunchKernelGGL((batched_filter_kernel<LA, LB, T, true, ELEMS>), grid, block, 0, s, p, a);
+    hipLaunchKernelGGL((batched_filter_kernel<LA, LB, T, true, FMODE>), grid, block, 0, s, p, a);
     rc = (int)hipGetLastError();
     if (rc) return rc;
     hipLaunchKernelGGL(series_loglik_kernel, dim3((unsigned)a.n_series), dim3(PSSGP_LL_THREADS), 0, s,
@@ -264,7 +265,7 @@ int launch_bs(const BatchLaunch &a, void *const *ev, hipStream_t s)
 template <class LA, class LB, typename T>
 int launch_bp(const BatchLaunch &a, hipStream_t s)
 {
-    int rc = launch_bf<LA, LB, T, true>(a, s);
+    int rc = launch_bf<LA, LB, T, F_ELEMS>(a, s);
     if (rc) return rc;
     return launch_bs<LA, LB, T, true>(a, a.ev ? a.ev + 4 : nullptr, s);
 }
@@ -279,8 +280,20 @@ int launch_batched_filter(const BatchLaunch &a, bool f64, hipStream_t s)
     const int d0 = a.bm[0].d, d1 = a.ngroups > 1 ? a.bm[1].d : d0;
 #define X(A, B)                                                                                   \
     if (d0 == A && d1 == B)                                                                       \
-        return f64 ? launch_bf<Layout<A, 0>, Layout<B, 0>, double, false>(a, s)                   \
-                   : launch_bf<Layout<A, 0>, Layout<B, 0>, float, false>(a, s);
+        return f64 ? launch_bf<Layout<A, 0>, Layout<B, 0>, double, F_MOMENTS>(a, s)               \
+                   : launch_bf<Layout<A, 0>, Layout<B, 0>, float, F_MOMENTS>(a, s);
+    PSSGP_BATCH_PAIRS(X)
+#undef X
+    return -1;
+}
+
+int launch_batched_loglik(const BatchLaunch &a, bool f64, hipStream_t s)
+{
+    const int d0 = a.bm[0].d, d1 = a.ngroups > 1 ? a.bm[1].d : d0;
+#define X(A, B)                                                                                   \
+    if (d0 == A && d1 == B)                                                                       \
+        return f64 ? launch_bf<Layout<A, 0>, Layout<B, 0>, double, 0>(a, s)                       \
+                   : launch_bf<Layout<A, 0>, Layout<B, 0>, float, 0>(a, s);
     PSSGP_BATCH_PAIRS(X)
 #undef X
     return -1;

@@ -367,7 +367,8 @@ int run_batched(const pssgp_batch_group *groups, int ngroups, int64_t n_series, 
     if (rc) return rc;
     // per-step arrays may be NULL when the batch holds no steps
     const bool steps = offsets_host[n_series] > 0;
-    if (!offsets || !params || (steps && (!t || (op != PSSGP_OP_PREDICT && (!m || !P))))) {
+    const bool moments = (op == PSSGP_OP_FILTER || op == PSSGP_OP_SMOOTH);
+    if (!offsets || !params || (steps && (!t || (moments && (!m || !P))))) {
         pssgp_set_error("batched: offsets, params, t, m and P must be device pointers");
         return PSSGP_EINVAL;
     }
@@ -375,7 +376,7 @@ int run_batched(const pssgp_batch_group *groups, int ngroups, int64_t n_series, 
         pssgp_set_error("batched filter: y and loglik must be device pointers");
         return PSSGP_EINVAL;
     }
-    if (op != PSSGP_OP_FILTER && steps && (!f_mean || !f_var)) {
+    if ((op == PSSGP_OP_SMOOTH || op == PSSGP_OP_PREDICT) && steps && (!f_mean || !f_var)) {
         pssgp_set_error("batched smoother: f_mean and f_var must be device pointers");
         return PSSGP_EINVAL;
     }
@@ -431,6 +432,8 @@ int run_batched(const pssgp_batch_group *groups, int ngroups, int64_t n_series, 
     const bool f64 = dtype == PSSGP_F64;
     if (op == PSSGP_OP_PREDICT)
         rc = launch_batched_predict(a, f64, s);
+    else if (op == PSSGP_OP_LOGLIK)
+        rc = launch_batched_loglik(a, f64, s);
     else
         rc = (op == PSSGP_OP_FILTER) ? launch_batched_filter(a, f64, s) : launch_batched_smooth(a, f64, s);
     return check_launch(rc, "batched launch");
@@ -721,7 +724,7 @@ size_t pssgp_batched_workspace_bytes(const pssgp_batch_group *groups_host, int n
                                      const int64_t *offsets_host, pssgp_dtype dtype, int op,
                                      const pssgp_options *opts)
 {
-    if (op != PSSGP_OP_FILTER && op != PSSGP_OP_SMOOTH && op != PSSGP_OP_PREDICT) return 0;
+    if (op != PSSGP_OP_FILTER && op != PSSGP_OP_SMOOTH && op != PSSGP_OP_PREDICT && op != PSSGP_OP_LOGLIK) return 0;
     BatchPlan bp;
     if (make_batch_plan(groups_host, n_groups, n_series, offsets_host, dtype, op, opts, bp)) return 0;
     return bp.total;
@@ -745,6 +748,15 @@ int pssgp_batched_smooth(const pssgp_batch_group *groups_host, int n_groups, int
     return run_batched(groups_host, n_groups, n_series, offsets, offsets_host, params, t, nullptr, nullptr,
                        dtype, (void *)m, (void *)P, nullptr, f_mean, f_var, ws, ws_bytes, opts, stream,
                        PSSGP_OP_SMOOTH);
+}
+
+int pssgp_batched_loglik(const pssgp_batch_group *groups_host, int n_groups, int64_t n_series,
+                         const int64_t *offsets, const int64_t *offsets_host, const double *params,
+                         const double *t, const void *y, const uint8_t *mask, pssgp_dtype dtype, double *loglik,
+                         void *ws, size_t ws_bytes, const pssgp_options *opts, void *stream)
+{
+    return run_batched(groups_host, n_groups, n_series, offsets, offsets_host, params, t, y, mask, dtype, nullptr,
+                       nullptr, loglik, nullptr, nullptr, ws, ws_bytes, opts, stream, PSSGP_OP_LOGLIK);
 }
 
 int pssgp_batched_predict(const pssgp_batch_group *groups_host, int n_groups, int64_t n_series,

@@ -128,6 +128,8 @@ struct BatchLaunch {
 };
 
 int launch_batched_filter(const BatchLaunch &a, bool f64, hipStream_t s);
+// the filter without moment outputs (log-likelihood only)
+int launch_batched_loglik(const BatchLaunch &a, bool f64, hipStream_t s);
 int launch_batched_smooth(const BatchLaunch &a, bool f64, hipStream_t s);
 // filter writing the handover, then the smoother reading it (a.tiled = 1;
 // a.ev, when set, holds 8 events: filter passes, then smoother passes)

@@ -176,6 +176,23 @@ def test_batched_empty_groups(fused):
     assert np.all(g3["loglik"] == 0.0)
 
 
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+def test_batched_loglik_only(dtype):
+    """pssgp_batched_loglik: the per-series log-likelihoods of the batched
+    filter (same arithmetic in the same order; only the moment stores are
+    left out) without moment outputs, and against the oracle."""
+    w = _batch(n_series=48, min_len=20, max_len=2000, seed=13)
+    g, _ = _gpu(w, dtype, fused=False)
+    ll = P.batched_loglik(w["kinds"], w["offsets"], w["params"], w["t"], np.nan_to_num(w["y"]), w["mask"],
+                          dtype=dtype)
+    torch.cuda.synchronize()
+    ll = ll.cpu().numpy()
+    assert np.allclose(ll, g["loglik"], rtol=1e-12, atol=0.0)
+    o = _oracle(w, dtype)
+    tol = {"float64": 1e-9, "float32": 1e-5}[dtype]
+    assert np.max(np.abs(ll - o["loglik"]) / o["loglik_abs_terms"]) <= tol
+
+
 def test_batched_equals_single_series_path():
     w = _batch(n_series=6, min_len=2000, max_len=5000, seed=9)
     g, _ = _gpu(w, "float32")
