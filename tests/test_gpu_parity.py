@@ -205,12 +205,15 @@ def test_fused_predict_vs_oracle(layout, dtype):
         assert errs["f_mean"] <= tol["mean"] and errs["f_var"] <= var_tol and errs["loglik"] <= tol["loglik"], errs
 
 
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
 @pytest.mark.parametrize("layout", ["m52", "rbf6", "m32+rbf6"])
-def test_fused_small_sizes_and_edge_cases(layout):
+def test_fused_small_sizes_and_edge_cases(layout, dtype):
     """pssgp_predict at sizes around the tile and lane boundaries (one step,
     two steps, one lane short of a tile, a tile, one step past it), and with
-    duplicated times and a long stretch of test points, in FP64 against the
-    oracle. The d = 8 sum kernel takes the path without lane aggregates."""
+    duplicated times and a long stretch of test points, against the oracle
+    (FP32: on the FP32-rounded observations, with the FP32 bars; the d = 8
+    f_var bar of reading 18). The d = 8 sum kernel takes the path without
+    lane aggregates."""
     comps = {"m52": [(MATERN52, 0, 0.9, 1.2)], "rbf6": [(RBF, 6, 1.0, 1.0)],
              "m32+rbf6": [(MATERN32, 0, 2.0, 0.5), (RBF, 6, 0.5, 0.5)]}[layout]
     model = P.make_model(comps, 0.01)
@@ -220,17 +223,21 @@ def test_fused_small_sizes_and_edge_cases(layout):
         w = workloads.random_series(n, comps, 0.01, missing=0.2, span=max(n * 0.02, 0.05), gap=gap, seed=n)
         if hole:
             w["mask"][hole[0]:hole[1]] = 0
-        o = run_oracle(w, "float64", filter_moments=False)
-        for chunk in (1, 16):
-            print("fused", layout, "n", n, gap, "chunk", chunk, flush=True)
-            r = P.predict(model, w["t"], np.nan_to_num(w["y"]), w["mask"], dtype="float64",
+        o = run_oracle(w, dtype, filter_moments=False)
+        if dtype == "float64":
+            bars = {"f_mean": 1e-9, "f_var": 1e-9, "loglik": 1e-9}
+        else:
+            bars = {"f_mean": 1e-4, "f_var": 5e-4 if layout == "m32+rbf6" else 1e-4, "loglik": 1e-5}
+        for chunk in (1, 16) if dtype == "float64" else (4, 16):
+            print("fused", layout, dtype, "n", n, gap, "chunk", chunk, flush=True)
+            r = P.predict(model, w["t"], np.nan_to_num(w["y"]), w["mask"], dtype=dtype,
                           options=P.make_options(chunk=chunk))
             torch.cuda.synchronize()
             assert P.status(r["ws"]) == 0
-            errs = {"f_mean": rel(r["f_mean"].cpu().numpy(), o["f_mean"]),
-                    "f_var": rel(r["f_var"].cpu().numpy(), o["f_var"]),
+            errs = {"f_mean": rel(r["f_mean"].double().cpu().numpy(), o["f_mean"]),
+                    "f_var": rel(r["f_var"].double().cpu().numpy(), o["f_var"]),
                     "loglik": abs(float(r["loglik"].cpu()[0]) - o["loglik"]) / max(abs(o["loglik"]), 1e-300)}
-            assert max(errs.values()) <= 1e-9, (n, gap, chunk, errs)
+            assert all(errs[k] <= bars[k] for k in bars), (n, gap, chunk, errs)
 
 
 def test_fused_matches_separate_calls():
