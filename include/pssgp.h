@@ -167,8 +167,9 @@ int pssgp_discretize(const pssgp_model *model, const double *t, int64_t n, doubl
 /*
  * Parallel Kalman filter (section 3): builds the elements (A, b, C, eta, J)
  * of every step (missing steps: A = F, b = 0, C = Q, eta = J = 0; observed:
- * supplement proof of Proposition 1; step 0: A = 0), runs one decoupled
- * look-back prefix scan with the filtering operator, and returns the
+ * supplement proof of Proposition 1; step 0: A = 0), runs the prefix scan
+ * with the filtering operator (three stream-ordered passes: per-tile fold,
+ * carry scan over the tiles, per-tile finish), and returns the
  * filter means m (device dtype[d][n], entry-major) and covariances P
  * (device dtype[NS][n], packed entry-major): b*_k and C*_k, Proposition 1.
  * m and P may be NULL (log-likelihood only). loglik (device double[1],
@@ -186,8 +187,9 @@ int pssgp_filter(const pssgp_model *model, const double *t, const void *y, const
  * Parallel RTS smoother (supplement, eq. smoother and Proposition 2): from
  * the filter moments (m, P) of pssgp_filter, builds (E_k, g_k, L_k)
  * (E_k = P_k F_k^T (F_k P_k F_k^T + Q_k)^-1, g_k = m_k - E_k F_k m_k,
- * L_k = P_k - E_k F_k P_k, last step (0, m, P)), runs one reverse
- * decoupled look-back scan and writes the posterior mean and variance of
+ * L_k = P_k - E_k F_k P_k, last step (0, m, P)), runs the reverse scan
+ * (the same three passes in reverse time order) and writes the posterior
+ * mean and variance of
  * f = H x at every step (f_mean, f_var: device dtype[n]) -- at the test
  * (missing) steps these are the GP predictions (supplement, Lemma 1). ms,
  * Ps (nullable) receive the full smoothed state moments in the layout of
