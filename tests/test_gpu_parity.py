@@ -120,6 +120,51 @@ def test_status_bits():
     assert g["status"][0] & P.STATUS_UNSORTED
 
 
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+def test_status_bits_fused_and_batched(dtype):
+    """Data errors found on the device are reported by the fused call and
+    the batched call: an unsorted pair of times, and a NaN observation
+    (a NaN at a missing step is ignored)."""
+    comps = [(MATERN32, 0, 1.0, 1.0)]
+    model = P.make_model(comps, 0.01)
+    w = workloads.random_series(3000, comps, 0.01, missing=0.2, seed=2)
+    ok = P.predict(model, w["t"], np.nan_to_num(w["y"]), w["mask"], dtype=dtype)
+    torch.cuda.synchronize()
+    assert P.status(ok["ws"]) == 0
+    t = w["t"].copy()
+    t[1500], t[1501] = t[1501], t[1500]
+    r = P.predict(model, t, np.nan_to_num(w["y"]), w["mask"], dtype=dtype)
+    torch.cuda.synchronize()
+    assert P.status(r["ws"]) & P.STATUS_UNSORTED
+    y = np.nan_to_num(w["y"]).copy()
+    miss = int(np.nonzero(w["mask"] == 0)[0][5])
+    y[miss] = np.nan  # ignored: a missing step
+    r = P.predict(model, w["t"], y, w["mask"], dtype=dtype)
+    torch.cuda.synchronize()
+    assert P.status(r["ws"]) == 0
+    assert np.all(np.isfinite(r["f_mean"].double().cpu().numpy()))
+    obs = int(np.nonzero(w["mask"] == 1)[0][7])
+    y[obs] = np.nan
+    r = P.predict(model, w["t"], y, w["mask"], dtype=dtype)
+    torch.cuda.synchronize()
+    assert P.status(r["ws"]) & P.STATUS_NONFINITE
+    # batched: the second of two series gets the unsorted pair
+    kinds = [P.MATERN32, P.MATERN32]
+    off = np.array([0, 1000, 3000], np.int64)
+    params = np.array([[1.0, 1.0, 0.01], [1.0, 1.0, 0.01]])
+    tb = np.concatenate([w["t"][:1000], w["t"][1000:3000] - w["t"][1000]])
+    pipe = P.BatchedPipeline(kinds, off, params, dtype=dtype)
+    yb = torch.as_tensor(np.nan_to_num(w["y"]), dtype=getattr(torch, dtype), device="cuda")
+    mb = torch.as_tensor(w["mask"], device="cuda")
+    pipe.run(torch.as_tensor(tb, device="cuda"), yb, mb)
+    torch.cuda.synchronize()
+    assert P.status(pipe.ws_p) == 0
+    tb[2000], tb[2001] = tb[2001], tb[2000]
+    pipe.run(torch.as_tensor(tb, device="cuda"), yb, mb)
+    torch.cuda.synchronize()
+    assert P.status(pipe.ws_p) & P.STATUS_UNSORTED
+
+
 @pytest.mark.parametrize("comps", LAYOUTS, ids=IDS)
 def test_discretize_matches_oracle(comps):
     import oracle
