@@ -542,10 +542,14 @@ int launch_filter_t(const DevModel &mdl, const FilterLaunch &a, hipStream_t s)
     if (rc) return rc;
     pass_event(a.ev, 1, s);
     if (a.ck) {
-        // forward pass of the gradient: the carries and lane-start moments in
-        // FP64, because the noise-variance derivative is sensitive to them
-        rc = launch_tile_scan<FilterScanOps<LY::D, T, double>>(a.ws.aggp, 0, a.ntiles, false, a.ws.inclp, a.ws.gagg,
-                                                                a.ws.gcarry, s);
+        // forward pass of the gradient: the lane-start moments (stored as
+        // checkpoints) in FP64, like every finish pass. (The carry scan in
+        // FP64 as well measured no gain in accuracy once the series-start
+        // prefixes and lane starts were conditioned in FP64: noise-variance
+        // derivative 8.6e-5 vs 7.0e-5 at d = 8, 2^20 steps, at 2.5x the carry
+        // time.)
+        rc = launch_tile_scan<FilterScanOps<LY::D, T, CT>>(a.ws.aggp, 0, a.ntiles, false, a.ws.inclp, a.ws.gagg,
+                                                            a.ws.gcarry, s);
         if (rc) return rc;
         pass_event(a.ev, 2, s);
         hipLaunchKernelGGL((filter_finish_kernel<LY, T, double, F_CKPT>), grid, block, 0, s, p, mdl);
