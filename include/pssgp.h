@@ -237,11 +237,12 @@ int pssgp_loglik(const pssgp_model *model, const double *t, const void *y, const
 /*
  * Log-likelihood and its gradient (the paper differentiates the parallel
  * filter by automatic differentiation, sections 2 and 4.4 item 6; here a
- * hand-written reverse-mode adjoint): a forward filter scan that stores one
- * (m, P) checkpoint per lane chunk, then a reverse scan over the affine
- * adjoint maps (mbar_k, Pbar_k) -> (mbar_{k-1}, Pbar_{k-1}) that recomputes
- * the forward quantities from the checkpoints and contracts them with the
- * parameter derivatives of F, Q, Pinf and R. grad (device double[2 n_comp
+ * hand-written reverse-mode adjoint): a forward filter scan whose finish
+ * pass stores the per-step forward quantities (predicted mean and
+ * covariance, gain, innovation and its variance) in the workspace, then a
+ * reverse scan over the affine adjoint maps (mbar_k, Pbar_k) ->
+ * (mbar_{k-1}, Pbar_{k-1}) built from them, whose finish pass contracts the
+ * adjoints with the parameter derivatives of F, Q, Pinf and R. grad (device double[2 n_comp
  * + 1]) receives d loglik / d (ell_0, var_0, ell_1, var_1, ..., noise_var).
  * noise_k must be NULL (the noise-variance derivative is for the scalar
  * noise_var).

@@ -433,8 +433,9 @@ def _make_autograd():
         """loglik(theta) with the hand-written adjoint as its backward.
 
         theta: float64 tensor (ell_0, var_0, ..., noise_var); the remaining
-        arguments are fixed data. Forward runs the filter scan with
-        checkpoints and the reverse adjoint scan together; backward scales the
+        arguments are fixed data. Forward runs the filter scan (which
+        stores the per-step forward quantities) and the reverse adjoint scan
+        together; backward scales the
         stored gradient by the incoming gradient."""
 
         @staticmethod

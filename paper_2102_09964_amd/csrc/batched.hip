@@ -183,7 +183,7 @@ int launch_bf(const BatchLaunch &a, hipStream_t s)
     p.m = (T *)a.m;
     p.P = (T *)a.P;
     p.loglik = nullptr;
-    p.ck = nullptr;
+    p.rec = nullptr;
     p.ll_terms = (double *)a.ll_terms;
     p.ctl = a.ws.ctl;
     p.inclp = (T *)a.ws.inclp;

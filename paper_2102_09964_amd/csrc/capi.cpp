@@ -22,7 +22,7 @@ size_t ctl_bytes() { return 256; }
 struct Plan {
     int d = 0, ns = 0, chunk = kDefaultChunk, ntiles = 0;
     size_t tsize = 4;
-    size_t off_incl = 0, off_lane = 0, off_part = 0, off_ck = 0, off_rec = 0, off_cst = 0, off_agg = 0;
+    size_t off_incl = 0, off_lane = 0, off_part = 0, off_rec = 0, off_cst = 0, off_agg = 0;
     size_t off_incl2 = 0, off_lane2 = 0, off_part2 = 0, off_agg2 = 0;
     size_t off_x = 0, off_xraw = 0;  // plain baseline element arrays
     size_t off_gagg = 0, off_gcarry = 0;  // carry pass group scratch
@@ -42,7 +42,7 @@ int filter_agg_elems(int d) { return d * d + 2 * d + d * (d + 1); }
 int filter_incl_elems(int d) { return d + d * (d + 1) / 2; }
 int smooth_agg_elems(int d) { return d * d + d + d * (d + 1) / 2; }
 int smooth_incl_elems(int d) { return d + d * (d + 1) / 2; }
-int grad_rec_elems(int d) { return 3 * d + d * (d + 1) / 2 + 2; }
+int grad_rec_elems(int d) { return 2 * d + d * (d + 1) / 2 + 2; }  // RecLayout
 int grad_agg_elems(int d) { return d * d + d + d * (d + 1) / 2; }
 int n_params(int ncomp) { return 2 * ncomp + 1; }
 
@@ -107,8 +107,7 @@ Plan make_plan(int d, int ncomp, int64_t n, pssgp_dtype dtype, int op, const pss
     }
     p.off_part = take(nt * sizeof(double) * n_params(ncomp));
     if (op == PSSGP_OP_LOGLIK_GRAD) {
-        p.off_ck = take(nt * 64 * filter_incl_elems(d) * p.tsize);
-        p.off_rec = take((size_t)(n > 0 ? n : 1) * grad_rec_elems(d) * p.tsize);
+        p.off_rec = take(nt * 64 * (size_t)p.chunk * grad_rec_elems(d) * p.tsize);  // tile layout
         p.off_incl2 = take(nt * (d + d * (d + 1) / 2) * p.tsize);
         p.off_agg2 = take(nt * grad_agg_elems(d) * p.tsize);
         p.off_lane2 = take(nt * 64 * grad_agg_elems(d) * p.tsize);
@@ -233,7 +232,7 @@ int run_filter(const pssgp_model *model, const double *t, const void *y, const u
     // the kernel always reduces the log-likelihood; without a caller buffer
     // it goes to a spare slot of the partials region (sized ntiles * np >= ntiles + 1)
     a.loglik = loglik ? loglik : sw.partials + p.ntiles;
-    a.ck = nullptr;
+    a.rec = nullptr;
     a.ws = sw;
     return check_launch(launch_filter(dm, b0, b1, dtype == PSSGP_F64, a, s), "filter launch");
 }
@@ -640,7 +639,7 @@ int pssgp_predict(const pssgp_model *model, const double *t, const void *y, cons
     a.m = hand;
     a.P = nullptr;
     a.loglik = loglik;
-    a.ck = nullptr;
+    a.rec = nullptr;
     a.tiled = 1;
     a.slane = b + p.off_slane;
     a.ws = sw;
@@ -699,7 +698,7 @@ int pssgp_loglik_grad(const pssgp_model *model, const double *t, const void *y, 
     a.m = nullptr;
     a.P = nullptr;
     a.loglik = loglik;
-    a.ck = b + p.off_ck;
+    a.rec = b + p.off_rec;
     a.ws = sw;
     rc = check_launch(launch_filter(dm, b0, b1, dtype == PSSGP_F64, a, s), "filter launch");
     if (rc) return rc;
@@ -713,7 +712,6 @@ int pssgp_loglik_grad(const pssgp_model *model, const double *t, const void *y, 
     g.n = n;
     g.chunk = p.chunk;
     g.ntiles = p.ntiles;
-    g.ck = b + p.off_ck;
     g.rec = b + p.off_rec;
     g.grad = grad;
     g.ws = sw2;

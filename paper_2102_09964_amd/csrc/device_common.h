@@ -161,9 +161,10 @@ __device__ __forceinline__ StepScale model_scale(const DevModel &mdl)
     return sc;
 }
 
+// F block of one component (no special cases)
 template <class LY, int b, bool ACC>
-__device__ __forceinline__ void disc_block(const DevModel &mdl, const StepScale &sc, double dt,
-                                           double (&F)[LY::D][LY::D], double (&Q)[LY::D][LY::D])
+__device__ __forceinline__ void trans_block(const DevModel &mdl, const StepScale &sc, double dt,
+                                            double (&F)[LY::D][LY::D])
 {
     constexpr int dc = LY::bdim(b);
     constexpr int o = LY::boff(b);
@@ -208,6 +209,15 @@ __device__ __forceinline__ void disc_block(const DevModel &mdl, const StepScale 
                 F[o + i][o + j] = acc;
             }
     }
+}
+
+template <class LY, int b, bool ACC>
+__device__ __forceinline__ void disc_block(const DevModel &mdl, const StepScale &sc, double dt,
+                                           double (&F)[LY::D][LY::D], double (&Q)[LY::D][LY::D])
+{
+    constexpr int dc = LY::bdim(b);
+    constexpr int o = LY::boff(b);
+    trans_block<LY, b, ACC>(mdl, sc, dt, F);
     // Q block = Pinf_b - F_b Pinf_b F_b^T
     double FP[dc][dc];
 #pragma unroll
@@ -252,6 +262,25 @@ __device__ __forceinline__ void discretize(const DevModel &mdl, const StepScale 
             F[i][j] = first ? 0.0 : (zero ? fid : F[i][j]);
             Q[i][j] = first ? mdl.Pinf[i * D + j] * sc.var_mult : (zero ? 0.0 : Q[i][j]);
         }
+}
+
+// F alone, with the special cases of discretize
+template <class LY, bool ACC>
+__device__ __forceinline__ void transition(const DevModel &mdl, const StepScale &sc, double dt, bool first,
+                                           double (&F)[LY::D][LY::D])
+{
+    constexpr int D = LY::D;
+#pragma unroll
+    for (int i = 0; i < D; i++)
+#pragma unroll
+        for (int j = 0; j < D; j++) F[i][j] = 0.0;
+    trans_block<LY, 0, ACC>(mdl, sc, dt, F);
+    if constexpr (LY::NB > 1) trans_block<LY, 1, ACC>(mdl, sc, dt, F);
+    const bool zero = (dt == 0.0);
+#pragma unroll
+    for (int i = 0; i < D; i++)
+#pragma unroll
+        for (int j = 0; j < D; j++) F[i][j] = first ? 0.0 : (zero ? ((i == j) ? 1.0 : 0.0) : F[i][j]);
 }
 
 // ------------------------------------------------------------------ transition for the FP32 scans

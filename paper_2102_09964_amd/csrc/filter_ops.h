@@ -345,6 +345,24 @@ struct AggLayout {
     static constexpr int INCL = D + NS;  // (b, C) of a prefix from step 0
 };
 
+// Per-step records of the forward filter for the adjoint: predicted mean
+// mu (D), predicted covariance Pi (NS packed), gain K (D), innovation
+// variance S, innovation v (K = 0 and v = 0 at a missing step).
+template <int D>
+struct RecLayout {
+    static constexpr int NS = D * (D + 1) / 2;
+    static constexpr int SIZE = 2 * D + NS + 2;
+};
+
+// Records in the tile layout: field f of step k0 + j of lane l of tile s at
+// ((s * chunk + j) * SIZE + f) * 64 + l, so that every access of a wave
+// covers 64 consecutive values.
+template <int D>
+__device__ __forceinline__ size_t rec_index(int tile, int chunk, int j, int lane)
+{
+    return ((size_t)tile * chunk + j) * RecLayout<D>::SIZE * PSSGP_WAVE + lane;
+}
+
 template <int D, typename T>
 __device__ __forceinline__ void agg_store(T *p, const FAgg<D, T> &a, size_t st = 1)
 {

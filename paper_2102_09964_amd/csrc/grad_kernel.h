@@ -26,11 +26,11 @@
 //   d/d R     : K^T Pbar K - (v/S) K^T mbar - 1/2 (1/S - v^2/S^2)   (observed steps)
 // where G1_c, Q_c, Pinf_c are restricted to component c.
 //
-// Memory: the forward filter stores one checkpoint (m, P) per lane chunk.
-// One wave per tile, `chunk` steps per lane:
-//   fold    each lane re-runs the filter over its chunk from its checkpoint,
-//           writes the per-step forward quantities (mu, Pi, K, S, v) to a
-//           scratch record, and composes its adjoint elements left to right;
+// Memory: the finish pass of the forward filter writes the per-step
+// quantities (mu, Pi, K, S, v) from its FP64 prediction to a record
+// (RecLayout, tile layout). One wave per tile, `chunk` steps per lane:
+//   fold    each lane composes the adjoint elements of its chunk left to
+//           right from the records and the transition;
 //           wave-level inclusive suffix scan of the chunk maps
 //   carry   one workgroup scans the tile maps from the end and stores the
 //           adjoint after every tile
@@ -134,8 +134,7 @@ struct GradParams {
     int64_t n;
     int chunk;
     int ntiles;
-    const T *ck;
-    T *rec;
+    const T *rec;
     double *grad;
     WsCtl *ctl;
     T *aggp;
@@ -144,12 +143,7 @@ struct GradParams {
     double *partials;
 };
 
-template <int D>
-struct RecLayout {
-    static constexpr int NS = D * (D + 1) / 2;
-    // mu (D), Pi (NS packed), K (D), S, v
-    static constexpr int SIZE = 2 * D + NS + 2;
-};
+
 
 template <class LY, typename T>
 __global__ __launch_bounds__(PSSGP_WAVE) void grad_fold_kernel(GradParams<T> p, DevModel mdl_arg)
@@ -157,9 +151,6 @@ __global__ __launch_bounds__(PSSGP_WAVE) void grad_fold_kernel(GradParams<T> p, 
     constexpr int D = LY::D;
     constexpr int NS = LY::NS;
     constexpr int AGG = SAggLayout<D>::SIZE;
-    constexpr int INCL = SAggLayout<D>::INCL;
-    constexpr int REC = RecLayout<D>::SIZE;
-    constexpr int NP = 2 * LY::NB + 1;
     __shared__ DevModel mdl;
     const int lane = lane_id();
     model_to_lds(mdl_arg, mdl);
@@ -170,65 +161,32 @@ __global__ __launch_bounds__(PSSGP_WAVE) void grad_fold_kernel(GradParams<T> p, 
     T h[D];
 #pragma unroll
     for (int i = 0; i < D; i++) h[i] = T(mdl.H[i]);
-    const T R = T(mdl.R);
     uint32_t bad = 0;
 
-    // forward recompute from the checkpoint, records, chunk adjoint map
+    // chunk adjoint map from the records of the forward filter
     {
         SAgg<D, T> agg;
         sagg_identity<D, T>(agg);
-        T m[D], P[D][D];
-#pragma unroll
-        for (int i = 0; i < D; i++) {
-            m[i] = T(0);
-#pragma unroll
-            for (int j = 0; j < D; j++) P[i][j] = T(0);
-        }
-        if (k0 < p.n) moments_load<D, T>(lane_rec(p.ck, tile, INCL, lane), m, P, PSSGP_WAVE);
         for (int64_t k = k0; k < k1; k++) {
             PSSGP_RELOAD_CONSTANTS();
-            T F[D][D], Q[D][D];
+            T F[D][D];
             {
-                double F64[D][D], Q64[D][D];
+                double F64[D][D];
                 const double dt = (k > 0) ? p.t[k] - p.t[k - 1] : 0.0;
-                discretize<LY, sizeof(T) == 8>(mdl, model_scale(mdl), dt, k == 0, F64, Q64);
+                transition<LY, sizeof(T) == 8>(mdl, model_scale(mdl), dt, k == 0, F64);
 #pragma unroll
                 for (int i = 0; i < D; i++)
 #pragma unroll
-                    for (int j = 0; j < D; j++) { F[i][j] = T(F64[i][j]); Q[i][j] = T(Q64[i][j]); }
+                    for (int j = 0; j < D; j++) F[i][j] = T(F64[i][j]);
             }
             const bool obs = p.mask ? (p.mask[k] != 0) : true;
-            const T yk = obs ? p.y[k] : T(0);
-            T mp[D], FP[D][D], Pp[D][D], Ph[D];
-            mat_vec<D, T>(F, m, mp);
-            mat_mul<D, T>(F, P, FP);
-            mat_mul_nt_sym_add<D, T>(FP, F, Q, Pp);
-            mat_vec<D, T>(Pp, h, Ph);
-            const T S = dot<D, T>(h, Ph) + R;
-            const T v = obs ? yk - dot<D, T>(h, mp) : T(0);
-            const T w = obs ? T(1) / S : T(0);
+            const T *rp = p.rec + rec_index<D>(tile, p.chunk, (int)(k - k0), lane);
+            constexpr size_t W = PSSGP_WAVE;
             T K[D];
 #pragma unroll
-            for (int i = 0; i < D; i++) K[i] = Ph[i] * w;
-            T *rp = p.rec + (size_t)k * REC;
-#pragma unroll
-            for (int i = 0; i < D; i++) { rp[i] = mp[i]; rp[D + NS + i] = K[i]; }
-#pragma unroll
-            for (int i = 0; i < D; i++)
-#pragma unroll
-                for (int j = i; j < D; j++) rp[D + sidx<D>(i, j)] = Pp[i][j];
-            rp[2 * D + NS] = S;
-            rp[2 * D + NS + 1] = v;
-#pragma unroll
-            for (int i = 0; i < D; i++) m[i] = fma(K[i], v, mp[i]);
-#pragma unroll
-            for (int i = 0; i < D; i++)
-#pragma unroll
-                for (int j = i; j < D; j++) {
-                    const T c = fma(-Ph[i], K[j], Pp[i][j]);
-                    P[i][j] = c;
-                    P[j][i] = c;
-                }
+            for (int i = 0; i < D; i++) K[i] = rp[(D + NS + i) * W];
+            const T S = rp[(2 * D + NS) * W], v = rp[(2 * D + NS + 1) * W];
+            const T w = obs ? T(1) / S : T(0);
             // fold the step's adjoint element on the right of the chunk map
             T u[D], wv[D], X[D][D];
 #pragma unroll
@@ -285,7 +243,6 @@ __global__ __launch_bounds__(PSSGP_WAVE) void grad_finish_kernel(GradParams<T> p
     constexpr int NS = LY::NS;
     constexpr int AGG = SAggLayout<D>::SIZE;
     constexpr int INCL = SAggLayout<D>::INCL;
-    constexpr int REC = RecLayout<D>::SIZE;
     constexpr int NP = 2 * LY::NB + 1;
     __shared__ DevModel mdl;
     const int lane = lane_id();
@@ -317,15 +274,16 @@ __global__ __launch_bounds__(PSSGP_WAVE) void grad_finish_kernel(GradParams<T> p
         double F64[D][D], Q64[D][D];
         discretize<LY, sizeof(T) == 8>(mdl, model_scale(mdl), dt, k == 0, F64, Q64);
         const bool obs = p.mask ? (p.mask[k] != 0) : true;
-        const T *rp = p.rec + (size_t)k * REC;
+        const T *rp = p.rec + rec_index<D>(tile, p.chunk, (int)(k - k0), lane);
+        constexpr size_t W = PSSGP_WAVE;
         T mu[D], Pi[D][D], K[D];
 #pragma unroll
-        for (int i = 0; i < D; i++) { mu[i] = rp[i]; K[i] = rp[D + NS + i]; }
+        for (int i = 0; i < D; i++) { mu[i] = rp[i * W]; K[i] = rp[(D + NS + i) * W]; }
 #pragma unroll
         for (int i = 0; i < D; i++)
 #pragma unroll
-            for (int j = i; j < D; j++) { Pi[i][j] = rp[D + sidx<D>(i, j)]; Pi[j][i] = Pi[i][j]; }
-        const T S = rp[2 * D + NS], v = rp[2 * D + NS + 1];
+            for (int j = i; j < D; j++) { Pi[i][j] = rp[(D + sidx<D>(i, j)) * W]; Pi[j][i] = Pi[i][j]; }
+        const T S = rp[(2 * D + NS) * W], v = rp[(2 * D + NS + 1) * W];
         // adjoints of the predicted moments
         T PK[D];
         mat_vec<D, T>(Pb, K, PK);
@@ -460,8 +418,7 @@ int launch_grad_t(const DevModel &mdl, const GradLaunch &a, hipStream_t s)
     p.n = a.n;
     p.chunk = a.chunk;
     p.ntiles = a.ntiles;
-    p.ck = (const T *)a.ck;
-    p.rec = (T *)a.rec;
+    p.rec = (const T *)a.rec;
     p.grad = a.grad;
     p.ctl = a.ws.ctl;
     p.inclp = (T *)a.ws.inclp;

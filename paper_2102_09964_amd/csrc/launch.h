@@ -46,7 +46,7 @@ struct FilterLaunch {
     void *m;         // nullable
     void *P;         // nullable
     double *loglik;  // nullable
-    void *ck;        // nullable: per-chunk checkpoints of the start moments
+    void *rec;       // nullable: per-step records of the adjoint (tile layout)
     int tiled;       // write smoother elements to m (P unused) in the tile layout of the handover
     void *slane;     // tiled: per-lane smoother aggregates (lane_aggregate_handover)
     ScanWs ws;
@@ -76,8 +76,7 @@ struct GradLaunch {
     int64_t n;
     int chunk;
     int ntiles;
-    const void *ck;     // checkpoints written by the forward filter
-    void *rec;          // per-step forward records (scratch)
+    const void *rec;    // per-step records written by the forward filter
     double *grad;       // device [2 n_comp + 1]
     ScanWs ws;
 };
