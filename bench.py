@@ -344,8 +344,9 @@ def measure_batched(steps, warmup, chunk=0):
 
 
 def measure_grad(steps, warmup, chunk=0):
-    """Log-likelihood and its gradient (hand-written adjoint with checkpoint
-    recompute) for the sum kernel Matern-3/2 + RBF-6 (d = 8), N = 2^20, FP32."""
+    """Log-likelihood and its gradient (hand-written adjoint over the forward
+    filter's per-step records) for the sum kernel Matern-3/2 + RBF-6 (d = 8),
+    N = 2^20, FP32."""
     import torch
     import workloads
     import paper_2102_09964_amd as P
@@ -415,6 +416,65 @@ def cpu_baseline_batched(target_s=10.0, max_threads=16):
                       % (ns, len(models), n, threads, dt)}
 
 
+def merge_bytes(n_train, n_test, ysize, with_mask):
+    """Algorithmic HBM bytes of one merge of n_test test times into n_train
+    training steps: reads t_train (8 B), y_train (ysize) and mask_train (1 B,
+    when given) per training step and t_test (8 B) per test step; writes t
+    (8 B), y (ysize) and mask (1 B) per merged step and test_pos (8 B) per
+    test step."""
+    return (n_train * (8 + ysize + (1 if with_mask else 0)) + n_test * 8
+            + (n_train + n_test) * (8 + ysize + 1) + n_test * 8)
+
+
+def measure_merge(steps, warmup):
+    """Merge of the missing steps of rbf6_lognormal (2^22 steps, 20 %
+    missing) as test times into its observed steps (FP32 y, all training
+    steps observed): one pssgp_merge_times launch per step, HIP events on
+    the launch stream, outputs preallocated."""
+    import torch
+    import workloads
+    import paper_2102_09964_amd as P
+    w = workloads.rbf6_lognormal()
+    obs = w["mask"] == 1
+    tr = torch.as_tensor(w["t"][obs], dtype=torch.float64, device="cuda")
+    te = torch.as_tensor(w["t"][~obs], dtype=torch.float64, device="cuda")
+    y = torch.as_tensor(w["y"][obs], dtype=torch.float32, device="cuda")
+    n, m = tr.shape[0], te.shape[0]
+    t_out = torch.empty(n + m, dtype=torch.float64, device="cuda")
+    y_out = torch.empty(n + m, dtype=torch.float32, device="cuda")
+    m_out = torch.empty(n + m, dtype=torch.uint8, device="cuda")
+    pos = torch.empty(m, dtype=torch.int64, device="cuda")
+    L = P.lib()
+    stream = P._stream()
+
+    def call():
+        rc = L.pssgp_merge_times(P._p(tr), P._p(y), None, n, P._p(te), m, P.F32, P._p(t_out), P._p(y_out),
+                                 P._p(m_out), P._p(pos), stream)
+        if rc != 0:
+            raise RuntimeError("pssgp_merge_times: %s" % L.pssgp_last_error().decode())
+
+    for _ in range(warmup):
+        call()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        call()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    if not np.array_equal(t_out.cpu().numpy(), w["t"]):
+        raise RuntimeError("merged grid differs from the original grid")
+    nbytes = merge_bytes(n, m, 4, False)
+    gbs = nbytes / (ms / 1e3) / 1e9
+    return {"workload": "merge_rbf6_lognormal", "dtype": "float32", "n_train": n, "n_test": m,
+            "steps_per_s": round((n + m) / (ms / 1e3), 1), "ms_per_step": round(ms, 4),
+            "roofline": {"bound": "hbm", "kernel": "merge_kernel", "achieved": round(gbs, 2), "peak": 8000.0,
+                         "unit": "GB/s", "frac": round(gbs / 8000.0, 5),
+                         "algorithmic_bytes_per_launch": nbytes,
+                         "traffic": measured_traffic("merge_kernel", "merge_rbf6_lognormal", "float32", 0)}}
+
+
 def copy_probe():
     """A plain device copy of known size (1 GiB, three times): the counter
     values FETCH_SIZE and WRITE_SIZE read for it give the factors that turn
@@ -442,9 +502,14 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB three times (calibration of the FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--merge-only", action="store_true",
+                    help="only the merge of test times into the training grid (one JSON line)")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe()
+        return
+    if args.merge_only:
+        print(json.dumps(measure_merge(args.steps, args.warmup)), flush=True)
         return
     if args.gpus != 1:
         print("bench.py: runs on one GPU only; sharding the time axis over several GPUs is designed "
@@ -486,6 +551,7 @@ def main():
             mb["cpu_baseline"] = cpu_baseline_batched()
         also.append(mb)
         also.append(measure_grad(max(3, args.steps // 2), 2))
+        also.append(measure_merge(max(3, args.steps // 2), 2))
     out = {
         "metric": "time steps/sec, filter+smoother+loglik(+grad), FP32 vs FP64, d=2..8, 1 GPU",
         "value": round(m["steps_per_s"], 1),

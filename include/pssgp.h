@@ -323,6 +323,36 @@ int pssgp_batched_predict(const pssgp_batch_group *groups_host, int n_groups, in
                           void *f_mean, void *f_var, double *loglik, void *ws, size_t ws_bytes,
                           const pssgp_options *opts, void *stream);
 
+/*
+ * Time grid of a prediction (section 4: test times enter the model as
+ * steps without a measurement, the missing-measurement elements of
+ * section 3): merges the sorted test times into the sorted training times
+ * on the device (merge path over tiles of 2048 outputs). The merge is
+ * stable: at equal times training steps precede test steps, and each
+ * sequence keeps its own order.
+ *  t_train   device double[n_train], non-decreasing
+ *  y_train   device dtype[n_train]; may be NULL when y_out is NULL (no
+ *            values merged) or n_train is 0
+ *  mask_train device uint8[n_train] (1 = observed), or NULL (all observed)
+ *  t_test    device double[n_test], non-decreasing
+ * Outputs, n_out = n_train + n_test, in merged order:
+ *  t_out     device double[n_out]
+ *  y_out     device dtype[n_out] or NULL: y_train at training steps, 0 at
+ *            test steps
+ *  mask_out  device uint8[n_out]: mask_train (or 1) at training steps, 0 at
+ *            test steps
+ *  test_pos  device int64[n_test] or NULL: the merged index of each test time
+ * Output buffers must not overlap the inputs. Needs no workspace. Errors:
+ * PSSGP_EINVAL for n < 0, a total beyond 2^42 steps, a bad dtype, or a
+ * missing pointer; PSSGP_EDEVICE for a launch failure. Unsorted inputs
+ * give an unspecified order (every output is still written once and no
+ * access leaves the buffers); the filter calls then report
+ * PSSGP_STATUS_UNSORTED.
+ */
+int pssgp_merge_times(const double *t_train, const void *y_train, const uint8_t *mask_train,
+                      int64_t n_train, const double *t_test, int64_t n_test, pssgp_dtype dtype,
+                      double *t_out, void *y_out, uint8_t *mask_out, int64_t *test_pos, void *stream);
+
 /* Status word of the most recent call that used workspace ws (read after
  * synchronising stream); bits: PSSGP_STATUS_*. */
 int pssgp_status(void *ws, void *stream, uint32_t *bits_host);

@@ -88,6 +88,7 @@ SIGNATURES = [
     ("pssgp_status", ctypes.c_int, [_VP, _VP, ctypes.POINTER(ctypes.c_uint32)]),
     ("pssgp_predict", ctypes.c_int, [_MP, _VP, _VP, _VP, _I64, ctypes.c_int, _VP, _VP, _VP, _VP, _SZ, _OP, _VP]),
     ("pssgp_plain_predict", ctypes.c_int, [_MP, _VP, _VP, _VP, _I64, _VP, _VP, _VP, _VP, _VP, _VP, _SZ, _VP]),
+    ("pssgp_merge_times", ctypes.c_int, [_VP, _VP, _VP, _I64, _VP, _I64, ctypes.c_int, _VP, _VP, _VP, _VP, _VP]),
 ]
 
 
@@ -343,6 +344,28 @@ def predict(model, t, y, mask=None, dtype="float32", options=None, device="cuda"
     f = filter(model, t, y, mask, dtype=dtype, options=options, device=device)
     s = smooth(model, t, f["m"], f["P"], dtype=dtype, options=options, device=device)
     return {"f_mean": s["f_mean"], "f_var": s["f_var"], "loglik": f["loglik"], "m": f["m"], "P": f["P"]}
+
+
+def merge_times(t_train, y_train, t_test, mask_train=None, dtype="float32", device="cuda"):
+    """Merged time grid of a prediction (pssgp_merge_times): returns
+    (t, y, mask, test_pos) with t float64 [n + m], y dtype [n + m] (0 at test
+    steps; None when y_train is None), mask uint8 [n + m] (0 at test steps)
+    and test_pos int64 [m], the merged index of every test time."""
+    _require_gpu()
+    torch = _torch()
+    code, tdt = _dt(dtype)
+    t_train = _dev(t_train, torch.float64, device)
+    t_test = _dev(t_test, torch.float64, device)
+    y_train = _dev(y_train, tdt, device)
+    mask_train = _dev(mask_train, torch.uint8, device)
+    n, m = t_train.shape[0], t_test.shape[0]
+    t = torch.empty(n + m, dtype=torch.float64, device=device)
+    y = torch.empty(n + m, dtype=tdt, device=device) if y_train is not None else None
+    mask = torch.empty(n + m, dtype=torch.uint8, device=device)
+    pos = torch.empty(m, dtype=torch.int64, device=device)
+    _check(lib().pssgp_merge_times(_p(t_train), _p(y_train), _p(mask_train), n, _p(t_test), m, code, _p(t),
+                                   _p(y), _p(mask), _p(pos), _stream()))
+    return t, y, mask, pos
 
 
 def plain_predict(model, t, y, mask=None, ws=None, device="cuda"):

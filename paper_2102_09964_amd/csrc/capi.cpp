@@ -767,6 +767,46 @@ int pssgp_batched_predict(const pssgp_batch_group *groups_host, int n_groups, in
                        nullptr, loglik, f_mean, f_var, ws, ws_bytes, opts, stream, PSSGP_OP_PREDICT);
 }
 
+int pssgp_merge_times(const double *t_train, const void *y_train, const uint8_t *mask_train, int64_t n_train,
+                      const double *t_test, int64_t n_test, pssgp_dtype dtype, double *t_out, void *y_out,
+                      uint8_t *mask_out, int64_t *test_pos, void *stream)
+{
+    if (n_train < 0 || n_test < 0) {
+        pssgp_set_error("n_train and n_test must be >= 0");
+        return PSSGP_EINVAL;
+    }
+    if (n_train > INT64_MAX / 2 - n_test || merge_tiles(n_train + n_test) > (int64_t)INT32_MAX) {
+        pssgp_set_error("n_train + n_test is too large");
+        return PSSGP_EINVAL;
+    }
+    if (dtype != PSSGP_F32 && dtype != PSSGP_F64) {
+        pssgp_set_error("dtype must be PSSGP_F32 or PSSGP_F64");
+        return PSSGP_EINVAL;
+    }
+    if (y_out && n_train > 0 && !y_train) {
+        pssgp_set_error("y_out needs y_train");
+        return PSSGP_EINVAL;
+    }
+    if ((n_train > 0 && !t_train) || (n_test > 0 && !t_test) ||
+        (n_train + n_test > 0 && (!t_out || !mask_out))) {
+        pssgp_set_error("t_train, t_test, t_out and mask_out must be device pointers");
+        return PSSGP_EINVAL;
+    }
+    MergeLaunch a;
+    a.t_train = t_train;
+    a.y_train = y_out ? y_train : nullptr;
+    a.mask_train = mask_train;
+    a.n_train = n_train;
+    a.t_test = t_test;
+    a.n_test = n_test;
+    a.f64 = dtype == PSSGP_F64;
+    a.t_out = t_out;
+    a.y_out = y_out;
+    a.mask_out = mask_out;
+    a.test_pos = n_test > 0 ? test_pos : nullptr;
+    return check_launch(launch_merge(a, (hipStream_t)stream), "merge launch");
+}
+
 int pssgp_status(void *ws, void *stream, uint32_t *bits_host)
 {
     if (!ws || !bits_host) {

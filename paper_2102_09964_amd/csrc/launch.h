@@ -182,3 +182,20 @@ inline void pass_event(void *const *ev, int i, hipStream_t s)
 // zero_out[0, nzero).
 int launch_ws_init(WsCtl *ctl, double *zero_out, int nzero, hipStream_t s, bool keep_status = false);
 bool layout_supported(int b0, int b1);
+
+// Merge of sorted test times into the sorted training grid (merge.hip).
+struct MergeLaunch {
+    const double *t_train;
+    const void *y_train;         // nullable when y_out is NULL or n_train is 0
+    const uint8_t *mask_train;   // nullable: every training step observed
+    int64_t n_train;
+    const double *t_test;
+    int64_t n_test;
+    bool f64;                    // y in FP64 (else FP32)
+    double *t_out;
+    void *y_out;
+    uint8_t *mask_out;
+    int64_t *test_pos;           // nullable
+};
+int64_t merge_tiles(int64_t total);
+int launch_merge(const MergeLaunch &a, hipStream_t s);

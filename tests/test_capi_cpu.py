@@ -136,3 +136,26 @@ def test_argument_errors_need_no_device():
     assert L.pssgp_filter(ctypes.byref(m9), fake, fake, None, None, n, P.F32, fake, fake, fake, fake, need, None,
                           None) == -2
     assert b"state size" in L.pssgp_last_error()
+
+
+def test_merge_argument_errors_need_no_device():
+    """pssgp_merge_times validates sizes, dtype and pointers on the host."""
+    L = P.lib()
+    fake = ctypes.c_void_p(0x1000)
+    mt = L.pssgp_merge_times
+    # negative sizes
+    assert mt(fake, fake, None, -1, fake, 5, P.F32, fake, fake, fake, fake, None) == -1
+    assert mt(fake, fake, None, 5, fake, -1, P.F32, fake, fake, fake, fake, None) == -1
+    # a total beyond 2^42 steps, and one that overflows int64
+    assert mt(fake, fake, None, 1 << 42, fake, 1, P.F32, fake, fake, fake, fake, None) == -1
+    assert mt(fake, fake, None, (1 << 62), fake, (1 << 62), P.F32, fake, fake, fake, fake, None) == -1
+    # bad dtype
+    assert mt(fake, fake, None, 5, fake, 5, 9, fake, fake, fake, fake, None) == -1
+    # y_out without y_train
+    assert mt(fake, None, None, 5, fake, 5, P.F32, fake, fake, fake, fake, None) == -1
+    # missing inputs or outputs
+    assert mt(None, None, None, 5, fake, 5, P.F32, fake, None, fake, fake, None) == -1
+    assert mt(fake, None, None, 5, None, 5, P.F32, fake, None, fake, fake, None) == -1
+    assert mt(fake, None, None, 5, fake, 5, P.F32, None, None, fake, fake, None) == -1
+    assert mt(fake, None, None, 5, fake, 5, P.F32, fake, None, None, fake, None) == -1
+    assert b"device pointers" in L.pssgp_last_error()
