@@ -475,6 +475,36 @@ def measure_merge(steps, warmup):
                          "traffic": measured_traffic("merge_kernel", "merge_rbf6_lognormal", "float32", 0)}}
 
 
+def measure_learning(max_iter=20, n_samples=4):
+    """Hyperparameter learning and sampling on the headline workload
+    (rbf6_lognormal, 2^22 steps, FP32 scans): L-BFGS over the
+    log-hyperparameters from (ell, var, noise) = (0.5, 2, 0.05), then HMC
+    (10 leapfrog steps per sample) started at the L-BFGS result. Every
+    function + gradient evaluation is one pssgp_loglik_grad call; the times
+    are wall clock, host work included."""
+    import workloads
+    from paper_2102_09964_amd.fit import LogLikObjective, fit_lbfgs, hmc
+    w = workloads.rbf6_lognormal()
+    n = w["t"].shape[0]
+    kinds = [(c[0], c[1]) for c in w["model"]["components"]]
+    obj = LogLikObjective(kinds, w["t"], w["y"], w["mask"], dtype="float32")
+    obj(np.log([0.5, 2.0, 0.05]))  # warm-up evaluation
+    t0 = time.perf_counter()
+    r = fit_lbfgs(obj, [0.5, 2.0, 0.05], max_iter=max_iter)
+    t_fit = time.perf_counter() - t0
+    mom, lu = workloads.hmc_draws(n_samples, 3)
+    t0 = time.perf_counter()
+    h = hmc(obj, r["theta"], 2e-4, mom, lu, n_leapfrog=10)
+    t_hmc = time.perf_counter() - t0
+    return {"workload": "rbf6_lognormal_learning", "dtype": "float32", "n": n,
+            "lbfgs": {"n_iter": r["n_iter"], "n_evals": r["n_evals"], "seconds": round(t_fit, 4),
+                      "ms_per_eval": round(1e3 * t_fit / max(r["n_evals"], 1), 4),
+                      "steps_per_s": round(n * r["n_evals"] / t_fit, 1), "loglik": round(r["loglik"], 4),
+                      "theta": [round(float(v), 6) for v in r["theta"]]},
+            "hmc": {"n_samples": n_samples, "n_leapfrog": 10, "n_evals": h["n_evals"], "seconds": round(t_hmc, 4),
+                    "samples_per_s": round(n_samples / t_hmc, 3), "accept_rate": float(h["accepted"].mean())}}
+
+
 def copy_probe():
     """A plain device copy of known size (1 GiB, three times): the counter
     values FETCH_SIZE and WRITE_SIZE read for it give the factors that turn
@@ -552,6 +582,7 @@ def main():
         also.append(mb)
         also.append(measure_grad(max(3, args.steps // 2), 2))
         also.append(measure_merge(max(3, args.steps // 2), 2))
+        also.append(measure_learning())
     out = {
         "metric": "time steps/sec, filter+smoother+loglik(+grad), FP32 vs FP64, d=2..8, 1 GPU",
         "value": round(m["steps_per_s"], 1),

@@ -1,0 +1,62 @@
+"""Hyperparameter learning (L-BFGS) and HMC sampling over the device
+log-likelihood and gradient (paper_2102_09964_amd.fit) against the same
+loops over the FP64 oracle (oracle/learn.py), on the same data and the
+same random draws."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import learn as OL
+from oracle.model import MATERN32, RBF
+
+pytestmark = pytest.mark.gpu
+
+# the paper's kernel: RBF approximated to Taylor order 6 (d = 6)
+RBF6 = [(RBF, 6)]
+TH0 = [1.0, 1.0, 0.05]
+
+
+def _data(n):
+    w = W.learning_data(n)
+    return w["t"], np.where(w["mask"] == 1, w["y"], 0.0), w["mask"]
+
+
+def test_lbfgs_fp64_matches_oracle():
+    from paper_2102_09964_amd.fit import LogLikObjective, fit_lbfgs
+    t, y, mask = _data(1500)
+    obj = LogLikObjective(RBF6, t, y, mask, dtype="float64")
+    r = fit_lbfgs(obj, TH0, max_iter=200, gtol=1e-8)
+    th_o, ll_o = OL.lbfgs(OL.log_objective(RBF6, t, y, mask), TH0, max_iter=200, gtol=1e-8)
+    print("gpu", r["theta"], r["loglik"], r["n_evals"], "oracle", th_o, ll_o, flush=True)
+    np.testing.assert_allclose(r["theta"], th_o, rtol=1e-4)
+    assert abs(r["loglik"] - ll_o) <= 1e-9 * abs(ll_o)
+
+
+def test_lbfgs_fp32_reaches_the_oracle_optimum():
+    """FP32 scans: the optimum's log-likelihood agrees with the FP64
+    oracle's to the FP32 log-likelihood tolerance (the objective is flat
+    there, so the hyperparameters agree less closely)."""
+    from paper_2102_09964_amd.fit import LogLikObjective, fit_lbfgs
+    t, y, mask = _data(1500)
+    obj = LogLikObjective(RBF6, t, y, mask, dtype="float32")
+    r = fit_lbfgs(obj, TH0, max_iter=200, gtol=1e-6)
+    th_o, ll_o = OL.lbfgs(OL.log_objective(RBF6, t, y, mask), TH0, max_iter=200, gtol=1e-8)
+    ll_at = OL.log_objective(RBF6, t, y, mask)(np.log(r["theta"]))[0]
+    print("gpu", r["theta"], r["loglik"], "oracle", th_o, ll_o, "oracle at gpu theta", ll_at, flush=True)
+    assert abs(ll_at - ll_o) <= 1e-5 * abs(ll_o)
+    np.testing.assert_allclose(r["theta"], th_o, rtol=2e-2)
+
+
+def test_hmc_fp64_matches_oracle():
+    from paper_2102_09964_amd.fit import LogLikObjective, hmc
+    t, y, mask = _data(800)
+    kinds = [(MATERN32, 0)]
+    th0 = [0.3, 1.5, 0.01]
+    mom, lu = W.hmc_draws(6, 3, seed_extra=2)
+    obj = LogLikObjective(kinds, t, y, mask, dtype="float64")
+    r = hmc(obj, th0, 0.02, mom, lu, n_leapfrog=10)
+    states, acc = OL.hmc(OL.log_posterior(kinds, t, y, mask), np.log(th0), 0.02, mom, lu, n_leapfrog=10)
+    print("accepted", r["accepted"], acc, flush=True)
+    np.testing.assert_array_equal(r["accepted"], acc)
+    np.testing.assert_allclose(r["samples"], np.exp(states), rtol=1e-7)
+    assert r["n_evals"] == 1 + 6 * 10

@@ -152,3 +152,25 @@ def random_series(n: int, components, noise_var: float, missing: float = 0.2, sp
     mask = (rng.uniform(size=n) >= missing).astype(np.uint8)
     model = {"components": [tuple(c) for c in components], "noise_var": float(noise_var)}
     return {"name": "random", "t": t, "y": y, "mask": mask, "model": model}
+
+
+def hmc_draws(n_samples: int, n_params: int, seed_extra: int = 0):
+    """Random numbers of an HMC chain: standard-normal momenta
+    [n_samples, n_params] and the logs of uniform(0, 1) draws [n_samples]
+    for the accept tests."""
+    rng = _rng(6, seed_extra)
+    momenta = rng.standard_normal((n_samples, n_params))
+    log_u = np.log(rng.uniform(size=n_samples))
+    return momenta, log_u
+
+
+def learning_data(n: int = 2000, seed_extra: int = 0):
+    """Data for hyperparameter learning: a Matern-3/2 + RBF-6 sum draws no
+    closed form, so y is the paper's simulated signal (sin pi t + sin 2 pi t
+    + sin 3 pi t) at n sorted uniform times on [0, 10] plus N(0, 0.1^2),
+    10% of the steps missing."""
+    rng = _rng(7, seed_extra)
+    t = np.sort(rng.uniform(0.0, 10.0, n))
+    y = np.sin(np.pi * t) + np.sin(2 * np.pi * t) + np.sin(3 * np.pi * t) + rng.normal(0.0, 0.1, n)
+    mask = (rng.uniform(size=n) >= 0.1).astype(np.uint8)
+    return {"name": "learning", "t": t, "y": y, "mask": mask}
