@@ -106,17 +106,26 @@ def algorithmic_bytes(tsize, n):
     return n * (8 + tsize + 1 + 2 * tsize)
 
 
-def sources_digest():
-    """SHA-256 of the kernel sources (the traffic figures of a profile
-    summary hold only for the sources they were taken with)."""
+MERGE_SOURCES = ("merge.hip", "launch.h")
+
+
+def sources_digest(kernel=None):
+    """SHA-256 of the sources a kernel is built from (the traffic figures of
+    a profile summary hold only for the sources they were taken with): for
+    the merge kernel merge.hip and launch.h, for the scan kernels every
+    other source file."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2102_09964_amd", "csrc")
+    merge = kernel == "merge_kernel"
     for name in sorted(os.listdir(csrc)):
-        if name.endswith((".h", ".hip", ".cpp")):
-            h.update(name.encode())
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(f.read())
+        if not name.endswith((".h", ".hip", ".cpp")):
+            continue
+        if (merge and name not in MERGE_SOURCES) or (not merge and name == "merge.hip"):
+            continue
+        h.update(name.encode())
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()
 
 
@@ -140,7 +149,7 @@ def measured_traffic(kernel, workload, dtype, chunk):
                 if (kv.get("kernel"), kv.get("workload"), kv.get("dtype"), kv.get("chunk")) != \
                         (kernel, workload, dtype, str(chunk)):
                     continue
-                digest = digest or sources_digest()
+                digest = digest or sources_digest(kernel)
                 if kv.get("sources") == digest:
                     return float(kv["bytes"])
     return None
