@@ -13,9 +13,10 @@
 // split of an output position d is the number i of training elements among
 // the first d outputs (the point where the cross diagonal i + j = d meets
 // the merge path); it is the smallest i with not (A[i] <= B[d - 1 - i]).
-//   1. waves 0 and 1 of a workgroup find the splits of the tile's two ends
-//      with a 64-way search (each round probes 64 points: 4 rounds for
-//      2^22 elements, against 22 dependent loads of a binary search)
+//   1. the two halves of wave 0 find the splits of the tile's two ends with
+//      a 32-way search on an aligned grid (4 rounds for 2^20 candidates,
+//      against 20 dependent loads of a binary search; neighbouring tiles
+//      share the probed lines)
 //   2. the workgroup stages both input segments (times, and the training
 //      values and mask) in LDS; each thread finds its split within the
 //      tile by binary search in LDS and merges its VT = 8 outputs
@@ -34,30 +35,43 @@
 #define MERGE_WAVE 64
 #define MERGE_THREADS 256
 #define MERGE_VT 8
+#define MERGE_PROBES 32  // probes per round of a split search (half a wave)
 #define MERGE_NV (MERGE_THREADS * MERGE_VT)
 
 namespace {
 
-// Split of output position d (one wave, uniform result): the smallest i in
-// [max(0, d - nb), min(d, na)] at which training element i does not precede
-// test element d - 1 - i (the upper end if there is none).
-__device__ int64_t wave_split(const double *A, int64_t na, const double *B, int64_t nb, int64_t d, int lane)
+// Split of output position d, found by one half wave (32 lanes; the result
+// is uniform over the half): the smallest i in [max(0, d - nb), min(d, na)]
+// at which training element i does not precede test element d - 1 - i (the
+// upper end if there is none). Each round probes 32 points of the current
+// range [lo, hi] on a grid of a power-of-two step aligned to multiples of
+// that step, so that the searches of neighbouring tiles probe the same
+// cache lines; points of the grid below lo count as preceding (they lie
+// below the answer) and are not loaded. The loop runs until both halves
+// are done.
+__device__ int64_t split_search(const double *A, int64_t na, const double *B, int64_t nb, int64_t d, int sub,
+                                int half)
 {
     int64_t lo = d > nb ? d - nb : 0;
     int64_t hi = d < na ? d : na;
-    while (lo < hi) {
-        const int64_t step = (hi - lo + 63) / 64;
-        const int64_t p = lo + (int64_t)lane * step;
-        // probes at p < hi only: then p <= d - 1 and d - 1 - p <= nb - 1
-        const bool before = (p < hi) && (A[p] <= B[d - 1 - p]);
-        // lanes with a probe form a prefix, and only they can vote, so
-        // c - 1 is a probing lane
-        const int c = __popcll(__ballot(before));
-        if (c == 0) {
-            hi = lo;
-        } else {
-            const int64_t nhi = lo + (int64_t)c * step;
-            lo = lo + (int64_t)(c - 1) * step + 1;
+    while (__ballot(lo < hi) != 0) {
+        const bool act = lo < hi;
+        int64_t step = 1;
+        while (act && step * (MERGE_PROBES - 1) < hi - lo) step <<= 1;
+        const int64_t base = lo & ~(step - 1);
+        const int64_t p = base + (int64_t)sub * step;
+        // loads only at lo <= p < hi: then p <= d - 1 and d - 1 - p <= nb - 1
+        const bool before = act && (p < lo || (p < hi && A[p] <= B[d - 1 - p]));
+        const uint64_t bal = __ballot(before);
+        // the probes below hi form a prefix of the half and only they can
+        // vote, so probe c - 1 lies below hi; probe c lies at or above lo
+        const int c = __popcll(half ? (bal >> 32) : (bal & 0xffffffffull));
+        if (act) {
+            const int64_t nhi = base + (int64_t)c * step;
+            if (c > 0) {
+                const int64_t nlo = base + (int64_t)(c - 1) * step + 1;
+                lo = nlo > lo ? nlo : lo;
+            }
             hi = nhi < hi ? nhi : hi;
         }
     }
@@ -84,9 +98,10 @@ __global__ __launch_bounds__(MERGE_THREADS) void merge_kernel(const double *__re
     const int64_t total = na + nb;
     const int64_t d0 = (int64_t)blockIdx.x * MERGE_NV;
     const int64_t d1 = (d0 + MERGE_NV < total) ? d0 + MERGE_NV : total;
-    if (wv < 2) {
-        const int64_t s = wave_split(ta, na, tb, nb, wv == 0 ? d0 : d1, lane);
-        if (lane == 0) s_split[wv] = s;
+    if (wv == 0) {
+        const int half = lane / MERGE_PROBES, sub = lane % MERGE_PROBES;
+        const int64_t s = split_search(ta, na, tb, nb, half ? d1 : d0, sub, half);
+        if (sub == 0) s_split[half] = s;
     }
     __syncthreads();
     const int64_t i0 = s_split[0];

@@ -10,31 +10,41 @@ import pytest
 from oracle.merge import merge_ranks
 
 
-def _wave_split(A, B, d, wave=64):
+def _split(A, B, d, lanes=32):
+    """The kernel's split search for one half wave of `lanes` probes."""
     na, nb = len(A), len(B)
     lo, hi = max(0, d - nb), min(d, na)
     while lo < hi:
-        step = (hi - lo + wave - 1) // wave
-        c = 0
-        for lane in range(wave):
-            p = lo + lane * step
-            if p < hi:
+        step = 1
+        while step * (lanes - 1) < hi - lo:
+            step <<= 1
+        base = lo & ~(step - 1)
+        votes = []
+        for sub in range(lanes):
+            p = base + sub * step
+            if p < lo:
+                votes.append(True)
+            elif p < hi:
                 assert 0 <= p < na and 0 <= d - 1 - p < nb
-                c += A[p] <= B[d - 1 - p]
-        if c == 0:
-            hi = lo
-        else:
-            lo, hi = lo + (c - 1) * step + 1, min(lo + c * step, hi)
+                votes.append(bool(A[p] <= B[d - 1 - p]))
+            else:
+                votes.append(False)
+        c = sum(votes)
+        assert c == 0 or base + (c - 1) * step < hi
+        nhi = base + c * step
+        nlo = max(lo, base + (c - 1) * step + 1) if c > 0 else lo
+        assert lo <= nlo <= min(hi, nhi) and (min(hi, nhi) - nlo) < (hi - lo)
+        lo, hi = nlo, min(hi, nhi)
     return lo
 
 
-def _emulate(A, B, threads, vt, wave):
+def _emulate(A, B, threads, vt, lanes):
     na, nb = len(A), len(B)
     total, nv = na + nb, threads * vt
     out = [None] * total
     for blk in range((total + nv - 1) // nv):
         d0, d1 = blk * nv, min(blk * nv + nv, total)
-        i0, i1 = _wave_split(A, B, d0, wave), _wave_split(A, B, d1, wave)
+        i0, i1 = _split(A, B, d0, lanes), _split(A, B, d1, lanes)
         i1 = min(max(i1, i0), i0 + (d1 - d0))
         j0, cnt = d0 - i0, d1 - d0
         na_t = i1 - i0
@@ -74,7 +84,7 @@ def test_emulation_matches_oracle_on_sorted_inputs(seed):
     n, m = rng.integers(0, 90, 2)
     A = np.sort(rng.integers(0, 15, n)).astype(float)
     B = np.sort(rng.integers(0, 15, m)).astype(float)
-    out = _emulate(A, B, threads=4, vt=3, wave=4)
+    out = _emulate(A, B, threads=4, vt=3, lanes=4)
     pa, pb = merge_ranks(A, B)
     for k, (s, i) in enumerate(out):
         assert (pa[i] if s == "a" else pb[i]) == k
@@ -88,4 +98,15 @@ def test_emulation_stays_in_bounds_on_unsorted_inputs(seed):
     B = rng.uniform(0, 1, m)
     if seed % 2 and n:
         A[rng.integers(0, n, 3)] = np.nan
-    _emulate(A, B, threads=4, vt=3, wave=4)
+    _emulate(A, B, threads=4, vt=3, lanes=4)
+
+
+def test_split_search_at_kernel_width():
+    """The 32-probe search gives the rank definition's split on a large
+    sorted input (every diagonal of a coarse sample)."""
+    rng = np.random.default_rng(9)
+    A = np.sort(rng.integers(0, 5000, 20000)).astype(float)
+    B = np.sort(rng.integers(0, 5000, 7000)).astype(float)
+    pa, _ = merge_ranks(A, B)
+    for d in list(range(0, 27001, 997)) + [27000]:
+        assert _split(A, B, d, 32) == int(np.sum(pa < d))
