@@ -109,3 +109,17 @@ def test_tune_cache_roundtrip(tmp_path, monkeypatch):
     assert tune._load()["k"]["chunk"] == 32
     path.write_text("not json")
     assert tune._load() == {}
+
+
+def test_merge_bytes_and_source_digests():
+    """Algorithmic bytes of the merge (reads t, y, mask per training step and
+    t per test step; writes t, y, mask per merged step and the test
+    positions) and the per-family source digests that key the traffic
+    figures."""
+    import bench
+    n, m = 1000, 300
+    assert bench.merge_bytes(n, m, 4, False) == n * 12 + m * 8 + (n + m) * 13 + m * 8
+    assert bench.merge_bytes(n, m, 8, True) - bench.merge_bytes(n, m, 8, False) == n
+    d_scan, d_merge = bench.sources_digest("filter_finish"), bench.sources_digest("merge_kernel")
+    assert d_scan != d_merge and len(d_scan) == 64
+    assert bench.sources_digest("smoother_finish") == d_scan
