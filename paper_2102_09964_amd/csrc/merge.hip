@@ -14,7 +14,7 @@
 // the first d outputs (the point where the cross diagonal i + j = d meets
 // the merge path); it is the smallest i with not (A[i] <= B[d - 1 - i]).
 //   1. the two halves of wave 0 find the splits of the tile's two ends with
-//      a 32-way search on an aligned grid (4 rounds for 2^20 candidates,
+//      a 32-way search on an aligned grid (5 rounds for 2^20 candidates,
 //      against 20 dependent loads of a binary search; neighbouring tiles
 //      share the probed lines)
 //   2. the workgroup stages both input segments (times, and the training
