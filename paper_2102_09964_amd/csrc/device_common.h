@@ -439,6 +439,71 @@ __device__ __forceinline__ void discretize_fast(const DevModel &mdl, cdouble *cs
     if constexpr (LY::NB > 1) disc_fast_block<LY, 1, T>(mdl, cst, sc, dt, first, Dl, Q);
 }
 
+// phi_r(s) of the closed-form expansion F = sum_r phi_r M_r of one block at
+// normalised time s = dt / ell (series-start case not applied); the same
+// values that disc_block and disc_fast_block form inline
+template <class LY, int b>
+__device__ __forceinline__ void block_phi(const DevModel &mdl, const StepScale &sc, double dt,
+                                          double (&phi)[LY::bdim(b)])
+{
+    constexpr int dc = LY::bdim(b);
+    const DevBlock &bk = mdl.blk[b];
+    const double s = dt * sc.inv_ell[b];
+    if (bk.kind == BLK_MATERN) {
+        double pw = exp(-bk.lam * s);
+#pragma unroll
+        for (int j = 0; j < dc; j++) {
+            phi[j] = pw;
+            pw *= s;
+        }
+    } else {
+        // RBF Taylor blocks: dc / 2 conjugate pairs and dc % 2 real roots
+#pragma unroll
+        for (int p = 0; p < dc / 2; p++) {
+            const double e = exp(bk.alpha[p] * s);
+            double sn, cs;
+            sincos(bk.beta[p] * s, &sn, &cs);
+            phi[2 * p] = e * cs;
+            phi[2 * p + 1] = e * sn;
+        }
+        if (dc % 2) phi[dc - 1] = exp(bk.alpha[dc / 2] * s);
+    }
+}
+
+// F alone in FP64 from the constants at cst (the expansion of the FP32
+// scans), with the special cases of discretize: F = 0 at a series start,
+// F = I exactly for a zero step.
+template <class LY>
+__device__ __forceinline__ void transition_fast(const DevModel &mdl, cdouble *cst, const StepScale &sc, double dt,
+                                                bool first, double (&F)[LY::D][LY::D])
+{
+    constexpr int D = LY::D;
+#pragma unroll
+    for (int i = 0; i < D; i++)
+#pragma unroll
+        for (int j = 0; j < D; j++) F[i][j] = 0.0;
+    const bool zero = (dt == 0.0);
+    auto block = [&](auto bc) {
+        constexpr int b = decltype(bc)::value;
+        constexpr int dc = LY::bdim(b);
+        constexpr int o = LY::boff(b);
+        double phi[dc];
+        block_phi<LY, b>(mdl, sc, dt, phi);
+        cdouble *M = cst + ConstLayout<LY>::m_off(b);
+#pragma unroll
+        for (int i = 0; i < dc; i++)
+#pragma unroll
+            for (int j = 0; j < dc; j++) {
+                double acc = 0.0;
+#pragma unroll
+                for (int r = 0; r < dc; r++) acc = fma(phi[r], M[r * dc * dc + i * dc + j], acc);
+                F[o + i][o + j] = first ? 0.0 : (zero ? ((i == j) ? 1.0 : 0.0) : acc);
+            }
+    };
+    block(std::integral_constant<int, 0>());
+    if constexpr (LY::NB > 1) block(std::integral_constant<int, 1>());
+}
+
 // ------------------------------------------------------------------ register linear algebra
 
 template <int D, typename T>

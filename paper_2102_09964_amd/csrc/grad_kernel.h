@@ -135,6 +135,7 @@ struct GradParams {
     int chunk;
     int ntiles;
     const T *rec;
+    const double *cst;  // FP32 scans: model constants of the transition (ConstLayout)
     double *grad;
     WsCtl *ctl;
     T *aggp;
@@ -173,7 +174,13 @@ __global__ __launch_bounds__(PSSGP_WAVE) void grad_fold_kernel(GradParams<T> p, 
             {
                 double F64[D][D];
                 const double dt = (k > 0) ? p.t[k] - p.t[k - 1] : 0.0;
-                transition<LY, sizeof(T) == 8>(mdl, model_scale(mdl), dt, k == 0, F64);
+                if constexpr (sizeof(T) == 4) {
+                    cdouble *c = (cdouble *)p.cst;
+                    PSSGP_LAUNDER(c);
+                    transition_fast<LY>(mdl, c, model_scale(mdl), dt, k == 0, F64);
+                } else {
+                    transition<LY, true>(mdl, model_scale(mdl), dt, k == 0, F64);
+                }
 #pragma unroll
                 for (int i = 0; i < D; i++)
 #pragma unroll
@@ -272,7 +279,16 @@ __global__ __launch_bounds__(PSSGP_WAVE) void grad_finish_kernel(GradParams<T> p
         PSSGP_RELOAD_CONSTANTS();
         const double dt = (k > 0) ? p.t[k] - p.t[k - 1] : 0.0;
         double F64[D][D], Q64[D][D];
-        discretize<LY, sizeof(T) == 8>(mdl, model_scale(mdl), dt, k == 0, F64, Q64);
+        if constexpr (sizeof(T) == 4) {
+            // the FP32 scans' transition (constants at cst): F = I + (F - I)
+            cdouble *c = (cdouble *)p.cst;
+            PSSGP_LAUNDER(c);
+            discretize_fast<LY, double>(mdl, c, model_scale(mdl), dt, k == 0, F64, Q64);
+#pragma unroll
+            for (int i = 0; i < D; i++) F64[i][i] += 1.0;
+        } else {
+            discretize<LY, true>(mdl, model_scale(mdl), dt, k == 0, F64, Q64);
+        }
         const bool obs = p.mask ? (p.mask[k] != 0) : true;
         const T *rp = p.rec + rec_index<D>(tile, p.chunk, (int)(k - k0), lane);
         constexpr size_t W = PSSGP_WAVE;
@@ -419,6 +435,7 @@ int launch_grad_t(const DevModel &mdl, const GradLaunch &a, hipStream_t s)
     p.chunk = a.chunk;
     p.ntiles = a.ntiles;
     p.rec = (const T *)a.rec;
+    p.cst = a.ws.cst;
     p.grad = a.grad;
     p.ctl = a.ws.ctl;
     p.inclp = (T *)a.ws.inclp;
