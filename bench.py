@@ -328,8 +328,8 @@ def measure_batched(steps, warmup, chunk=0):
             pass_ms[scan + "_" + name] = float(np.mean([e[g][j].elapsed_time(e[g][j + 1]) for e in evs]))
     n = int(w["offsets"][-1])
     # cost per step: the layout groups weighted by their steps; the filter's
-    # finish also writes the per-step log-likelihood terms (FP64) that the
-    # per-series sum reads back
+    # finish also writes one FP64 log-likelihood partial per lane (and per
+    # series start) that the per-series sum reads back
     off = np.asarray(w["offsets"])
     costs = {k: [0.0, 0.0] for k in PASSES}
     for kind, dd in ((P.MATERN32, 2), (P.MATERN52, 3)):
@@ -338,7 +338,7 @@ def measure_batched(steps, warmup, chunk=0):
         for k, (b, f) in pass_costs(dd, 4, chunk).items():
             costs[k][0] += frac * b
             costs[k][1] += frac * f
-    costs["filter_finish"][0] += 16.0
+    costs["filter_finish"][0] += 16.0 * (1.0 / chunk + len(w["kinds"]) / n)
     m = {"n": n, "chunk": chunk, "pass_ms": pass_ms, "ms_per_step": ms, "path_bytes": algorithmic_bytes(4, n)}
     rf = roofline_of(m, costs={k: tuple(v) for k, v in costs.items()})
     return {"workload": "batched_matern", "dtype": "float32", "n": n, "n_series": int(len(w["kinds"])),

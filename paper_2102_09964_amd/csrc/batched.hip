@@ -142,23 +142,29 @@ __global__ __launch_bounds__(PSSGP_WAVE) void batched_smoother_kernel(SmoothPara
     }
 }
 
-// One workgroup per series: sum of its per-step log-likelihood terms in
-// FP64. Threads take the steps strided by the workgroup size (coalesced
-// loads, several in flight per thread), then a fixed-order tree: wave sums,
-// then the wave totals in wave order, so the result does not depend on
-// timing. (One wave per series left the longest series, 65 536 steps, as a
-// chain of 1 024 dependent load rounds.)
+// One workgroup per series: the log-likelihood of series s from the
+// partial sums the filter's finish pass left at the first step of every
+// series segment of a lane, i.e. at the series start and at each lane start
+// inside the series (k_begin + j * chunk of its group). Threads take those
+// positions strided by the workgroup size, then a fixed-order tree: wave
+// sums, then the wave totals in wave order, so the result does not depend
+// on timing. (One wave per series over per-step terms left the longest
+// series, 65 536 steps, as a chain of 1 024 dependent load rounds.)
 #define PSSGP_LL_THREADS 1024
 __global__ __launch_bounds__(PSSGP_LL_THREADS) void series_loglik_kernel(const double *terms, const int64_t *off,
-                                                                       double *out)
+                                                                       BatchLaunch a, double *out)
 {
     __shared__ double s_w[PSSGP_LL_THREADS / PSSGP_WAVE];
     const int64_t s = blockIdx.x;
     const int64_t beg = off[s], end = off[s + 1];
+    const BatchGroup &g = a.g[(a.ngroups > 1 && s >= a.g[1].s_begin) ? 1 : 0];
     const int tid = (int)threadIdx.x;
-    double acc = 0.0;
-#pragma unroll 8
-    for (int64_t k = beg + tid; k < end; k += PSSGP_LL_THREADS) acc += terms[k];
+    const int64_t ch = a.chunk;
+    // first lane start after the series start
+    const int64_t kb = g.k_begin + ((beg - g.k_begin) / ch + 1) * ch;
+    double acc = (tid == 0 && beg < end) ? terms[beg] : 0.0;
+#pragma unroll 4
+    for (int64_t k = kb + tid * ch; k < end; k += (int64_t)PSSGP_LL_THREADS * ch) acc += terms[k];
     acc = wave_sum(acc);
     if (lane_id() == 0) s_w[tid / PSSGP_WAVE] = acc;
     __syncthreads();
@@ -212,7 +218,7 @@ int launch_bf(const BatchLaunch &a, hipStream_t s)
     rc = (int)hipGetLastError();
     if (rc) return rc;
     hipLaunchKernelGGL(series_loglik_kernel, dim3((unsigned)a.n_series), dim3(PSSGP_LL_THREADS), 0, s,
-                       (const double *)a.ll_terms, a.offsets, a.loglik);
+                       (const double *)a.ll_terms, a.offsets, a, a.loglik);
     rc = (int)hipGetLastError();
     pass_event(a.ev, 3, s);
     return rc;

@@ -18,8 +18,8 @@
 // One series: the last tile to finish reduces the per-tile log-likelihood
 // partials in a fixed order. Batched: the fold and finish grids cover up to
 // two groups of series with different state layouts (one carry scan per
-// group) and write per-step log-likelihood terms that a second kernel sums
-// per series.
+// group) and write one log-likelihood partial per series segment of a lane
+// (at the segment's first step) that a second kernel sums per series.
 #pragma once
 #include "device_common.h"
 #include "filter_ops.h"
@@ -45,7 +45,7 @@ struct FilterParams {
     T *P;
     double *loglik;
     T *rec;             // F_RECS: per-step records (RecLayout, tile layout)
-    double *ll_terms;  // batched: per-step log-likelihood terms
+    double *ll_terms;  // batched: per-segment log-likelihood partials, at each segment's first step
     const double *cst;  // model constants of the FP32 transition (ConstLayout)
     WsCtl *ctl;
     T *aggp;
@@ -329,6 +329,12 @@ __device__ __forceinline__ void filter_tile_finish(const FilterParams<T> &p, con
     }
 
     double ll = 0.0;  // FP64 per-lane sum of the log-likelihood terms
+    // many series: one FP64 partial sum of the terms per series segment of
+    // the lane, stored at the segment's first step (series_loglik_kernel
+    // reads the series start and the lane starts inside the series)
+    constexpr bool SEG = !std::is_same<SV, OneSeries>::value;
+    double seg = 0.0;
+    int64_t seg_k = k0;
     StepInputs<T> in;
     in.start(p.t, p.y, p.mask, k0, k1, tr.k_begin);
     for (int64_t k = k0; k < k1; k++) {
@@ -385,7 +391,16 @@ __device__ __forceinline__ void filter_tile_finish(const FilterParams<T> &p, con
         bad |= (obs && (!(S > 0.0) || !isfinite(S))) ? PSSGP_STATUS_BAD_S : 0u;
         bad |= (obs && !isfinite(yk)) ? PSSGP_STATUS_NONFINITE : 0u;
         const double term = obs ? -0.5 * (log(6.283185307179586 * S) + v * v * w) : 0.0;
-        if (p.ll_terms) p.ll_terms[k] = term;
+        if constexpr (SEG) {
+            if (first && k > k0) {
+                if (p.ll_terms) p.ll_terms[seg_k] = seg;
+                seg = 0.0;
+                seg_k = k;
+            }
+            seg += term;
+        } else {
+            if (p.ll_terms) p.ll_terms[k] = term;
+        }
         ll += term;
         double K[D];
 #pragma unroll
@@ -441,6 +456,9 @@ __device__ __forceinline__ void filter_tile_finish(const FilterParams<T> &p, con
         }
         // the lane's smoother aggregate (identity for a lane without steps)
         if constexpr (LANEAGG) sagg_store<D, T>(lane_rec(p.slane, slot, SAggLayout<D>::SIZE, lane), sacc, PSSGP_WAVE);
+    }
+    if constexpr (SEG) {
+        if (p.ll_terms && k1 > k0) p.ll_terms[seg_k] = seg;
     }
     if (bad) status_or(&p.ctl->status, bad);
     ll_out = ll;

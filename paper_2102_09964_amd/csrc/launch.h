@@ -120,7 +120,7 @@ struct BatchLaunch {
     void *f_mean;
     void *f_var;
     double *loglik;           // device [n_series]
-    void *ll_terms;           // workspace: per-step terms
+    void *ll_terms;           // workspace [n]: log-likelihood partials at segment starts
     int tiled;                // m: smoother-element handover (filter then smoother in one call)
     void *slane;              // tiled: per-lane smoother aggregates
     ScanWs ws;
