@@ -244,13 +244,26 @@ int pssgp_loglik(const pssgp_model *model, const double *t, const void *y, const
  * (mbar_{k-1}, Pbar_{k-1}) built from them, whose finish pass contracts the
  * adjoints with the parameter derivatives of F, Q, Pinf and R. grad (device double[2 n_comp
  * + 1]) receives d loglik / d (ell_0, var_0, ell_1, var_1, ..., noise_var).
- * noise_k must be NULL (the noise-variance derivative is for the scalar
- * noise_var).
+ * The noise variance is the model's scalar noise_var (see
+ * pssgp_loglik_grad_noise for per-step variances).
  */
 int pssgp_loglik_grad(const pssgp_model *model, const double *t, const void *y,
                       const uint8_t *mask, int64_t n, pssgp_dtype dtype, double *loglik,
                       double *grad, void *ws, size_t ws_bytes, const pssgp_options *opts,
                       void *stream);
+
+/*
+ * pssgp_loglik_grad with heteroscedastic measurements: step k has the
+ * noise variance noise_k[k] (device double[n], > 0 at observed steps),
+ * fixed data rather than a hyperparameter, and the model's noise_var is
+ * not used. grad has the same 2 n_comp + 1 entries; the last one (the
+ * derivative with respect to noise_var) is 0. Workspace and errors as for
+ * pssgp_loglik_grad; noise_k NULL with n > 0 is PSSGP_EINVAL.
+ */
+int pssgp_loglik_grad_noise(const pssgp_model *model, const double *t, const void *y,
+                            const uint8_t *mask, const double *noise_k, int64_t n, pssgp_dtype dtype,
+                            double *loglik, double *grad, void *ws, size_t ws_bytes,
+                            const pssgp_options *opts, void *stream);
 
 /*
  * Batched form: n_series independent series concatenated along the time

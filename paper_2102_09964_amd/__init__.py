@@ -75,6 +75,8 @@ SIGNATURES = [
                                     _VP]),
     ("pssgp_loglik_grad", ctypes.c_int, [_MP, _VP, _VP, _VP, _I64, ctypes.c_int, _VP, _VP, _VP, _SZ,
                                          _OP, _VP]),
+    ("pssgp_loglik_grad_noise", ctypes.c_int, [_MP, _VP, _VP, _VP, _VP, _I64, ctypes.c_int, _VP, _VP, _VP, _SZ,
+                                               _OP, _VP]),
     ("pssgp_batched_workspace_bytes", _SZ, [ctypes.c_void_p, ctypes.c_int, _I64, _VP, ctypes.c_int, ctypes.c_int,
                                             _OP]),
     ("pssgp_batched_filter", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, _I64, _VP, _VP, _VP, _VP, _VP, _VP,
@@ -396,9 +398,11 @@ def loglik(model, t, y, mask=None, noise_k=None, dtype="float32", options=None, 
     return filter(model, t, y, mask, noise_k, dtype, moments=False, options=options, device=device)["loglik"]
 
 
-def loglik_grad(model, t, y, mask=None, dtype="float32", options=None, ws=None, device="cuda"):
+def loglik_grad(model, t, y, mask=None, dtype="float32", options=None, ws=None, device="cuda", noise_k=None):
     """Log-likelihood and its gradient with respect to
-    (ell_0, var_0, ell_1, var_1, ..., noise_var)."""
+    (ell_0, var_0, ell_1, var_1, ..., noise_var). With noise_k (per-step
+    noise variances, fixed data) the model's noise_var is unused and the
+    last gradient entry is 0."""
     _require_gpu()
     torch = _torch()
     m = _as_model(model)
@@ -411,9 +415,14 @@ def loglik_grad(model, t, y, mask=None, dtype="float32", options=None, ws=None, 
         ws = alloc_workspace(m, n, code, OP_LOGLIK_GRAD, options, device)
     ll = torch.empty(1, dtype=torch.float64, device=device)
     g = torch.empty(2 * m.n_comp + 1, dtype=torch.float64, device=device)
-    _check(lib().pssgp_loglik_grad(ctypes.byref(m), _p(t), _p(y), _p(mask), n, code, _p(ll), _p(g), _p(ws),
-                                   ws.numel(), ctypes.byref(options) if options is not None else None,
-                                   _stream()))
+    opt = ctypes.byref(options) if options is not None else None
+    if noise_k is None:
+        _check(lib().pssgp_loglik_grad(ctypes.byref(m), _p(t), _p(y), _p(mask), n, code, _p(ll), _p(g), _p(ws),
+                                       ws.numel(), opt, _stream()))
+    else:
+        nk = _dev(noise_k, torch.float64, device)
+        _check(lib().pssgp_loglik_grad_noise(ctypes.byref(m), _p(t), _p(y), _p(mask), _p(nk), n, code, _p(ll),
+                                             _p(g), _p(ws), ws.numel(), opt, _stream()))
     return ll, g
 
 

@@ -661,9 +661,9 @@ int pssgp_predict(const pssgp_model *model, const double *t, const void *y, cons
     return check_launch(launch_smoother(dm, b0, b1, dtype == PSSGP_F64, sm, s), "smoother launch");
 }
 
-int pssgp_loglik_grad(const pssgp_model *model, const double *t, const void *y, const uint8_t *mask,
-                      int64_t n, pssgp_dtype dtype, double *loglik, double *grad, void *ws,
-                      size_t ws_bytes, const pssgp_options *opts, void *stream)
+static int run_loglik_grad(const pssgp_model *model, const double *t, const void *y, const uint8_t *mask,
+                           const double *noise_k, int64_t n, pssgp_dtype dtype, double *loglik, double *grad,
+                           void *ws, size_t ws_bytes, const pssgp_options *opts, void *stream)
 {
     DevModel dm;
     int b0, b1;
@@ -691,7 +691,7 @@ int pssgp_loglik_grad(const pssgp_model *model, const double *t, const void *y, 
     a.t = t;
     a.y = y;
     a.mask = mask;
-    a.noise_k = nullptr;
+    a.noise_k = noise_k;
     a.n = n;
     a.chunk = p.chunk;
     a.ntiles = p.ntiles;
@@ -714,8 +714,27 @@ int pssgp_loglik_grad(const pssgp_model *model, const double *t, const void *y, 
     g.ntiles = p.ntiles;
     g.rec = b + p.off_rec;
     g.grad = grad;
+    g.noise_fixed = noise_k != nullptr;
     g.ws = sw2;
     return check_launch(launch_grad(dm, b0, b1, dtype == PSSGP_F64, g, s), "adjoint launch");
+}
+
+int pssgp_loglik_grad(const pssgp_model *model, const double *t, const void *y, const uint8_t *mask,
+                      int64_t n, pssgp_dtype dtype, double *loglik, double *grad, void *ws,
+                      size_t ws_bytes, const pssgp_options *opts, void *stream)
+{
+    return run_loglik_grad(model, t, y, mask, nullptr, n, dtype, loglik, grad, ws, ws_bytes, opts, stream);
+}
+
+int pssgp_loglik_grad_noise(const pssgp_model *model, const double *t, const void *y, const uint8_t *mask,
+                            const double *noise_k, int64_t n, pssgp_dtype dtype, double *loglik, double *grad,
+                            void *ws, size_t ws_bytes, const pssgp_options *opts, void *stream)
+{
+    if (n > 0 && !noise_k) {
+        pssgp_set_error("noise_k must be a device pointer");
+        return PSSGP_EINVAL;
+    }
+    return run_loglik_grad(model, t, y, mask, noise_k, n, dtype, loglik, grad, ws, ws_bytes, opts, stream);
 }
 
 size_t pssgp_batched_workspace_bytes(const pssgp_batch_group *groups_host, int n_groups, int64_t n_series,

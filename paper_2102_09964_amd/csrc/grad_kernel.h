@@ -136,6 +136,7 @@ struct GradParams {
     int ntiles;
     const T *rec;
     const double *cst;  // FP32 scans: model constants of the transition (ConstLayout)
+    int noise_fixed;    // per-step noise variances: the model's noise variance enters nowhere
     double *grad;
     WsCtl *ctl;
     T *aggp;
@@ -328,7 +329,7 @@ __global__ __launch_bounds__(PSSGP_WAVE) void grad_finish_kernel(GradParams<T> p
                 Pib[i][j] = acc;
                 Pib[j][i] = acc;
             }
-        gacc[NP - 1] += (double)kpk - (double)gs * (double)km + (double)cl;
+        if (!p.noise_fixed) gacc[NP - 1] += (double)kpk - (double)gs * (double)km + (double)cl;
         // parameter contractions, block by block, in FP64
 #pragma unroll
         for (int b = 0; b < LY::NB; b++) {
@@ -436,6 +437,7 @@ int launch_grad_t(const DevModel &mdl, const GradLaunch &a, hipStream_t s)
     p.ntiles = a.ntiles;
     p.rec = (const T *)a.rec;
     p.cst = a.ws.cst;
+    p.noise_fixed = a.noise_fixed;
     p.grad = a.grad;
     p.ctl = a.ws.ctl;
     p.inclp = (T *)a.ws.inclp;

@@ -77,6 +77,7 @@ struct GradLaunch {
     int chunk;
     int ntiles;
     const void *rec;    // per-step records written by the forward filter
+    int noise_fixed;    // per-step noise variances given: the noise-variance derivative is 0
     double *grad;       // device [2 n_comp + 1]
     ScanWs ws;
 };

@@ -129,6 +129,9 @@ def test_argument_errors_need_no_device():
     assert L.pssgp_loglik(mp, fake, fake, None, None, n, P.F32, None, fake, need, None, None) == -1
     ng = P.workspace_bytes(m, n, P.F32, P.OP_LOGLIK_GRAD)
     assert L.pssgp_loglik_grad(mp, fake, fake, None, n, P.F32, fake, None, fake, ng, None, None) == -1
+    # per-step noise variances are required by the heteroscedastic entry
+    assert L.pssgp_loglik_grad_noise(mp, fake, fake, None, None, n, P.F32, fake, fake, fake, ng, None, None) == -1
+    assert b"noise_k" in L.pssgp_last_error()
     # status needs a workspace and an output
     assert L.pssgp_status(None, None, None) == -1
     # unsupported model

@@ -108,3 +108,34 @@ def test_autograd_function():
     ll.backward()
     _, g_o = _oracle(w, comps, noise, "float64")
     assert np.max(np.abs(theta.grad.numpy() - g_o)) <= 1e-8 * np.max(np.abs(g_o))
+
+
+NOISE_CASES = [CASES[1], CASES[3], CASES[4]]
+NOISE_IDS = ["m32", "rbf6", "m32+rbf6"]
+
+
+@pytest.mark.parametrize("comps,noise,n", NOISE_CASES, ids=NOISE_IDS)
+@pytest.mark.parametrize("dtype", ["float64", "float32"])
+def test_grad_per_step_noise_vs_oracle(comps, noise, n, dtype):
+    """Heteroscedastic measurements (pssgp_loglik_grad_noise): per-step
+    noise variances log-normal around the model's, as fixed data; the
+    noise-variance derivative is 0 on both sides."""
+    w = workloads.random_series(n, comps, noise, missing=0.15, span=n * 0.02, gap="exponential", seed=n + 1)
+    nk = noise * np.exp(np.random.default_rng(n).normal(0.0, 0.7, n))
+    y = np.asarray(w["y"], np.float64)
+    if dtype == "float32":
+        y = y.astype(np.float32).astype(np.float64)
+    om = OracleModel(comps, noise, with_derivatives=True)
+    r = oracle.run(om, w["t"], y, w["mask"], noise_k=nk, gradient=True, smoother=False, filter_moments=False)
+    m = P.make_model(comps, noise)
+    t = torch.as_tensor(w["t"], dtype=torch.float64, device="cuda")
+    yt = torch.as_tensor(np.nan_to_num(w["y"]), dtype=getattr(torch, dtype), device="cuda")
+    mask = torch.as_tensor(w["mask"], dtype=torch.uint8, device="cuda")
+    ll, g = P.loglik_grad(m, t, yt, mask, dtype=dtype, options=P.make_options(chunk=4), noise_k=nk)
+    ll, g = float(ll.cpu()[0]), g.cpu().numpy()
+    err = np.max(np.abs(g - r["grad"])) / np.max(np.abs(r["grad"]))
+    lerr = abs(ll - r["loglik"]) / abs(r["loglik"])
+    print("per-step noise", dtype, "grad err %.2e loglik err %.2e" % (err, lerr), g, r["grad"], flush=True)
+    assert r["grad"][-1] == 0.0 and g[-1] == 0.0
+    assert err <= (1e-8 if dtype == "float64" else 1e-3)
+    assert lerr <= (1e-9 if dtype == "float64" else 1e-5)
