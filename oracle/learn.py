@@ -24,14 +24,18 @@ from . import run
 from .model import OracleModel
 
 
-def log_objective(kinds_orders, t, y, mask=None):
-    """u -> (loglik(theta(u)), d loglik / d u) on the oracle."""
+def log_objective(kinds_orders, t, y, mask=None, noise_k=None):
+    """u -> (loglik(theta(u)), d loglik / d u) on the oracle. With noise_k
+    (per-step noise variances, fixed data) theta has no noise variance."""
+    p = 2 * len(kinds_orders) + (0 if noise_k is not None else 1)
+
     def f(u):
         th = np.exp(np.asarray(u, np.float64))
         comps = [(k, o, th[2 * i], th[2 * i + 1]) for i, (k, o) in enumerate(kinds_orders)]
-        out = run(OracleModel(comps, th[-1], with_derivatives=True), t, y, mask, filter_moments=False,
-                  smoother=False, gradient=True)
-        return out["loglik"], out["grad"] * th
+        noise = th[-1] if noise_k is None else 1.0
+        out = run(OracleModel(comps, noise, with_derivatives=True), t, y, mask, noise_k=noise_k,
+                  filter_moments=False, smoother=False, gradient=True)
+        return out["loglik"], out["grad"][:p] * th
     return f
 
 
@@ -71,9 +75,9 @@ def hmc(log_pi, u0, eps, momenta, log_uniforms, n_leapfrog=10):
     return np.array(states), np.array(acc)
 
 
-def log_posterior(kinds_orders, t, y, mask=None):
+def log_posterior(kinds_orders, t, y, mask=None, noise_k=None):
     """log pi(u) = loglik(theta(u)) + sum(u) and its gradient."""
-    f = log_objective(kinds_orders, t, y, mask)
+    f = log_objective(kinds_orders, t, y, mask, noise_k)
 
     def lp(u):
         ll, g = f(u)

@@ -26,10 +26,12 @@ class LogLikObjective:
     """loglik and its gradient in log-hyperparameters for fixed data.
 
     kinds_orders: [(kind, order), ...] per component; t, y, mask as for
-    loglik_grad (device tensors are used as they are). The workspace is
-    allocated once and reused by every evaluation."""
+    loglik_grad (device tensors are used as they are). With noise_k
+    (per-step noise variances, heteroscedastic measurements as fixed data)
+    the hyperparameters are (ell_0, var_0, ...) without a noise variance.
+    The workspace is allocated once and reused by every evaluation."""
 
-    def __init__(self, kinds_orders, t, y, mask=None, dtype="float32", device="cuda"):
+    def __init__(self, kinds_orders, t, y, mask=None, dtype="float32", device="cuda", noise_k=None):
         import torch
         code, tdt = _dt(dtype)
         self.kinds_orders = list(kinds_orders)
@@ -39,6 +41,7 @@ class LogLikObjective:
         self.y = torch.as_tensor(np.nan_to_num(np.asarray(y)) if not isinstance(y, torch.Tensor) else y,
                                  dtype=tdt, device=device)
         self.mask = None if mask is None else torch.as_tensor(mask, dtype=torch.uint8, device=device)
+        self.noise_k = None if noise_k is None else torch.as_tensor(noise_k, dtype=torch.float64, device=device)
         probe = self._model(np.zeros(self.n_params))
         self.ws = alloc_workspace(probe, self.t.shape[0], code, OP_LOGLIK_GRAD, device=device)
         self.n_evals = 0
@@ -46,20 +49,21 @@ class LogLikObjective:
 
     @property
     def n_params(self):
-        return 2 * len(self.kinds_orders) + 1
+        return 2 * len(self.kinds_orders) + (0 if self.noise_k is not None else 1)
 
     def _model(self, u):
         th = np.exp(np.asarray(u, np.float64))
         comps = [(k, o, th[2 * i], th[2 * i + 1]) for i, (k, o) in enumerate(self.kinds_orders)]
-        return make_model(comps, th[-1])
+        # with per-step noise variances the model's noise variance is unused
+        return make_model(comps, th[-1] if self.noise_k is None else 1.0)
 
     def __call__(self, u):
         """(loglik, d loglik / d u) as host float64 values."""
         t0 = time.perf_counter()
         ll, g = loglik_grad(self._model(u), self.t, self.y, self.mask, dtype=self.dtype, ws=self.ws,
-                            device=self.device)
+                            device=self.device, noise_k=self.noise_k)
         ll = float(ll.item())
-        g = g.cpu().numpy() * np.exp(np.asarray(u, np.float64))
+        g = g.cpu().numpy()[:self.n_params] * np.exp(np.asarray(u, np.float64))
         self.eval_seconds += time.perf_counter() - t0
         self.n_evals += 1
         return ll, g

@@ -60,3 +60,22 @@ def test_hmc_fp64_matches_oracle():
     np.testing.assert_array_equal(r["accepted"], acc)
     np.testing.assert_allclose(r["samples"], np.exp(states), rtol=1e-7)
     assert r["n_evals"] == 1 + 6 * 10
+
+
+def test_hmc_per_step_noise_fp64_matches_oracle():
+    """HMC over (ell, var) with heteroscedastic measurements: per-step noise
+    variances as fixed data (the paper's second workload)."""
+    from paper_2102_09964_amd.fit import LogLikObjective, hmc
+    t, y, mask = _data(800)
+    nk = 0.01 * np.exp(np.random.default_rng(5).normal(0.0, 0.7, t.shape[0]))
+    kinds = [(MATERN32, 0)]
+    th0 = [0.3, 1.5]
+    mom, lu = W.hmc_draws(6, 2, seed_extra=4)
+    obj = LogLikObjective(kinds, t, y, mask, dtype="float64", noise_k=nk)
+    assert obj.n_params == 2
+    r = hmc(obj, th0, 0.02, mom, lu, n_leapfrog=10)
+    states, acc = OL.hmc(OL.log_posterior(kinds, t, y, mask, noise_k=nk), np.log(th0), 0.02, mom, lu,
+                         n_leapfrog=10)
+    print("accepted", r["accepted"], acc, flush=True)
+    np.testing.assert_array_equal(r["accepted"], acc)
+    np.testing.assert_allclose(r["samples"], np.exp(states), rtol=1e-7)
