@@ -91,7 +91,9 @@ typedef struct pssgp_model {
 typedef enum { PSSGP_F32 = 0, PSSGP_F64 = 1 } pssgp_dtype;
 
 typedef struct pssgp_options {
-    uint32_t chunk;          /* steps per lane, 0 = default (16); 1..64 */
+    uint32_t chunk;          /* steps per lane, 0 = default (16); 1..64 for FP64
+                                scans, 4..64 for FP32 scans (PSSGP_EINVAL
+                                otherwise) */
     uint32_t deterministic;  /* accepted for compatibility; every scan combines its
                                 partial results in a fixed order, so results are
                                 always bitwise reproducible for a given chunk */

@@ -12,9 +12,12 @@
 //
 // The per-series hyperparameters (length-scale, variance, noise variance)
 // come from a device table; the model constants of a group are those of
-// unit length-scale and unit variance, scaled per step. The per-step
-// log-likelihood terms are written out and summed per series, one wave per
-// series in a fixed order, by a second kernel.
+// unit length-scale and unit variance, scaled per step. The filter's finish
+// pass keeps one FP64 partial sum of the log-likelihood terms per series
+// segment of a lane (a lane's steps inside one series) and stores it at the
+// segment's first step; a second kernel then sums, with one workgroup per
+// series and in a fixed order, the partials at the series start and at the
+// lane starts inside the series.
 #include "filter_kernel.h"
 #include "launch.h"
 #include "smoother_kernel.h"

@@ -153,10 +153,20 @@ int prepare(const pssgp_model *model, int64_t n, pssgp_dtype dtype, DevModel &dm
     return PSSGP_OK;
 }
 
-int check_opts(const pssgp_options *opts)
+// FP32 scans need at least kMinChunkF32 steps per lane: with fewer, most
+// moments come through the FP32 lane aggregates stored between the passes
+// rather than the lane's own FP64-conditioned sequential run, and the
+// variances lose the FP32 accuracy bar.
+constexpr int kMinChunkF32 = 4;
+
+int check_opts(const pssgp_options *opts, pssgp_dtype dtype)
 {
     if (opts && opts->chunk > 64) {
         pssgp_set_error("options.chunk must be <= 64");
+        return PSSGP_EINVAL;
+    }
+    if (opts && opts->chunk && dtype == PSSGP_F32 && (int)opts->chunk < kMinChunkF32) {
+        pssgp_set_error("options.chunk must be 0 or >= %d for FP32 scans", kMinChunkF32);
         return PSSGP_EINVAL;
     }
     return PSSGP_OK;
@@ -198,7 +208,7 @@ int run_filter(const pssgp_model *model, const double *t, const void *y, const u
     int b0, b1;
     int rc = prepare(model, n, dtype, dm, b0, b1);
     if (rc) return rc;
-    if ((rc = check_opts(opts))) return rc;
+    if ((rc = check_opts(opts, dtype))) return rc;
     if (n > 0 && (!t || !y)) {
         pssgp_set_error("t and y must be device pointers");
         return PSSGP_EINVAL;
@@ -257,10 +267,8 @@ int make_batch_plan(const pssgp_batch_group *groups, int ngroups, int64_t n_seri
         pssgp_set_error("dtype must be PSSGP_F32 or PSSGP_F64");
         return PSSGP_EINVAL;
     }
-    if (opts && opts->chunk > 64) {
-        pssgp_set_error("options.chunk must be <= 64");
-        return PSSGP_EINVAL;
-    }
+    int rc_opts;
+    if ((rc_opts = check_opts(opts, dtype))) return rc_opts;
     if (off[0] != 0) {
         pssgp_set_error("batched: offsets[0] must be 0");
         return PSSGP_EINVAL;
@@ -573,7 +581,7 @@ int pssgp_smooth(const pssgp_model *model, const double *t, const void *m, const
     int b0, b1;
     int rc = prepare(model, n, dtype, dm, b0, b1);
     if (rc) return rc;
-    if ((rc = check_opts(opts))) return rc;
+    if ((rc = check_opts(opts, dtype))) return rc;
     if (n > 0 && (!t || !m || !P || !f_mean || !f_var)) {
         pssgp_set_error("t, m, P, f_mean and f_var must be device pointers");
         return PSSGP_EINVAL;
@@ -613,7 +621,7 @@ int pssgp_predict(const pssgp_model *model, const double *t, const void *y, cons
     int b0, b1;
     int rc = prepare(model, n, dtype, dm, b0, b1);
     if (rc) return rc;
-    if ((rc = check_opts(opts))) return rc;
+    if ((rc = check_opts(opts, dtype))) return rc;
     if (!loglik || (n > 0 && (!t || !y || !f_mean || !f_var))) {
         pssgp_set_error("t, y, f_mean, f_var and loglik must be device pointers");
         return PSSGP_EINVAL;
@@ -669,7 +677,7 @@ static int run_loglik_grad(const pssgp_model *model, const double *t, const void
     int b0, b1;
     int rc = prepare(model, n, dtype, dm, b0, b1);
     if (rc) return rc;
-    if ((rc = check_opts(opts))) return rc;
+    if ((rc = check_opts(opts, dtype))) return rc;
     if (!loglik || !grad || (n > 0 && (!t || !y))) {
         pssgp_set_error("t, y, loglik and grad must be device pointers");
         return PSSGP_EINVAL;

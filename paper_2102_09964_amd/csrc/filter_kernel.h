@@ -12,9 +12,10 @@
 //           moments entering every tile (tile_scan.h)
 //   finish  each lane applies its exclusive lane prefix to the tile's carry,
 //           which gives the filter moments just before its chunk, then
-//           re-runs its steps as a plain Kalman filter, writing (m, P) and
-//           accumulating the log-likelihood terms with compensated
-//           summation.
+//           re-runs its steps as a plain Kalman filter (prediction and
+//           conditioning in FP64), writing (m, P), the adjoint's records or
+//           the smoother elements, and summing the log-likelihood terms in
+//           FP64 per lane.
 // One series: the last tile to finish reduces the per-tile log-likelihood
 // partials in a fixed order. Batched: the fold and finish grids cover up to
 // two groups of series with different state layouts (one carry scan per
@@ -117,8 +118,9 @@ struct StepInputs {
 //   E = (C^-T Y)^T = P F^T Pp^-1, g = m - E mp.
 // At the last step of a series the caller passes the prior transition
 // (F = 0, Q = Pinf), for which these give exactly the element (0, m, P).
-// e receives the element rounded to T.
-template <int D, typename T>
+// e receives the element rounded to T, in the smoother's coordinates
+// z' = S z, S = I + e_0 e_B^T (smoother_shear_col; B = 0: identity).
+template <int D, int B, typename T>
 __device__ __forceinline__ void smoother_element_from_prediction(const T (&m)[D], const T (&P)[D][D],
                                                                  double (&Y)[D][D], const double (&mp)[D],
                                                                  const double (&Pp)[D][D], SAgg<D, T> &e,
@@ -143,11 +145,19 @@ __device__ __forceinline__ void smoother_element_from_prediction(const T (&m)[D]
             for (int q = 0; q < i; q++) acc = fma(-C[i][q], Y[q][j], acc);
             Y[i][j] = acc * rd[i];
         }
+    // L' = S P S^T - (Y S^T)^T (Y S^T); Y S^T is column 0 plus column B
+    if constexpr (B > 0) {
+#pragma unroll
+        for (int q = 0; q < D; q++) Y[q][0] += Y[q][B];
+    }
 #pragma unroll
     for (int i = 0; i < D; i++)
 #pragma unroll
         for (int j = i; j < D; j++) {
             double acc = (double)P[i][j];
+            if constexpr (B > 0) {
+                if (i == 0) acc += (double)P[B][j] + (j == 0 ? (double)P[0][B] + (double)P[B][B] : 0.0);
+            }
 #pragma unroll
             for (int q = 0; q < D; q++) acc = fma(-Y[q][i], Y[q][j], acc);
             e.L[i][j] = T(acc);
@@ -162,14 +172,18 @@ __device__ __forceinline__ void smoother_element_from_prediction(const T (&m)[D]
             for (int q = i + 1; q < D; q++) acc = fma(-C[q][i], Y[q][j], acc);
             Y[i][j] = acc * rd[i];
         }
+    // Y = (S E)^T: g' = S m - (S E) mp, E' = (S E) S^-1 (column B minus column 0)
 #pragma unroll
     for (int i = 0; i < D; i++) {
         double acc = (double)m[i];
+        if constexpr (B > 0) {
+            if (i == 0) acc += (double)m[B];
+        }
 #pragma unroll
         for (int q = 0; q < D; q++) acc = fma(-Y[q][i], mp[q], acc);
         e.g[i] = T(acc);
 #pragma unroll
-        for (int j = 0; j < D; j++) e.E[i][j] = T(Y[j][i]);
+        for (int j = 0; j < D; j++) e.E[i][j] = T((B > 0 && j == B) ? Y[B][i] - Y[0][i] : Y[j][i]);
     }
 }
 
@@ -294,9 +308,8 @@ __device__ __forceinline__ void filter_tile_fold(const FilterParams<T> &p, const
 // Finish pass of one tile: each lane takes the moments entering the tile
 // (carry pass), applies its exclusive lane prefix (every prefix from a
 // series start has A = 0, so only (b, C) are carried) and re-runs its steps
-// as a plain Kalman filter, writing (m, P) and accumulating the
-// log-likelihood terms with compensated summation. ll_out receives this
-// lane's partial.
+// as a plain Kalman filter, writing (m, P) and summing the log-likelihood
+// terms in FP64. ll_out receives this lane's partial.
 template <class LY, typename T, typename CT, int MODE, class SV>
 __device__ __forceinline__ void filter_tile_finish(const FilterParams<T> &p, const DevModel &mdl,
                                                    cdouble *cst, SV &sv, const TileRange &tr, int tile,
@@ -366,7 +379,7 @@ __device__ __forceinline__ void filter_tile_finish(const FilterParams<T> &p, con
             // smoother element of the previous step of this lane
             if (k > k0) {
                 SAgg<D, T> e;
-                smoother_element_from_prediction<D, T>(m, P, Y, mp, Pp, e, bad);
+                smoother_element_from_prediction<D, smoother_shear_col<LY>(), T>(m, P, Y, mp, Pp, e, bad);
                 hand_over_element<D, T, LANEAGG>(e, p.m + elem_index<D>(slot, p.chunk, (int)(k - 1 - k0), lane),
                                                  sacc);
             }
@@ -450,7 +463,7 @@ __device__ __forceinline__ void filter_tile_finish(const FilterParams<T> &p, con
             step_transition<LY, double, T>(mdl, c, sv.sc, dt, end, Dl, Q);
             predict_step<D, T>(m, P, Dl, Q, mp, Y, Pp);
             SAgg<D, T> e;
-            smoother_element_from_prediction<D, T>(m, P, Y, mp, Pp, e, bad);
+            smoother_element_from_prediction<D, smoother_shear_col<LY>(), T>(m, P, Y, mp, Pp, e, bad);
             hand_over_element<D, T, LANEAGG>(e, p.m + elem_index<D>(slot, p.chunk, (int)(k1 - 1 - k0), lane),
                                              sacc);
         }

@@ -193,12 +193,15 @@ __global__ __launch_bounds__(128) void plain_smoother_finish(DevModel mdl, int64
     SAgg<D, double> ex = Y[j], raw = Yraw[j];
     double g[D], L[D][D];
     sagg_apply<D, double>(raw, ex.g, ex.L, g, L);
+    // (g, L) are in the smoother's coordinates (smoother_shear_col)
+    double h[D];
+    smoother_obs_row<D, smoother_shear_col<LY>(), double>(mdl, h);
     double fm = 0.0, fv = 0.0;
 #pragma unroll
     for (int r = 0; r < D; r++) {
-        fm += mdl.H[r] * g[r];
+        fm += h[r] * g[r];
 #pragma unroll
-        for (int c = 0; c < D; c++) fv += mdl.H[r] * L[r][c] * mdl.H[c];
+        for (int c = 0; c < D; c++) fv += h[r] * L[r][c] * h[c];
     }
     f_mean[n - 1 - j] = fm;
     f_var[n - 1 - j] = fv;

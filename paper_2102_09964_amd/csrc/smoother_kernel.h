@@ -114,9 +114,10 @@ __device__ __forceinline__ void smoother_tile_finish(const SmoothParams<T> &p, c
     const int64_t k0 = tr.k_begin + ((int64_t)tile * PSSGP_WAVE + lane) * p.chunk;
     const int64_t k1 = (k0 + p.chunk < tr.k_end) ? k0 + p.chunk : tr.k_end;
     uint32_t bad = 0;
+    // the elements and moments are in the smoother's coordinates
+    constexpr int B = smoother_shear_col<LY>();
     T h[D];
-#pragma unroll
-    for (int i = 0; i < D; i++) h[i] = T(mdl.H[i]);
+    smoother_obs_row<D, B, T>(mdl, h);
     const int64_t tile_start = tr.k_begin + (int64_t)tile * PSSGP_WAVE * p.chunk;
     const int tile_len = PSSGP_WAVE * p.chunk;
 
@@ -145,12 +146,14 @@ __device__ __forceinline__ void smoother_tile_finish(const SmoothParams<T> &p, c
         s_out[k - tile_start] = dot<D, T>(h, ms);
         s_out[tile_len + (k - tile_start)] = dot<D, T>(h, Ph);
         if constexpr (FULL) {
+            T mo[D], Po[D][D];
+            from_smoother_coords<D, B, T>(ms, Ps, mo, Po);
 #pragma unroll
-            for (int i = 0; i < D; i++) p.ms[(size_t)i * p.n + k] = ms[i];
+            for (int i = 0; i < D; i++) p.ms[(size_t)i * p.n + k] = mo[i];
 #pragma unroll
             for (int i = 0; i < D; i++)
 #pragma unroll
-                for (int j = i; j < D; j++) p.Ps[(size_t)sidx<D>(i, j) * p.n + k] = Ps[i][j];
+                for (int j = i; j < D; j++) p.Ps[(size_t)sidx<D>(i, j) * p.n + k] = Po[i][j];
         }
     }
     __syncthreads();

@@ -165,6 +165,54 @@ __device__ __forceinline__ size_t elem_index(int slot, int chunk, int j, int lan
 template <int D>
 constexpr bool lane_aggregate_handover() { return D <= PSSGP_LANEAGG_MAXD; }
 
+// Coordinates of the smoother state. For a sum of two components the
+// latent function is the sum of the first states of the two blocks,
+// f = z_0 + z_B (B = offset of the second block), and each component alone is
+// poorly determined when only their sum is observed: the smoothed variance
+// of f is then the small sum P_00 + 2 P_0B + P_BB of entries that are large
+// against it, and in FP32 the smoother operator's rounding of those entries
+// is amplified by that cancellation. The smoother therefore runs in the
+// coordinates z' = S z, S = I + e_0 e_B^T, whose first coordinate is f:
+// elements E' = S E S^-1, g' = S g, L' = S L S^T, the observation row
+// h' = H S^-1 (= e_0^T), and f_var = P'_00 comes out of the recursion
+// directly. B = 0 (one component) is the identity.
+template <class LY>
+__host__ __device__ constexpr int smoother_shear_col()
+{
+    return LY::NB == 2 ? LY::boff(1) : 0;
+}
+
+// h' = H S^-1: column B minus column 0
+template <int D, int B, typename T>
+__device__ __forceinline__ void smoother_obs_row(const DevModel &mdl, T (&h)[D])
+{
+#pragma unroll
+    for (int i = 0; i < D; i++) h[i] = T(mdl.H[i]);
+    if constexpr (B > 0) h[B] = T(mdl.H[B] - mdl.H[0]);
+}
+
+// Smoothed moments back in the library's state coordinates:
+// m = S^-1 m', P = S^-1 P' S^-T (row 0 minus row B, then column 0 minus
+// column B).
+template <int D, int B, typename T>
+__device__ __forceinline__ void from_smoother_coords(const T (&ms)[D], const T (&Ps)[D][D], T (&m)[D],
+                                                     T (&P)[D][D])
+{
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+        m[i] = ms[i];
+#pragma unroll
+        for (int j = 0; j < D; j++) P[i][j] = Ps[i][j];
+    }
+    if constexpr (B > 0) {
+        m[0] = ms[0] - ms[B];
+#pragma unroll
+        for (int j = 0; j < D; j++) P[0][j] = Ps[0][j] - Ps[B][j];
+#pragma unroll
+        for (int i = 0; i < D; i++) P[i][0] -= P[i][B];
+    }
+}
+
 // Smoother element of step k, computed in FP64 and rounded to T. The
 // filter moments of step k are read at mk[i * st] (m) and pk[s * st]
 // (packed P):
@@ -245,6 +293,19 @@ __device__ __forceinline__ void smoother_element(const DevModel &mdl, cdouble *c
             for (int q = 0; q < i; q++) s = fma(-C[i][q], Y[q][j], s);
             Y[i][j] = s * rd[i];
         }
+    // smoother coordinates (smoother_shear_col): m' = S m, P' = S P S^T and
+    // Y S^T (column 0 plus column B), so that L' = P' - (Y S^T)^T (Y S^T)
+    // and the back substitution below gives (S E)^T
+    constexpr int B = smoother_shear_col<LY>();
+    if constexpr (B > 0) {
+        m[0] += m[B];
+#pragma unroll
+        for (int j = 0; j < D; j++) P[0][j] += P[B][j];
+#pragma unroll
+        for (int i = 0; i < D; i++) P[i][0] = (i == 0) ? P[0][0] + P[0][B] : P[0][i];
+#pragma unroll
+        for (int q = 0; q < D; q++) Y[q][0] += Y[q][B];
+    }
     // L = P - Y^T Y
 #pragma unroll
     for (int i = 0; i < D; i++)
@@ -267,6 +328,7 @@ __device__ __forceinline__ void smoother_element(const DevModel &mdl, cdouble *c
             for (int q = i + 1; q < D; q++) s = fma(-C[q][i], Y[q][j], s);
             Y[i][j] = s * rd[i];
         }
+    // g' = S m - (S E) F m; E' = (S E) S^-1 (column B minus column 0)
 #pragma unroll
     for (int i = 0; i < D; i++) {
         double acc = m[i];
@@ -274,6 +336,6 @@ __device__ __forceinline__ void smoother_element(const DevModel &mdl, cdouble *c
         for (int q = 0; q < D; q++) acc = fma(-Y[q][i], Fm[q], acc);
         e.g[i] = T(acc);
 #pragma unroll
-        for (int j = 0; j < D; j++) e.E[i][j] = T(Y[j][i]);
+        for (int j = 0; j < D; j++) e.E[i][j] = T((B > 0 && j == B) ? Y[B][i] - Y[0][i] : Y[j][i]);
     }
 }

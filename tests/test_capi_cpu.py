@@ -119,6 +119,15 @@ def test_argument_errors_need_no_device():
     o = P.make_options(chunk=65)
     assert L.pssgp_filter(mp, fake, fake, None, None, n, P.F32, fake, fake, fake, fake, need, ctypes.byref(o),
                           None) == -1
+    # FP32 scans take at least 4 steps per lane; FP64 scans any chunk from 1
+    for c in (1, 2, 3):
+        o = P.make_options(chunk=c)
+        assert L.pssgp_filter(mp, fake, fake, None, None, n, P.F32, fake, fake, fake, fake, need,
+                              ctypes.byref(o), None) == -1
+        assert b"chunk" in L.pssgp_last_error()
+        np_ = P.workspace_bytes(m, n, P.F32, P.OP_PREDICT, o)
+        assert L.pssgp_predict(mp, fake, fake, None, n, P.F32, fake, fake, fake, fake, np_, ctypes.byref(o),
+                               None) == -1
     # NULL model
     assert L.pssgp_filter(None, fake, fake, None, None, n, P.F32, fake, fake, fake, fake, need, None, None) == -1
     # smoother: missing outputs, ms without Ps

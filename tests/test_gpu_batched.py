@@ -51,21 +51,37 @@ def _gpu(w, dtype, options=None, pipe=None, fused=True):
 
 
 def _check(g, o, off, dtype):
-    """Per series: normwise relative errors of f_mean and f_var; the
-    log-likelihood error relative to the sum of the absolute per-step terms
-    (the condition number of the sum; short series can cancel to a small
-    total), with the plain relative error reported beside it."""
+    """Per series: normwise relative errors of f_mean and f_var. The
+    log-likelihood's plain relative error |dl| / |l| is held to the bar on
+    the series whose per-step terms do not cancel much (condition number
+    sum_k |l_k| / |l| below 10); on series that cancel (short series with
+    small noise), where no fixed precision meets a relative bound on |l|,
+    the error relative to sum_k |l_k| is held to the bar. Both maxima and the
+    group sizes are printed."""
     tol = {"float64": (1e-9, 1e-9), "float32": (1e-4, 1e-5)}[dtype]
-    worst = {"f_mean": 0.0, "f_var": 0.0, "loglik": 0.0, "loglik_plain_rel": 0.0}
+    worst = {"f_mean": 0.0, "f_var": 0.0, "loglik_plain_rel_well": 0.0, "loglik_abs_terms_rel_cancelling": 0.0,
+             "loglik_plain_rel_all": 0.0}
+    n_well = 0
     for s in range(len(off) - 1):
         a, b = off[s], off[s + 1]
         worst["f_mean"] = max(worst["f_mean"], rel(g["f_mean"][a:b], o["f_mean"][a:b]))
         worst["f_var"] = max(worst["f_var"], rel(g["f_var"][a:b], o["f_var"][a:b]))
         d = abs(g["loglik"][s] - o["loglik"][s])
-        worst["loglik"] = max(worst["loglik"], d / o["loglik_abs_terms"][s])
-        worst["loglik_plain_rel"] = max(worst["loglik_plain_rel"], d / abs(o["loglik"][s]))
-    print(dtype, {k: "%.2e" % v for k, v in worst.items()}, flush=True)
-    assert worst["f_mean"] <= tol[0] and worst["f_var"] <= tol[0] and worst["loglik"] <= tol[1], worst
+        if o["loglik"][s] == 0.0:
+            assert d == 0.0
+            continue
+        plain = d / abs(o["loglik"][s])
+        worst["loglik_plain_rel_all"] = max(worst["loglik_plain_rel_all"], plain)
+        if o["loglik_abs_terms"][s] < 10.0 * abs(o["loglik"][s]):
+            n_well += 1
+            worst["loglik_plain_rel_well"] = max(worst["loglik_plain_rel_well"], plain)
+        else:
+            worst["loglik_abs_terms_rel_cancelling"] = max(worst["loglik_abs_terms_rel_cancelling"],
+                                                           d / o["loglik_abs_terms"][s])
+    print(dtype, {k: "%.2e" % v for k, v in worst.items()}, "series: %d well-conditioned of %d"
+          % (n_well, len(off) - 1), flush=True)
+    assert worst["f_mean"] <= tol[0] and worst["f_var"] <= tol[0], worst
+    assert worst["loglik_plain_rel_well"] <= tol[1] and worst["loglik_abs_terms_rel_cancelling"] <= tol[1], worst
 
 
 @pytest.mark.parametrize("fused", [True, False])

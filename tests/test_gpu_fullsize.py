@@ -1,5 +1,7 @@
-"""GPU parity at the full workload sizes, in the launch configuration the
-benchmark times (default chunk, Pipeline / BatchedPipeline): the HIP path's
+"""GPU parity at the full workload sizes, through the pipelines the
+benchmark times (Pipeline / BatchedPipeline, the fused call), at the
+default chunk and at the chunks the tuner picks for the single-series
+workloads (32 and 64 steps per lane): the HIP path's
 outputs at sampled steps, its log-likelihood (per series when batched) and
 its gradient against oracle values stored by tests/golden/make_golden.py
 (which calls only the oracle). Tolerances as in the other parity tests:
@@ -40,10 +42,10 @@ def _checksums(w, dtype):
     return np.array([np.sum(w["t"]), np.sum(y), float(np.sum(w["mask"]))])
 
 
-def _single(w, dtype):
+def _single(w, dtype, chunk):
     model = P.make_model(w["model"]["components"], w["model"]["noise_var"])
     n = w["t"].shape[0]
-    pipe = P.Pipeline(model, n, dtype)
+    pipe = P.Pipeline(model, n, dtype, options=P.make_options(chunk=chunk))
     t = torch.as_tensor(w["t"], dtype=torch.float64, device="cuda")
     y = torch.as_tensor(np.nan_to_num(w["y"]), dtype=getattr(torch, dtype), device="cuda")
     mask = torch.as_tensor(w["mask"], dtype=torch.uint8, device="cuda")
@@ -53,17 +55,20 @@ def _single(w, dtype):
         (P.status(pipe.ws_f), P.status(pipe.ws_s))
 
 
-@pytest.mark.parametrize("name,gen,dtype", [
-    ("full_matern52_exp_f64", workloads.matern52_exp, "float64"),
-    ("full_matern52_exp_f32", workloads.matern52_exp, "float32"),
-    ("full_rbf6_lognormal_f32", workloads.rbf6_lognormal, "float32"),
+@pytest.mark.parametrize("name,gen,dtype,chunk", [
+    ("full_matern52_exp_f64", workloads.matern52_exp, "float64", 16),
+    ("full_matern52_exp_f32", workloads.matern52_exp, "float32", 16),
+    ("full_matern52_exp_f32", workloads.matern52_exp, "float32", 32),
+    ("full_rbf6_lognormal_f32", workloads.rbf6_lognormal, "float32", 16),
+    ("full_rbf6_lognormal_f32", workloads.rbf6_lognormal, "float32", 32),
+    ("full_rbf6_lognormal_f32", workloads.rbf6_lognormal, "float32", 64),
 ])
-def test_full_size_single_series(name, gen, dtype):
+def test_full_size_single_series(name, gen, dtype, chunk):
     g = _gold(name)
     w = gen()
     assert np.allclose(_checksums(w, dtype), g["checksums"], rtol=1e-12, atol=0), "input generator changed"
-    print(name, "n =", w["t"].shape[0], flush=True)
-    fm, fv, ll, status = _single(w, dtype)
+    print(name, "n =", w["t"].shape[0], "chunk", chunk, flush=True)
+    fm, fv, ll, status = _single(w, dtype, chunk)
     idx = g["idx"]
     errs = {"f_mean": rel(fm[idx], g["f_mean"]), "f_var": rel(fv[idx], g["f_var"]),
             "loglik": abs(ll - g["loglik"][0]) / abs(g["loglik"][0])}
@@ -104,13 +109,24 @@ def test_full_size_batched():
     fm = fm.double().cpu().numpy()[idx]
     fv = fv.double().cpu().numpy()[idx]
     ll = ll.cpu().numpy()
-    # per-series log-likelihood error relative to the sum of the absolute
-    # per-step terms (condition number of the sum), plain relative reported
-    el = np.abs(ll - g["loglik"]) / g["loglik_abs_terms"]
+    # per-series log-likelihood: the plain relative error |dl| / |l| is held
+    # to the bar on the series whose per-step terms do not cancel much
+    # (condition number sum_k |l_k| / |l| below 10); on the rest, where no
+    # fixed precision meets a relative bound on |l|, the error is held to the
+    # bar relative to sum_k |l_k|. Both maxima and the group sizes are printed.
+    cond = g["loglik_abs_terms"] / np.abs(g["loglik"])
+    well = cond < 10.0
     ep = np.abs(ll - g["loglik"]) / np.abs(g["loglik"])
-    errs = {"f_mean": rel(fm, g["f_mean"]), "f_var": rel(fv, g["f_var"]), "loglik_max": float(np.max(el)),
-            "loglik_median": float(np.median(el)), "loglik_plain_rel_max": float(np.max(ep))}
-    print("batched", {k: "%.2e" % v for k, v in errs.items()}, flush=True)
+    el = np.abs(ll - g["loglik"]) / g["loglik_abs_terms"]
+    errs = {"f_mean": rel(fm, g["f_mean"]), "f_var": rel(fv, g["f_var"]),
+            "loglik_plain_rel_max_well": float(np.max(ep[well])) if well.any() else 0.0,
+            "loglik_plain_rel_max_all": float(np.max(ep)),
+            "loglik_abs_terms_rel_max_cancelling": float(np.max(el[~well])) if (~well).any() else 0.0,
+            "loglik_plain_rel_median": float(np.median(ep))}
+    print("batched", {k: "%.2e" % v for k, v in errs.items()}, "series: %d well-conditioned, %d cancelling"
+          % (int(well.sum()), int((~well).sum())), flush=True)
     assert (P.status(pipe.ws_f), P.status(pipe.ws_s)) == (0, 0)
     tol = TOL["float32"]
-    assert errs["f_mean"] <= tol["mean"] and errs["f_var"] <= tol["var"] and errs["loglik_max"] <= tol["loglik"], errs
+    assert errs["f_mean"] <= tol["mean"] and errs["f_var"] <= tol["var"], errs
+    assert errs["loglik_plain_rel_max_well"] <= tol["loglik"], errs
+    assert errs["loglik_abs_terms_rel_max_cancelling"] <= tol["loglik"], errs
