@@ -20,6 +20,20 @@ constructions rather than printing them; the textbook forms used here are:
   monic polynomial whose roots are the left-half-plane roots of
   T_n(-ell^2 s^2 / 2); G is the companion matrix of p and
   Qc = sigma^2 sqrt(2 pi) ell / kappa, kappa = ell^(2n) / (2^n n!).
+* Quasi-periodic: a periodic kernel times a Matern-3/2 kernel (the paper's
+  CO2 model, section 5, multiplies these and adds a second Matern). The
+  periodic covariance sigma^2 exp(-2 sin^2(w0 tau / 2) / ell_p^2),
+  w0 = 2 pi / period, equals sigma^2 exp(-a) exp(a cos(w0 tau)) with
+  a = ell_p^-2; with the exponential replaced by its degree-J Taylor
+  polynomial and each cos^n written as a sum of cos(j w0 tau), it is the
+  finite cosine series sum_{j<=J} q_j^2 cos(j w0 tau) (Solin & Sarkka 2014).
+  Each harmonic is a two-state undamped oscillator (G_j = [[0, -j w0],
+  [j w0, 0]], no driving noise, stationary covariance q_j^2 I, H_j =
+  [1, 0]). The product of two state-space kernels is the Kronecker
+  construction G = G_per (x) I + I (x) G_mat, H = H_per (x) H_mat, whose
+  stationary covariance is Pinf_per (x) Pinf_mat; the driving noise follows
+  from the Lyapunov equation as W = Pinf_per (x) W_mat. State size
+  4 (J + 1).
 * Sums of kernels: block-diagonal G, L, Qc, Pinf and H = [H_1, H_2, ...].
 
 Pinf is solved here by the vectorised (Kronecker) form of the Lyapunov
@@ -37,7 +51,7 @@ import math
 
 import numpy as np
 
-MATERN12, MATERN32, MATERN52, RBF = 1, 2, 3, 4
+MATERN12, MATERN32, MATERN52, RBF, QUASIPERIODIC = 1, 2, 3, 4, 5
 
 
 def _companion(coeffs_low_to_high):
@@ -64,9 +78,55 @@ def rbf_taylor_roots(n: int) -> np.ndarray:
     return stable
 
 
-def component_ssm(kind: int, order: int, ell, var):
+def periodic_coefficients(J: int, ell_p: float) -> np.ndarray:
+    """q_j^2 (j = 0..J) of the degree-J Taylor form of the unit-variance
+    periodic kernel: with a = ell_p^-2,
+    exp(-a) sum_{n<=J} a^n cos^n(x) / n! = sum_{j<=J} q_j^2 cos(j x), where
+    cos^n x = 2^-n sum_k binom(n, k) cos((n - 2k) x) gives
+    q_j^2 = c_j exp(-a) sum_{m=0}^{floor((J-j)/2)} (a/2)^(j+2m) / (m! (j+m)!),
+    c_0 = 1, c_j = 2 for j >= 1 (the truncated series of 2 I_j(a))."""
+    a = 1.0 / (ell_p * ell_p)
+    q = np.zeros(J + 1)
+    for j in range(J + 1):
+        acc = 0.0
+        for m in range((J - j) // 2 + 1):
+            acc += (a / 2.0) ** (j + 2 * m) / (math.factorial(m) * math.factorial(j + m))
+        q[j] = (1.0 if j == 0 else 2.0) * math.exp(-a) * acc
+    return q
+
+
+def quasiperiodic_ssm(J: int, ell_p: float, var: float, period: float, ell_m: float):
+    """(G, W, Pinf, H) of sigma^2 k_per(tau) k_M32(tau) (unit-variance
+    Matern-3/2 of length-scale ell_m): Kronecker product of the periodic
+    oscillators and the Matern-3/2 model (state order: harmonic j, oscillator
+    coordinate c, Matern coordinate r at index 4 j + 2 c + r)."""
+    w0 = 2.0 * math.pi / period
+    q = periodic_coefficients(J, ell_p)
+    dp = 2 * (J + 1)
+    Gp = np.zeros((dp, dp))
+    Pp = np.zeros((dp, dp))
+    Hp = np.zeros(dp)
+    for j in range(J + 1):
+        Gp[2 * j, 2 * j + 1] = -j * w0
+        Gp[2 * j + 1, 2 * j] = j * w0
+        Pp[2 * j, 2 * j] = Pp[2 * j + 1, 2 * j + 1] = var * q[j]
+        Hp[2 * j] = 1.0
+    Gm, Wm, Pm, Hm = component_ssm(MATERN32, 0, ell_m, 1.0)
+    I2 = np.eye(2)
+    G = np.kron(Gp, I2) + np.kron(np.eye(dp), Gm)
+    W = np.kron(Pp, Wm)
+    Pinf = np.kron(Pp, Pm)
+    H = np.kron(Hp, Hm)
+    return G, W, Pinf, H
+
+
+def component_ssm(kind: int, order: int, ell, var, *extra):
     """(G, W, Pinf, H) of one kernel component; ell and var may be complex
-    (complex-step derivatives)."""
+    (complex-step derivatives). extra: (period, ell_m) of a quasi-periodic
+    component."""
+    if kind == QUASIPERIODIC:
+        period, ell_m = extra
+        return quasiperiodic_ssm(int(order), ell, var, period, ell_m)
     dtype = np.result_type(np.asarray(ell), np.asarray(var), np.float64)
     if kind in (MATERN12, MATERN32, MATERN52):
         d = {MATERN12: 1, MATERN32: 2, MATERN52: 3}[kind]
@@ -127,10 +187,11 @@ def model_ssm(components, theta=None):
     Returns G, W, Pinf, H in the canonical companion coordinates.
     """
     parts = []
-    for c, (kind, order, ell, var) in enumerate(components):
+    for c, comp in enumerate(components):
+        kind, order, ell, var = comp[:4]
         if theta is not None:
             ell, var = theta[2 * c], theta[2 * c + 1]
-        parts.append(component_ssm(kind, order, ell, var))
+        parts.append(component_ssm(kind, order, ell, var, *comp[4:]))
     G = _blockdiag([p[0] for p in parts])
     W = _blockdiag([p[1] for p in parts])
     Pinf = _blockdiag([p[2] for p in parts])
@@ -194,6 +255,8 @@ class OracleModel:
         self.Hb = H * D
         self.n_params = 2 * len(self.components) + 1
         if with_derivatives:
+            if any(c[0] == QUASIPERIODIC for c in self.components):
+                raise ValueError("parameter derivatives are not built for quasi-periodic components")
             theta = []
             for (_, _, ell, var) in self.components:
                 theta += [ell, var]

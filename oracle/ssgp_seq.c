@@ -37,7 +37,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-#define MAXD 8
+#define MAXD 18
 #define MAXB (4 * MAXD)
 
 /* ---------------------------------------------------------------- linear algebra */
