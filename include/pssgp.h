@@ -372,6 +372,38 @@ int pssgp_merge_times(const double *t_train, const void *y_train, const uint8_t 
  * synchronising stream); bits: PSSGP_STATUS_*. */
 int pssgp_status(void *ws, void *stream, uint32_t *bits_host);
 
+/* Size of the device scratch array behind pssgp_loglik_static (per device). */
+#define PSSGP_STATIC_SCRATCH_BYTES (64u << 20)
+
+/*
+ * pssgp_loglik without a workspace argument, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving or
+ * optimisation loops, harnesses that forbid hipMalloc. The call allocates
+ * nothing (no hipMalloc, hipFree or allocating library routine): its
+ * workspace is a device array of PSSGP_STATIC_SCRATCH_BYTES (64 MiB) that the
+ * library holds on every device it runs on until the process ends; the
+ * array's address on the current device is looked up on the first call on
+ * that device. Arguments, layout, result and errors as pssgp_loglik (the
+ * same kernels run, so the result equals pssgp_loglik's with the same
+ * options), except:
+ *  - an input whose workspace (pssgp_workspace_bytes with PSSGP_OP_LOGLIK)
+ *    exceeds the scratch returns PSSGP_EWORKSPACE with nothing launched
+ *    (about 2^22 steps fit at d <= 6 with chunk 64, 2^20 at d = 8 with
+ *    chunk 32);
+ *  - the stream must belong to the current device;
+ *  - every call on a device shares that device's scratch, which keeps the
+ *    last call's contents: calls that overlap on one device (on different
+ *    streams, or from several host threads without ordering) race and give
+ *    undefined results. Calls ordered on one stream are safe; each call
+ *    clears what must start at zero with a kernel (no memset);
+ *  - the device status word lives in the shared scratch and is not
+ *    readable through pssgp_status; callers that need the status bits use
+ *    pssgp_loglik with their own workspace.
+ */
+int pssgp_loglik_static(const pssgp_model *model, const double *t, const void *y, const uint8_t *mask,
+                        const double *noise_k, int64_t n, pssgp_dtype dtype, double *loglik,
+                        const pssgp_options *opts, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libpssgp.so")
 
 MATERN12, MATERN32, MATERN52, RBF = 1, 2, 3, 4
 F32, F64 = 0, 1
+STATIC_SCRATCH_BYTES = 64 << 20  # PSSGP_STATIC_SCRATCH_BYTES: the scratch behind pssgp_loglik_static
 OP_FILTER, OP_SMOOTH, OP_LOGLIK, OP_LOGLIK_GRAD, OP_DISCRETIZE, OP_PLAIN, OP_PREDICT = 1, 2, 3, 4, 5, 6, 7
 STATUS_UNSORTED, STATUS_NONFINITE, STATUS_BAD_S, STATUS_CHOLESKY = 1, 2, 4, 8
 
@@ -91,6 +92,7 @@ SIGNATURES = [
     ("pssgp_predict", ctypes.c_int, [_MP, _VP, _VP, _VP, _I64, ctypes.c_int, _VP, _VP, _VP, _VP, _SZ, _OP, _VP]),
     ("pssgp_plain_predict", ctypes.c_int, [_MP, _VP, _VP, _VP, _I64, _VP, _VP, _VP, _VP, _VP, _VP, _SZ, _VP]),
     ("pssgp_merge_times", ctypes.c_int, [_VP, _VP, _VP, _I64, _VP, _I64, ctypes.c_int, _VP, _VP, _VP, _VP, _VP]),
+    ("pssgp_loglik_static", ctypes.c_int, [_MP, _VP, _VP, _VP, _VP, _I64, ctypes.c_int, _VP, _OP, _VP]),
 ]
 
 
@@ -396,6 +398,27 @@ def plain_predict(model, t, y, mask=None, ws=None, device="cuda"):
 
 def loglik(model, t, y, mask=None, noise_k=None, dtype="float32", options=None, device="cuda"):
     return filter(model, t, y, mask, noise_k, dtype, moments=False, options=options, device=device)["loglik"]
+
+
+def loglik_static(model, t, y, mask=None, noise_k=None, dtype="float32", options=None, out=None, device="cuda"):
+    """Log-likelihood through pssgp_loglik_static: no workspace, the library's
+    per-device static scratch instead (nothing is allocated by the library;
+    out, a device float64[1] tensor, may be given so that the call allocates
+    nothing at all). Calls that overlap on one device race on that scratch."""
+    _require_gpu()
+    torch = _torch()
+    m = _as_model(model)
+    code, tdt = _dt(dtype)
+    t = _dev(t, torch.float64, device)
+    y = _dev(y, tdt, device)
+    mask = _dev(mask, torch.uint8, device)
+    noise_k = _dev(noise_k, torch.float64, device)
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device=device)
+    rc = lib().pssgp_loglik_static(ctypes.byref(m), _p(t), _p(y), _p(mask), _p(noise_k), t.shape[0], code, _p(out),
+                                   ctypes.byref(options) if options is not None else None, _stream())
+    _check(rc)
+    return out
 
 
 def loglik_grad(model, t, y, mask=None, dtype="float32", options=None, ws=None, device="cuda", noise_k=None):

@@ -150,6 +150,38 @@ def test_argument_errors_need_no_device():
     assert b"state size" in L.pssgp_last_error()
 
 
+def test_static_loglik_rejects_oversized_inputs_without_device():
+    """pssgp_loglik_static checks its arguments and the scratch size on the
+    host before it touches a device: n < 0, a bad dtype and an input whose
+    workspace exceeds the static scratch return errors (the fake device
+    pointers are never dereferenced)."""
+    L = P.lib()
+    m = P.make_model([(RBF, 6, 1.0, 1.0)], 0.01)
+    mp = ctypes.byref(m)
+    fake = ctypes.c_void_p(0x1000)
+    cap = P.STATIC_SCRATCH_BYTES
+    assert L.pssgp_loglik_static(mp, fake, fake, None, None, -1, P.F32, fake, None, None) == -1
+    assert L.pssgp_loglik_static(mp, fake, fake, None, None, 10, 7, fake, None, None) == -1
+    assert L.pssgp_loglik_static(None, fake, fake, None, None, 10, P.F32, fake, None, None) == -1
+    # the largest n that fits at the default chunk, found from the workspace
+    # size; one tile more does not fit
+    lo, hi = 1, 1 << 30
+    while lo < hi:
+        mid = (lo + hi + 1) // 2
+        if P.workspace_bytes(m, mid, P.F32, P.OP_LOGLIK) <= cap:
+            lo = mid
+        else:
+            hi = mid - 1
+    assert lo >= 1 << 20
+    big = lo + 64 * 16
+    assert P.workspace_bytes(m, big, P.F32, P.OP_LOGLIK) > cap
+    assert L.pssgp_loglik_static(mp, fake, fake, None, None, big, P.F32, fake, None, None) == -3
+    assert b"static scratch" in L.pssgp_last_error()
+    # an FP32 chunk below 4 is rejected as for pssgp_loglik
+    o = P.make_options(chunk=2)
+    assert L.pssgp_loglik_static(mp, fake, fake, None, None, 100, P.F32, fake, ctypes.byref(o), None) == -1
+
+
 def test_merge_argument_errors_need_no_device():
     """pssgp_merge_times validates sizes, dtype and pointers on the host."""
     L = P.lib()
