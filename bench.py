@@ -49,6 +49,7 @@ WORKLOADS = {
 
 
 FP32_UNPACKED_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (= FP64 vector)
+FP32_PACKED_PEAK_TFLOPS = 157.3    # published FP32 vector peak (packed FP32 instructions)
 
 PASSES = ("filter_fold", "filter_carry", "filter_finish", "smoother_fold", "smoother_carry", "smoother_finish")
 
@@ -100,6 +101,28 @@ def pass_costs(d, tsize, chunk):
     }
 
 
+def path_bytes_per_step(d, tsize):
+    """Algorithmic HBM bytes per time step of the whole filter + smoother
+    path: the inputs t (8 B), y and mask (1 B) read once, the filter moments
+    (m, P) handed to the smoother (d(d+3)/2 values, written once and read
+    once), t read again by the smoother, f_mean and f_var written once:
+    29 + 4 d(d+3) bytes in FP32, 41 + 8 d(d+3) in FP64 (245 and 473 at
+    d = 6). The fused call hands over the smoother elements instead of the
+    moments; the figure is the method's, not this implementation's."""
+    return 8 + tsize + 1 + 2 * tsize * (d * (d + 3) // 2) + 8 + 2 * tsize
+
+
+def grad_bytes_per_step(d, tsize):
+    """HBM bytes per step of log-likelihood + gradient as built: the inputs
+    t, y, mask read by the forward filter's two passes and the adjoint's two
+    passes (4 x (9 + s)), and the per-step forward records (mu, Pi, K, S, v:
+    2d + d(d+1)/2 + 2 values) written once by the forward finish and read by
+    both adjoint passes. The method's own floor with checkpoint recompute
+    instead of records is the inputs read twice (2 x (9 + s))."""
+    rec = 2 * d + d * (d + 1) // 2 + 2
+    return 4 * (9 + tsize) + 3 * tsize * rec
+
+
 def algorithmic_bytes(tsize, n):
     """HBM bytes the whole path must move: the step inputs (t, y, mask) read
     once and f_mean, f_var written once."""
@@ -107,22 +130,23 @@ def algorithmic_bytes(tsize, n):
 
 
 MERGE_SOURCES = ("merge.hip", "launch.h")
+SCAN_SOURCES = ("device_common.h", "filter_kernel.h", "filter_ops.h", "smoother_kernel.h", "smoother_ops.h",
+                "tile_scan.h", "launch.h", "model.h", "inst_filter.hip", "inst_smoother.hip")
+GRAD_SOURCES = SCAN_SOURCES + ("grad_kernel.h", "inst_grad.hip")
 
 
 def sources_digest(kernel=None):
-    """SHA-256 of the sources a kernel is built from (the traffic figures of
-    a profile summary hold only for the sources they were taken with): for
-    the merge kernel merge.hip and launch.h, for the scan kernels every
-    other source file."""
+    """SHA-256 of the sources a kernel is built from (the counter figures of
+    a profile summary hold only for the sources they were taken with): the
+    merge kernel from merge.hip and launch.h, the scan kernels from the
+    filter and smoother headers and their instantiation units, the gradient
+    path ('path' of the log-likelihood + gradient workload) from those and
+    the adjoint's."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2102_09964_amd", "csrc")
-    merge = kernel == "merge_kernel"
-    for name in sorted(os.listdir(csrc)):
-        if not name.endswith((".h", ".hip", ".cpp")):
-            continue
-        if (merge and name not in MERGE_SOURCES) or (not merge and name == "merge.hip"):
-            continue
+    names = MERGE_SOURCES if kernel == "merge_kernel" else (GRAD_SOURCES if kernel == "path" else SCAN_SOURCES)
+    for name in sorted(names):
         h.update(name.encode())
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(f.read())
@@ -152,6 +176,34 @@ def measured_traffic(kernel, workload, dtype, chunk):
                 digest = digest or sources_digest(kernel)
                 if kv.get("sources") == digest:
                     return float(kv["bytes"])
+    return None
+
+
+def measured_valu(kernel, workload, dtype, chunk):
+    """Counter-measured vector ALU work of one launch of a kernel from the
+    committed summaries (profiles/valu_*.txt, lines 'valu: kernel=...
+    workload=... dtype=... chunk=... flops=... f64_flops=... f32_flops=...
+    sources=...'): flops = 64 lanes x (ADD + MUL + TRANS + 2 FMA) VALU
+    instructions of FP32 and FP64 per launch. None when no line matches or
+    the sources changed since the counters were taken."""
+    pdir = os.path.join(ROOT, "profiles")
+    if not os.path.isdir(pdir):
+        return None
+    digest = None
+    for name in sorted(os.listdir(pdir)):
+        if not (name.startswith("valu_") and name.endswith(".txt")):
+            continue
+        with open(os.path.join(pdir, name)) as f:
+            for line in f:
+                if not line.startswith("valu:"):
+                    continue
+                kv = dict(x.split("=", 1) for x in line.split()[1:])
+                if (kv.get("kernel"), kv.get("workload"), kv.get("dtype"), kv.get("chunk")) != \
+                        (kernel, workload, dtype, str(chunk)):
+                    continue
+                digest = digest or sources_digest(kernel)
+                if kv.get("sources") == digest:
+                    return {k: float(kv[k]) for k in ("flops", "f64_flops", "f32_flops") if k in kv}
     return None
 
 
@@ -194,6 +246,14 @@ def measure(w, dtype, steps, warmup, chunk=0):
         graph.replay()
     torch.cuda.synchronize()
     ms_step = (time.perf_counter() - t0) * 1e3 / steps
+    # per-replay durations (events on the replay stream) for the median
+    rev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for a, b in rev:
+        a.record()
+        graph.replay()
+        b.record()
+    torch.cuda.synchronize()
+    ms_median = float(np.median([a.elapsed_time(b) for a, b in rev]))
     graph_ll = float(pipe.loglik.cpu()[0])
     del graph
     # per-pass timing: HIP events recorded by the library on the launch
@@ -217,6 +277,7 @@ def measure(w, dtype, steps, warmup, chunk=0):
     status = (P.status(pipe.ws_f), P.status(pipe.ws_s))
     tsize = 4 if dtype == "float32" else 8
     return {"n": n, "d": d, "tsize": tsize, "chunk": chunk or 16, "ms_per_step": ms_step, "ms_eager": ms_eager,
+            "ms_median": ms_median,
             "filter_ms": sum(v for k, v in pass_ms.items() if k.startswith("filter")),
             "smoother_ms": sum(v for k, v in pass_ms.items() if k.startswith("smoother")),
             "pass_ms": pass_ms, "steps_per_s": n / (ms_step / 1e3), "loglik": ll, "status": status,
@@ -283,14 +344,78 @@ def roofline_of(m, workload=None, dtype=None, costs=None):
     return out
 
 
-def measure_batched(steps, warmup, chunk=0):
+KERNEL_NAMES = {"filter_fold": "filter_fold", "filter_finish": "filter_finish", "smoother_fold": "smoother_fold",
+                "smoother_finish": "smoother_finish"}
+
+
+def path_roofline(m, workload=None, dtype=None):
+    """Roofline of the whole timed path (one fused filter + smoother call per
+    step): the method's algorithmic bytes per step (path_bytes_per_step) times
+    the steps, over the time per step, against the 8 TB/s HBM3E peak. The
+    dominant kernel (longest pass) is reported beside it: its HIP-event
+    duration, its vector ALU rate from the committed VALU counter summary
+    (FP32 and FP64 flops per launch) against the FP64 / unpacked FP32 vector
+    peak (78.6 TFLOP/s) and the packed FP32 peak (157.3 TFLOP/s), its
+    algorithmic bytes and its measured HBM traffic."""
+    bps = path_bytes_per_step(m["d"], m["tsize"])
+    gbs = bps * m["n"] / (m["ms_per_step"] / 1e3) / 1e9
+    k = roofline_of(m, workload, dtype)
+    valu = measured_valu(k["kernel"], workload, dtype, m["chunk"]) if workload else None
+    kern = {"name": k["kernel"], "ms": k["kernel_ms"],
+            "hbm_gbs": k["achieved_gbs"], "hbm_frac": k["hbm_frac"],
+            "algorithmic_bytes_per_launch": k["algorithmic_bytes_per_launch"], "traffic": k["traffic"],
+            "model_flops_per_step": k["flops_per_step"]}
+    if k.get("traffic_over_algorithmic"):
+        kern["traffic_over_algorithmic"] = k["traffic_over_algorithmic"]
+    if valu:
+        tfl = valu["flops"] / (k["kernel_ms"] / 1e3) / 1e12
+        kern.update({"valu_flops_per_launch": valu["flops"], "valu_flops_per_step": round(valu["flops"] / m["n"], 1),
+                     "valu_tflops": round(tfl, 3),
+                     "valu_frac": round(tfl / FP32_UNPACKED_PEAK_TFLOPS, 5),
+                     "valu_frac_packed_fp32_peak": round(tfl / FP32_PACKED_PEAK_TFLOPS, 5),
+                     "valu_f64_share": round(valu.get("f64_flops", 0.0) / max(valu["flops"], 1.0), 3)})
+    else:
+        kern.update({"valu_flops_per_launch": None, "model_tflops": k["achieved_tflops"],
+                     "model_frac": round(k["achieved_tflops"] / FP32_UNPACKED_PEAK_TFLOPS, 5)})
+    return {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 5), "traffic": path_traffic(m, workload, dtype),
+            "scope": "whole path per step (fused filter + smoother call)",
+            "bytes_per_step": bps, "steps_per_s_at_peak": round(HBM_PEAK_GBS * 1e9 / bps, 1),
+            "dominant_kernel": kern}
+
+
+def path_traffic(m, workload, dtype):
+    """Measured HBM bytes of one step: the sum of the counter-measured
+    traffic of the step's kernels (fold, carry and finish of both scans),
+    when the committed summary covers all of them for these sources,
+    workload, dtype and chunk; otherwise None."""
+    if not workload:
+        return None
+    tot = 0.0
+    for name in PASSES:
+        if name.endswith("_carry"):
+            parts = [measured_traffic(name + "_" + x, workload, dtype, m["chunk"])
+                     for x in ("scan", "reduce", "apply")]
+            if any(v is None for v in parts):
+                return None
+            tot += sum(parts)
+            continue
+        v = measured_traffic(name, workload, dtype, m["chunk"])
+        if v is None:
+            return None
+        tot += v
+    return tot
+
+
+def measure_batched(steps, warmup, chunk=0, missing=0.0):
     """Batched workload (4096 series, Matern-3/2 and -5/2) in FP32: filter +
-    smoother over all series captured once in a HIP graph and replayed."""
+    smoother over all series captured once in a HIP graph and replayed
+    (missing: fraction of steps masked missing)."""
     import torch
     import workloads
     import paper_2102_09964_amd as P
     from paper_2102_09964_amd import tune
-    w = workloads.batched_matern()
+    w = workloads.batched_matern(missing=missing)
     t = torch.as_tensor(w["t"], dtype=torch.float64, device="cuda")
     y = torch.as_tensor(np.nan_to_num(w["y"]), dtype=torch.float32, device="cuda")
     mask = torch.as_tensor(w["mask"], dtype=torch.uint8, device="cuda")
@@ -339,23 +464,38 @@ def measure_batched(steps, warmup, chunk=0):
             costs[k][0] += frac * b
             costs[k][1] += frac * f
     costs["filter_finish"][0] += 16.0 * (1.0 / chunk + len(w["kinds"]) / n)
+    pbytes = 0.0
+    for kind, dd in ((P.MATERN32, 2), (P.MATERN52, 3)):
+        idx = np.nonzero(np.asarray(w["kinds"]) == kind)[0]
+        pbytes += float(np.sum(off[idx + 1] - off[idx])) / n * path_bytes_per_step(dd, 4)
     m = {"n": n, "chunk": chunk, "pass_ms": pass_ms, "ms_per_step": ms, "path_bytes": algorithmic_bytes(4, n)}
     rf = roofline_of(m, costs={k: tuple(v) for k, v in costs.items()})
-    return {"workload": "batched_matern", "dtype": "float32", "n": n, "n_series": int(len(w["kinds"])),
+    return {"workload": "batched_matern" + ("_missing%d" % round(100 * missing) if missing else ""),
+            "dtype": "float32", "n": n, "n_series": int(len(w["kinds"])),
             "chunk": int(chunk), "graph": True, "steps_per_s": round(n / (ms / 1e3), 1), "ms_per_step": round(ms, 4),
             "pass_ms": {k: round(v, 4) for k, v in pass_ms.items()},
-            "roofline": {k: rf[k] for k in ("bound", "kernel", "achieved", "unit", "frac", "achieved_gbs", "hbm_frac",
-                                            "path_hbm_frac")},
+            # the method's bytes per step (path_bytes_per_step, weighted by the
+            # layouts' steps) over the step time, against the HBM peak; the
+            # dominant kernel's figures beside it
+            "roofline": {"bound": "hbm", "achieved": round(pbytes * n / (ms / 1e3) / 1e9, 2), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(pbytes * n / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 5),
+                         "bytes_per_step": round(pbytes, 2), "traffic": None,
+                         "dominant_kernel": {k: rf[k] for k in ("kernel", "achieved", "unit", "frac", "achieved_gbs",
+                                                                "hbm_frac")}},
             # all passes' algorithmic bytes (inputs, handover, lane records,
             # outputs) over the whole step
             "step_gbs": round(sum(v[0] for v in costs.values()) * n / (ms / 1e3) / 1e9, 1),
             "status": [P.status(pipe.ws_f), P.status(pipe.ws_s)]}
 
 
-def measure_grad(steps, warmup, chunk=0):
+def measure_grad(steps, warmup, chunk=0, cpu=True):
     """Log-likelihood and its gradient (hand-written adjoint over the forward
     filter's per-step records) for the sum kernel Matern-3/2 + RBF-6 (d = 8),
-    N = 2^20, FP32."""
+    N = 2^20, FP32. Roofline: the call's HBM bytes per step as built
+    (grad_bytes_per_step) against the HBM peak, and the counter-measured
+    vector ALU flops of the whole call (committed VALU summary) against the
+    vector peak; cpu_baseline: the oracle's sequential FP64 log-likelihood
+    with forward-mode gradient on a prefix, one core."""
     import torch
     import workloads
     import paper_2102_09964_amd as P
@@ -375,28 +515,58 @@ def measure_grad(steps, warmup, chunk=0):
         ll, g = P.loglik_grad(model, t, y, mask, dtype="float32", options=opts, ws=ws)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / steps
-    return {"workload": "sum_m32_rbf6_loglik_grad", "dtype": "float32", "n": n, "d": P.state_dim(model),
-            "steps_per_s": round(n / (ms / 1e3), 1), "ms_per_step": round(ms, 4),
-            "grad": [round(float(v), 6) for v in g.cpu().numpy()]}
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for a, b in evs:
+        a.record()
+        P.loglik_grad(model, t, y, mask, dtype="float32", options=opts, ws=ws)
+        b.record()
+    torch.cuda.synchronize()
+    ms_median = float(np.median([a.elapsed_time(b) for a, b in evs]))
+    d = P.state_dim(model)
+    bps = grad_bytes_per_step(d, 4)
+    gbs = bps * n / (ms / 1e3) / 1e9
+    valu = measured_valu("path", "sum_m32_rbf6_loglik_grad", "float32", chunk or 16)
+    rf = {"bound": "alu" if valu else "hbm", "achieved": None, "peak": None, "unit": None, "frac": None,
+          "traffic": None, "bytes_per_step": bps, "hbm_gbs": round(gbs, 2), "hbm_frac": round(gbs / HBM_PEAK_GBS, 5),
+          "method_floor_bytes_per_step": 2 * (9 + 4)}
+    if valu:
+        tfl = valu["flops"] / (ms / 1e3) / 1e12
+        rf.update({"achieved": round(tfl, 3), "peak": FP32_UNPACKED_PEAK_TFLOPS, "unit": "TFLOP/s",
+                   "frac": round(tfl / FP32_UNPACKED_PEAK_TFLOPS, 5),
+                   "frac_packed_fp32_peak": round(tfl / FP32_PACKED_PEAK_TFLOPS, 5),
+                   "valu_flops_per_step": round(valu["flops"] / n, 1)})
+    else:
+        rf.update({"achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                   "frac": round(gbs / HBM_PEAK_GBS, 5)})
+    out = {"workload": "sum_m32_rbf6_loglik_grad", "dtype": "float32", "n": n, "d": d, "chunk": chunk or 16,
+           "steps_per_s": round(n / (ms / 1e3), 1), "ms_per_step": round(ms, 4),
+           "ms_per_step_median": round(ms_median, 4), "roofline": rf,
+           "grad": [round(float(v), 6) for v in g.cpu().numpy()]}
+    if cpu:
+        out["cpu_baseline"] = cpu_baseline(w, target_s=10.0, gradient=True)
+    return out
 
 
-def cpu_baseline(w, target_s=12.0):
-    """Sequential FP64 oracle (filter + smoother + log-likelihood) on a
-    prefix of the workload sized for about target_s seconds of one core."""
+def cpu_baseline(w, target_s=12.0, gradient=False):
+    """Sequential FP64 oracle (filter + smoother + log-likelihood, or with
+    gradient: log-likelihood and its forward-mode gradient) on a prefix of
+    the workload sized for about target_s seconds of one core."""
     import oracle
     from oracle.model import OracleModel
-    m = OracleModel(w["model"]["components"], w["model"]["noise_var"])
+    m = OracleModel(w["model"]["components"], w["model"]["noise_var"], with_derivatives=gradient)
     n_all = w["t"].shape[0]
     probe = min(2000, n_all)
+    kw = {"filter_moments": False, "smoother": not gradient, "gradient": gradient}
     t0 = time.perf_counter()
-    oracle.run(m, w["t"][:probe], w["y"][:probe], w["mask"][:probe], filter_moments=False)
+    oracle.run(m, w["t"][:probe], w["y"][:probe], w["mask"][:probe], **kw)
     per = (time.perf_counter() - t0) / probe
     n = int(min(n_all, max(probe, target_s / per)))
     t0 = time.perf_counter()
-    oracle.run(m, w["t"][:n], w["y"][:n], w["mask"][:n], filter_moments=False)
+    oracle.run(m, w["t"][:n], w["y"][:n], w["mask"][:n], **kw)
     dt = time.perf_counter() - t0
+    what = "loglik + forward-mode gradient" if gradient else "filter+smoother+loglik"
     return {"value": round(n / dt, 1), "unit": "time steps/s", "cores": 1, "kind": "oracle",
-            "sample": "first %d of %d steps, filter+smoother+loglik, FP64 sequential C, %.1f s" % (n, n_all, dt)}
+            "sample": "first %d of %d steps, %s, FP64 sequential C, %.1f s" % (n, n_all, what, dt)}
 
 
 def cpu_baseline_batched(target_s=10.0, max_threads=16):
@@ -514,6 +684,80 @@ def measure_learning(max_iter=20, n_samples=4):
                     "samples_per_s": round(n_samples / t_hmc, 3), "accept_rate": float(h["accepted"].mean())}}
 
 
+# The paper's own run times (section 5; GPflow/TensorFlow on an NVIDIA
+# GeForce RTX 3090 with an AMD Ryzen Threadripper 3960X host, numeric
+# precision not stated): context beside this machine's numbers, not a
+# target. steps/s are derived as steps / time.
+PAPER_CONTEXT = {
+    "hardware": "NVIDIA GeForce RTX 3090 24 GB + AMD Ryzen Threadripper 3960X, GPflow/TensorFlow, precision not stated",
+    "loglik_grad_per_eval_ms": {"1200_steps": 39, "2200_steps": 46, "3200_steps": 48},
+    "loglik_grad_steps_per_s": {"1200_steps": round(1200 / 0.039), "2200_steps": round(2200 / 0.046),
+                                "3200_steps": round(3200 / 0.048)},
+    "filter_smoother_interpolation": {"steps": 99200, "seconds": 0.14, "steps_per_s": round(99200 / 0.14)},
+}
+
+
+def tuned_chunk(w, dtype):
+    """The autotuner's chunk for a single-series workload (cached per layout,
+    precision and size bucket)."""
+    import torch
+    import paper_2102_09964_amd as P
+    from paper_2102_09964_amd import tune
+    model = P.make_model(w["model"]["components"], w["model"]["noise_var"])
+    chunk, _ = tune.tune_chunk(model, torch.as_tensor(w["t"], dtype=torch.float64, device="cuda"),
+                               torch.as_tensor(np.nan_to_num(w["y"]), dtype=getattr(torch, dtype), device="cuda"),
+                               torch.as_tensor(w["mask"], dtype=torch.uint8, device="cuda"), dtype=dtype)
+    return chunk
+
+
+def summary(name, dtype, mm, workload_key=None):
+    """One measured single-series configuration, with its path roofline and
+    dominant kernel."""
+    rf = path_roofline(mm, workload_key, dtype)
+    return {"workload": name, "dtype": dtype, "n": mm["n"], "d": mm["d"], "chunk": mm["chunk"],
+            "steps_per_s": round(mm["steps_per_s"], 1), "ms_per_step": round(mm["ms_per_step"], 4),
+            "ms_per_step_median": round(mm["ms_median"], 4),
+            "filter_ms": round(mm["filter_ms"], 4), "smoother_ms": round(mm["smoother_ms"], 4),
+            "pass_ms": {k: round(v, 4) for k, v in mm["pass_ms"].items()},
+            "roofline": {"bound": rf["bound"], "achieved": rf["achieved"], "unit": rf["unit"], "frac": rf["frac"],
+                         "bytes_per_step": rf["bytes_per_step"],
+                         "dominant_kernel": rf["dominant_kernel"]["name"],
+                         "dominant_kernel_ms": rf["dominant_kernel"]["ms"]}}
+
+
+SWEEP_MODELS = {
+    2: [(2, 0, 1.0, 1.0)],                      # Matern-3/2
+    3: [(3, 0, 1.0, 1.0)],                      # Matern-5/2
+    6: [(4, 6, 1.0, 1.0)],                      # RBF Taylor order 6
+    8: [(2, 0, 2.0, 0.5), (4, 6, 0.5, 0.5)],    # Matern-3/2 + RBF-6
+}
+
+
+def d_sweep(steps, headline=None):
+    """The metric over state sizes: the rbf6_lognormal generator (log-normal
+    gaps, the paper's three-tone signal, 20 % missing) at N = 2^20 and 2^22
+    with the models of d = 2, 3, 6 and 8, FP32 and FP64 scans, each at its
+    tuned chunk. headline: (workload, dtype, measurement) already taken for
+    one cell."""
+    import workloads
+    cells = []
+    for n in (1 << 20, 1 << 22):
+        base = workloads.rbf6_lognormal(n=n)
+        for d, comps in SWEEP_MODELS.items():
+            w = dict(base)
+            w["model"] = {"components": comps, "noise_var": 0.01}
+            for dt in ("float32", "float64"):
+                if headline and d == 6 and n == (1 << 22) and dt == headline[1]:
+                    mm = headline[2]
+                else:
+                    mm = measure(w, dt, steps, 2, tuned_chunk(w, dt))
+                c = summary("sweep_d%d_n%d" % (d, n), dt, mm,
+                            "rbf6_lognormal" if (d == 6 and n == (1 << 22)) else None)
+                print("sweep d=%d n=%d %s: %.3g steps/s" % (d, n, dt, c["steps_per_s"]), file=sys.stderr, flush=True)
+                cells.append(c)
+    return cells
+
+
 def copy_probe():
     """A plain device copy of known size (1 GiB, three times): the counter
     values FETCH_SIZE and WRITE_SIZE read for it give the factors that turn
@@ -526,6 +770,27 @@ def copy_probe():
         b.copy_(a)
     torch.cuda.synchronize()
     print(json.dumps({"copy_probe_bytes": n * 4, "copies": 3}), flush=True)
+
+
+def flop_probe():
+    """Elementwise kernels of known arithmetic (2^26 elements, three times
+    each): one FP32 multiply, one FP64 multiply and one FP64 fused
+    multiply-add per element. What the SQ_INSTS_VALU_FLOPS_* counters read
+    for them gives the factor from counter units to flops."""
+    import torch
+    n = 1 << 26
+    a = torch.full((n,), 1.0001, dtype=torch.float32, device="cuda")
+    b = torch.full((n,), 1.0001, dtype=torch.float64, device="cuda")
+    c = torch.full((n,), 0.5, dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        a.mul_(1.0001)
+    for _ in range(3):
+        b.mul_(1.0001)
+    for _ in range(3):
+        b.addcmul_(c, c)
+    torch.cuda.synchronize()
+    print(json.dumps({"flop_probe_elements": n, "kernels": ["f32 mul x3", "f64 mul x3", "f64 addcmul x3"]}),
+          flush=True)
 
 
 def main():
@@ -541,11 +806,21 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB three times (calibration of the FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--flop-probe", action="store_true",
+                    help="only elementwise kernels of known flops (calibration of the VALU FLOPS counters)")
+    ap.add_argument("--grad-only", action="store_true",
+                    help="only the log-likelihood + gradient workload (one JSON line)")
     ap.add_argument("--merge-only", action="store_true",
                     help="only the merge of test times into the training grid (one JSON line)")
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe()
+        return
+    if args.flop_probe:
+        flop_probe()
+        return
+    if args.grad_only:
+        print(json.dumps(measure_grad(args.steps, args.warmup, args.chunk, cpu=False)), flush=True)
         return
     if args.merge_only:
         print(json.dumps(measure_merge(args.steps, args.warmup)), flush=True)
@@ -570,26 +845,23 @@ def main():
                                    _t.as_tensor(np.nan_to_num(w["y"]), dtype=tdt, device="cuda"),
                                    _t.as_tensor(w["mask"], dtype=_t.uint8, device="cuda"), dtype=args.dtype)
     m = measure(w, args.dtype, args.steps, args.warmup, chunk)
-    also = []
+    also, sweep = [], []
     if not args.no_also:
-        other = "float64" if args.dtype == "float32" else "float32"
-        for name, dt in [(args.workload, other), ("matern52_exp", "float32"), ("matern52_exp", "float64"),
+        sweep = d_sweep(max(3, args.steps // 2), (args.workload, args.dtype, m) if args.workload == "rbf6_lognormal"
+                        else None)
+        for name, dt in [("matern52_exp", "float32"), ("matern52_exp", "float64"),
                          ("matern32_interp", "float64"), ("sum_m32_rbf6", "float32")]:
             if name == args.workload and dt == args.dtype:
                 continue
             ww = w if name == args.workload else WORKLOADS[name]()
-            mm = measure(ww, dt, max(3, args.steps // 2), 2)
-            also.append({"workload": name, "dtype": dt, "n": mm["n"], "d": mm["d"], "chunk": mm["chunk"],
-                         "steps_per_s": round(mm["steps_per_s"], 1), "ms_per_step": round(mm["ms_per_step"], 4),
-                         "filter_ms": round(mm["filter_ms"], 4), "smoother_ms": round(mm["smoother_ms"], 4),
-                         "pass_ms": {k: round(v, 4) for k, v in mm["pass_ms"].items()},
-                         "roofline": {k: roofline_of(mm)[k] for k in ("bound", "kernel", "achieved", "unit", "frac")}})
-    if not args.no_also:
-        mb = measure_batched(max(3, args.steps // 2), 2)
-        if not args.no_cpu_baseline:
-            mb["cpu_baseline"] = cpu_baseline_batched()
-        also.append(mb)
-        also.append(measure_grad(max(3, args.steps // 2), 2))
+            mm = measure(ww, dt, max(3, args.steps // 2), 2, tuned_chunk(ww, dt))
+            also.append(summary(name, dt, mm))
+        for missing in (0.0, 0.1):
+            mb = measure_batched(max(3, args.steps // 2), 2, missing=missing)
+            if not args.no_cpu_baseline and missing == 0.0:
+                mb["cpu_baseline"] = cpu_baseline_batched()
+            also.append(mb)
+        also.append(measure_grad(max(3, args.steps // 2), 2, cpu=not args.no_cpu_baseline))
         also.append(measure_merge(max(3, args.steps // 2), 2))
         also.append(measure_learning())
     out = {
@@ -609,7 +881,8 @@ def main():
         "config": {"workload": args.workload, "n_steps": m["n"], "state_dim": m["d"], "chunk": m["chunk"],
                    "kernel": "RBF Taylor order 6" if args.workload == "rbf6_lognormal" else args.workload,
                    "scan_dtype": args.dtype, "discretisation": "f64"},
-        "roofline": roofline_of(m, args.workload, args.dtype),
+        "roofline": path_roofline(m, args.workload, args.dtype),
+        "ms_per_step_median": round(m["ms_median"], 4),
         "filter_ms": round(m["filter_ms"], 4),
         "smoother_ms": round(m["smoother_ms"], 4),
         "pass_ms": {k: round(v, 4) for k, v in m["pass_ms"].items()},
@@ -622,8 +895,11 @@ def main():
         out["plain_f64_gpu_scan"] = pl
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
+    if sweep:
+        out["d_sweep"] = sweep
     if also:
         out["also"] = also
+    out["paper_context"] = PAPER_CONTEXT
     print(json.dumps(out), flush=True)
 
 

@@ -87,7 +87,8 @@ def test_cost_model():
 def test_traffic_lookup(tmp_path, monkeypatch):
     (tmp_path / "profiles").mkdir()
     (tmp_path / "paper_2102_09964_amd" / "csrc").mkdir(parents=True)
-    (tmp_path / "paper_2102_09964_amd" / "csrc" / "k.hip").write_text("kernel source\n")
+    for name in bench.GRAD_SOURCES + bench.MERGE_SOURCES:
+        (tmp_path / "paper_2102_09964_amd" / "csrc" / name).write_text("source of %s\n" % name)
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     digest = bench.sources_digest()
     lines = ["header text", "traffic: kernel=filter_finish workload=w dtype=float32 chunk=32 bytes=123 sources=" + digest,
@@ -96,8 +97,15 @@ def test_traffic_lookup(tmp_path, monkeypatch):
     assert bench.measured_traffic("filter_finish", "w", "float32", 32) == 123.0
     assert bench.measured_traffic("filter_finish", "w", "float32", 64) is None  # sources changed
     assert bench.measured_traffic("filter_fold", "w", "float32", 32) is None
-    (tmp_path / "paper_2102_09964_amd" / "csrc" / "k.hip").write_text("kernel source, edited\n")
+    # a source the merge kernel is not built from leaves its digest alone
+    d_merge = bench.sources_digest("merge_kernel")
+    (tmp_path / "paper_2102_09964_amd" / "csrc" / "filter_kernel.h").write_text("kernel source, edited\n")
     assert bench.measured_traffic("filter_finish", "w", "float32", 32) is None
+    assert bench.sources_digest("merge_kernel") == d_merge
+    # a file outside the scan kernels' sources leaves their digest alone
+    d_scan = bench.sources_digest("filter_finish")
+    (tmp_path / "paper_2102_09964_amd" / "csrc" / "other.hip").write_text("unrelated\n")
+    assert bench.sources_digest("filter_finish") == d_scan
 
 
 def test_tune_cache_roundtrip(tmp_path, monkeypatch):
