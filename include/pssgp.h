@@ -67,20 +67,32 @@ enum {
 
 /* Kernel components (paper section 2: Matern covariances have an exact
  * state-space form; the RBF covariance is approximated in the spectral
- * domain by a Taylor series of the given order, section 5.1 uses order 6). */
-enum { PSSGP_MATERN12 = 1, PSSGP_MATERN32 = 2, PSSGP_MATERN52 = 3, PSSGP_RBF = 4 };
+ * domain by a Taylor series of the given order, section 5.1 uses order 6;
+ * the quasi-periodic component is the periodic covariance times a
+ * Matern-3/2, the product in the CO2 experiment of section 5, with the
+ * periodic factor in its Taylor-series state-space form). */
+enum { PSSGP_MATERN12 = 1, PSSGP_MATERN32 = 2, PSSGP_MATERN52 = 3, PSSGP_RBF = 4, PSSGP_QUASIPERIODIC = 5 };
 
 typedef struct pssgp_component {
-    int32_t kind;        /* PSSGP_MATERN12/32/52 or PSSGP_RBF */
-    int32_t order;       /* RBF: Taylor order = state size, 1..6; ignored otherwise */
-    double lengthscale;  /* > 0 */
+    int32_t kind;        /* PSSGP_MATERN12/32/52, PSSGP_RBF or PSSGP_QUASIPERIODIC */
+    int32_t order;       /* RBF: Taylor order = state size, 1..6; quasi-periodic: J,
+                            the harmonics beyond the constant (Taylor degree of the
+                            periodic factor), 1..3; ignored otherwise */
+    double lengthscale;  /* > 0; quasi-periodic: length-scale ell_p of the periodic
+                            factor sigma^2 exp(-2 sin^2(pi tau / period) / ell_p^2) */
     double variance;     /* > 0 */
+    double period;       /* quasi-periodic only: > 0 */
+    double lengthscale2; /* quasi-periodic only: > 0, length-scale of the
+                            Matern-3/2 factor */
 } pssgp_component;
 
 /* Sum of 1 or 2 components, total state size d <= 8 (e.g. Matern-3/2 +
  * RBF order 6 gives d = 8); noise_var > 0 is the measurement noise
  * variance sigma_n^2 of eq. gp-def (a per-step variance can be passed as
- * noise_k instead). */
+ * noise_k instead). Quasi-periodic models: component 0 quasi-periodic with
+ * J = order harmonics beyond the constant, component 1 Matern-3/2, state
+ * size d = 4 (J + 1) + 2 = 10, 14 or 18; they run through pssgp_predict
+ * and pssgp_loglik (the other calls return PSSGP_EUNSUPPORTED). */
 typedef struct pssgp_model {
     int32_t n_comp;
     int32_t reserved;

@@ -19,7 +19,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpssgp.so")
 
-MATERN12, MATERN32, MATERN52, RBF = 1, 2, 3, 4
+MATERN12, MATERN32, MATERN52, RBF, QUASIPERIODIC = 1, 2, 3, 4, 5
 F32, F64 = 0, 1
 STATIC_SCRATCH_BYTES = 64 << 20  # PSSGP_STATIC_SCRATCH_BYTES: the scratch behind pssgp_loglik_static
 OP_FILTER, OP_SMOOTH, OP_LOGLIK, OP_LOGLIK_GRAD, OP_DISCRETIZE, OP_PLAIN, OP_PREDICT = 1, 2, 3, 4, 5, 6, 7
@@ -37,7 +37,8 @@ class PssgpError(RuntimeError):
 
 class Component(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("order", ctypes.c_int32),
-                ("lengthscale", ctypes.c_double), ("variance", ctypes.c_double)]
+                ("lengthscale", ctypes.c_double), ("variance", ctypes.c_double),
+                ("period", ctypes.c_double), ("lengthscale2", ctypes.c_double)]
 
 
 class Model(ctypes.Structure):
@@ -122,16 +123,22 @@ def _check(rc):
 
 
 def make_model(components, noise_var) -> Model:
-    """components: list of (kind, order, lengthscale, variance)."""
+    """components: list of (kind, order, lengthscale, variance) or, for a
+    quasi-periodic component, (QUASIPERIODIC, J, ell_p, variance, period,
+    ell_matern)."""
     m = Model()
     m.n_comp = len(components)
     if not 1 <= m.n_comp <= 4:
         raise ValueError("1 to 4 components")
-    for i, (kind, order, ell, var) in enumerate(components):
+    for i, comp in enumerate(components):
+        kind, order, ell, var = comp[:4]
         m.comp[i].kind = int(kind)
         m.comp[i].order = int(order)
         m.comp[i].lengthscale = float(ell)
         m.comp[i].variance = float(var)
+        if len(comp) > 4:
+            m.comp[i].period = float(comp[4])
+            m.comp[i].lengthscale2 = float(comp[5])
     m.noise_var = float(noise_var)
     return m
 

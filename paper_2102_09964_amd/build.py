@@ -28,7 +28,8 @@ CFLAGS = ["-O3", "--offload-arch=" + ARCH, "-std=c++17", "-fPIC",
           ] + (["-DPSSGP_WITH_GRAD"] if os.path.exists(os.path.join(CSRC, "inst_grad.hip")) else [])
 
 INST_UNITS = ["inst_filter.hip", "inst_smoother.hip", "inst_grad.hip", "inst_plain.hip"]
-PLAIN_UNITS = ["model.cpp", "capi.cpp", "dispatch.hip", "batched.hip", "merge.hip", "noalloc.hip"]
+PLAIN_UNITS = ["model.cpp", "capi.cpp", "dispatch.hip", "batched.hip", "merge.hip", "noalloc.hip",
+               "qp_host.cpp", "qp.hip"]
 
 
 def layouts():

@@ -9,6 +9,7 @@
 #include "../../include/pssgp.h"
 #include "launch.h"
 #include "model.h"
+#include "qp_launch.h"
 
 namespace {
 
@@ -446,13 +447,122 @@ int run_batched(const pssgp_batch_group *groups, int ngroups, int64_t n_series, 
     return check_launch(rc, "batched launch");
 }
 
+// ------------------------------------------------------------------ quasi-periodic models (d = 10..18)
+
+constexpr int kQPDefaultChunk = 256;
+constexpr int kQPMaxChunk = 4096;
+
+struct QPPlan {
+    int chunk = kQPDefaultChunk, G = 0;
+    size_t tsize = 4;
+    size_t off_f[2] = {0, 0}, off_s[2] = {0, 0}, off_elem = 0, off_part = 0, total = 0;
+};
+
+int qp_check_opts(const pssgp_options *opts)
+{
+    if (opts && opts->chunk && (opts->chunk < 4 || opts->chunk > (uint32_t)kQPMaxChunk)) {
+        pssgp_set_error("quasi-periodic models: options.chunk (steps per 16-lane team) must be 0 or 4..%d",
+                        kQPMaxChunk);
+        return PSSGP_EINVAL;
+    }
+    return PSSGP_OK;
+}
+
+QPPlan qp_plan(int d, int64_t n, pssgp_dtype dtype, bool elems, const pssgp_options *opts)
+{
+    QPPlan p;
+    p.chunk = (opts && opts->chunk) ? (int)opts->chunk : kQPDefaultChunk;
+    p.tsize = dtype == PSSGP_F64 ? 8 : 4;
+    p.G = (int)((n + p.chunk - 1) / p.chunk);
+    const size_t G = (size_t)(p.G > 0 ? p.G : 1);
+    size_t off = ctl_bytes();
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    const size_t nf_f = (size_t)d * (3 * d + 2), nf_s = (size_t)d * (2 * d + 1);
+    p.off_f[0] = take(G * nf_f * p.tsize);
+    p.off_f[1] = take(G * nf_f * p.tsize);
+    if (elems) {
+        p.off_s[0] = take(G * nf_s * p.tsize);
+        p.off_s[1] = take(G * nf_s * p.tsize);
+        p.off_elem = take((size_t)(n > 0 ? n : 1) * nf_s * p.tsize);
+    }
+    p.off_part = take(G * sizeof(double));
+    p.total = off;
+    return p;
+}
+
+// Fused filter + smoother (f_mean, f_var non-NULL) or log-likelihood only.
+int qp_run(const pssgp_model *model, const double *t, const void *y, const uint8_t *mask, int64_t n,
+           pssgp_dtype dtype, bool elems, void *f_mean, void *f_var, double *loglik, void *ws, size_t ws_bytes,
+           const pssgp_options *opts, void *stream)
+{
+    QPDev qm;
+    int d = qp_build(model, &qm, nullptr);
+    if (d < 0) return d;
+    if (n < 0 || (dtype != PSSGP_F32 && dtype != PSSGP_F64)) {
+        pssgp_set_error("n must be >= 0 and dtype PSSGP_F32 or PSSGP_F64");
+        return PSSGP_EINVAL;
+    }
+    int rc = qp_check_opts(opts);
+    if (rc) return rc;
+    if (!loglik || (n > 0 && (!t || !y || (elems && (!f_mean || !f_var))))) {
+        pssgp_set_error("t, y, loglik (and f_mean, f_var for the smoother) must be device pointers");
+        return PSSGP_EINVAL;
+    }
+    if (n > (int64_t)INT32_MAX * 4) {
+        pssgp_set_error("quasi-periodic models: at most 2^33 steps");
+        return PSSGP_EINVAL;
+    }
+    QPPlan p = qp_plan(d, n, dtype, elems, opts);
+    if (!ws) {
+        pssgp_set_error("workspace is NULL");
+        return PSSGP_EINVAL;
+    }
+    if (ws_bytes < p.total) {
+        pssgp_set_error("workspace too small: %zu < %zu bytes", ws_bytes, p.total);
+        return PSSGP_EWORKSPACE;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    char *b = (char *)ws;
+    WsCtl *ctl = (WsCtl *)b;
+    rc = launch_ws_init(ctl, n == 0 ? loglik : nullptr, n == 0 ? 1 : 0, s);
+    if ((rc = hip_err((hipError_t)rc, "workspace init"))) return rc;
+    if (n == 0) return PSSGP_OK;
+    QPLaunch q{};
+    q.ev = opts ? opts->pass_events : nullptr;
+    q.t = t;
+    q.y = y;
+    q.mask = mask;
+    q.n = n;
+    q.chunk = p.chunk;
+    q.G = p.G;
+    q.fagg[0] = b + p.off_f[0];
+    q.fagg[1] = b + p.off_f[1];
+    q.sagg[0] = elems ? b + p.off_s[0] : nullptr;
+    q.sagg[1] = elems ? b + p.off_s[1] : nullptr;
+    q.elem = elems ? b + p.off_elem : nullptr;
+    q.partials = (double *)(b + p.off_part);
+    q.loglik = loglik;
+    q.f_mean = f_mean;
+    q.f_var = f_var;
+    q.status = &ctl->status;
+    return check_launch(qp_launch(qm, dtype == PSSGP_F64, q, s), "quasi-periodic launch");
+}
+
 }  // namespace
 
 extern "C" {
 
 int pssgp_version(void) { return 100; }
 
-int pssgp_state_dim(const pssgp_model *model) { return pssgp_build_devmodel(model, nullptr, nullptr); }
+int pssgp_state_dim(const pssgp_model *model)
+{
+    if (qp_is_model(model)) return qp_build(model, nullptr, nullptr);
+    return pssgp_build_devmodel(model, nullptr, nullptr);
+}
 
 int pssgp_state_basis(const pssgp_model *model, double *tdiag_host)
 {
@@ -460,12 +570,20 @@ int pssgp_state_basis(const pssgp_model *model, double *tdiag_host)
         pssgp_set_error("tdiag_host is NULL");
         return PSSGP_EINVAL;
     }
-    int rc = pssgp_build_devmodel(model, nullptr, tdiag_host);
+    int rc = qp_is_model(model) ? qp_build(model, nullptr, tdiag_host)
+                                : pssgp_build_devmodel(model, nullptr, tdiag_host);
     return rc < 0 ? rc : PSSGP_OK;
 }
 
 int pssgp_model_matrices(const pssgp_model *model, double *G_host, double *Pinf_host, double *H_host)
 {
+    if (qp_is_model(model)) {
+        QPDev qm;
+        int d = qp_build(model, &qm, nullptr);
+        if (d < 0) return d;
+        qp_matrices(qm, G_host, Pinf_host, H_host);
+        return PSSGP_OK;
+    }
     DevModel dm;
     int d = pssgp_build_devmodel(model, &dm, nullptr);
     if (d < 0) return d;
@@ -490,6 +608,11 @@ int pssgp_model_matrices(const pssgp_model *model, double *G_host, double *Pinf_
 size_t pssgp_workspace_bytes(const pssgp_model *model, int64_t n, pssgp_dtype dtype, int op,
                              const pssgp_options *opts)
 {
+    if (qp_is_model(model)) {
+        int d = qp_build(model, nullptr, nullptr);
+        if (d < 0 || n < 0 || (op != PSSGP_OP_PREDICT && op != PSSGP_OP_LOGLIK) || qp_check_opts(opts)) return 0;
+        return qp_plan(d, n, dtype, op == PSSGP_OP_PREDICT, opts).total;
+    }
     int d = pssgp_build_devmodel(model, nullptr, nullptr);
     if (d < 0 || n < 0 || op < PSSGP_OP_FILTER || op > PSSGP_OP_PREDICT) return 0;
     return make_plan(d, model->n_comp, n, dtype, op, opts).total;
@@ -569,6 +692,13 @@ int pssgp_loglik(const pssgp_model *model, const double *t, const void *y, const
         pssgp_set_error("loglik is NULL");
         return PSSGP_EINVAL;
     }
+    if (qp_is_model(model)) {
+        if (noise_k) {
+            pssgp_set_error("quasi-periodic models: per-step noise variances are not supported");
+            return PSSGP_EUNSUPPORTED;
+        }
+        return qp_run(model, t, y, mask, n, dtype, false, nullptr, nullptr, loglik, ws, ws_bytes, opts, stream);
+    }
     return run_filter(model, t, y, mask, noise_k, n, dtype, nullptr, nullptr, loglik, ws, ws_bytes,
                       opts, stream, PSSGP_OP_LOGLIK);
 }
@@ -617,6 +747,8 @@ int pssgp_predict(const pssgp_model *model, const double *t, const void *y, cons
                   pssgp_dtype dtype, void *f_mean, void *f_var, double *loglik, void *ws, size_t ws_bytes,
                   const pssgp_options *opts, void *stream)
 {
+    if (qp_is_model(model))
+        return qp_run(model, t, y, mask, n, dtype, true, f_mean, f_var, loglik, ws, ws_bytes, opts, stream);
     DevModel dm;
     int b0, b1;
     int rc = prepare(model, n, dtype, dm, b0, b1);

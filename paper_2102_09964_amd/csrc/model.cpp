@@ -349,6 +349,10 @@ int pssgp_build_devmodel(const pssgp_model *spec, DevModel *out, double *tdiag)
     int d = 0;
     for (int c = 0; c < spec->n_comp; c++) {
         const pssgp_component &cp = spec->comp[c];
+        if (cp.kind == PSSGP_QUASIPERIODIC) {
+            pssgp_set_error("component %d: quasi-periodic models run through pssgp_predict and pssgp_loglik only", c);
+            return PSSGP_EUNSUPPORTED;
+        }
         if (cp.kind < PSSGP_MATERN12 || cp.kind > PSSGP_RBF) {
             pssgp_set_error("component %d: unknown kind %d", c, cp.kind);
             return PSSGP_EINVAL;
