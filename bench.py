@@ -359,6 +359,16 @@ def path_roofline(m, workload=None, dtype=None):
     algorithmic bytes and its measured HBM traffic."""
     bps = path_bytes_per_step(m["d"], m["tsize"])
     gbs = bps * m["n"] / (m["ms_per_step"] / 1e3) / 1e9
+    if m.get("team_path"):
+        # quasi-periodic models (16-lane teams): the pass model of the
+        # per-lane kernels does not apply; the dominant pass by time
+        dom = max(m["pass_ms"], key=lambda q: m["pass_ms"][q])
+        valu = measured_valu(dom, workload, dtype, m["chunk"]) if workload else None
+        kern = {"name": dom, "ms": round(m["pass_ms"][dom], 4), "valu_flops_per_launch": valu["flops"] if valu else None}
+        return {"bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(gbs / HBM_PEAK_GBS, 5), "traffic": None,
+                "scope": "whole path per step (fused filter + smoother call)", "bytes_per_step": bps,
+                "steps_per_s_at_peak": round(HBM_PEAK_GBS * 1e9 / bps, 1), "dominant_kernel": kern}
     k = roofline_of(m, workload, dtype)
     valu = measured_valu(k["kernel"], workload, dtype, m["chunk"]) if workload else None
     kern = {"name": k["kernel"], "ms": k["kernel_ms"],
@@ -697,16 +707,17 @@ PAPER_CONTEXT = {
 }
 
 
-def tuned_chunk(w, dtype):
+def tuned_chunk(w, dtype, candidates=None):
     """The autotuner's chunk for a single-series workload (cached per layout,
     precision and size bucket)."""
     import torch
     import paper_2102_09964_amd as P
     from paper_2102_09964_amd import tune
     model = P.make_model(w["model"]["components"], w["model"]["noise_var"])
+    kw = {"candidates": candidates} if candidates else {}
     chunk, _ = tune.tune_chunk(model, torch.as_tensor(w["t"], dtype=torch.float64, device="cuda"),
                                torch.as_tensor(np.nan_to_num(w["y"]), dtype=getattr(torch, dtype), device="cuda"),
-                               torch.as_tensor(w["mask"], dtype=torch.uint8, device="cuda"), dtype=dtype)
+                               torch.as_tensor(w["mask"], dtype=torch.uint8, device="cuda"), dtype=dtype, **kw)
     return chunk
 
 
@@ -731,6 +742,21 @@ SWEEP_MODELS = {
     6: [(4, 6, 1.0, 1.0)],                      # RBF Taylor order 6
     8: [(2, 0, 2.0, 0.5), (4, 6, 0.5, 0.5)],    # Matern-3/2 + RBF-6
 }
+
+
+def measure_qp(steps, J, dtype):
+    """Quasi-periodic model of state size 4 (J + 1) + 2 (periodic x
+    Matern-3/2 + Matern-3/2, the paper's CO2 composite) on the co2_like
+    workload, N = 2^20: the fused filter + smoother of the 16-lane team path
+    at its tuned chunk."""
+    import workloads
+    w = workloads.co2_like(n=1 << 20, J=J)
+    chunk = tuned_chunk(w, dtype, candidates=(64, 128, 256, 512))
+    mm = measure(w, dtype, steps, 2, chunk)
+    mm["team_path"] = True
+    c = summary("co2_like_d%d" % mm["d"], dtype, mm)
+    print("qp d=%d %s: %.3g steps/s" % (mm["d"], dtype, c["steps_per_s"]), file=sys.stderr, flush=True)
+    return c
 
 
 def d_sweep(steps, headline=None):
@@ -810,6 +836,8 @@ def main():
                     help="only elementwise kernels of known flops (calibration of the VALU FLOPS counters)")
     ap.add_argument("--grad-only", action="store_true",
                     help="only the log-likelihood + gradient workload (one JSON line)")
+    ap.add_argument("--qp-only", action="store_true",
+                    help="only the quasi-periodic models (d = 10, 14, 18, N = 2^20), one JSON line each")
     ap.add_argument("--merge-only", action="store_true",
                     help="only the merge of test times into the training grid (one JSON line)")
     args = ap.parse_args()
@@ -821,6 +849,11 @@ def main():
         return
     if args.grad_only:
         print(json.dumps(measure_grad(args.steps, args.warmup, args.chunk, cpu=False)), flush=True)
+        return
+    if args.qp_only:
+        for J in (1, 2, 3):
+            for dt in ("float32", "float64"):
+                print(json.dumps(measure_qp(args.steps, J, dt)), flush=True)
         return
     if args.merge_only:
         print(json.dumps(measure_merge(args.steps, args.warmup)), flush=True)
@@ -862,6 +895,9 @@ def main():
                 mb["cpu_baseline"] = cpu_baseline_batched()
             also.append(mb)
         also.append(measure_grad(max(3, args.steps // 2), 2, cpu=not args.no_cpu_baseline))
+        for J in (1, 2, 3):
+            for dt in ("float32", "float64"):
+                also.append(measure_qp(3, J, dt))
         also.append(measure_merge(max(3, args.steps // 2), 2))
         also.append(measure_learning())
     out = {

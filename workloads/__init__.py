@@ -27,7 +27,12 @@ missing measurements on the merged time grid. Sizes and distributions:
   noise 0.01, n (2^20) times as in ``matern52_exp``, two-tone signal,
   10% missing.
 
-Kernel kinds: 1 = Matern-1/2, 2 = Matern-3/2, 3 = Matern-5/2, 4 = RBF Taylor.
+* ``co2_like``: seasonal series for the quasi-periodic models (state sizes
+  10, 14, 18), see the function.
+
+Kernel kinds: 1 = Matern-1/2, 2 = Matern-3/2, 3 = Matern-5/2, 4 = RBF Taylor,
+5 = quasi-periodic (periodic x Matern-3/2, components
+(5, J, ell_p, var, period, ell_matern)).
 A model is ``{"components": [(kind, order, ell, var), ...], "noise_var": s}``.
 """
 from __future__ import annotations
@@ -36,7 +41,7 @@ import numpy as np
 
 SEED0 = 20210219
 
-MATERN12, MATERN32, MATERN52, RBF = 1, 2, 3, 4
+MATERN12, MATERN32, MATERN52, RBF, QUASIPERIODIC = 1, 2, 3, 4, 5
 
 
 def _rng(k: int, extra: int = 0) -> np.random.Generator:
@@ -132,6 +137,22 @@ def sum_m32_rbf6(n: int = 1 << 20, missing: float = 0.1, seed_extra: int = 0):
     mask = (rng.uniform(size=n) >= missing).astype(np.uint8)
     model = {"components": [(MATERN32, 0, 2.0, 0.5), (RBF, 6, 0.5, 0.5)], "noise_var": 0.01}
     return {"name": "sum_m32_rbf6", "t": t, "y": y, "mask": mask, "model": model}
+
+
+def co2_like(n: int = 1 << 20, J: int = 3, missing: float = 0.1, seed_extra: int = 0):
+    """Seasonal data for the quasi-periodic models of the paper's CO2
+    experiment (its dataset is not used): n times on [0, 1000] with
+    exponential gaps, a yearly cycle with a second harmonic and a slowly
+    varying level, y = sin(2 pi t) + 0.5 sin(4 pi t + 1) + 0.5 sin(t / 30) +
+    N(0, 0.1^2), 10% missing. Model: quasi-periodic (J + 1 harmonics,
+    ell_p 1, var 1, period 1, Matern-3/2 factor ell 50) + Matern-3/2
+    (ell 20, var 0.3), noise 0.01; state size 4 (J + 1) + 2."""
+    rng = _rng(8, seed_extra)
+    t = _exp_gap_times(rng, n, 1000.0)
+    y = np.sin(2 * np.pi * t) + 0.5 * np.sin(4 * np.pi * t + 1.0) + 0.5 * np.sin(t / 30.0) + rng.normal(0.0, 0.1, n)
+    mask = (rng.uniform(size=n) >= missing).astype(np.uint8)
+    model = {"components": [(QUASIPERIODIC, J, 1.0, 1.0, 1.0, 50.0), (MATERN32, 0, 20.0, 0.3)], "noise_var": 0.01}
+    return {"name": "co2_like_J%d" % J, "t": t, "y": y, "mask": mask, "model": model}
 
 
 def random_series(n: int, components, noise_var: float, missing: float = 0.2, span: float = 10.0,
