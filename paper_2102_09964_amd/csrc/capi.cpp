@@ -28,6 +28,7 @@ struct Plan {
     size_t off_x = 0, off_xraw = 0;  // plain baseline element arrays
     size_t off_gagg = 0, off_gcarry = 0;  // carry pass group scratch
     size_t off_hand = 0;             // predict: filter-to-smoother handover
+    size_t off_fagg2 = 0;            // second buffer of filter tile aggregates (team carry)
     size_t off_slane = 0;            // predict: per-lane smoother aggregates
     size_t total = 0;
 };
@@ -90,6 +91,7 @@ Plan make_plan(int d, int ncomp, int64_t n, pssgp_dtype dtype, int op, const pss
         // elements of every step, written by the filter in the tile layout
         p.off_incl = take(nt * filter_incl_elems(d) * p.tsize);
         p.off_agg = take(nt * filter_agg_elems(d) * p.tsize);
+        p.off_fagg2 = take(nt * filter_agg_elems(d) * p.tsize);
         p.off_lane = take(nt * 64 * filter_agg_elems(d) * p.tsize);
         p.off_part = take(nt * sizeof(double) * n_params(ncomp));
         p.off_hand = take(nt * 64 * (size_t)p.chunk * (d * d + d + d * (d + 1) / 2) * p.tsize);
@@ -104,6 +106,7 @@ Plan make_plan(int d, int ncomp, int64_t n, pssgp_dtype dtype, int op, const pss
     } else {
         p.off_incl = take(nt * filter_incl_elems(d) * p.tsize);
         p.off_agg = take(nt * filter_agg_elems(d) * p.tsize);
+        p.off_fagg2 = take(nt * filter_agg_elems(d) * p.tsize);
         p.off_lane = take(nt * 64 * filter_agg_elems(d) * p.tsize);
     }
     p.off_part = take(nt * sizeof(double) * n_params(ncomp));
@@ -198,6 +201,7 @@ ScanWs scan_ws(void *ws, const Plan &p, bool second = false)
     s.lanep = b + (second ? p.off_lane2 : p.off_lane);
     s.partials = (double *)(b + (second ? p.off_part2 : p.off_part));
     s.cst = (double *)(b + p.off_cst);
+    s.agg2 = (!second && p.off_fagg2) ? b + p.off_fagg2 : nullptr;
     return s;
 }
 
@@ -426,6 +430,7 @@ int run_batched(const pssgp_batch_group *groups, int ngroups, int64_t n_series, 
     a.ws.lanep = b + bp.off_lane;
     a.ws.partials = (double *)(b + bp.off_part);
     a.ws.cst = (double *)(b + bp.off_cst);
+    a.ws.agg2 = nullptr;
     if (op == PSSGP_OP_PREDICT) {
         a.m = b + bp.off_hand;
         a.slane = b + bp.off_slane;

@@ -27,6 +27,7 @@
 #include "launch.h"
 #include "smoother_ops.h"
 #include "tile_scan.h"
+#include "tile_scan_team.h"
 
 // Finish-pass outputs: filter moments in the [entry][n] layout, per-step
 // records for the adjoint (RecLayout, tile layout), smoother elements in the
@@ -589,14 +590,12 @@ int launch_filter_t(const DevModel &mdl, const FilterLaunch &a, hipStream_t s)
         // prefixes and lane starts were conditioned in FP64: noise-variance
         // derivative 8.6e-5 vs 7.0e-5 at d = 8, 2^20 steps, at 2.5x the carry
         // time.)
-        rc = launch_tile_scan<FilterScanOps<LY::D, T, CT>>(a.ws.aggp, 0, a.ntiles, false, a.ws.inclp, a.ws.gagg,
-                                                            a.ws.gcarry, s);
+        rc = launch_filter_carry<LY::D, T, CT>(a.ws, 0, a.ntiles, s);
         if (rc) return rc;
         pass_event(a.ev, 2, s);
         hipLaunchKernelGGL((filter_finish_kernel<LY, T, double, F_RECS>), grid, block, 0, s, p, mdl);
     } else {
-        rc = launch_tile_scan<FilterScanOps<LY::D, T, CT>>(a.ws.aggp, 0, a.ntiles, false, a.ws.inclp, a.ws.gagg,
-                                                            a.ws.gcarry, s);
+        rc = launch_filter_carry<LY::D, T, CT>(a.ws, 0, a.ntiles, s);
         if (rc) return rc;
         pass_event(a.ev, 2, s);
         // lane-start moments (the lane's exclusive prefix applied to the

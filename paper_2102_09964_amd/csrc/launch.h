@@ -32,6 +32,7 @@ struct ScanWs {
     void *lanep;     // per-lane inclusive aggregates within the tile
     double *partials;  // per-tile partial sums (loglik, gradient)
     double *cst;       // model constants of the FP32 transition (8 KB per model)
+    void *agg2;        // nullable: second buffer of tile aggregates (team carry of the filter)
 };
 
 struct FilterLaunch {
