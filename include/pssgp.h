@@ -384,6 +384,30 @@ int pssgp_merge_times(const double *t_train, const void *y_train, const uint8_t 
  * synchronising stream); bits: PSSGP_STATUS_*. */
 int pssgp_status(void *ws, void *stream, uint32_t *bits_host);
 
+/*
+ * Plans (HIP graphs). pssgp_plan_create records one call, pssgp_predict
+ * (op PSSGP_OP_PREDICT) or pssgp_loglik (op PSSGP_OP_LOGLIK, no per-step
+ * noise), with the given arguments into a HIP graph on a stream of its own
+ * (validation, planning and the kernel launches happen once, at creation);
+ * pssgp_plan_launch replays it on `stream`, stream-ordered, with no other
+ * host work; pssgp_plan_destroy releases the graph. The device buffers
+ * (t, y, mask, outputs, ws) are bound at creation: a replay reads whatever
+ * they hold when it runs (refill them between replays to process new data
+ * of the same size) and every replay clears what must start at zero with a
+ * kernel of its own (no memset node). Replays of one plan, or of plans that
+ * share a workspace, must not overlap. options.pass_events must be NULL.
+ * Errors: argument errors as the direct call (nothing is recorded);
+ * PSSGP_EDEVICE for a HIP failure during capture or launch. The plan owns
+ * its graph; the caller owns every buffer. Creation allocates host memory
+ * and graph objects; launches allocate nothing.
+ */
+typedef struct pssgp_plan pssgp_plan;
+int pssgp_plan_create(pssgp_plan **out, int op, const pssgp_model *model, const double *t, const void *y,
+                      const uint8_t *mask, int64_t n, pssgp_dtype dtype, void *f_mean, void *f_var,
+                      double *loglik, void *ws, size_t ws_bytes, const pssgp_options *opts);
+int pssgp_plan_launch(pssgp_plan *plan, void *stream);
+int pssgp_plan_destroy(pssgp_plan *plan);
+
 /* Size of the device scratch array behind pssgp_loglik_static (per device). */
 #define PSSGP_STATIC_SCRATCH_BYTES (64u << 20)
 

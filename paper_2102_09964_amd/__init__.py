@@ -94,6 +94,10 @@ SIGNATURES = [
     ("pssgp_plain_predict", ctypes.c_int, [_MP, _VP, _VP, _VP, _I64, _VP, _VP, _VP, _VP, _VP, _VP, _SZ, _VP]),
     ("pssgp_merge_times", ctypes.c_int, [_VP, _VP, _VP, _I64, _VP, _I64, ctypes.c_int, _VP, _VP, _VP, _VP, _VP]),
     ("pssgp_loglik_static", ctypes.c_int, [_MP, _VP, _VP, _VP, _VP, _I64, ctypes.c_int, _VP, _OP, _VP]),
+    ("pssgp_plan_create", ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, _MP, _VP, _VP, _VP, _I64,
+                                         ctypes.c_int, _VP, _VP, _VP, _VP, _SZ, _OP]),
+    ("pssgp_plan_launch", ctypes.c_int, [_VP, _VP]),
+    ("pssgp_plan_destroy", ctypes.c_int, [_VP]),
 ]
 
 
@@ -525,6 +529,46 @@ def loglik_autograd(theta, kinds_orders, t, y, mask=None, dtype="float32"):
     if _autograd_cls is None:
         _autograd_cls = _make_autograd()
     return _autograd_cls.apply(theta, kinds_orders, t, y, mask, dtype)
+
+
+class Plan:
+    """pssgp_plan: one pssgp_predict (or pssgp_loglik) call recorded into a
+    HIP graph by the library, with device buffers bound at creation;
+    ``launch()`` replays it on the current stream. Refill ``t``, ``y``,
+    ``mask`` in place between launches to process new data of the same
+    size."""
+
+    def __init__(self, model, n, dtype="float32", options=None, loglik_only=False, device="cuda"):
+        _require_gpu()
+        torch = _torch()
+        self.model = _as_model(model)
+        self.code, self.tdt = _dt(dtype)
+        self.n = int(n)
+        op = OP_LOGLIK if loglik_only else OP_PREDICT
+        self.ws = alloc_workspace(self.model, self.n, self.code, op, options, device)
+        self.t = torch.zeros(self.n, dtype=torch.float64, device=device)
+        self.y = torch.zeros(self.n, dtype=self.tdt, device=device)
+        self.mask = torch.ones(self.n, dtype=torch.uint8, device=device)
+        self.f_mean = None if loglik_only else torch.empty(self.n, dtype=self.tdt, device=device)
+        self.f_var = None if loglik_only else torch.empty(self.n, dtype=self.tdt, device=device)
+        self.loglik = torch.empty(1, dtype=torch.float64, device=device)
+        torch.cuda.synchronize()
+        h = ctypes.c_void_p()
+        _check(lib().pssgp_plan_create(ctypes.byref(h), op, ctypes.byref(self.model), _p(self.t), _p(self.y),
+                                       _p(self.mask), self.n, self.code, _p(self.f_mean), _p(self.f_var),
+                                       _p(self.loglik), _p(self.ws), self.ws.numel(),
+                                       ctypes.byref(options) if options is not None else None))
+        self.handle = h
+
+    def launch(self):
+        _check(lib().pssgp_plan_launch(self.handle, _stream()))
+        return self.f_mean, self.f_var, self.loglik
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            lib().pssgp_plan_destroy(h)
+            self.handle = None
 
 
 class Pipeline:

@@ -29,7 +29,7 @@ CFLAGS = ["-O3", "--offload-arch=" + ARCH, "-std=c++17", "-fPIC",
 
 INST_UNITS = ["inst_filter.hip", "inst_smoother.hip", "inst_grad.hip", "inst_plain.hip"]
 PLAIN_UNITS = ["model.cpp", "capi.cpp", "dispatch.hip", "batched.hip", "merge.hip", "noalloc.hip",
-               "qp_host.cpp", "qp.hip"]
+               "qp_host.cpp", "qp.hip", "plan.cpp"]
 
 
 def layouts():

@@ -182,6 +182,31 @@ def test_static_loglik_rejects_oversized_inputs_without_device():
     assert L.pssgp_loglik_static(mp, fake, fake, None, None, 100, P.F32, fake, ctypes.byref(o), None) == -1
 
 
+def test_plan_argument_errors_need_no_device():
+    """pssgp_plan_create refuses a bad op, pass events and a missing output
+    pointer before it records anything."""
+    L = P.lib()
+    m = P.make_model([(MATERN32, 0, 0.5, 1.0)], 0.01)
+    fake = ctypes.c_void_p(0x1000)
+    h = ctypes.c_void_p()
+    n = 100
+    need = P.workspace_bytes(m, n, P.F32, P.OP_PREDICT)
+    assert L.pssgp_plan_create(None, P.OP_PREDICT, ctypes.byref(m), fake, fake, None, n, P.F32, fake, fake, fake,
+                               fake, need, None) == -1
+    assert L.pssgp_plan_create(ctypes.byref(h), P.OP_FILTER, ctypes.byref(m), fake, fake, None, n, P.F32, fake,
+                               fake, fake, fake, need, None) == -1
+    o = P.make_options()
+    o.pass_events[0] = 0x1234
+    assert L.pssgp_plan_create(ctypes.byref(h), P.OP_PREDICT, ctypes.byref(m), fake, fake, None, n, P.F32, fake,
+                               fake, fake, fake, need, ctypes.byref(o)) == -1
+    assert b"pass_events" in L.pssgp_last_error()
+    # workspace too small: the direct call's check, no capture
+    assert L.pssgp_plan_create(ctypes.byref(h), P.OP_PREDICT, ctypes.byref(m), fake, fake, None, n, P.F32, fake,
+                               fake, fake, fake, need - 1, None) == -3
+    assert h.value is None
+    assert L.pssgp_plan_destroy(None) == 0
+
+
 def test_merge_argument_errors_need_no_device():
     """pssgp_merge_times validates sizes, dtype and pointers on the host."""
     L = P.lib()
