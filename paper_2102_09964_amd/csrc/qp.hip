@@ -351,11 +351,10 @@ int qp_launch_t(const QPDev &m, const QPLaunch &q, hipStream_t s)
 
 int qp_launch(const QPDev &m, bool f64, const QPLaunch &q, hipStream_t s)
 {
-    if (m.A != 2) return -1;
     switch (m.J) {
-    case 1: return f64 ? qp_launch_t<QPL<1, 2>, double>(m, q, s) : qp_launch_t<QPL<1, 2>, float>(m, q, s);
-    case 2: return f64 ? qp_launch_t<QPL<2, 2>, double>(m, q, s) : qp_launch_t<QPL<2, 2>, float>(m, q, s);
-    case 3: return f64 ? qp_launch_t<QPL<3, 2>, double>(m, q, s) : qp_launch_t<QPL<3, 2>, float>(m, q, s);
+    case 1: return f64 ? qp_launch_t<QPL<1>, double>(m, q, s) : qp_launch_t<QPL<1>, float>(m, q, s);
+    case 2: return f64 ? qp_launch_t<QPL<2>, double>(m, q, s) : qp_launch_t<QPL<2>, float>(m, q, s);
+    case 3: return f64 ? qp_launch_t<QPL<3>, double>(m, q, s) : qp_launch_t<QPL<3>, float>(m, q, s);
     default: return -1;
     }
 }

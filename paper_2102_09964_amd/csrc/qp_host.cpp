@@ -16,6 +16,12 @@
 // states are (f, f' / lam), lam = sqrt(3) / ell, and harmonic j's states are
 // divided by sigma q_j; the observation row then carries sigma q_j at the
 // first state of harmonic j and sigma_a at the additive Matern's first state.
+//
+// The model's state (what pssgp_model_matrices and pssgp_state_basis
+// describe) is harmonic j at 4 j .. 4 j + 3 (state 2 c + r) and the additive
+// Matern at 4 (J + 1), 4 (J + 1) + 1. The kernels propagate the 4 (J + 1)
+// coupled or observed ones only (qp_team.h): harmonic 0's c = 1 pair is
+// neither observed nor coupled to the rest.
 #include <cmath>
 #include <cstring>
 
@@ -63,7 +69,6 @@ int qp_build(const pssgp_model *spec, QPDev *out, double *tdiag)
     QPDev m;
     std::memset(&m, 0, sizeof(m));
     m.J = J;
-    m.A = 2;
     m.d = d;
     m.w0 = 2.0 * M_PI / p.period;
     m.lam_m = std::sqrt(3.0) / p.lengthscale2;
@@ -78,20 +83,23 @@ int qp_build(const pssgp_model *spec, QPDev *out, double *tdiag)
         double acc = 0.0;
         for (int mm = 0; j + 2 * mm <= J; mm++) acc += std::pow(0.5 * ia, j + 2 * mm) / (fact[mm] * fact[j + mm]);
         const double q2 = (j == 0 ? 1.0 : 2.0) * std::exp(-ia) * acc;
-        const double scale = sd * std::sqrt(q2);
-        m.h[4 * j] = scale;
+        m.hq[j] = sd * std::sqrt(q2);
         if (tdiag)
             for (int c = 0; c < 2; c++) {
-                tdiag[4 * j + 2 * c] = scale;
-                tdiag[4 * j + 2 * c + 1] = scale * m.lam_m;
+                tdiag[4 * j + 2 * c] = m.hq[j];
+                tdiag[4 * j + 2 * c + 1] = m.hq[j] * m.lam_m;
             }
     }
-    m.h[4 * (J + 1)] = sa;
+    m.ha = sa;
     if (tdiag) {
         tdiag[4 * (J + 1)] = sa;
         tdiag[4 * (J + 1) + 1] = sa * m.lam_a;
     }
-    for (int i = 0; i < d; i++) m.u[i] = (i == 0) ? 0.0 : m.h[i] / m.h[0];
+    // propagated states: observed rows 0 (harmonic 0), 2 (additive), 4 j
+    m.h[0] = m.hq[0];
+    m.h[2] = sa;
+    for (int j = 1; j <= J; j++) m.h[4 * j] = m.hq[j];
+    for (int i = 0; i < 4 * (J + 1); i++) m.u[i] = (i == 0) ? 0.0 : m.h[i] / m.h[0];
     if (out) *out = m;
     return d;
 }
@@ -100,7 +108,7 @@ void qp_matrices(const QPDev &m, double *G, double *Pinf, double *H)
 {
     const int d = m.d, hb = 4 * (m.J + 1);
     for (int i = 0; i < d; i++) {
-        if (H) H[i] = m.h[i];
+        if (H) H[i] = (i == hb) ? m.ha : ((i & 3) == 0 && i < hb) ? m.hq[i >> 2] : 0.0;
         for (int j = 0; j < d; j++) {
             if (Pinf) Pinf[i * d + j] = (i == j) ? 1.0 : 0.0;
             if (G) G[i * d + j] = 0.0;

@@ -61,15 +61,15 @@ template <class L, typename U>
 __device__ __forceinline__ void qp_right_Ft_plus_Q(const QPStep<L::J> &st, const U (&Y)[L::RPL][L::D],
                                                    U (&Z)[L::RPL][L::D])
 {
-    constexpr int HB = 4 * (L::J + 1);
     U out[L::RPL][L::D];
 #pragma unroll
     for (int s = 0; s < L::RPL; s++) {
         const int row = team_lane() + QP_TEAM * s;
 #pragma unroll
         for (int k = 0; k < L::D; k++) {
-            const int b0 = k < HB ? (k & ~3) : HB;
-            const int bn = k < HB ? 4 : L::A;
+            // column k's block: 2 x 2 in group 0, 4 x 4 for the harmonics
+            const int b0 = k < 4 ? (k & ~1) : (k & ~3);
+            const int bn = k < 4 ? 2 : 4;
             U acc = Y[s][k] + U(qp_q_at<L>(st, row, k));
 #pragma unroll
             for (int l = 0; l < 4; l++)
@@ -215,7 +215,7 @@ __device__ __forceinline__ void qp_symmetrize(T (&X)[L::RPL][L::D], T *lds)
 }
 
 // h-weighted sum of the observed rows of X: (X^T h) = X h for symmetric X,
-// uniform on the team (h is nonzero only at the first state of each block)
+// uniform on the team (h is nonzero only at the observed rows)
 template <class L, typename T>
 __device__ __forceinline__ void qp_obs_combo(const QPDev &m, const T (&X)[L::RPL][L::D], double (&c)[L::D])
 {

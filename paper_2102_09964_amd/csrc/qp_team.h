@@ -1,25 +1,30 @@
-// Large state sizes (d = 10..18): the quasi-periodic models of the paper's
-// CO2 experiment (section 5), a periodic kernel times a Matern-3/2 kernel,
-// optionally plus a second Matern-3/2. Their per-lane matrices no longer fit
+// Large state sizes (n_x = 10, 14, 18): the quasi-periodic models of the
+// paper's CO2 experiment (section 5), a periodic kernel times a Matern-3/2
+// kernel plus a second Matern-3/2. Their per-lane matrices no longer fit
 // one lane's registers, so every chunk of steps is processed by a team of
 // 16 lanes (one DPP row of a wave) that owns the rows of each matrix: row r
 // lives on team lane r % 16, in register slot r / 16. Four teams share a
 // wave and run independent chunks.
 //
-// Model in the library's coordinates (every state has unit stationary
-// variance, P_inf = I):
-//   harmonic j = 0..J of the periodic factor, oscillator coordinate c,
-//   Matern coordinate r (f, f' / lam_m) at state 4 j + 2 c + r, scaled by
-//   sigma q_j (q_j^2: cosine-series coefficients of the periodic kernel's
-//   Taylor form); the additive Matern-3/2 (f, f' / lam_a) / sigma_a at
-//   states 4 (J + 1), 4 (J + 1) + 1.
-// The transition is block diagonal: F = (R_j (x) F_m) per harmonic, with the
-// rotation R_j by the angle j w0 dt and the Matern-3/2 transition
-// F_m = exp(-x) [[1 + x, x], [-x, 1 - x]], x = lam dt, and F_a for the
-// additive block; Q = I - F F^T = I_2 (x) (I - F_m F_m^T) per harmonic.
-// Left products with F mix the rows of one 4-row block, which sit on the
-// 4 lanes of one DPP quad; right products with F^T mix columns inside a
-// lane.
+// Model state (n_x = 4 (J + 1) + 2): harmonic j = 0..J of the periodic
+// factor is an oscillator (coordinates c = 0, 1) times the Matern-3/2
+// (coordinates r = f, f'), plus the additive Matern-3/2 (2 states). The
+// constant harmonic j = 0 does not rotate, so its c = 1 pair is a Matern-3/2
+// process that is neither observed nor coupled to any other state: its
+// posterior is its prior and it is not propagated. The kernels carry
+// D = 4 (J + 1) states (8, 12, 16: one row per team lane), each with unit
+// stationary variance (P_inf = I):
+//   rows 0, 1   harmonic 0, c = 0: (f, f' / lam_m) / (sigma q_0)
+//   rows 2, 3   the additive Matern-3/2: (f, f' / lam_a) / sigma_a
+//   rows 4 j .. 4 j + 3 (j >= 1): harmonic j, state 2 c + r, / (sigma q_j)
+// (q_j^2: cosine-series coefficients of the periodic kernel's Taylor form).
+// The transition is block diagonal: 2 x 2 blocks F_m, F_a in rows 0..3 and
+// R_j (x) F_m per harmonic j >= 1 (R_j the rotation by j w0 dt,
+// F_m = exp(-x) [[1 + x, x], [-x, 1 - x]], x = lam dt); Q = I - F F^T is
+// block diagonal in 2 x 2 blocks. Left products with F mix the rows of one
+// 4-row group, which sit on the 4 lanes of one DPP quad; right products
+// with F^T mix columns inside a lane. The observed states are rows 0, 2
+// and 4 j.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -30,26 +35,28 @@
 #define QP_MAXD 18
 #define QP_TEAM 16
 
-// Device constants of a quasi-periodic (+ Matern-3/2) model.
+// Device constants of a quasi-periodic + Matern-3/2 model.
 struct QPDev {
-    int32_t J, A, d, pad;
-    double w0;            // 2 pi / period
-    double lam_m;         // sqrt(3) / ell of the product's Matern-3/2
-    double lam_a;         // sqrt(3) / ell of the additive Matern-3/2
-    double R;             // measurement noise variance
-    double h[QP_MAXD];    // observation row (nonzero at the observed states)
-    double u[QP_MAXD];    // smoother shear S = I + e_0 u^T (u = h / h_0 - e_0)
+    int32_t J, d, pad[2];        // d: the model's state size n_x = 4 (J + 1) + 2
+    double w0;                   // 2 pi / period
+    double lam_m;                // sqrt(3) / ell of the product's Matern-3/2
+    double lam_a;                // sqrt(3) / ell of the additive Matern-3/2
+    double R;                    // measurement noise variance
+    double hq[QP_MAXJ + 1];      // sigma q_j: scale of harmonic j
+    double ha;                   // sigma_a: scale of the additive Matern
+    double h[QP_MAXD];           // observation row of the propagated states (rows 0, 2, 4 j)
+    double u[QP_MAXD];           // smoother shear S = I + e_0 u^T (u = h / h_0 - e_0)
 };
 
-template <int J_, int A_>
+template <int J_>
 struct QPL {
     static constexpr int J = J_;
-    static constexpr int A = A_;                 // additive block size (0 or 2)
-    static constexpr int D = 4 * (J + 1) + A;
+    static constexpr int D = 4 * (J + 1);        // propagated states
     static constexpr int RPL = (D + QP_TEAM - 1) / QP_TEAM;
-    static constexpr int NO = J + 1 + (A > 0 ? 1 : 0);  // observed states
-    // index of the q-th observed state (first state of each block)
-    __host__ __device__ static constexpr int obs_row(int q) { return 4 * q; }
+    static constexpr int NO = J + 2;             // observed states
+    // index of the q-th observed state: rows 0 (harmonic 0), 2 (additive),
+    // 4 j (harmonic j >= 1)
+    __host__ __device__ static constexpr int obs_row(int q) { return q == 0 ? 0 : (q == 1 ? 2 : 4 * (q - 1)); }
 };
 
 __device__ __forceinline__ int team_lane() { return (int)(threadIdx.x & (QP_TEAM - 1)); }
@@ -183,13 +190,12 @@ __device__ __forceinline__ double qp_dl_harm(const QPStep<J> &st, double cmj, do
     return (c == 0 ? -snj : snj) * fv;
 }
 
-// (F - I)[row][quad base + q] for this lane's row (runtime; the row's 4-row
-// block sits on its quad), q = 0..3; zero for padding rows. Every value is
-// selected, never indexed at run time, so that nothing leaves registers.
+// (F - I)[row][quad base + q] for this lane's row (runtime; the row's
+// 4-row group sits on its quad), q = 0..3; zero for padding rows. Every value
+// is selected, never indexed at run time, so that nothing leaves registers.
 template <class L>
 __device__ __forceinline__ void qp_dl_row(const QPStep<L::J> &st, int row, double (&dl)[4])
 {
-    constexpr int HB = 4 * (L::J + 1);
     const int jr = row >> 2, ir = row & 3;
     double cmj = st.cm[0], snj = st.sn[0];
 #pragma unroll
@@ -199,17 +205,21 @@ __device__ __forceinline__ void qp_dl_row(const QPStep<L::J> &st, int row, doubl
     }
 #pragma unroll
     for (int q = 0; q < 4; q++) {
-        // the four possible rows of a harmonic block, selected by ir
+        // harmonic j >= 1: the four rows of R_j (x) F_m, selected by ir
         double vh = 0.0;
 #pragma unroll
         for (int i = 0; i < 4; i++) vh = (ir == i) ? qp_dl_harm<L::J>(st, cmj, snj, i, q) : vh;
-        double va = 0.0;
-        if constexpr (L::A > 0) {
-            if (q < 2) va = (ir == 0) ? st.fa[q] : ((ir == 1) ? st.fa[2 + q] : 0.0);
+        // group 0: the 2 x 2 blocks F_m (rows 0, 1) and F_a (rows 2, 3)
+        double v0 = 0.0;
+        if ((q >> 1) == (ir >> 1)) {
+            const int a = ir & 1, b = q & 1;
+            const double vm = a == 0 ? (b == 0 ? st.fm[0] : st.fm[1]) : (b == 0 ? st.fm[2] : st.fm[3]);
+            const double va = a == 0 ? (b == 0 ? st.fa[0] : st.fa[1]) : (b == 0 ? st.fa[2] : st.fa[3]);
+            v0 = (ir < 2) ? vm : va;
         }
-        double v = (row < HB) ? vh : ((row < L::D) ? va : 0.0);
-        if (st.first) v = (row < L::D && q == ir) ? -1.0 : 0.0;
-        dl[q] = st.pad ? 0.0 : v;
+        double v = (jr == 0) ? v0 : vh;
+        if (st.first) v = (q == ir) ? -1.0 : 0.0;
+        dl[q] = (st.pad || row >= L::D) ? 0.0 : v;
     }
 }
 
@@ -218,25 +228,24 @@ __device__ __forceinline__ void qp_dl_row(const QPStep<L::J> &st, int row, doubl
 template <class L>
 __device__ __forceinline__ double qp_dl_at(const QPStep<L::J> &st, int k, int l)
 {
-    constexpr int HB = 4 * (L::J + 1);
     double v;
-    if (k < HB) {
-        if ((k >> 2) != (l >> 2) || l >= HB) return 0.0;
+    if (k < 4) {
+        if ((k >> 1) != (l >> 1) || l >= 4) return 0.0;
+        v = (k < 2) ? st.fm[2 * (k & 1) + (l & 1)] : st.fa[2 * (k & 1) + (l & 1)];
+    } else {
+        if ((k >> 2) != (l >> 2)) return 0.0;
         const int j = k >> 2;
         v = qp_dl_harm<L::J>(st, st.cm[j], st.sn[j], k & 3, l & 3);
-    } else {
-        if (l < HB || k >= L::D || l >= L::D) return 0.0;
-        v = st.fa[2 * (k - HB) + (l - HB)];
     }
     if (st.first) v = (k == l) ? -1.0 : 0.0;
     return st.pad ? 0.0 : v;
 }
 
-// Q[row][k] (runtime row, compile-time k): block diagonal in 2x2 blocks
+// Q[row][k] (runtime row, compile-time k): block diagonal in 2 x 2 blocks,
+// the additive Matern's in rows 2, 3 and the product Matern's elsewhere
 template <class L>
 __device__ __forceinline__ double qp_q_at(const QPStep<L::J> &st, int row, int k)
 {
-    constexpr int HB = 4 * (L::J + 1);
     const int a = row & 1, b = k & 1;
     double vm, va;
     if (b == 0) {
@@ -246,8 +255,7 @@ __device__ __forceinline__ double qp_q_at(const QPStep<L::J> &st, int row, int k
         vm = a == 0 ? st.qm[1] : st.qm[2];
         va = a == 0 ? st.qa[1] : st.qa[2];
     }
-    double v = (row < HB) ? vm : va;
+    double v = ((row >> 1) == 1) ? va : vm;
     if (st.first) v = (row == k) ? 1.0 : 0.0;
     return (st.pad || row >= L::D || (row >> 1) != (k >> 1)) ? 0.0 : v;
 }
-
