@@ -22,9 +22,16 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 # packed FP32 instructions are disabled for all device code (v_pk_* forms
 # are avoided on this target); the host pass warns about the unknown
-# feature, which is harmless
+# feature, which is harmless.
+# Register spills go to scratch memory, not to accumulation registers: with
+# spills to accumulation registers the FP64 adjoint fold at d = 8 (512
+# registers per lane) returned wrong chunk maps in one build of otherwise
+# unchanged source, deterministically, and correct ones with this option
+# (the kernels that reach the register limit in FP32 allocate accumulation
+# registers directly and are unaffected).
 CFLAGS = ["-O3", "--offload-arch=" + ARCH, "-std=c++17", "-fPIC",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-mllvm", "-amdgpu-spill-vgpr-to-agpr=0",
           ] + (["-DPSSGP_WITH_GRAD"] if os.path.exists(os.path.join(CSRC, "inst_grad.hip")) else [])
 
 INST_UNITS = ["inst_filter.hip", "inst_smoother.hip", "inst_grad.hip", "inst_plain.hip"]

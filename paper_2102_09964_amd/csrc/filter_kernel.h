@@ -133,10 +133,8 @@ __device__ __forceinline__ void smoother_element_from_prediction(const T (&m)[D]
     for (int i = 0; i < D; i++)
 #pragma unroll
         for (int j = 0; j <= i; j++) C[i][j] = Pp[i][j];
-    if (!cholesky<D, double>(C)) bad |= PSSGP_STATUS_CHOLESKY;
     double rd[D];  // reciprocals of the Cholesky diagonal
-#pragma unroll
-    for (int i = 0; i < D; i++) rd[i] = 1.0 / C[i][i];
+    if (!cholesky<D, double>(C, rd)) bad |= PSSGP_STATUS_CHOLESKY;
 #pragma unroll
     for (int j = 0; j < D; j++)
 #pragma unroll
@@ -400,7 +398,7 @@ __device__ __forceinline__ void filter_tile_finish(const FilterParams<T> &p, con
 #pragma unroll
         for (int i = 0; i < D; i++) S = fma((double)h[i], Ph[i], S);
         const double v = (double)yk - hm;
-        const double w = obs ? 1.0 / S : 0.0;
+        const double w = obs ? rcp64(S) : 0.0;
         // branch-free: missing steps add an exact zero
         bad |= (obs && (!(S > 0.0) || !isfinite(S))) ? PSSGP_STATUS_BAD_S : 0u;
         bad |= (obs && !isfinite(yk)) ? PSSGP_STATUS_NONFINITE : 0u;

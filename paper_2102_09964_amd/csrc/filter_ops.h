@@ -94,7 +94,7 @@ __device__ __forceinline__ void agg_fold(FAgg<D, T> &a, const T (&Dl)[D][D], con
         S = fma((double)h[i], Ch[i], S);
         hb = fma((double)h[i], (double)b1[i], hb);
     }
-    const double w = obs ? 1.0 / S : 0.0;
+    const double w = obs ? rcp64(S) : 0.0;
     const double r = obs ? ((double)y - hb) : 0.0;
     double K[D];
 #pragma unroll

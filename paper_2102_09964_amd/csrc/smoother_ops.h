@@ -279,10 +279,8 @@ __device__ __forceinline__ void smoother_element(const DevModel &mdl, cdouble *c
             for (int q = 0; q < D; q++) acc = fma(Y[i][q], Dl[j][q], acc);
             C[i][j] = acc;
         }
-    if (!cholesky<D, double>(C)) bad |= PSSGP_STATUS_CHOLESKY;
     double rd[D];  // reciprocals of the Cholesky diagonal
-#pragma unroll
-    for (int i = 0; i < D; i++) rd[i] = 1.0 / C[i][i];
+    if (!cholesky<D, double>(C, rd)) bad |= PSSGP_STATUS_CHOLESKY;
     // Y <- C^-1 Y (forward substitution, column by column)
 #pragma unroll
     for (int j = 0; j < D; j++)
