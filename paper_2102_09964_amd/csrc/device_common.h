@@ -18,9 +18,11 @@
 // where it does not, so that the accumulation registers hold what would
 // otherwise spill to scratch memory, which misses in L2 and goes to HBM
 // (at d = 8 the FP32 filter fold and finish ran 2.6x faster with one wave
-// than with two). FP64 scans always take one.
+// than with two; at d = 6 the FP32 fold's lane scan spilled 300 B per lane
+// with two, and one made the fold 11 % faster at 2^22 steps, chunk 64,
+// where every SIMD holds one wave anyway). FP64 scans always take one.
 template <int D, typename T>
-constexpr int fold_waves() { return sizeof(T) == 8 ? 1 : (D >= 7 ? 1 : 2); }
+constexpr int fold_waves() { return sizeof(T) == 8 ? 1 : (D >= 6 ? 1 : 2); }
 template <int D, typename T>
 constexpr int finish_waves() { return sizeof(T) == 8 ? 1 : (D >= 6 ? 1 : 2); }
 template <int D, typename T>
