@@ -89,6 +89,31 @@ __device__ __forceinline__ void step_transition(const DevModel &mdl, cdouble *cs
     }
 }
 
+// Optional per-step arrays (observation mask, noise variances) read without
+// a branch: a missing array is replaced by one that is always there and at
+// least as long (the times), whose values are then ignored. A load inside a
+// branch made the compiler wait for every outstanding memory operation,
+// the previous step's element stores included, right after the load.
+struct OptInputs {
+    const uint8_t *mask;
+    const double *noise;
+    bool has_mask, has_noise;
+    __device__ __forceinline__ OptInputs(const uint8_t *m, const double *nk, const double *t)
+        : mask(m ? m : (const uint8_t *)t), noise(nk ? nk : t), has_mask(m != nullptr), has_noise(nk != nullptr)
+    {
+    }
+    __device__ __forceinline__ bool observed(int64_t k) const
+    {
+        const uint8_t b = mask[k];
+        return !has_mask || b != 0;
+    }
+    __device__ __forceinline__ double noise_var(int64_t k) const
+    {
+        const double r = noise[k];
+        return has_noise ? r : 0.0;
+    }
+};
+
 // Per-lane view of the step inputs with the next step's values loaded one
 // iteration ahead.
 template <typename T>
@@ -255,12 +280,13 @@ __device__ __forceinline__ void filter_tile_fold(const FilterParams<T> &p, const
     bool from_start = false;  // the aggregate covers a series start, so its A is 0
     StepInputs<T> in;
     in.start(p.t, p.y, p.mask, k0, k1, tr.k_begin);
+    const OptInputs opt(p.mask, p.noise_k, p.t);
     for (int64_t k = k0; k < k1; k++) {
         const int64_t kn = (k + 1 < k1) ? k + 1 : k;
         const double tn = p.t[kn];
         const T yn = p.y[kn];
-        const bool on = p.mask ? (p.mask[kn] != 0) : true;
-        const T R = p.noise_k ? T(p.noise_k[k]) : T(0);
+        const bool on = opt.observed(kn);
+        const T R = T(opt.noise_var(k));
         PSSGP_RELOAD_CONSTANTS();
         sv.seek(k);
         const bool first = sv.first(k);
@@ -349,12 +375,16 @@ __device__ __forceinline__ void filter_tile_finish(const FilterParams<T> &p, con
     int64_t seg_k = k0;
     StepInputs<T> in;
     in.start(p.t, p.y, p.mask, k0, k1, tr.k_begin);
+    // the first step's inputs are waited for before the loop, so that the
+    // loop's first use of them carries no wait into later iterations
+    asm volatile("" ::"v"(in.tc), "v"(in.tp), "v"(in.yc), "v"((int)in.oc));
+    const OptInputs opt(p.mask, p.noise_k, p.t);
     for (int64_t k = k0; k < k1; k++) {
         const int64_t kn = (k + 1 < k1) ? k + 1 : k;
         const double tn = p.t[kn];
         const T yn = p.y[kn];
-        const bool on = p.mask ? (p.mask[kn] != 0) : true;
-        const T Rk = p.noise_k ? T(p.noise_k[k]) : T(0);
+        const bool on = opt.observed(kn);
+        const T Rk = T(opt.noise_var(k));
         PSSGP_RELOAD_CONSTANTS();
         sv.seek(k);
         const bool first = sv.first(k);
@@ -374,6 +404,10 @@ __device__ __forceinline__ void filter_tile_finish(const FilterParams<T> &p, con
         // predict in FP64 (mp = F m, Y = F P, Pp = F P F^T + Q)
         double mp[D], Y[D][D], Pp[D][D];
         predict_step<D, T>(m, P, Dl, Q, mp, Y, Pp);
+        // the loads of this iteration are waited for here, before the
+        // element stores: the wait counter is in order, so a wait after
+        // the stores would also wait for all of them
+        asm volatile("" ::"v"(tn), "v"(yn), "v"((int)on), "v"(Rk));
         if constexpr ((MODE & F_ELEMS) != 0) {
             // smoother element of the previous step of this lane
             if (k > k0) {
