@@ -195,31 +195,48 @@ __device__ __forceinline__ void rbf_phi(const DevBlock &bk, double s, double (&p
     (void)frexp(x, &e);  // x < 2^e
     const int j = (x > 0.5) ? e + 1 : 0;
     const double ss = ldexp(s, -j);
-    double re[NP + 1], im[NP + 1];
+    // the Horner recurrences of all pairs advance together, so that their
+    // chains of dependent multiply-adds interleave
+    constexpr int NE = NP + (dc & 1);
+    double u[NE], eu[NE], v[NP > 0 ? NP : 1], w[NP > 0 ? NP : 1], c[NP > 0 ? NP : 1], sn[NP > 0 ? NP : 1];
 #pragma unroll
-    for (int p = 0; p < NP + (dc & 1); p++) {
-        const double u = bk.alpha[p] * ss;
-        double eu = inv_factorial(15);
+    for (int p = 0; p < NE; p++) {
+        u[p] = bk.alpha[p] * ss;
+        eu[p] = inv_factorial(15);
+    }
 #pragma unroll
-        for (int k = 14; k >= 0; k--) eu = fma(eu, u, inv_factorial(k));
-        if (p < NP) {
-            const double v = bk.beta[p] * ss, w = v * v;
-            double c = inv_factorial(16), sn = inv_factorial(17);
+    for (int p = 0; p < NP; p++) {
+        v[p] = bk.beta[p] * ss;
+        w[p] = v[p] * v[p];
+        c[p] = inv_factorial(16);
+        sn[p] = inv_factorial(17);
+    }
 #pragma unroll
-            for (int k = 7; k >= 0; k--) {
-                c = fma(c, w, (k & 1) ? -inv_factorial(2 * k) : inv_factorial(2 * k));
-                sn = fma(sn, w, (k & 1) ? -inv_factorial(2 * k + 1) : inv_factorial(2 * k + 1));
+    for (int k = 14; k >= 0; k--) {
+#pragma unroll
+        for (int p = 0; p < NE; p++) eu[p] = fma(eu[p], u[p], inv_factorial(k));
+        if (k <= 7) {
+#pragma unroll
+            for (int p = 0; p < NP; p++) {
+                c[p] = fma(c[p], w[p], (k & 1) ? -inv_factorial(2 * k) : inv_factorial(2 * k));
+                sn[p] = fma(sn[p], w[p], (k & 1) ? -inv_factorial(2 * k + 1) : inv_factorial(2 * k + 1));
             }
-            re[p] = eu * c;
-            im[p] = eu * (sn * v);
+        }
+    }
+    double re[NE], im[NE];
+#pragma unroll
+    for (int p = 0; p < NE; p++) {
+        if (p < NP) {
+            re[p] = eu[p] * c[p];
+            im[p] = eu[p] * (sn[p] * v[p]);
         } else {
-            re[p] = eu;
+            re[p] = eu[p];
             im[p] = 0.0;
         }
     }
     for (int q = 0; q < j; q++) {
 #pragma unroll
-        for (int p = 0; p < NP + (dc & 1); p++) {
+        for (int p = 0; p < NE; p++) {
             const double a = re[p], bb = im[p];
             re[p] = (a - bb) * (a + bb);
             im[p] = 2.0 * a * bb;

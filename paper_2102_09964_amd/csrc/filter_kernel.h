@@ -436,7 +436,15 @@ __device__ __forceinline__ void filter_tile_finish(const FilterParams<T> &p, con
         // branch-free: missing steps add an exact zero
         bad |= (obs && (!(S > 0.0) || !isfinite(S))) ? PSSGP_STATUS_BAD_S : 0u;
         bad |= (obs && !isfinite(yk)) ? PSSGP_STATUS_NONFINITE : 0u;
-        const double term = obs ? -0.5 * (log(6.283185307179586 * S) + v * v * w) : 0.0;
+        // log(2 pi S): in FP32 for the FP32 scans (the hardware base-2
+        // logarithm, about 1e-7 absolute on a term of size 1, far below the
+        // FP32 tolerance of the sum), in FP64 otherwise
+        double lg;
+        if constexpr (sizeof(T) == 4)
+            lg = (double)__builtin_amdgcn_logf((float)(6.283185307179586 * S)) * 0.6931471805599453;
+        else
+            lg = log(6.283185307179586 * S);
+        const double term = obs ? -0.5 * (lg + v * v * w) : 0.0;
         if constexpr (SEG) {
             if (first && k > k0) {
                 if (p.ll_terms) p.ll_terms[seg_k] = seg;
