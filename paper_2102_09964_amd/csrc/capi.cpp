@@ -80,7 +80,9 @@ Plan make_plan(int d, int ncomp, int64_t n, pssgp_dtype dtype, int op, const pss
     }
     p.off_cst = take(PSSGP_CONST_DOUBLES * sizeof(double));
     {
-        const size_t ng = (nt + 63) / 64 + 1;
+        // group aggregates and carries of the carry pass (groups of 64 tiles
+        // for the one-lane scan, of 32 for the team scan)
+        const size_t ng = (nt + 31) / 32 + 1;
         const size_t agg_max = (size_t)(filter_agg_elems(d) > grad_agg_elems(d) ? filter_agg_elems(d) : grad_agg_elems(d));
         p.off_gagg = take(ng * agg_max * p.tsize);
         p.off_gcarry = take(ng * (size_t)filter_incl_elems(d) * p.tsize);
@@ -352,8 +354,8 @@ int make_batch_plan(const pssgp_batch_group *groups, int ngroups, int64_t n_seri
     const int incl = (op == PSSGP_OP_SMOOTH) ? smooth_incl_elems(d) : filter_incl_elems(d);
     bp.off_incl = take(nt * incl * bp.tsize);
     bp.off_agg = take(nt * agg * bp.tsize);
-    bp.off_gagg = take(((nt + 63) / 64 + 1) * agg * bp.tsize);
-    bp.off_gcarry = take(((nt + 63) / 64 + 1) * incl * bp.tsize);
+    bp.off_gagg = take(((nt + 31) / 32 + 1) * agg * bp.tsize);
+    bp.off_gcarry = take(((nt + 31) / 32 + 1) * incl * bp.tsize);
     bp.off_lane = take(nt * 64 * agg * bp.tsize);
     bp.off_part = take(nt * sizeof(double) * 3);
     bp.off_cst = take(2 * PSSGP_CONST_DOUBLES * sizeof(double));

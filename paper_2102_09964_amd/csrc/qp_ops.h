@@ -174,8 +174,7 @@ __device__ __forceinline__ void qp_matvec(const T (&X)[L::RPL][L::D], const U (&
     }
 }
 
-// Transpose through LDS: Y = X^T (lds: D * D values of this team; one wave
-// per workgroup, uniform control flow)
+// Transpose through LDS: Y = X^T (lds: D * D values of this team)
 template <class L, typename T>
 __device__ __forceinline__ void qp_transpose(const T (&X)[L::RPL][L::D], T (&Y)[L::RPL][L::D], T *lds)
 {
@@ -186,7 +185,7 @@ __device__ __forceinline__ void qp_transpose(const T (&X)[L::RPL][L::D], T (&Y)[
 #pragma unroll
             for (int j = 0; j < L::D; j++) lds[row * L::D + j] = X[s][j];
     }
-    __syncthreads();
+    team_sync();
     T out[L::RPL][L::D];
 #pragma unroll
     for (int s = 0; s < L::RPL; s++) {
@@ -195,7 +194,7 @@ __device__ __forceinline__ void qp_transpose(const T (&X)[L::RPL][L::D], T (&Y)[
 #pragma unroll
         for (int j = 0; j < L::D; j++) out[s][j] = row < L::D ? lds[j * L::D + r] : T(0);
     }
-    __syncthreads();
+    team_sync();
 #pragma unroll
     for (int s = 0; s < L::RPL; s++)
 #pragma unroll
@@ -240,35 +239,35 @@ __device__ __forceinline__ double qp_obs_dot(const QPDev &m, const T (&x)[L::RPL
     return acc;
 }
 
-// Solve M Z = B (M: D x D, B: D x NB, row-distributed, FP64) by Gauss-Jordan
+// Solve M Z = B (M: D x D, B: D x NB, row-distributed, in CT) by Gauss-Jordan
 // elimination with partial pivoting over the rows (the largest |M_ik| of the
 // rows not yet used; ties to the lower row). The pivot row is broadcast
-// through LDS (prow: D + NB doubles of this team). B receives Z.
-template <class L, int NB>
-__device__ __forceinline__ void qp_solve(double (&M)[L::RPL][L::D], double (&B)[L::RPL][NB], double *prow,
-                                         double *zbuf, uint32_t &bad)
+// through LDS (prow: D + NB values of this team). B receives Z.
+template <class L, int NB, typename CT = double>
+__device__ __forceinline__ void qp_solve(CT (&M)[L::RPL][L::D], CT (&B)[L::RPL][NB], CT *prow, CT *zbuf,
+                                         uint32_t &bad)
 {
     int pc[L::RPL];
-    double pv[L::RPL];
+    CT pv[L::RPL];
 #pragma unroll
     for (int s = 0; s < L::RPL; s++) {
         pc[s] = (team_lane() + QP_TEAM * s < L::D) ? -1 : L::D;
-        pv[s] = 1.0;
+        pv[s] = CT(1);
     }
     sfor<0, L::D>([&](auto kc) {
         constexpr int k = decltype(kc)::value;
-        double best = -1.0;
+        CT best = CT(-1);
         int brow = 1 << 20;
 #pragma unroll
         for (int s = 0; s < L::RPL; s++) {
-            const double a = fabs(M[s][k]);
+            const CT a = fabs(M[s][k]);
             const int row = team_lane() + QP_TEAM * s;
             const bool take = pc[s] < 0 && (a > best || (a == best && row < brow));
             best = take ? a : best;
             brow = take ? row : brow;
         }
         // team argmax (exact: every lane ends with the same pair)
-        auto step = [&](double ob, int orow) {
+        auto step = [&](CT ob, int orow) {
             const bool take = ob > best || (ob == best && orow < brow);
             best = take ? ob : best;
             brow = take ? orow : brow;
@@ -288,25 +287,25 @@ __device__ __forceinline__ void qp_solve(double (&M)[L::RPL][L::D], double (&B)[
                 for (int j = 0; j < NB; j++) prow[L::D + j] = B[s][j];
             }
         }
-        __syncthreads();
-        double pm[L::D], pb[NB];
+        team_sync();
+        CT pm[L::D], pb[NB];
 #pragma unroll
         for (int j = k; j < L::D; j++) pm[j] = prow[j];
 #pragma unroll
         for (int j = 0; j < NB; j++) pb[j] = prow[L::D + j];
-        __syncthreads();
-        if (!(fabs(pm[k]) > 0.0)) bad |= 16u;
-        const double inv = 1.0 / pm[k];
+        team_sync();
+        if (!(fabs(pm[k]) > CT(0))) bad |= 16u;
+        const CT inv = CT(1) / pm[k];
 #pragma unroll
         for (int s = 0; s < L::RPL; s++) {
             const int row = team_lane() + QP_TEAM * s;
             const bool is_p = row == p;
-            const double f = is_p ? 0.0 : M[s][k] * inv;
+            const CT f = is_p ? CT(0) : M[s][k] * inv;
 #pragma unroll
             for (int j = k + 1; j < L::D; j++) M[s][j] = fma(-f, pm[j], M[s][j]);
 #pragma unroll
             for (int j = 0; j < NB; j++) B[s][j] = fma(-f, pb[j], B[s][j]);
-            M[s][k] = is_p ? M[s][k] : 0.0;
+            M[s][k] = is_p ? M[s][k] : CT(0);
             pc[s] = is_p ? k : pc[s];
             pv[s] = is_p ? pm[k] : pv[s];
         }
@@ -316,20 +315,20 @@ __device__ __forceinline__ void qp_solve(double (&M)[L::RPL][L::D], double (&B)[
 #pragma unroll
     for (int s = 0; s < L::RPL; s++) {
         if (pc[s] >= 0 && pc[s] < L::D) {
-            const double inv = 1.0 / pv[s];
+            const CT inv = CT(1) / pv[s];
 #pragma unroll
             for (int j = 0; j < NB; j++) zbuf[pc[s] * NB + j] = B[s][j] * inv;
         }
     }
-    __syncthreads();
+    team_sync();
 #pragma unroll
     for (int s = 0; s < L::RPL; s++) {
         const int row = team_lane() + QP_TEAM * s;
         const int r = row < L::D ? row : 0;
 #pragma unroll
-        for (int j = 0; j < NB; j++) B[s][j] = row < L::D ? zbuf[r * NB + j] : 0.0;
+        for (int j = 0; j < NB; j++) B[s][j] = row < L::D ? zbuf[r * NB + j] : CT(0);
     }
-    __syncthreads();
+    team_sync();
 }
 
 // ------------------------------------------------------------------ filter elements and operator
@@ -449,42 +448,48 @@ __device__ __forceinline__ void qp_fold(QAgg<L, T> &a, const QPDev &m, const QPS
     }
 }
 
-// General filtering operator (paper, section 3), x earlier than y, in FP64:
+// Values of scratch that qp_combine takes per team: transposes (D^2), the
+// pivot row (D + NB) and the permuted solution (D NB), NB = 2 D + 1.
+template <int D>
+__host__ __device__ constexpr int qp_combine_scratch() { return D * D + (D + 2 * D + 1) + D * (2 * D + 1); }
+
+// General filtering operator (paper, section 3), x earlier than y, in CT:
 //   M = I + C_x J_y,  Z = M^-1 [A_x | b_x + C_x eta_y | C_x]
 //   A = A_y Z_A,  b = A_y z_b + b_y,  C = A_y Z_C A_y^T + C_y,
 //   J = A_x^T (J_y - J_y Z_C J_y) A_x + J_x    (J_y M^-1 = J_y - J_y M^-1 C_x J_y)
 //   eta = A_x^T (u - J_y Z_C u) + eta_x,  u = eta_y - J_y b_x
-// C and J are symmetrised. lds: this team's scratch (3 D^2 + 4 D doubles).
-template <class L, typename T>
-__device__ __forceinline__ void qp_combine(const QAgg<L, T> &x, const QAgg<L, T> &y, QAgg<L, T> &out, double *lds,
+// C and J are symmetrised. lds: this team's scratch (qp_combine_scratch<D>()
+// values of CT).
+template <class L, typename T, typename CT = double>
+__device__ __forceinline__ void qp_combine(const QAgg<L, T> &x, const QAgg<L, T> &y, QAgg<L, T> &out, CT *lds,
                                            uint32_t &bad)
 {
     constexpr int D = L::D, R = L::RPL, NB = 2 * D + 1;
-    double *tbuf = lds;                 // D * D (transposes)
-    double *prow = lds + D * D;         // D + NB
-    double *zbuf = prow + D + NB;       // D * NB
-    double M[R][D], B[R][NB];
+    CT *tbuf = lds;                 // D * D (transposes)
+    CT *prow = lds + D * D;         // D + NB
+    CT *zbuf = prow + D + NB;       // D * NB
+    CT M[R][D], B[R][NB];
     {
-        double CJ[R][D];
-        qp_matmul<L, T, double>(x.C, y.Jm, CJ);
-        double ey[D];
-        qp_gather<L, T, double>(y.eta, ey);
+        CT CJ[R][D];
+        qp_matmul<L, T, CT>(x.C, y.Jm, CJ);
+        CT ey[D];
+        qp_gather<L, T, CT>(y.eta, ey);
 #pragma unroll
         for (int s = 0; s < R; s++) {
             const int row = team_lane() + QP_TEAM * s;
-            double ce = 0.0;
+            CT ce = CT(0);
 #pragma unroll
             for (int j = 0; j < D; j++) {
-                M[s][j] = CJ[s][j] + ((row == j) ? 1.0 : 0.0);
-                B[s][j] = (double)x.A[s][j];
-                B[s][D + 1 + j] = (double)x.C[s][j];
-                ce = fma((double)x.C[s][j], ey[j], ce);
+                M[s][j] = CJ[s][j] + ((row == j) ? CT(1) : CT(0));
+                B[s][j] = (CT)x.A[s][j];
+                B[s][D + 1 + j] = (CT)x.C[s][j];
+                ce = fma((CT)x.C[s][j], ey[j], ce);
             }
-            B[s][D] = (double)x.b[s] + ce;
+            B[s][D] = (CT)x.b[s] + ce;
         }
     }
-    qp_solve<L, NB>(M, B, prow, zbuf, bad);
-    double ZA[R][D], zb[R], ZC[R][D];
+    qp_solve<L, NB, CT>(M, B, prow, zbuf, bad);
+    CT ZA[R][D], zb[R], ZC[R][D];
 #pragma unroll
     for (int s = 0; s < R; s++) {
 #pragma unroll
@@ -494,78 +499,78 @@ __device__ __forceinline__ void qp_combine(const QAgg<L, T> &x, const QAgg<L, T>
         }
         zb[s] = B[s][D];
     }
-    double Ay[R][D];
+    CT Ay[R][D];
 #pragma unroll
     for (int s = 0; s < R; s++)
 #pragma unroll
-        for (int j = 0; j < D; j++) Ay[s][j] = (double)y.A[s][j];
+        for (int j = 0; j < D; j++) Ay[s][j] = (CT)y.A[s][j];
     // A, b
-    double nA[R][D], nb[R];
-    qp_matmul<L, double, double>(Ay, ZA, nA);
+    CT nA[R][D], nb[R];
+    qp_matmul<L, CT, CT>(Ay, ZA, nA);
     {
-        double zbu[D];
-        qp_gather<L, double, double>(zb, zbu);
-        qp_matvec<L, double, double>(Ay, zbu, nb);
+        CT zbu[D];
+        qp_gather<L, CT, CT>(zb, zbu);
+        qp_matvec<L, CT, CT>(Ay, zbu, nb);
 #pragma unroll
-        for (int s = 0; s < R; s++) nb[s] += (double)y.b[s];
+        for (int s = 0; s < R; s++) nb[s] += (CT)y.b[s];
     }
     // C = A_y (Z_C A_y^T) + C_y
-    double nC[R][D];
+    CT nC[R][D];
     {
-        double W[R][D];
-        qp_matmul_nt<L, double, double>(ZC, Ay, W);
-        qp_matmul<L, double, double>(Ay, W, nC);
+        CT W[R][D];
+        qp_matmul_nt<L, CT, CT>(ZC, Ay, W);
+        qp_matmul<L, CT, CT>(Ay, W, nC);
 #pragma unroll
         for (int s = 0; s < R; s++)
 #pragma unroll
-            for (int j = 0; j < D; j++) nC[s][j] += (double)y.C[s][j];
-        qp_symmetrize<L, double>(nC, tbuf);
+            for (int j = 0; j < D; j++) nC[s][j] += (CT)y.C[s][j];
+        qp_symmetrize<L, CT>(nC, tbuf);
     }
     // J and eta
-    double nJ[R][D], neta[R];
+    CT nJ[R][D], neta[R];
     {
-        double Jy[R][D], Ax[R][D], AxT[R][D];
+        CT Jy[R][D], Ax[R][D], AxT[R][D];
 #pragma unroll
         for (int s = 0; s < R; s++)
 #pragma unroll
             for (int j = 0; j < D; j++) {
-                Jy[s][j] = (double)y.Jm[s][j];
-                Ax[s][j] = (double)x.A[s][j];
+                Jy[s][j] = (CT)y.Jm[s][j];
+                Ax[s][j] = (CT)x.A[s][j];
             }
-        qp_transpose<L, double>(Ax, AxT, tbuf);
+        qp_transpose<L, CT>(Ax, AxT, tbuf);
         // u = eta_y - J_y b_x
-        double bx[D], u[R];
-        qp_gather<L, T, double>(x.b, bx);
-        qp_matvec<L, double, double>(Jy, bx, u);
+        CT bx[D], u[R];
+        qp_gather<L, T, CT>(x.b, bx);
+        qp_matvec<L, CT, CT>(Jy, bx, u);
 #pragma unroll
-        for (int s = 0; s < R; s++) u[s] = (double)y.eta[s] - u[s];
+        for (int s = 0; s < R; s++) u[s] = (CT)y.eta[s] - u[s];
         // JZ = J_y Z_C, Bm = J_y - JZ J_y
-        double JZ[R][D], Bm[R][D];
-        qp_matmul<L, double, double>(Jy, ZC, JZ);
-        qp_matmul<L, double, double>(JZ, Jy, Bm);
+        CT JZ[R][D], Bm[R][D];
+        qp_matmul<L, CT, CT>(Jy, ZC, JZ);
+        qp_matmul<L, CT, CT>(JZ, Jy, Bm);
 #pragma unroll
         for (int s = 0; s < R; s++)
 #pragma unroll
             for (int j = 0; j < D; j++) Bm[s][j] = Jy[s][j] - Bm[s][j];
         // J = A_x^T (Bm A_x) + J_x
-        double V[R][D];
-        qp_matmul<L, double, double>(Bm, Ax, V);
-        qp_matmul<L, double, double>(AxT, V, nJ);
+        CT V[R][D];
+        qp_matmul<L, CT, CT>(Bm, Ax, V);
+        qp_matmul<L, CT, CT>(AxT, V, nJ);
 #pragma unroll
         for (int s = 0; s < R; s++)
 #pragma unroll
-            for (int j = 0; j < D; j++) nJ[s][j] += (double)x.Jm[s][j];
-        qp_symmetrize<L, double>(nJ, tbuf);
+            for (int j = 0; j < D; j++) nJ[s][j] += (CT)x.Jm[s][j];
+        qp_symmetrize<L, CT>(nJ, tbuf);
         // eta = A_x^T (u - JZ u) + eta_x
-        double uu[D], q[R], qu[D];
-        qp_gather<L, double, double>(u, uu);
-        qp_matvec<L, double, double>(JZ, uu, q);
+        CT uu[D], q[R], qu[D];
+        qp_gather<L, CT, CT>(u, uu);
+        qp_matvec<L, CT, CT>(JZ, uu, q);
 #pragma unroll
         for (int s = 0; s < R; s++) q[s] = u[s] - q[s];
-        qp_gather<L, double, double>(q, qu);
-        qp_matvec<L, double, double>(AxT, qu, neta);
+        qp_gather<L, CT, CT>(q, qu);
+        qp_matvec<L, CT, CT>(AxT, qu, neta);
 #pragma unroll
-        for (int s = 0; s < R; s++) neta[s] += (double)x.eta[s];
+        for (int s = 0; s < R; s++) neta[s] += (CT)x.eta[s];
     }
 #pragma unroll
     for (int s = 0; s < R; s++) {

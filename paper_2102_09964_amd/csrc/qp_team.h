@@ -61,6 +61,17 @@ struct QPL {
 
 __device__ __forceinline__ int team_lane() { return (int)(threadIdx.x & (QP_TEAM - 1)); }
 
+// Orders this wave's LDS accesses around an exchange between the lanes of
+// one team (a team never spans waves, and the LDS executes one wave's
+// accesses in issue order): a compiler barrier at wavefront scope, so that
+// workgroups of several waves need no workgroup barrier for it.
+__device__ __forceinline__ void team_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // compile-time loop: f(std::integral_constant<int, I>) for I in [B, E)
 template <int B, int E, class F>
 __device__ __forceinline__ void sfor(F &&f)

@@ -204,7 +204,8 @@ __global__ __launch_bounds__(PSSGP_WAVE) void group_reduce_kernel(typename Ops::
     if (lane == act - 1) Ops::store(gagg + (size_t)blockIdx.x * Ops::AGG, acc);  // group total
 }
 
-template <class Ops>
+// (G: tiles per group of the first level)
+template <class Ops, int G = PSSGP_WAVE>
 __global__ __launch_bounds__(256) void tile_carry_kernel(const typename Ops::T *aggp, const typename Ops::T *gcarry,
                                                         int slot_base, int ntiles, int reverse,
                                                         typename Ops::T *carry)
@@ -214,7 +215,7 @@ __global__ __launch_bounds__(256) void tile_carry_kernel(const typename Ops::T *
     constexpr int D = Ops::D;
     const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (i >= ntiles) return;
-    const int g = i / PSSGP_WAVE, j = i - g * PSSGP_WAVE;
+    const int g = i / G, j = i - g * G;
     T v[D], M[D][D];
     Ops::mom_load(gcarry + (size_t)g * Ops::MOM, v, M);
     if (j > 0) {

@@ -122,6 +122,122 @@ int launch_team_carry(void *aggp, void *agg2, int slot_base, int ntiles, void *c
     return (int)hipGetLastError();
 }
 
+// Team scan in groups (FP32 and FP64 aggregates, operator in CT): one
+// workgroup per group of TG consecutive tiles, one 16-lane team per tile
+// (TG teams, TG / 4 waves). The group's aggregates are scanned
+// (Kogge-Stone) through LDS, each tile's aggregate is overwritten with its
+// inclusive aggregate within the group and the last one is the group total.
+// The combinations of one level run in parallel on all teams; LDS holds the
+// level's aggregates (workgroup barriers between levels) and each team's
+// scratch of the operator (exchanges inside a team, which lies in one wave,
+// need no workgroup barrier).
+constexpr int kTeamGroupTiles = 32;
+
+template <int D, typename T, typename CT>
+__host__ __device__ constexpr size_t team_group_lds()
+{
+    return (((size_t)kTeamGroupTiles * AggLayout<D>::SIZE * sizeof(T) + 15) / 16) * 16 +
+           (size_t)kTeamGroupTiles * qp_combine_scratch<D>() * sizeof(CT);
+}
+
+// Kogge-Stone over the aggregates of one group (first tile: blockIdx.x * TG)
+// held by the teams; act: tiles in the group.
+template <int D, typename T, typename CT>
+__device__ __forceinline__ void team_group_kogge_stone(QAgg<TeamL<D>, T> &acc, int act, unsigned char *smem,
+                                                       uint32_t &bad)
+{
+    constexpr int AGG = AggLayout<D>::SIZE;
+    constexpr size_t OFF = (((size_t)kTeamGroupTiles * AGG * sizeof(T) + 15) / 16) * 16;
+    T *sagg = (T *)smem;
+    const int t = (int)(threadIdx.x >> 4);
+    CT *scr = (CT *)(smem + OFF) + (size_t)t * qp_combine_scratch<D>();
+    for (int o = 1; o < act; o <<= 1) {
+        tagg_store<D, T>(sagg + (size_t)t * AGG, acc, true);
+        __syncthreads();
+        if (t >= o) {
+            QAgg<TeamL<D>, T> other;
+            tagg_load<D, T>(sagg + (size_t)(t - o) * AGG, other, true);
+            qp_combine<TeamL<D>, T, CT>(other, acc, acc, scr, bad);
+        }
+        __syncthreads();
+    }
+}
+
+// Level A: every group of tiles [slot_base + g TG, ...) is scanned; gagg[g]
+// receives the group total.
+template <int D, typename T, typename CT>
+__global__ __launch_bounds__(kTeamGroupTiles * QP_TEAM) void team_group_reduce(T *aggp, int slot_base, int ntiles,
+                                                                               T *gagg, uint32_t *status)
+{
+    constexpr int AGG = AggLayout<D>::SIZE;
+    extern __shared__ __align__(16) unsigned char tg_smem[];
+    const int t = (int)(threadIdx.x >> 4);
+    const int i = (int)blockIdx.x * kTeamGroupTiles + t;
+    const int act = min(ntiles - (int)blockIdx.x * kTeamGroupTiles, kTeamGroupTiles);
+    QAgg<TeamL<D>, T> acc;
+    tagg_load<D, T>(aggp + (size_t)(slot_base + (i < ntiles ? i : 0)) * AGG, acc, i < ntiles);
+    uint32_t bad = 0;
+    team_group_kogge_stone<D, T, CT>(acc, act, tg_smem, bad);
+    if (i < ntiles) tagg_store<D, T>(aggp + (size_t)(slot_base + i) * AGG, acc, true);
+    if (t == act - 1) tagg_store<D, T>(gagg + (size_t)blockIdx.x * AGG, acc, true);
+    if (bad && team_lane() == 0) status_or(status, PSSGP_STATUS_BAD_S);
+}
+
+// Level B: the ng <= TG group totals in one workgroup; every prefix from the
+// first tile has A = 0, so gcarry[g + 1] is the (b, C) of the inclusive
+// prefix of groups 0..g and gcarry[0] = 0.
+template <int D, typename T, typename CT>
+__global__ __launch_bounds__(kTeamGroupTiles * QP_TEAM) void team_group_scan(const T *gagg, int ng, T *gcarry,
+                                                                             uint32_t *status)
+{
+    constexpr int AGG = AggLayout<D>::SIZE, INCL = AggLayout<D>::INCL;
+    extern __shared__ __align__(16) unsigned char tg_smem[];
+    const int t = (int)(threadIdx.x >> 4);
+    QAgg<TeamL<D>, T> acc;
+    tagg_load<D, T>(gagg + (size_t)(t < ng ? t : 0) * AGG, acc, t < ng);
+    uint32_t bad = 0;
+    team_group_kogge_stone<D, T, CT>(acc, ng, tg_smem, bad);
+    if (t + 1 < ng) tmom_store<D, T>(gcarry + (size_t)(t + 1) * INCL, acc, false);
+    if (t == 0) tmom_store<D, T>(gcarry, acc, true);
+    if (bad && team_lane() == 0) status_or(status, PSSGP_STATUS_BAD_S);
+}
+
+// Carries of tiles [slot_base, slot_base + ntiles) by the group scan: level
+// A, level B (ng <= TG teams; more groups: the one-lane scan over the group
+// totals), then each tile's moments from its group's carry and the
+// inclusive aggregate of the tile before it in the group (tile_carry_kernel
+// of tile_scan.h, in groups of TG tiles). aggp is overwritten. Returns a
+// hipError_t.
+template <int D, typename T, typename CT>
+int launch_team_group_carry(const ScanWs &ws, int slot_base, int ntiles, hipStream_t s)
+{
+    using Ops = FilterScanOps<D, T, CT>;
+    const size_t lds = team_group_lds<D, T, CT>();
+    static bool attr_set = false;  // per process: the attribute is a property of the kernel
+    if (!attr_set) {
+        if (hipFuncSetAttribute((const void *)team_group_reduce<D, T, CT>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess ||
+            hipFuncSetAttribute((const void *)team_group_scan<D, T, CT>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+            return (int)hipErrorInvalidValue;
+        attr_set = true;
+    }
+    const int ng = (ntiles + kTeamGroupTiles - 1) / kTeamGroupTiles;
+    const dim3 block(kTeamGroupTiles * QP_TEAM);
+    hipLaunchKernelGGL((team_group_reduce<D, T, CT>), dim3(ng), block, lds, s, (T *)ws.aggp, slot_base, ntiles,
+                       (T *)ws.gagg, &ws.ctl->status);
+    if (ng <= kTeamGroupTiles) {
+        hipLaunchKernelGGL((team_group_scan<D, T, CT>), dim3(1), block, lds, s, (const T *)ws.gagg, ng,
+                           (T *)ws.gcarry, &ws.ctl->status);
+    } else {
+        hipLaunchKernelGGL((tile_scan_kernel<Ops>), dim3(1), dim3(PSSGP_TS_THREADS), 0, s, (const T *)ws.gagg, 0, ng,
+                           0, (T *)ws.gcarry);
+    }
+    hipLaunchKernelGGL((tile_carry_kernel<Ops, kTeamGroupTiles>), dim3((ntiles + 255) / 256), dim3(256), 0, s,
+                       (const T *)ws.aggp, (const T *)ws.gcarry, slot_base, ntiles, 0, (T *)ws.inclp);
+    return (int)hipGetLastError();
+}
+
 // Carry pass of a filter scan: the team scan for d = 8, where one lane's
 // general combination is longest (measured at 2^20 steps, chunk 16: 0.141
 // against 0.245 ms), when the workspace has the second aggregate buffer;
@@ -132,6 +248,12 @@ int launch_team_carry(void *aggp, void *agg2, int slot_base, int ntiles, void *c
 template <int D, typename T, typename CT>
 int launch_filter_carry(const ScanWs &ws, int slot_base, int ntiles, hipStream_t s)
 {
+#ifndef PSSGP_CARRY_PATH
+#define PSSGP_CARRY_PATH 1
+#endif
+    if constexpr (D >= 6 && sizeof(T) == 4 && PSSGP_CARRY_PATH == 1) {
+        if (ntiles > 2 * PSSGP_WAVE) return launch_team_group_carry<D, T, CT>(ws, slot_base, ntiles, s);
+    }
     if constexpr (D >= 8) {
         if (ws.agg2 && ntiles >= 2)
             return launch_team_carry<D, T>(ws.aggp, ws.agg2, slot_base, ntiles, ws.inclp, &ws.ctl->status, s);
