@@ -131,7 +131,8 @@ def algorithmic_bytes(tsize, n):
 
 MERGE_SOURCES = ("merge.hip", "launch.h")
 SCAN_SOURCES = ("device_common.h", "filter_kernel.h", "filter_ops.h", "smoother_kernel.h", "smoother_ops.h",
-                "tile_scan.h", "launch.h", "model.h", "inst_filter.hip", "inst_smoother.hip")
+                "tile_scan.h", "tile_scan_team.h", "qp_ops.h", "qp_team.h", "launch.h", "model.h", "inst_filter.hip",
+                "inst_smoother.hip")
 GRAD_SOURCES = SCAN_SOURCES + ("grad_kernel.h", "inst_grad.hip")
 
 

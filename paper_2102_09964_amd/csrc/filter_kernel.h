@@ -211,14 +211,17 @@ __device__ __forceinline__ void smoother_element_from_prediction(const T (&m)[D]
     }
 }
 
-// The smoother element of a step is handed over (stored in the tile layout)
-// and, where the smoother takes lane aggregates from the filter
+// The smoother element of a step is handed over (stored in the tile layout
+// with non-temporal stores: it is read back only after the whole filter, and
+// with ordinary stores the caches fetched every line before writing it,
+// which doubled the pass's HBM traffic) and, where the smoother takes lane
+// aggregates from the filter
 // (lane_aggregate_handover), also appended to the lane's running smoother
 // aggregate: acc <- acc (x) e (acc covers the lane's earlier steps).
 template <int D, typename T, bool LANEAGG>
 __device__ __forceinline__ void hand_over_element(const SAgg<D, T> &e, T *out, SAgg<D, T> &acc)
 {
-    sagg_store<D, T>(out, e, PSSGP_WAVE);
+    sagg_store_nt<D, T>(out, e, PSSGP_WAVE);
     if constexpr (LANEAGG) sagg_combine<D, T>(acc, e, acc);
 }
 
@@ -462,15 +465,20 @@ __device__ __forceinline__ void filter_tile_finish(const FilterParams<T> &p, con
         if constexpr ((MODE & F_RECS) != 0) {
             constexpr int NS = RecLayout<D>::NS;
             constexpr size_t W = PSSGP_WAVE;
+            // non-temporal: the records are read back by the adjoint only
+            // after all of them have been written
             T *rp = p.rec + rec_index<D>(slot, p.chunk, (int)(k - k0), lane);
 #pragma unroll
-            for (int i = 0; i < D; i++) { rp[i * W] = T(mp[i]); rp[(D + NS + i) * W] = T(K[i]); }
+            for (int i = 0; i < D; i++) {
+                __builtin_nontemporal_store(T(mp[i]), rp + i * W);
+                __builtin_nontemporal_store(T(K[i]), rp + (D + NS + i) * W);
+            }
 #pragma unroll
             for (int i = 0; i < D; i++)
 #pragma unroll
-                for (int j = i; j < D; j++) rp[(D + sidx<D>(i, j)) * W] = T(Pp[i][j]);
-            rp[(2 * D + NS) * W] = T(S);
-            rp[(2 * D + NS + 1) * W] = obs ? T(v) : T(0);
+                for (int j = i; j < D; j++) __builtin_nontemporal_store(T(Pp[i][j]), rp + (D + sidx<D>(i, j)) * W);
+            __builtin_nontemporal_store(T(S), rp + (2 * D + NS) * W);
+            __builtin_nontemporal_store(obs ? T(v) : T(0), rp + (2 * D + NS + 1) * W);
         }
 #pragma unroll
         for (int i = 0; i < D; i++) m[i] = T(fma(K[i], v, mp[i]));

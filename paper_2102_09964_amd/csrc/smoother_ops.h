@@ -105,6 +105,23 @@ __device__ __forceinline__ void sagg_store(T *p, const SAgg<D, T> &a, size_t st 
         for (int j = i; j < D; j++) p[(size_t)(D * D + D + sidx<D>(i, j)) * st] = a.L[i][j];
 }
 
+// sagg_store with non-temporal stores: for the per-step handover, which is
+// read back only after far more data than the caches hold has been written
+template <int D, typename T>
+__device__ __forceinline__ void sagg_store_nt(T *p, const SAgg<D, T> &a, size_t st)
+{
+#pragma unroll
+    for (int i = 0; i < D; i++)
+#pragma unroll
+        for (int j = 0; j < D; j++) __builtin_nontemporal_store(a.E[i][j], p + (size_t)(i * D + j) * st);
+#pragma unroll
+    for (int i = 0; i < D; i++) __builtin_nontemporal_store(a.g[i], p + (size_t)(D * D + i) * st);
+#pragma unroll
+    for (int i = 0; i < D; i++)
+#pragma unroll
+        for (int j = i; j < D; j++) __builtin_nontemporal_store(a.L[i][j], p + (size_t)(D * D + D + sidx<D>(i, j)) * st);
+}
+
 template <int D, typename T>
 __device__ __forceinline__ void sagg_load(const T *p, SAgg<D, T> &a, size_t st = 1)
 {
