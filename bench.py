@@ -752,7 +752,9 @@ def measure_qp(steps, J, dtype):
     at its tuned chunk."""
     import workloads
     w = workloads.co2_like(n=1 << 20, J=J)
-    chunk = tuned_chunk(w, dtype, candidates=(64, 128, 256, 512))
+    # chunks that give at least one wave per SIMD (four teams per wave):
+    # at 2^20 steps, 512 would leave half the chip idle
+    chunk = tuned_chunk(w, dtype, candidates=(64, 128, 256))
     mm = measure(w, dtype, steps, 2, chunk)
     mm["team_path"] = True
     c = summary("co2_like_d%d" % mm["d"], dtype, mm)

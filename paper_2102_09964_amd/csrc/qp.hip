@@ -57,11 +57,54 @@ struct QPArgs {
     uint32_t *status;
 };
 
-// inputs of step k (0 <= k < n), every lane of the team reading the same
-__device__ __forceinline__ double qp_dt(const double *t, int64_t k)
-{
-    return k > 0 ? t[k] - t[k - 1] : 0.0;
-}
+// Inputs of consecutive steps of a team's chunk (every lane reading the
+// same), the next step's loaded one step ahead so that they are in flight
+// while the current step is computed. Reads are clamped into the series and
+// never branch on the optional mask (a missing mask reads the times, whose
+// bytes are then ignored): a load inside a branch made the compiler wait
+// for every outstanding memory operation right after it.
+template <typename T>
+struct QPInputs {
+    const double *t;
+    const T *y;
+    const uint8_t *mk;
+    bool has_mask;
+    int64_t n;
+    double tp, tc;  // times of steps k - 1 and k
+    T yc;
+    uint8_t mc;
+    __device__ __forceinline__ void start(const QPArgs<T> &a, int64_t k)
+    {
+        t = a.t;
+        y = a.y;
+        mk = a.mask ? a.mask : (const uint8_t *)a.t;
+        has_mask = a.mask != nullptr;
+        n = a.n;
+        const int64_t kc = k < n ? k : n - 1;
+        tc = t[kc];
+        tp = kc > 0 ? t[kc - 1] : tc;
+        yc = y[kc];
+        mc = mk[kc];
+    }
+    // loads of step k + 1 (clamped), issued now
+    __device__ __forceinline__ void fetch(int64_t k, double &tn, T &yn, uint8_t &mn) const
+    {
+        const int64_t kn = k + 1 < n ? k + 1 : n - 1;
+        tn = t[kn];
+        yn = y[kn];
+        mn = mk[kn];
+    }
+    __device__ __forceinline__ void advance(double tn, T yn, uint8_t mn)
+    {
+        tp = tc;
+        tc = tn;
+        yc = yn;
+        mc = mn;
+    }
+    // dt of step k (0 at the series start) and whether it is observed
+    __device__ __forceinline__ double dt(int64_t k) const { return k > 0 ? tc - tp : 0.0; }
+    __device__ __forceinline__ bool observed() const { return !has_mask || mc != 0; }
+};
 
 template <class L, typename T>
 __global__ __launch_bounds__(64) void qp_filter_fold(QPArgs<T> a, QPDev m)
@@ -72,16 +115,22 @@ __global__ __launch_bounds__(64) void qp_filter_fold(QPArgs<T> a, QPDev m)
     QAgg<L, T> agg;
     qagg_identity<L, T>(agg);
     uint32_t bad = 0;
+    QPInputs<T> in;
+    in.start(a, k0);
     for (int it = 0; it < a.chunk; it++) {
         const int64_t k = k0 + it;
         const bool real = k < k1;
-        const int64_t kk = real ? k : 0;
-        const double dt = real ? qp_dt(a.t, kk) : 0.0;
+        double tn;
+        T yn;
+        uint8_t mn;
+        in.fetch(k, tn, yn, mn);
+        const double dt = real ? in.dt(k) : 0.0;
         if (real && !(dt >= 0.0)) bad |= (dt < 0.0) ? PSSGP_STATUS_UNSORTED : PSSGP_STATUS_NONFINITE;
         QPStep<L::J> st;
-        qp_step<L::J>(m, dt, real && kk == 0, !real, st);
-        const bool obs = real && (a.mask ? a.mask[kk] != 0 : true);
-        const T y = obs ? a.y[kk] : T(0);
+        qp_step<L::J>(m, dt, real && k == 0, !real, st);
+        const bool obs = real && in.observed();
+        const T y = obs ? in.yc : T(0);
+        in.advance(tn, yn, mn);
         qp_fold<L, T>(agg, m, st, y, obs);
     }
     qagg_store<L, T, T>(a.fagg[0] + (size_t)g * L::D * qagg_fields<L>(), agg, g < a.G);
@@ -137,16 +186,24 @@ __global__ __launch_bounds__(64) void qp_filter_finish(QPArgs<T> a, QPDev m, con
     uint32_t bad = 0;
     double ll = 0.0;
     constexpr int NFS = D * qsagg_fields<L>();
+    QPInputs<T> in;
+    in.start(a, k0);
     for (int it = 0; it <= a.chunk; it++) {
         const int64_t k = k0 + it;
         const bool real = k < k1;
         const bool next = ELEMS && k == k1 && k1 > k0;  // element of the chunk's last step
         const bool end = next && k1 >= a.n;             // past the series end: prior transition
-        const int64_t kk = (real || (next && !end)) ? k : 0;
-        const double dt = (real || (next && !end)) ? qp_dt(a.t, kk) : 0.0;
+        double tn;
+        T yn;
+        uint8_t mn;
+        in.fetch(k, tn, yn, mn);
+        const double dt = (real || (next && !end)) ? in.dt(k) : 0.0;
         if (real && !(dt >= 0.0)) bad |= (dt < 0.0) ? PSSGP_STATUS_UNSORTED : PSSGP_STATUS_NONFINITE;
+        const bool obs = real && in.observed();
+        const double yk = obs ? (double)in.yc : 0.0;
+        in.advance(tn, yn, mn);
         QPStep<L::J> st;
-        qp_step<L::J>(m, dt, (real && kk == 0) || end, !(real || next), st);
+        qp_step<L::J>(m, dt, (real && k == 0) || end, !(real || next), st);
         // prediction in FP64: Y = F P, mp = F m, Pp = F P F^T + Q
         double Y[R][D], mp[R], Pp[R][D];
         qp_left_F<L, double, double>(st, P, Y, true);
@@ -160,12 +217,13 @@ __global__ __launch_bounds__(64) void qp_filter_finish(QPArgs<T> a, QPDev m, con
             QSAgg<L, T> e;
             uint32_t ebad = 0;
             qp_element<L, T>(m, mf, P, Y, mp, Pp, e, tbuf, ebad);
+            // the next step's loads are waited for before the element stores
+            // (the wait counter is in order)
+            asm volatile("" ::"v"(tn), "v"(yn), "v"((int)mn));
             qsagg_store<L, T, T>(a.elem + (size_t)(keep ? k - 1 : 0) * NFS, e, keep);
             bad |= keep ? ebad : 0u;
         }
         // conditioning on y_k in FP64
-        const bool obs = real && (a.mask ? a.mask[kk] != 0 : true);
-        const double yk = obs ? (double)a.y[kk] : 0.0;
         double c[D];
         qp_obs_combo<L, double>(m, Pp, c);
         const double hm = qp_obs_dot<L, double>(m, mp);
