@@ -65,8 +65,11 @@ def pass_costs(d, tsize, chunk):
     finish pass hands to the smoother (E, g, packed L: d^2 + d + d(d+1)/2
     values), the per-lane aggregates of the fold passes (one per chunk of
     steps, read back by the finish passes) and the outputs f_mean, f_var.
-    Flops: the FP64 discretisation from the pair constants (F - I: d^3,
-    Q: (d(d+1)/2)^2), the filter fold (element of one step folded into the
+    Flops: the FP64 discretisation over the companion structure (phi of the
+    generator's eigenvalues, about 25 multiply-adds each; row 0 of F - I from
+    the expansion, d^2; the other rows by the commutation recurrence, 2d per
+    row; row 0 of Q, 2 d^2; the other rows by the Lyapunov recurrence, 3d
+    per row), the filter fold (element of one step folded into the
     lane aggregate), the FP64 prediction (F m, F P, F P F^T + Q), the FP64
     conditioning, the smoother element from the prediction (Cholesky of the
     predicted covariance, two triangular solves, the Gram matrix), the
@@ -80,7 +83,7 @@ def pass_costs(d, tsize, chunk):
     fagg = tsize * (d * d + 2 * d + 2 * ns) / chunk  # filter lane aggregate (A, b, C, eta, J)
     sagg = tsize * (d * d + d + ns) / chunk          # smoother lane aggregate (E, g, L)
     inputs = 8 + tsize + 1                           # t (FP64), y, mask
-    disc = d ** 3 + ns * ns + ns
+    disc = 25 * d + d * d + 2 * d * (d - 1) + 2 * d * d + 3 * d * (d - 1)
     fold = 2 * d ** 3 + ns * d + 3 * d * d + 4 * ns
     combine = 5 * d ** 3                             # general filtering operator
     predict = d ** 3 + d * d + ns * d + ns
