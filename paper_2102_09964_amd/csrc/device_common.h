@@ -62,6 +62,27 @@ struct Layout {
     // block of a state index
     __host__ __device__ static constexpr int blk_of(int i) { return i < B0 ? 0 : 1; }
     __host__ __device__ static constexpr bool same_blk(int i, int j) { return blk_of(i) == blk_of(j); }
+    // observation row: in the balanced companion coordinates the function
+    // value of a component is the first state of its block, so H is 1 at
+    // every block start and 0 elsewhere (the model builder writes exactly
+    // this row). Known at compile time, the products with H reduce to
+    // picking rows and columns.
+    __host__ __device__ static constexpr double hobs(int i) { return (i == 0 || (NB > 1 && i == B0)) ? 1.0 : 0.0; }
+};
+
+// Compile-time zero pattern of the step operands of a layout: F - I and Q
+// are block diagonal and H is nonzero only at the block starts. Products
+// with them skip the terms that are products with an exact zero, which add
+// nothing to a finite sum, so the results are those of the dense products.
+template <class LY>
+struct Sparsity {
+    __host__ __device__ static constexpr bool dl(int i, int k) { return LY::same_blk(i, k); }
+    __host__ __device__ static constexpr bool obs(int i) { return LY::hobs(i) != 0.0; }
+};
+// no known zeros: general transition and observation row
+struct NoSparsity {
+    __host__ __device__ static constexpr bool dl(int, int) { return true; }
+    __host__ __device__ static constexpr bool obs(int) { return true; }
 };
 
 // packed upper-triangular index, row-major

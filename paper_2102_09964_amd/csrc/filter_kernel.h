@@ -230,7 +230,7 @@ __device__ __forceinline__ void hand_over_element(const SAgg<D, T> &e, T *out, S
 // Pp = Y F^T + Q = Y + Y Dl^T + Q. FP64 keeps Pp consistent with P to
 // the precision the smoother element needs (its L is P minus a Gram matrix
 // that nearly equals P when Q is small).
-template <int D, typename T>
+template <int D, typename T, class SP>
 __device__ __forceinline__ void predict_step(const T (&m)[D], const T (&P)[D][D], const double (&Dl)[D][D],
                                              const double (&Q)[D][D], double (&mp)[D], double (&Y)[D][D],
                                              double (&Pp)[D][D])
@@ -239,13 +239,15 @@ __device__ __forceinline__ void predict_step(const T (&m)[D], const T (&P)[D][D]
     for (int i = 0; i < D; i++) {
         double acc = (double)m[i];
 #pragma unroll
-        for (int k2 = 0; k2 < D; k2++) acc = fma(Dl[i][k2], (double)m[k2], acc);
+        for (int k2 = 0; k2 < D; k2++)
+            if (SP::dl(i, k2)) acc = fma(Dl[i][k2], (double)m[k2], acc);
         mp[i] = acc;
 #pragma unroll
         for (int j = 0; j < D; j++) {
             double y = (double)P[i][j];
 #pragma unroll
-            for (int k2 = 0; k2 < D; k2++) y = fma(Dl[i][k2], (double)P[k2][j], y);
+            for (int k2 = 0; k2 < D; k2++)
+                if (SP::dl(i, k2)) y = fma(Dl[i][k2], (double)P[k2][j], y);
             Y[i][j] = y;
         }
     }
@@ -253,9 +255,10 @@ __device__ __forceinline__ void predict_step(const T (&m)[D], const T (&P)[D][D]
     for (int i = 0; i < D; i++)
 #pragma unroll
         for (int j = i; j < D; j++) {
-            double acc = Y[i][j] + Q[i][j];
+            double acc = SP::dl(i, j) ? Y[i][j] + Q[i][j] : Y[i][j];
 #pragma unroll
-            for (int k2 = 0; k2 < D; k2++) acc = fma(Y[i][k2], Dl[j][k2], acc);
+            for (int k2 = 0; k2 < D; k2++)
+                if (SP::dl(j, k2)) acc = fma(Y[i][k2], Dl[j][k2], acc);
             Pp[i][j] = acc;
             Pp[j][i] = acc;
         }
@@ -277,7 +280,7 @@ __device__ __forceinline__ void filter_tile_fold(const FilterParams<T> &p, const
     const int64_t k1 = (k0 + p.chunk < tr.k_end) ? k0 + p.chunk : tr.k_end;
     T h[D];
 #pragma unroll
-    for (int i = 0; i < D; i++) h[i] = T(mdl.H[i]);
+    for (int i = 0; i < D; i++) h[i] = T(LY::hobs(i));
     FAgg<D, T> agg;
     agg_identity<D, T>(agg);
     bool from_start = false;  // the aggregate covers a series start, so its A is 0
@@ -300,7 +303,7 @@ __device__ __forceinline__ void filter_tile_fold(const FilterParams<T> &p, const
         T Dl[D][D], Q[D][D];
         step_transition<LY, T, T>(mdl, c, sv.sc, dt, first, Dl, Q);
         const T yk = in.oc ? in.yc : T(0);
-        agg_fold<D, T>(agg, Dl, Q, h, p.noise_k ? R : T(sv.R), yk, in.oc);
+        agg_fold<D, T, Sparsity<LY>>(agg, Dl, Q, h, p.noise_k ? R : T(sv.R), yk, in.oc);
         in.tp = in.tc;
         in.tc = tn;
         in.yc = yn;
@@ -351,9 +354,10 @@ __device__ __forceinline__ void filter_tile_finish(const FilterParams<T> &p, con
     const int64_t chunk_id = (int64_t)slot * PSSGP_WAVE + lane;
     const int64_t k0 = tr.k_begin + ((int64_t)tile * PSSGP_WAVE + lane) * p.chunk;
     const int64_t k1 = (k0 + p.chunk < tr.k_end) ? k0 + p.chunk : tr.k_end;
+    using SP = Sparsity<LY>;
     T h[D];
 #pragma unroll
-    for (int i = 0; i < D; i++) h[i] = T(mdl.H[i]);
+    for (int i = 0; i < D; i++) h[i] = T(LY::hobs(i));
     uint32_t bad = 0;
 
     // smoother lane aggregate accumulated from the handed-over elements
@@ -406,7 +410,7 @@ __device__ __forceinline__ void filter_tile_finish(const FilterParams<T> &p, con
         in.oc = on;
         // predict in FP64 (mp = F m, Y = F P, Pp = F P F^T + Q)
         double mp[D], Y[D][D], Pp[D][D];
-        predict_step<D, T>(m, P, Dl, Q, mp, Y, Pp);
+        predict_step<D, T, Sparsity<LY>>(m, P, Dl, Q, mp, Y, Pp);
         // the loads of this iteration are waited for here, before the
         // element stores: the wait counter is in order, so a wait after
         // the stores would also wait for all of them
@@ -428,12 +432,14 @@ __device__ __forceinline__ void filter_tile_finish(const FilterParams<T> &p, con
         for (int i = 0; i < D; i++) {
             double acc = 0.0;
 #pragma unroll
-            for (int j = 0; j < D; j++) acc = fma(Pp[i][j], (double)h[j], acc);
+            for (int j = 0; j < D; j++)
+                if (SP::obs(j)) acc = fma(Pp[i][j], (double)h[j], acc);
             Ph[i] = acc;
-            hm = fma((double)h[i], mp[i], hm);
+            if (SP::obs(i)) hm = fma((double)h[i], mp[i], hm);
         }
 #pragma unroll
-        for (int i = 0; i < D; i++) S = fma((double)h[i], Ph[i], S);
+        for (int i = 0; i < D; i++)
+            if (SP::obs(i)) S = fma((double)h[i], Ph[i], S);
         const double v = (double)yk - hm;
         const double w = obs ? rcp64(S) : 0.0;
         // branch-free: missing steps add an exact zero
@@ -510,7 +516,7 @@ __device__ __forceinline__ void filter_tile_finish(const FilterParams<T> &p, con
             PSSGP_LAUNDER(c);
             double Dl[D][D], Q[D][D], mp[D], Y[D][D], Pp[D][D];
             step_transition<LY, double, T>(mdl, c, sv.sc, dt, end, Dl, Q);
-            predict_step<D, T>(m, P, Dl, Q, mp, Y, Pp);
+            predict_step<D, T, Sparsity<LY>>(m, P, Dl, Q, mp, Y, Pp);
             SAgg<D, T> e;
             smoother_element_from_prediction<D, smoother_shear_col<LY>(), T>(m, P, Y, mp, Pp, e, bad);
             hand_over_element<D, T, LANEAGG>(e, p.m + elem_index<D>(slot, p.chunk, (int)(k1 - 1 - k0), lane),

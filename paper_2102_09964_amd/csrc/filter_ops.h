@@ -39,7 +39,8 @@ __device__ __forceinline__ void agg_identity(FAgg<D, T> &a)
 // is formed symmetrically, C' - K c^T - c K^T + S K K^T with c = C' H^T and
 // K = c / S (the rank-one form of the Joseph update), which keeps it
 // accurate when the measurement noise is small against the prior.
-template <int D, typename T>
+// SP gives the zero pattern of Dl, Q and h known at compile time.
+template <int D, typename T, class SP = NoSparsity>
 __device__ __forceinline__ void agg_fold(FAgg<D, T> &a, const T (&Dl)[D][D], const T (&Q)[D][D],
                                          const T (&h)[D], T R, T y, bool obs)
 {
@@ -48,13 +49,15 @@ __device__ __forceinline__ void agg_fold(FAgg<D, T> &a, const T (&Dl)[D][D], con
     for (int i = 0; i < D; i++) {
         T acc = a.b[i];
 #pragma unroll
-        for (int k = 0; k < D; k++) acc = fma(Dl[i][k], a.b[k], acc);
+        for (int k = 0; k < D; k++)
+            if (SP::dl(i, k)) acc = fma(Dl[i][k], a.b[k], acc);
         b1[i] = acc;
 #pragma unroll
         for (int j = 0; j < D; j++) {
             T aa = a.A[i][j], xx = T(0);
 #pragma unroll
             for (int k = 0; k < D; k++) {
+                if (!SP::dl(i, k)) continue;
                 aa = fma(Dl[i][k], a.A[k][j], aa);
                 xx = fma(Dl[i][k], a.C[k][j], xx);
             }
@@ -68,8 +71,10 @@ __device__ __forceinline__ void agg_fold(FAgg<D, T> &a, const T (&Dl)[D][D], con
         for (int j = i; j < D; j++) {
             T acc = T(0);
 #pragma unroll
-            for (int k = 0; k < D; k++) acc = fma(X[i][k], Dl[j][k], acc);
-            const T c = a.C[i][j] + ((X[i][j] + X[j][i]) + acc) + Q[i][j];
+            for (int k = 0; k < D; k++)
+                if (SP::dl(j, k)) acc = fma(X[i][k], Dl[j][k], acc);
+            T c = a.C[i][j] + ((X[i][j] + X[j][i]) + acc);
+            if (SP::dl(i, j)) c += Q[i][j];
             C1[i][j] = c;
             C1[j][i] = c;
         }
@@ -82,6 +87,7 @@ __device__ __forceinline__ void agg_fold(FAgg<D, T> &a, const T (&Dl)[D][D], con
         double acc = 0.0, av = 0.0;
 #pragma unroll
         for (int j = 0; j < D; j++) {
+            if (!SP::obs(j)) continue;
             acc = fma((double)C1[i][j], (double)h[j], acc);
             av = fma((double)h[j], (double)A1[j][i], av);
         }
@@ -91,6 +97,7 @@ __device__ __forceinline__ void agg_fold(FAgg<D, T> &a, const T (&Dl)[D][D], con
     double S = (double)R, hb = 0.0;
 #pragma unroll
     for (int i = 0; i < D; i++) {
+        if (!SP::obs(i)) continue;
         S = fma((double)h[i], Ch[i], S);
         hb = fma((double)h[i], (double)b1[i], hb);
     }

@@ -162,7 +162,8 @@ __global__ __launch_bounds__(PSSGP_WAVE) void grad_fold_kernel(GradParams<T> p, 
     const int64_t k1 = (k0 + p.chunk < p.n) ? k0 + p.chunk : p.n;
     T h[D];
 #pragma unroll
-    for (int i = 0; i < D; i++) h[i] = T(mdl.H[i]);
+    for (int i = 0; i < D; i++) h[i] = T(LY::hobs(i));
+    using SP = Sparsity<LY>;
     uint32_t bad = 0;
 
     // chunk adjoint map from the records of the forward filter
@@ -201,7 +202,8 @@ __global__ __launch_bounds__(PSSGP_WAVE) void grad_fold_kernel(GradParams<T> p, 
             for (int j = 0; j < D; j++) {
                 T acc = T(0);
 #pragma unroll
-                for (int i = 0; i < D; i++) acc = fma(h[i], F[i][j], acc);
+                for (int i = 0; i < D; i++)
+                    if (SP::obs(i) && SP::dl(i, j)) acc = fma(h[i], F[i][j], acc);
                 u[j] = acc;
             }
             mat_vec<D, T>(agg.E, u, wv);
@@ -211,7 +213,8 @@ __global__ __launch_bounds__(PSSGP_WAVE) void grad_fold_kernel(GradParams<T> p, 
                 for (int j = 0; j < D; j++) {
                     T acc = T(0);
 #pragma unroll
-                    for (int k2 = 0; k2 < D; k2++) acc = fma(agg.E[i][k2], F[j][k2], acc);
+                    for (int k2 = 0; k2 < D; k2++)
+                        if (SP::dl(j, k2)) acc = fma(agg.E[i][k2], F[j][k2], acc);
                     X[i][j] = acc;
                 }
             const T gs = v * w;                       // v / S (0 when missing)
@@ -261,7 +264,8 @@ __global__ __launch_bounds__(PSSGP_WAVE) void grad_finish_kernel(GradParams<T> p
     const int64_t k1 = (k0 + p.chunk < p.n) ? k0 + p.chunk : p.n;
     T h[D];
 #pragma unroll
-    for (int i = 0; i < D; i++) h[i] = T(mdl.H[i]);
+    for (int i = 0; i < D; i++) h[i] = T(LY::hobs(i));
+    using SP = Sparsity<LY>;
     const T R = T(mdl.R);
     uint32_t bad = 0;
 
@@ -314,18 +318,19 @@ __global__ __launch_bounds__(PSSGP_WAVE) void grad_finish_kernel(GradParams<T> p
         // and gs = cl = 0, so every update term below vanishes exactly
 #pragma unroll
         for (int i = 0; i < D; i++) {
-            am[i] = fma(-h[i], km, mb[i]);
-            mub[i] = fma(h[i], gs, am[i]);
+            am[i] = SP::obs(i) ? fma(-h[i], km, mb[i]) : mb[i];
+            mub[i] = SP::obs(i) ? fma(h[i], gs, am[i]) : am[i];
         }
 #pragma unroll
         for (int i = 0; i < D; i++)
 #pragma unroll
             for (int j = i; j < D; j++) {
                 T acc = Pb[i][j];
-                acc = fma(-h[i], PK[j], acc);
-                acc = fma(-PK[i], h[j], acc);
-                acc = fma(kpk + cl, h[i] * h[j], acc);
-                acc = fma(T(0.5) * gs, am[i] * h[j] + h[i] * am[j], acc);
+                if (SP::obs(i)) acc = fma(-h[i], PK[j], acc);
+                if (SP::obs(j)) acc = fma(-PK[i], h[j], acc);
+                if (SP::obs(i) && SP::obs(j)) acc = fma(kpk + cl, h[i] * h[j], acc);
+                if (SP::obs(i) || SP::obs(j))
+                    acc = fma(T(0.5) * gs, (SP::obs(j) ? am[i] * h[j] : T(0)) + (SP::obs(i) ? h[i] * am[j] : T(0)), acc);
                 Pib[i][j] = acc;
                 Pib[j][i] = acc;
             }
@@ -380,12 +385,22 @@ __global__ __launch_bounds__(PSSGP_WAVE) void grad_finish_kernel(GradParams<T> p
 #pragma unroll
             for (int j = 0; j < D; j++) F[i][j] = T(F64[i][j]);
         T PF[D][D];
-        mat_mul<D, T>(Pib, F, PF);
+#pragma unroll
+        for (int i = 0; i < D; i++)
+#pragma unroll
+            for (int j = 0; j < D; j++) {
+                T acc = T(0);
+#pragma unroll
+                for (int k2 = 0; k2 < D; k2++)
+                    if (SP::dl(k2, j)) acc = fma(Pib[i][k2], F[k2][j], acc);
+                PF[i][j] = acc;
+            }
 #pragma unroll
         for (int i = 0; i < D; i++) {
             T acc = T(0);
 #pragma unroll
-            for (int k2 = 0; k2 < D; k2++) acc = fma(F[k2][i], mub[k2], acc);
+            for (int k2 = 0; k2 < D; k2++)
+                if (SP::dl(k2, i)) acc = fma(F[k2][i], mub[k2], acc);
             mb[i] = acc;
         }
 #pragma unroll
@@ -394,7 +409,8 @@ __global__ __launch_bounds__(PSSGP_WAVE) void grad_finish_kernel(GradParams<T> p
             for (int j = i; j < D; j++) {
                 T acc = T(0);
 #pragma unroll
-                for (int k2 = 0; k2 < D; k2++) acc = fma(F[k2][i], PF[k2][j], acc);
+                for (int k2 = 0; k2 < D; k2++)
+                    if (SP::dl(k2, i)) acc = fma(F[k2][i], PF[k2][j], acc);
                 Pb[i][j] = acc;
                 Pb[j][i] = acc;
             }

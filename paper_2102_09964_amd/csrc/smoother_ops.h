@@ -199,13 +199,15 @@ __host__ __device__ constexpr int smoother_shear_col()
     return LY::NB == 2 ? LY::boff(1) : 0;
 }
 
-// h' = H S^-1: column B minus column 0
+// h' = H S^-1: column B minus column 0. H is 1 at the block starts 0 and B
+// and 0 elsewhere, so h' is the first unit vector: the first smoother
+// coordinate is f itself.
 template <int D, int B, typename T>
 __device__ __forceinline__ void smoother_obs_row(const DevModel &mdl, T (&h)[D])
 {
+    (void)mdl;
 #pragma unroll
-    for (int i = 0; i < D; i++) h[i] = T(mdl.H[i]);
-    if constexpr (B > 0) h[B] = T(mdl.H[B] - mdl.H[0]);
+    for (int i = 0; i < D; i++) h[i] = T(i == 0 ? 1 : 0);
 }
 
 // Smoothed moments back in the library's state coordinates:
@@ -247,6 +249,7 @@ __device__ __forceinline__ void smoother_element(const DevModel &mdl, cdouble *c
                                                  SAgg<LY::D, T> &e, uint32_t &bad)
 {
     constexpr int D = LY::D;
+    using SP = Sparsity<LY>;
     const bool is_last = sv.last(k);
     const int64_t kn = is_last ? k : k + 1;  // never reads past the series
     const double dt = t[kn] - t[k];
@@ -273,7 +276,8 @@ __device__ __forceinline__ void smoother_element(const DevModel &mdl, cdouble *c
     for (int i = 0; i < D; i++) {
         double acc = m[i];
 #pragma unroll
-        for (int q = 0; q < D; q++) acc = fma(Dl[i][q], m[q], acc);
+        for (int q = 0; q < D; q++)
+            if (SP::dl(i, q)) acc = fma(Dl[i][q], m[q], acc);
         Fm[i] = acc;
     }
     // Y = F P = P + Dl P
@@ -283,7 +287,8 @@ __device__ __forceinline__ void smoother_element(const DevModel &mdl, cdouble *c
         for (int j = 0; j < D; j++) {
             double acc = P[i][j];
 #pragma unroll
-            for (int q = 0; q < D; q++) acc = fma(Dl[i][q], P[q][j], acc);
+            for (int q = 0; q < D; q++)
+                if (SP::dl(i, q)) acc = fma(Dl[i][q], P[q][j], acc);
             Y[i][j] = acc;
         }
     // lower triangle of Pp = Y F^T + Q = Y + Y Dl^T + Q
@@ -291,9 +296,10 @@ __device__ __forceinline__ void smoother_element(const DevModel &mdl, cdouble *c
     for (int i = 0; i < D; i++)
 #pragma unroll
         for (int j = 0; j <= i; j++) {
-            double acc = Y[i][j] + Q[i][j];
+            double acc = SP::dl(i, j) ? Y[i][j] + Q[i][j] : Y[i][j];
 #pragma unroll
-            for (int q = 0; q < D; q++) acc = fma(Y[i][q], Dl[j][q], acc);
+            for (int q = 0; q < D; q++)
+                if (SP::dl(j, q)) acc = fma(Y[i][q], Dl[j][q], acc);
             C[i][j] = acc;
         }
     double rd[D];  // reciprocals of the Cholesky diagonal
