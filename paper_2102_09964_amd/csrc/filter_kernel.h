@@ -367,6 +367,10 @@ __device__ __forceinline__ void filter_tile_finish(const FilterParams<T> &p, con
 
     T m[D], P[D][D];
     moments_load<D, T>(p.inclp + (size_t)slot * INCL, m, P);
+    // the first step's inputs are requested before the lane's entering
+    // moments are formed, so that their latency overlaps that arithmetic
+    StepInputs<T> in;
+    in.start(p.t, p.y, p.mask, k0, k1, tr.k_begin);
     if (lane > 0) {
         FAgg<D, T> excl;
         agg_load<D, T>(lane_rec(p.lanep, slot, AGG, lane - 1), excl, PSSGP_WAVE);
@@ -380,14 +384,15 @@ __device__ __forceinline__ void filter_tile_finish(const FilterParams<T> &p, con
     constexpr bool SEG = !std::is_same<SV, OneSeries>::value;
     double seg = 0.0;
     int64_t seg_k = k0;
-    StepInputs<T> in;
-    in.start(p.t, p.y, p.mask, k0, k1, tr.k_begin);
     // the first step's inputs are waited for before the loop, so that the
     // loop's first use of them carries no wait into later iterations
     asm volatile("" ::"v"(in.tc), "v"(in.tp), "v"(in.yc), "v"((int)in.oc));
     const OptInputs opt(p.mask, p.noise_k, p.t);
     for (int64_t k = k0; k < k1; k++) {
-        const int64_t kn = (k + 1 < k1) ? k + 1 : k;
+        // the last step of the lane loads the time of the next lane's first
+        // step, which its smoother element needs after the loop: no load
+        // after the loop waits behind the element stores
+        const int64_t kn = (k + 1 < tr.k_end) ? k + 1 : k;
         const double tn = p.t[kn];
         const T yn = p.y[kn];
         const bool on = opt.observed(kn);
@@ -511,7 +516,7 @@ __device__ __forceinline__ void filter_tile_finish(const FilterParams<T> &p, con
         if (k1 > k0) {
             sv.seek(k1 - 1);
             const bool end = (k1 >= tr.k_end) || sv.last(k1 - 1);
-            const double dt = end ? 0.0 : p.t[k1] - p.t[k1 - 1];
+            const double dt = end ? 0.0 : in.tc - in.tp;  // t[k1] - t[k1 - 1]
             cdouble *c = cst;
             PSSGP_LAUNDER(c);
             double Dl[D][D], Q[D][D], mp[D], Y[D][D], Pp[D][D];
