@@ -238,13 +238,11 @@ int launch_team_group_carry(const ScanWs &ws, int slot_base, int ntiles, hipStre
     return (int)hipGetLastError();
 }
 
-// Carry pass of a filter scan: the team scan for d = 8, where one lane's
-// general combination is longest (measured at 2^20 steps, chunk 16: 0.141
-// against 0.245 ms), when the workspace has the second aggregate buffer;
-// else the one-lane hierarchical scan of tile_scan.h (at d = 6 the team
-// combination is no shorter: about 2 900 instructions per lane, a quarter
-// of them DPP moves, against 3 200, and its ten levels took 0.104 against
-// 0.094 ms).
+// Carry pass of a filter scan: above 128 tiles in FP32 at d >= 6, the team
+// group scan (the general combination split over the rows of a team, all
+// the teams of a group in one workgroup); at d = 8 with fewer tiles, team
+// Hillis-Steele levels when the workspace has the second aggregate buffer;
+// else the one-lane hierarchical scan of tile_scan.h.
 template <int D, typename T, typename CT>
 int launch_filter_carry(const ScanWs &ws, int slot_base, int ntiles, hipStream_t s)
 {

@@ -312,3 +312,23 @@ def test_separate_calls_tuned_chunks(layout, chunk):
     assert g["status"] == (0, 0)
     check(compare(g, o, "float32", what=("f_mean", "f_var", "loglik", "mf", "Pf", "ms", "Ps")), "float32",
           "%s chunk=%d" % (layout, chunk))
+
+
+@pytest.mark.parametrize("layout,ntiles", [("rbf6", 129), ("rbf6", 300), ("rbf6", 4100), ("m32+rbf6", 200),
+                                           ("m32+rbf6", 300)])
+def test_filter_carry_group_levels(layout, ntiles):
+    """The FP32 filter carry at d >= 6 above 128 tiles scans the tile
+    aggregates on teams in groups of 32, then the group totals on teams (up
+    to 32 groups: 129, 200, 300 tiles) or in one lane (4 100 tiles, 129
+    groups). Chunk 4, the last tile ragged; the filter moments check the
+    carries directly."""
+    comps = {"rbf6": [(RBF, 6, 1.0, 1.0)], "m32+rbf6": [(MATERN32, 0, 2.0, 0.5), (RBF, 6, 0.5, 0.5)]}[layout]
+    chunk = 4
+    n = (ntiles - 1) * 64 * chunk + 77
+    w = workloads.random_series(n, comps, 0.01, missing=0.2, span=n / 200.0, gap="exponential", seed=ntiles)
+    print("carry levels", layout, "tiles", ntiles, "n", n, flush=True)
+    o = run_oracle(w, "float32", smoother=True, filter_moments=True)
+    g = run_gpu(w, "float32", options=P.make_options(chunk=chunk), full_state=False)
+    assert g["status"] == (0, 0)
+    check(compare(g, o, "float32", what=("f_mean", "f_var", "loglik", "mf", "Pf")), "float32",
+          "%s tiles=%d" % (layout, ntiles))
