@@ -146,8 +146,9 @@ struct StepInputs {
 // (F = 0, Q = Pinf), for which these give exactly the element (0, m, P).
 // e receives the element rounded to T, in the smoother's coordinates
 // z' = S z, S = I + e_0 e_B^T (smoother_shear_col; B = 0: identity).
-template <int D, int B, typename T>
-__device__ __forceinline__ void smoother_element_from_prediction(const T (&m)[D], const T (&P)[D][D],
+// (m, P) come in U (the filter carries them in FP64).
+template <int D, int B, typename T, typename U = T>
+__device__ __forceinline__ void smoother_element_from_prediction(const U (&m)[D], const U (&P)[D][D],
                                                                  double (&Y)[D][D], const double (&mp)[D],
                                                                  const double (&Pp)[D][D], SAgg<D, T> &e,
                                                                  uint32_t &bad)
@@ -225,7 +226,7 @@ __device__ __forceinline__ void hand_over_element(const SAgg<D, T> &e, T *out, S
     if constexpr (LANEAGG) sagg_combine<D, T>(acc, e, acc);
 }
 
-// Predicted moments of one step in FP64 from (m, P) in T and the FP64
+// Predicted moments of one step in FP64 from (m, P) (in T) and the FP64
 // transition Dl = F - I, Q: mp = m + Dl m, Y = F P = P + Dl P,
 // Pp = Y F^T + Q = Y + Y Dl^T + Q. FP64 keeps Pp consistent with P to
 // the precision the smoother element needs (its L is P minus a Gram matrix
@@ -365,8 +366,8 @@ __device__ __forceinline__ void filter_tile_finish(const FilterParams<T> &p, con
     SAgg<D, T> sacc;
     if constexpr (LANEAGG) sagg_identity<D, T>(sacc);
 
-    T m[D], P[D][D];
-    moments_load<D, T>(p.inclp + (size_t)slot * INCL, m, P);
+    T m0[D], P0[D][D];
+    moments_load<D, T>(p.inclp + (size_t)slot * INCL, m0, P0);
     // the first step's inputs are requested before the lane's entering
     // moments are formed, so that their latency overlaps that arithmetic
     StepInputs<T> in;
@@ -374,7 +375,17 @@ __device__ __forceinline__ void filter_tile_finish(const FilterParams<T> &p, con
     if (lane > 0) {
         FAgg<D, T> excl;
         agg_load<D, T>(lane_rec(p.lanep, slot, AGG, lane - 1), excl, PSSGP_WAVE);
-        moments_apply<D, T, CT>(m, P, excl, m, P);
+        moments_apply<D, T, CT>(m0, P0, excl, m0, P0);
+    }
+    // the lane carries its filter moments in FP64 from step to step: the
+    // prediction and the conditioning are FP64 anyway, and the moments in T
+    // would cost a conversion each way per step
+    double m[D], P[D][D];
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+        m[i] = (double)m0[i];
+#pragma unroll
+        for (int j = 0; j < D; j++) P[i][j] = (double)P0[i][j];
     }
 
     double ll = 0.0;  // FP64 per-lane sum of the log-likelihood terms
@@ -415,7 +426,7 @@ __device__ __forceinline__ void filter_tile_finish(const FilterParams<T> &p, con
         in.oc = on;
         // predict in FP64 (mp = F m, Y = F P, Pp = F P F^T + Q)
         double mp[D], Y[D][D], Pp[D][D];
-        predict_step<D, T, Sparsity<LY>>(m, P, Dl, Q, mp, Y, Pp);
+        predict_step<D, double, Sparsity<LY>>(m, P, Dl, Q, mp, Y, Pp);
         // the loads of this iteration are waited for here, before the
         // element stores: the wait counter is in order, so a wait after
         // the stores would also wait for all of them
@@ -424,14 +435,14 @@ __device__ __forceinline__ void filter_tile_finish(const FilterParams<T> &p, con
             // smoother element of the previous step of this lane
             if (k > k0) {
                 SAgg<D, T> e;
-                smoother_element_from_prediction<D, smoother_shear_col<LY>(), T>(m, P, Y, mp, Pp, e, bad);
+                smoother_element_from_prediction<D, smoother_shear_col<LY>(), T, double>(m, P, Y, mp, Pp, e, bad);
                 hand_over_element<D, T, LANEAGG>(e, p.m + elem_index<D>(slot, p.chunk, (int)(k - 1 - k0), lane),
                                                  sacc);
             }
         }
-        // conditioning on y_k in FP64 (symmetric form), from the predicted
-        // moments in T: the subtraction that cancels when the noise is
-        // small against the predicted variance is done in FP64
+        // conditioning on y_k in FP64 (symmetric form): the subtraction
+        // that cancels when the noise is small against the predicted
+        // variance is done in FP64
         double Ph[D], S = (double)R, hm = 0.0;
 #pragma unroll
         for (int i = 0; i < D; i++) {
@@ -492,22 +503,22 @@ __device__ __forceinline__ void filter_tile_finish(const FilterParams<T> &p, con
             __builtin_nontemporal_store(obs ? T(v) : T(0), rp + (2 * D + NS + 1) * W);
         }
 #pragma unroll
-        for (int i = 0; i < D; i++) m[i] = T(fma(K[i], v, mp[i]));
+        for (int i = 0; i < D; i++) m[i] = fma(K[i], v, mp[i]);
 #pragma unroll
         for (int i = 0; i < D; i++)
 #pragma unroll
             for (int j = i; j < D; j++) {
-                const T c = T(fma(S * K[i], K[j], fma(-Ph[i], K[j], fma(-K[i], Ph[j], Pp[i][j]))));
+                const double c = fma(S * K[i], K[j], fma(-Ph[i], K[j], fma(-K[i], Ph[j], Pp[i][j])));
                 P[i][j] = c;
                 P[j][i] = c;
             }
         if constexpr ((MODE & F_MOMENTS) != 0) {
 #pragma unroll
-            for (int i = 0; i < D; i++) p.m[(size_t)i * p.n + k] = m[i];
+            for (int i = 0; i < D; i++) p.m[(size_t)i * p.n + k] = T(m[i]);
 #pragma unroll
             for (int i = 0; i < D; i++)
 #pragma unroll
-                for (int j = i; j < D; j++) p.P[(size_t)sidx<D>(i, j) * p.n + k] = P[i][j];
+                for (int j = i; j < D; j++) p.P[(size_t)sidx<D>(i, j) * p.n + k] = T(P[i][j]);
         }
     }
     if constexpr ((MODE & F_ELEMS) != 0) {
@@ -521,9 +532,9 @@ __device__ __forceinline__ void filter_tile_finish(const FilterParams<T> &p, con
             PSSGP_LAUNDER(c);
             double Dl[D][D], Q[D][D], mp[D], Y[D][D], Pp[D][D];
             step_transition<LY, double, T>(mdl, c, sv.sc, dt, end, Dl, Q);
-            predict_step<D, T, Sparsity<LY>>(m, P, Dl, Q, mp, Y, Pp);
+            predict_step<D, double, Sparsity<LY>>(m, P, Dl, Q, mp, Y, Pp);
             SAgg<D, T> e;
-            smoother_element_from_prediction<D, smoother_shear_col<LY>(), T>(m, P, Y, mp, Pp, e, bad);
+            smoother_element_from_prediction<D, smoother_shear_col<LY>(), T, double>(m, P, Y, mp, Pp, e, bad);
             hand_over_element<D, T, LANEAGG>(e, p.m + elem_index<D>(slot, p.chunk, (int)(k1 - 1 - k0), lane),
                                              sacc);
         }
