@@ -251,7 +251,13 @@ int launch_bs(const BatchLaunch &a, void *const *ev, hipStream_t s)
     pass_event(ev, 0, s);
     if constexpr (sizeof(T) == 4 && !ELEMS)
         hipLaunchKernelGGL((batched_consts_kernel<LA, LB>), dim3(a.ngroups), dim3(256), 0, s, a);
-    hipLaunchKernelGGL((batched_smoother_kernel<LA, LB, T, false, ELEMS>), grid, block, 0, s, p, a);
+    if constexpr (ELEMS && lane_aggregate_handover<LA::D>() && lane_aggregate_handover<LB::D>()) {
+        // the filter's finish pass of the same call did the fold pass (lane
+        // records at slane, tile aggregates at aggp)
+        p.lanep = const_cast<T *>(p.slane);
+    } else {
+        hipLaunchKernelGGL((batched_smoother_kernel<LA, LB, T, false, ELEMS>), grid, block, 0, s, p, a);
+    }
     int rc = (int)hipGetLastError();
     if (rc) return rc;
     pass_event(ev, 1, s);

@@ -29,7 +29,7 @@ struct Plan {
     size_t off_gagg = 0, off_gcarry = 0;  // carry pass group scratch
     size_t off_hand = 0;             // predict: filter-to-smoother handover
     size_t off_fagg2 = 0;            // second buffer of filter tile aggregates (team carry)
-    size_t off_slane = 0;            // predict: per-lane smoother aggregates
+    size_t off_slane = 0;            // predict: the smoother's lane records
     size_t total = 0;
 };
 

@@ -54,7 +54,7 @@ struct FilterParams {
     T *inclp;
     T *lanep;
     double *partials;
-    T *slane;  // fused call: per-lane smoother aggregates (lane_aggregate_handover)
+    T *slane;  // fused call: the smoother's lane records, written by the finish (lane_aggregate_handover)
 };
 
 // Tile geometry: steps [k_begin, k_end) split into ntiles tiles; workspace
@@ -538,8 +538,21 @@ __device__ __forceinline__ void filter_tile_finish(const FilterParams<T> &p, con
             hand_over_element<D, T, LANEAGG>(e, p.m + elem_index<D>(slot, p.chunk, (int)(k1 - 1 - k0), lane),
                                              sacc);
         }
-        // the lane's smoother aggregate (identity for a lane without steps)
-        if constexpr (LANEAGG) sagg_store<D, T>(lane_rec(p.slane, slot, SAggLayout<D>::SIZE, lane), sacc, PSSGP_WAVE);
+        // the smoother's fold pass over this tile, done here: the wave scans
+        // the lanes' smoother aggregates (identity for a lane without steps)
+        // as suffixes (inclusive, reverse time order) into the lane records
+        // at slane, and lane 0 stores the tile aggregate in the scan region
+        // the two scans share (the filter's carry has consumed it)
+        if constexpr (LANEAGG) {
+            constexpr int SAGG = SAggLayout<D>::SIZE;
+            for (int o = 1; o < PSSGP_WAVE; o <<= 1) {
+                SAgg<D, T> other;
+                sagg_shfl_down<D, T>(sacc, other, o);
+                if (lane + o < PSSGP_WAVE) sagg_combine<D, T>(sacc, other, sacc);
+            }
+            sagg_store<D, T>(lane_rec(p.slane, slot, SAGG, lane), sacc, PSSGP_WAVE);
+            if (lane == 0) sagg_store<D, T>(p.aggp + (size_t)slot * SAGG, sacc);
+        }
     }
     if constexpr (SEG) {
         if (p.ll_terms && k1 > k0) p.ll_terms[seg_k] = seg;

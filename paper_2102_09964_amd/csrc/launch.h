@@ -49,7 +49,7 @@ struct FilterLaunch {
     double *loglik;  // nullable
     void *rec;       // nullable: per-step records of the adjoint (tile layout)
     int tiled;       // write smoother elements to m (P unused) in the tile layout of the handover
-    void *slane;     // tiled: per-lane smoother aggregates (lane_aggregate_handover)
+    void *slane;     // tiled: the smoother's lane records, written by the finish (lane_aggregate_handover)
     ScanWs ws;
 };
 
@@ -66,7 +66,7 @@ struct SmoothLaunch {
     void *ms;  // nullable
     void *Ps;  // nullable
     int tiled; // m holds the smoother elements in the tile layout (P unused)
-    const void *slane;  // tiled: per-lane smoother aggregates written by the filter
+    const void *slane;  // tiled: the smoother's lane records written by the filter's finish
     ScanWs ws;
 };
 
@@ -124,7 +124,7 @@ struct BatchLaunch {
     double *loglik;           // device [n_series]
     void *ll_terms;           // workspace [n]: log-likelihood partials at segment starts
     int tiled;                // m: smoother-element handover (filter then smoother in one call)
-    void *slane;              // tiled: per-lane smoother aggregates
+    void *slane;              // tiled: the smoother's lane records (written by the filter's finish)
     ScanWs ws;
 };
 

@@ -43,7 +43,7 @@ struct SmoothParams {
     T *inclp;
     T *lanep;
     const double *cst;  // model constants of the FP32 transition (ConstLayout)
-    const T *slane;     // fused call: per-lane aggregates from the filter
+    const T *slane;     // fused call: lane records written by the filter's finish
 };
 
 struct STileRange {
@@ -70,10 +70,8 @@ __device__ __forceinline__ void smoother_tile_fold(const SmoothParams<T> &p, con
     uint32_t bad = 0;  // reported by the finish pass
     SAgg<D, T> agg;
     sagg_identity<D, T>(agg);
-    if constexpr (ELEMS && lane_aggregate_handover<D>()) {
-        // the filter composed this lane's elements while building them
-        sagg_load<D, T>(lane_rec(p.slane, slot, AGG, lane), agg, PSSGP_WAVE);
-    } else {
+    // (a fused call with lane aggregates has its fold pass done by the
+    // filter's finish pass and does not launch this one)
     for (int64_t k = k1 - 1; k >= k0; k--) {
         PSSGP_RELOAD_CONSTANTS();
         sv.seek(k);
@@ -86,7 +84,6 @@ __device__ __forceinline__ void smoother_tile_fold(const SmoothParams<T> &p, con
             smoother_element<LY, T, SV>(mdl, c, sv, p.t, p.m + k, p.P + k, (size_t)p.n, k, e, bad);
         }
         sagg_combine<D, T>(e, agg, agg);
-    }
     }
     for (int o = 1; o < PSSGP_WAVE; o <<= 1) {
         SAgg<D, T> other;
@@ -217,7 +214,11 @@ int launch_smoother_t(const DevModel &mdl, const SmoothLaunch &a, hipStream_t s)
     p.slane = (const T *)a.slane;
     const dim3 grid(a.ntiles), block(PSSGP_WAVE);
     pass_event(a.ev, 0, s);
-    if (a.tiled) {
+    if (a.tiled && lane_aggregate_handover<LY::D>()) {
+        // the filter's finish pass of the same call did this pass (lane
+        // records at slane, tile aggregates at aggp)
+        p.lanep = const_cast<T *>(p.slane);
+    } else if (a.tiled) {
         // elements from the filter of the same call: no transition needed
         hipLaunchKernelGGL((smoother_fold_kernel<LY, T, true>), grid, block, 0, s, p, mdl);
     } else {

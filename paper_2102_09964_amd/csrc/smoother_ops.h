@@ -170,12 +170,13 @@ __device__ __forceinline__ size_t elem_index(int slot, int chunk, int j, int lan
     return ((size_t)slot * chunk + j) * (D * D + D + D * (D + 1) / 2) * 64 + lane;
 }
 
-// Whether the filter of a fused call also hands over, per lane, the
-// smoother aggregate of the lane's elements (accumulated while it builds
-// them), so that the smoother's fold pass reads one aggregate per lane
-// instead of every element. It costs the filter one FP32 smoother
-// combination per step and a working set of SIZE more values per lane,
-// which the register budget allows up to d = 6.
+// Whether the filter of a fused call also composes, per lane, the smoother
+// aggregate of the lane's elements while it builds them, and then does the
+// smoother's fold pass itself (the wave's suffix scan of those aggregates):
+// the smoother reads no element before its finish pass, and its fold
+// launch disappears. It costs the filter one FP32 smoother combination per
+// step and a working set of SIZE more values per lane, which the register
+// budget allows up to d = 6.
 #ifndef PSSGP_LANEAGG_MAXD
 #define PSSGP_LANEAGG_MAXD 6
 #endif
