@@ -76,8 +76,9 @@ def pass_costs(d, tsize, chunk):
     smoother operator and its application, and the lane scans (6 operator
     applications per lane and tile, i.e. per chunk of steps). Up to d = 6 the
     filter's finish pass also composes each lane's smoother elements into a
-    lane aggregate (one smoother operator per step) and the smoother's fold
-    pass reads those aggregates instead of the elements."""
+    lane aggregate (one smoother operator per step) and does the smoother's
+    fold pass itself (the lane scan of those aggregates, its records
+    written), so that pass has no launch of its own."""
     ns = d * (d + 1) // 2
     elem = tsize * (d * d + d + ns)                  # smoother element in the handover
     fagg = tsize * (d * d + 2 * d + 2 * ns) / chunk  # filter lane aggregate (A, b, C, eta, J)
@@ -96,8 +97,9 @@ def pass_costs(d, tsize, chunk):
         "filter_fold": (inputs + fagg, 2 * (disc + fold + 6 * combine / chunk)),
         "filter_carry": (0.0, 0.0),
         "filter_finish": (inputs + fagg + elem + (sagg if lane_agg else 0.0),
-                          2 * (disc + predict + cond + selem + (scomb if lane_agg else 0) + combine / chunk)),
-        "smoother_fold": ((2 * sagg, 2 * 6 * scomb / chunk) if lane_agg else
+                          2 * (disc + predict + cond + selem + (scomb + 6 * scomb / chunk if lane_agg else 0)
+                               + combine / chunk)),
+        "smoother_fold": ((0.0, 0.0) if lane_agg else
                           (elem + sagg, 2 * (scomb + 6 * scomb / chunk))),
         "smoother_carry": (0.0, 0.0),
         "smoother_finish": (elem + sagg + 2 * tsize, 2 * (sapply + sapply / chunk)),
