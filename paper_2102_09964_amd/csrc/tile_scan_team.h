@@ -238,18 +238,19 @@ int launch_team_group_carry(const ScanWs &ws, int slot_base, int ntiles, hipStre
     return (int)hipGetLastError();
 }
 
-// Carry pass of a filter scan: above 128 tiles in FP32 at d >= 6, the team
-// group scan (the general combination split over the rows of a team, all
-// the teams of a group in one workgroup); at d = 8 with fewer tiles, team
-// Hillis-Steele levels when the workspace has the second aggregate buffer;
-// else the one-lane hierarchical scan of tile_scan.h.
+// Carry pass of a filter scan. Above 128 tiles at d >= 6: the team group
+// scan (the general combination split over the rows of a team, all the
+// teams of a group in one workgroup), in FP64 at d = 6 only (at d = 8 the
+// FP64 group scan took 0.28 against 0.12 ms for the levels below). At d = 8
+// otherwise: team Hillis-Steele levels when the workspace has the second
+// aggregate buffer. Else the one-lane hierarchical scan of tile_scan.h.
 template <int D, typename T, typename CT>
 int launch_filter_carry(const ScanWs &ws, int slot_base, int ntiles, hipStream_t s)
 {
 #ifndef PSSGP_CARRY_PATH
 #define PSSGP_CARRY_PATH 1
 #endif
-    if constexpr (D >= 6 && sizeof(T) == 4 && PSSGP_CARRY_PATH == 1) {
+    if constexpr (D >= 6 && (sizeof(T) == 4 || D < 8) && PSSGP_CARRY_PATH == 1) {
         if (ntiles > 2 * PSSGP_WAVE) return launch_team_group_carry<D, T, CT>(ws, slot_base, ntiles, s);
     }
     if constexpr (D >= 8) {
