@@ -228,7 +228,11 @@ int launch_smoother_t(const DevModel &mdl, const SmoothLaunch &a, hipStream_t s)
     int rc = (int)hipGetLastError();
     if (rc) return rc;
     pass_event(a.ev, 1, s);
-    rc = launch_tile_scan<SmootherScanOps<LY::D, T>>(a.ws.aggp, 0, a.ntiles, true, a.ws.inclp, a.ws.gagg, a.ws.gcarry, s);
+    if constexpr (rows_smoother_carry<LY::D, T>())
+        rc = launch_smoother_rows_carry<LY::D, T>(a.ws.aggp, 0, a.ntiles, a.ws.inclp, a.ws.gagg, a.ws.gcarry, s);
+    else
+        rc = launch_tile_scan<SmootherScanOps<LY::D, T>>(a.ws.aggp, 0, a.ntiles, true, a.ws.inclp, a.ws.gagg,
+                                                         a.ws.gcarry, s);
     if (rc) return rc;
     pass_event(a.ev, 2, s);
     const size_t smem = (size_t)2 * PSSGP_WAVE * a.chunk * sizeof(T);

@@ -251,3 +251,167 @@ int launch_tile_scan(void *aggp, int slot_base, int ntiles, bool reverse, void *
                        (const T *)gcarry, slot_base, ntiles, reverse ? 1 : 0, (T *)carry);
     return (int)hipGetLastError();
 }
+
+// ------------------------------------------------------------------ smoother carry by rows
+//
+// The one-lane form above holds three smoother aggregates per lane; in FP64
+// at d >= 7 that is more than the register file, and the spills to scratch
+// memory made its two serial kernels take about 0.5 ms. Here the aggregates
+// of a group of 64 tiles sit in LDS (the stored layout: E row-major, g,
+// packed L, padded to an odd stride so that the eight aggregates one wave
+// reads at a time fall on distinct banks) and every combination
+//   E = E_x E_y,  g = E_x g_y + g_x,  L = E_x L_y E_x^T + L_x
+// (x the later aggregate in processing order, as in sagg_combine) runs on D
+// lanes, lane r forming row r of E, g[r] and the upper part of row r of L
+// from operands read out of LDS. Kogge-Stone levels are separated by
+// workgroup barriers. Level B scans up to 64 group totals the same way;
+// level C is tile_carry_kernel.
+#define PSSGP_ROWS_TG 64
+
+template <int D>
+struct RowsLayout {
+    static constexpr int SZ = SAggLayout<D>::SIZE;
+    static constexpr int ST = SZ | 1;  // LDS stride of one aggregate
+    static constexpr int G = D * D, L = D * D + D;
+};
+
+// Kogge-Stone over act aggregates in sh (processing order); thread (a, r)
+// owns row r of aggregate a. Every thread of the workgroup calls it.
+template <int D, typename T>
+__device__ __forceinline__ void rows_kogge_stone(T *sh, int a, int r, int act)
+{
+    using RL = RowsLayout<D>;
+    for (int o = 1; o < act; o <<= 1) {
+        const bool on = a >= o && a < act;
+        T nE[D], nL[D], ng = T(0);
+        if (on) {
+            const T *x = sh + a * RL::ST, *y = sh + (a - o) * RL::ST;
+            T xr[D], w[D];
+#pragma unroll
+            for (int k = 0; k < D; k++) xr[k] = x[r * D + k];
+            ng = x[RL::G + r];
+#pragma unroll
+            for (int c = 0; c < D; c++) {
+                nE[c] = T(0);
+                w[c] = T(0);
+            }
+#pragma unroll
+            for (int k = 0; k < D; k++) {
+                ng = fma(xr[k], y[RL::G + k], ng);
+#pragma unroll
+                for (int c = 0; c < D; c++) {
+                    nE[c] = fma(xr[k], y[k * D + c], nE[c]);
+                    w[c] = fma(xr[k], y[RL::L + sidx<D>(k, c)], w[c]);
+                }
+            }
+            // row r of (E_x L_y) E_x^T + L_x, upper part (c >= r)
+#pragma unroll
+            for (int c = 0; c < D; c++) {
+                T acc = T(0);
+                if (c >= r) {
+                    acc = x[RL::L + sidx<D>(r, c)];
+#pragma unroll
+                    for (int l = 0; l < D; l++) acc = fma(w[l], x[c * D + l], acc);
+                }
+                nL[c] = acc;
+            }
+        }
+        __syncthreads();
+        if (on) {
+            T *z = sh + a * RL::ST;
+#pragma unroll
+            for (int c = 0; c < D; c++) {
+                z[r * D + c] = nE[c];
+                if (c >= r) z[RL::L + sidx<D>(r, c)] = nL[c];
+            }
+            z[RL::G + r] = ng;
+        }
+        __syncthreads();
+    }
+}
+
+// Level A: the tiles of group blockIdx.x (processing order, slot as in
+// group_reduce_kernel) are replaced by their inclusive aggregates within the
+// group; gagg[group] receives the group total.
+template <int D, typename T>
+__global__ __launch_bounds__(PSSGP_ROWS_TG * 8) void rows_group_reduce(T *aggp, int slot_base, int ntiles, int reverse,
+                                                                      T *gagg)
+{
+    using RL = RowsLayout<D>;
+    __shared__ T sh[PSSGP_ROWS_TG * RL::ST];
+    const int tid = (int)threadIdx.x, nth = PSSGP_ROWS_TG * D;
+    const int i0 = (int)blockIdx.x * PSSGP_ROWS_TG;
+    const int act = min(ntiles - i0, PSSGP_ROWS_TG);
+    auto slot_of = [&](int i) { return slot_base + (reverse ? ntiles - 1 - i : i); };
+    for (int e = tid; e < act * RL::SZ; e += nth) {
+        const int q = e / RL::SZ, f = e - q * RL::SZ;
+        sh[q * RL::ST + f] = aggp[(size_t)slot_of(i0 + q) * RL::SZ + f];
+    }
+    __syncthreads();
+    rows_kogge_stone<D, T>(sh, tid / D, tid % D, act);
+    for (int e = tid; e < act * RL::SZ; e += nth) {
+        const int q = e / RL::SZ, f = e - q * RL::SZ;
+        aggp[(size_t)slot_of(i0 + q) * RL::SZ + f] = sh[q * RL::ST + f];
+    }
+    for (int f = tid; f < RL::SZ; f += nth) gagg[(size_t)blockIdx.x * RL::SZ + f] = sh[(act - 1) * RL::ST + f];
+}
+
+// Level B (ng <= 64 groups, one workgroup): gcarry[g] receives the moments
+// entering group g, the (g, L) of the inclusive aggregate of groups
+// 0 .. g - 1 (every prefix from the end of the series has E = 0); gcarry[0]
+// is zero.
+template <int D, typename T>
+__global__ __launch_bounds__(PSSGP_ROWS_TG * 8) void rows_group_scan(const T *gagg, int ng, T *gcarry)
+{
+    using RL = RowsLayout<D>;
+    constexpr int MOM = SAggLayout<D>::INCL;
+    __shared__ T sh[PSSGP_ROWS_TG * RL::ST];
+    const int tid = (int)threadIdx.x, nth = PSSGP_ROWS_TG * D;
+    for (int e = tid; e < ng * RL::SZ; e += nth) {
+        const int q = e / RL::SZ, f = e - q * RL::SZ;
+        sh[q * RL::ST + f] = gagg[(size_t)q * RL::SZ + f];
+    }
+    __syncthreads();
+    rows_kogge_stone<D, T>(sh, tid / D, tid % D, ng);
+    for (int e = tid; e < ng * MOM; e += nth) {
+        const int q = e / MOM, f = e - q * MOM;
+        gcarry[(size_t)q * MOM + f] = q == 0 ? T(0) : sh[(q - 1) * RL::ST + RL::G + f];
+    }
+}
+
+#ifndef PSSGP_ROWS_MIND
+#define PSSGP_ROWS_MIND 7
+#endif
+#ifndef PSSGP_ROWS_F32
+#define PSSGP_ROWS_F32 0
+#endif
+// Which smoother carries run by rows: FP64 at d >= 7.
+template <int D, typename T>
+constexpr bool rows_smoother_carry()
+{
+    return D >= PSSGP_ROWS_MIND && D <= 8 && (sizeof(T) == 8 || PSSGP_ROWS_F32);
+}
+
+// Smoother carries of tiles [slot_base, slot_base + ntiles) in reverse time
+// order by rows (levels A, B, C); aggp is overwritten, gagg and gcarry hold
+// ceil(ntiles / 64) group aggregates and moments. Above 64 groups level B is
+// the one-lane tile_scan_kernel over the group totals. Returns a hipError_t.
+template <int D, typename T>
+int launch_smoother_rows_carry(void *aggp, int slot_base, int ntiles, void *carry, void *gagg, void *gcarry,
+                               hipStream_t s)
+{
+    static_assert(D <= 8, "rows carry: at most 8 rows per aggregate");
+    if (ntiles <= 0) return 0;
+    const int ng = (ntiles + PSSGP_ROWS_TG - 1) / PSSGP_ROWS_TG;
+    hipLaunchKernelGGL((rows_group_reduce<D, T>), dim3(ng), dim3(PSSGP_ROWS_TG * D), 0, s, (T *)aggp, slot_base,
+                       ntiles, 1, (T *)gagg);
+    if (ng <= PSSGP_ROWS_TG)
+        hipLaunchKernelGGL((rows_group_scan<D, T>), dim3(1), dim3(PSSGP_ROWS_TG * D), 0, s, (const T *)gagg, ng,
+                           (T *)gcarry);
+    else
+        hipLaunchKernelGGL((tile_scan_kernel<SmootherScanOps<D, T>>), dim3(1), dim3(PSSGP_TS_THREADS), 0, s,
+                           (const T *)gagg, 0, ng, 0, (T *)gcarry);
+    hipLaunchKernelGGL((tile_carry_kernel<SmootherScanOps<D, T>, PSSGP_ROWS_TG>), dim3((ntiles + 255) / 256),
+                       dim3(256), 0, s, (const T *)aggp, (const T *)gcarry, slot_base, ntiles, 1, (T *)carry);
+    return (int)hipGetLastError();
+}

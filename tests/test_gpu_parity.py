@@ -332,3 +332,21 @@ def test_filter_carry_group_levels(layout, ntiles):
     assert g["status"] == (0, 0)
     check(compare(g, o, "float32", what=("f_mean", "f_var", "loglik", "mf", "Pf")), "float32",
           "%s tiles=%d" % (layout, ntiles))
+
+
+@pytest.mark.parametrize("ntiles,chunk", [(1, 4), (2, 4), (64, 4), (65, 4), (300, 4), (4100, 1)])
+def test_smoother_carry_rows(ntiles, chunk):
+    """The FP64 smoother carry at d = 8 combines the tile aggregates by rows
+    in LDS, in groups of 64 tiles, then the group totals the same way (up to
+    64 groups: 1 to 300 tiles) or in one lane (4 100 tiles, 65 groups). The
+    last tile ragged; the smoother moments check the carries directly."""
+    comps = [(MATERN32, 0, 2.0, 0.5), (RBF, 6, 0.5, 0.5)]
+    n = (ntiles - 1) * 64 * chunk + min(77, 64 * chunk - 3)
+    w = workloads.random_series(n, comps, 0.01, missing=0.2, span=n / 200.0, gap="exponential", seed=ntiles + 11)
+    print("smoother rows carry tiles", ntiles, "chunk", chunk, "n", n, flush=True)
+    full = ntiles <= 300
+    o = run_oracle(w, "float64", smoother=True, filter_moments=False)
+    g = run_gpu(w, "float64", options=P.make_options(chunk=chunk), full_state=full)
+    assert g["status"] == (0, 0)
+    check(compare(g, o, "float64", what=("f_mean", "f_var", "loglik") + (("ms", "Ps") if full else ())), "float64",
+          "tiles=%d" % ntiles)
