@@ -85,13 +85,18 @@ __device__ __forceinline__ void smoother_tile_fold(const SmoothParams<T> &p, con
         }
         sagg_combine<D, T>(e, agg, agg);
     }
-    for (int o = 1; o < PSSGP_WAVE; o <<= 1) {
-        SAgg<D, T> other;
-        sagg_shfl_down<D, T>(agg, other, o);
-        if (lane + o < PSSGP_WAVE) sagg_combine<D, T>(agg, other, agg);
+    if constexpr (smoother_by_rows<D, T>()) {
+        // the lane scan runs by rows (rows_lane_scan)
+        sagg_store<D, T>(lane_rec(p.lanep, slot, AGG, lane), agg, PSSGP_WAVE);
+    } else {
+        for (int o = 1; o < PSSGP_WAVE; o <<= 1) {
+            SAgg<D, T> other;
+            sagg_shfl_down<D, T>(agg, other, o);
+            if (lane + o < PSSGP_WAVE) sagg_combine<D, T>(agg, other, agg);
+        }
+        sagg_store<D, T>(lane_rec(p.lanep, slot, AGG, lane), agg, PSSGP_WAVE);
+        if (lane == 0) sagg_store<D, T>(p.aggp + (size_t)slot * AGG, agg);  // tile aggregate
     }
-    sagg_store<D, T>(lane_rec(p.lanep, slot, AGG, lane), agg, PSSGP_WAVE);
-    if (lane == 0) sagg_store<D, T>(p.aggp + (size_t)slot * AGG, agg);  // tile aggregate
 }
 
 // Finish pass of one tile: each lane takes the smoothed moments entering
@@ -225,10 +230,14 @@ int launch_smoother_t(const DevModel &mdl, const SmoothLaunch &a, hipStream_t s)
         if constexpr (sizeof(T) == 4) hipLaunchKernelGGL((consts_kernel<LY>), dim3(1), dim3(256), 0, s, mdl, a.ws.cst);
         hipLaunchKernelGGL((smoother_fold_kernel<LY, T, false>), grid, block, 0, s, p, mdl);
     }
+    if constexpr (smoother_by_rows<LY::D, T>()) {
+        if (!(a.tiled && lane_aggregate_handover<LY::D>()))
+            hipLaunchKernelGGL((rows_lane_scan<LY::D, T>), grid, dim3(PSSGP_WAVE * LY::D), 0, s, p.lanep, p.aggp, 0);
+    }
     int rc = (int)hipGetLastError();
     if (rc) return rc;
     pass_event(a.ev, 1, s);
-    if constexpr (rows_smoother_carry<LY::D, T>())
+    if constexpr (smoother_by_rows<LY::D, T>())
         rc = launch_smoother_rows_carry<LY::D, T>(a.ws.aggp, 0, a.ntiles, a.ws.inclp, a.ws.gagg, a.ws.gcarry, s);
     else
         rc = launch_tile_scan<SmootherScanOps<LY::D, T>>(a.ws.aggp, 0, a.ntiles, true, a.ws.inclp, a.ws.gagg,

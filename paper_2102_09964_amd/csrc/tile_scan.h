@@ -385,9 +385,10 @@ __global__ __launch_bounds__(PSSGP_ROWS_TG * 8) void rows_group_scan(const T *ga
 #ifndef PSSGP_ROWS_F32
 #define PSSGP_ROWS_F32 0
 #endif
-// Which smoother carries run by rows: FP64 at d >= 7.
+// Smoother scans whose lane scan (fold pass) and carry run by rows: FP64 at
+// d >= 7 (the batched layouts, d <= 3, never do).
 template <int D, typename T>
-constexpr bool rows_smoother_carry()
+constexpr bool smoother_by_rows()
 {
     return D >= PSSGP_ROWS_MIND && D <= 8 && (sizeof(T) == 8 || PSSGP_ROWS_F32);
 }
@@ -414,4 +415,30 @@ int launch_smoother_rows_carry(void *aggp, int slot_base, int ntiles, void *carr
     hipLaunchKernelGGL((tile_carry_kernel<SmootherScanOps<D, T>, PSSGP_ROWS_TG>), dim3((ntiles + 255) / 256),
                        dim3(256), 0, s, (const T *)aggp, (const T *)gcarry, slot_base, ntiles, 1, (T *)carry);
     return (int)hipGetLastError();
+}
+
+// Lane scan of the smoother's fold pass by rows (the scans of
+// smoother_by_rows): the fold stores each lane's own aggregate in its lane
+// record; one workgroup per tile scans the tile's 64 records as suffixes
+// (processing order from lane 63 down) in LDS, writes the inclusive records
+// back and the tile aggregate (lane 0's record) to aggp.
+template <int D, typename T>
+__global__ __launch_bounds__(PSSGP_WAVE * 8) void rows_lane_scan(T *lanep, T *aggp, int slot_base)
+{
+    using RL = RowsLayout<D>;
+    __shared__ T sh[PSSGP_WAVE * RL::ST];
+    const int tid = (int)threadIdx.x, nth = PSSGP_WAVE * D;
+    const size_t slot = (size_t)slot_base + blockIdx.x;
+    T *rec = lanep + slot * RL::SZ * PSSGP_WAVE;  // field f of lane l at rec[f * 64 + l]
+    for (int e = tid; e < PSSGP_WAVE * RL::SZ; e += nth) {
+        const int f = e / PSSGP_WAVE, l = e - f * PSSGP_WAVE;
+        sh[(PSSGP_WAVE - 1 - l) * RL::ST + f] = rec[e];
+    }
+    __syncthreads();
+    rows_kogge_stone<D, T>(sh, tid / D, tid % D, PSSGP_WAVE);
+    for (int e = tid; e < PSSGP_WAVE * RL::SZ; e += nth) {
+        const int f = e / PSSGP_WAVE, l = e - f * PSSGP_WAVE;
+        rec[e] = sh[(PSSGP_WAVE - 1 - l) * RL::ST + f];
+    }
+    for (int f = tid; f < RL::SZ; f += nth) aggp[slot * RL::SZ + f] = sh[(PSSGP_WAVE - 1) * RL::ST + f];
 }
