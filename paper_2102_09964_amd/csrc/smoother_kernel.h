@@ -77,7 +77,7 @@ __device__ __forceinline__ void smoother_tile_fold(const SmoothParams<T> &p, con
         sv.seek(k);
         SAgg<D, T> e;
         if constexpr (ELEMS) {
-            sagg_load<D, T>(p.m + elem_index<D>(slot, p.chunk, (int)(k - k0), lane), e, PSSGP_WAVE);
+            sagg_load_nt<D, T>(p.m + elem_index<D>(slot, p.chunk, (int)(k - k0), lane), e, PSSGP_WAVE);
         } else {
             cdouble *c = cst;
             PSSGP_LAUNDER(c);
@@ -135,7 +135,7 @@ __device__ __forceinline__ void smoother_tile_finish(const SmoothParams<T> &p, c
         sv.seek(k);
         SAgg<D, T> e;
         if constexpr (ELEMS) {
-            sagg_load<D, T>(p.m + elem_index<D>(slot, p.chunk, (int)(k - k0), lane), e, PSSGP_WAVE);
+            sagg_load_nt<D, T>(p.m + elem_index<D>(slot, p.chunk, (int)(k - k0), lane), e, PSSGP_WAVE);
         } else {
             cdouble *c = cst;
             PSSGP_LAUNDER(c);

@@ -137,6 +137,25 @@ __device__ __forceinline__ void sagg_load(const T *p, SAgg<D, T> &a, size_t st =
         for (int j = i; j < D; j++) { a.L[i][j] = p[(size_t)(D * D + D + sidx<D>(i, j)) * st]; a.L[j][i] = a.L[i][j]; }
 }
 
+// sagg_load with non-temporal loads: for the per-step handover, read once
+template <int D, typename T>
+__device__ __forceinline__ void sagg_load_nt(const T *p, SAgg<D, T> &a, size_t st)
+{
+#pragma unroll
+    for (int i = 0; i < D; i++)
+#pragma unroll
+        for (int j = 0; j < D; j++) a.E[i][j] = __builtin_nontemporal_load(p + (size_t)(i * D + j) * st);
+#pragma unroll
+    for (int i = 0; i < D; i++) a.g[i] = __builtin_nontemporal_load(p + (size_t)(D * D + i) * st);
+#pragma unroll
+    for (int i = 0; i < D; i++)
+#pragma unroll
+        for (int j = i; j < D; j++) {
+            a.L[i][j] = __builtin_nontemporal_load(p + (size_t)(D * D + D + sidx<D>(i, j)) * st);
+            a.L[j][i] = a.L[i][j];
+        }
+}
+
 template <int D, typename T>
 __device__ __forceinline__ void gl_store(T *p, const T (&g)[D], const T (&L)[D][D], size_t st = 1)
 {
