@@ -310,6 +310,22 @@ __device__ __forceinline__ void filter_tile_fold(const FilterParams<T> &p, const
         in.yc = yn;
         in.oc = on;
     }
+    if constexpr (sizeof(T) == 8 && D >= 7) {
+        // FP64 at d >= 7: the operator reads the predecessor's entries by
+        // shuffles where it uses them (agg_combine_lane); a shuffled copy of
+        // the whole aggregate spilled 3.3 KB per lane. (In FP32 the d = 8
+        // scan does not spill that way; there the first tile's FP64
+        // combinations of a series-start prefix made this form slower.)
+        for (int o = 1; o < PSSGP_WAVE; o <<= 1) {
+            const bool other_from_start = __shfl_up((int)from_start, o, PSSGP_WAVE) != 0;
+            const bool on = lane >= o;
+            agg_combine_lane<D, T, double>(agg, o, on);
+            from_start = from_start || (on && other_from_start);
+        }
+        agg_store<D, T>(lane_rec(p.lanep, slot, AGG, lane), agg, PSSGP_WAVE);
+        if (lane == PSSGP_WAVE - 1) agg_store<D, T>(p.aggp + (size_t)slot * AGG, agg);  // tile aggregate
+        return;
+    }
     for (int o = 1; o < PSSGP_WAVE; o <<= 1) {
         FAgg<D, T> other;
         agg_shfl_up<D, T>(agg, other, o);

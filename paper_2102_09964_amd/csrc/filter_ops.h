@@ -343,6 +343,180 @@ __device__ __forceinline__ void agg_shfl_up(const FAgg<D, T> &in, FAgg<D, T> &ou
     }
 }
 
+// y <- x (x) y for the fold's lane scan, x the aggregate of lane - o of the
+// same wave (the identity for lanes below o, which leaves y unchanged
+// exactly): the formulas of agg_combine with x's entries read by lane
+// shuffles where they are used instead of a shuffled copy of the whole
+// aggregate, so that a d = 8 combination fits the register file. Each output
+// field replaces y's only after the last shuffle of that field (every lane
+// reads its predecessor's old entries), the shuffle distance passing through
+// an empty asm statement at each step so that the compiler neither hoists
+// nor reuses the shuffles of an earlier step. A prefix x from the series
+// start (A = 0, eta = 0, J = 0 exactly) yields its conditioning by y with
+// A, eta and J zero. Every lane of the wave calls it.
+template <int D, typename T, typename CT>
+__device__ __forceinline__ void agg_combine_lane(FAgg<D, T> &y, int o, bool on)
+{
+    int ol = o;
+    auto step = [&]() { asm volatile("" : "+s"(ol)); };
+    auto xs = [&](T v, T id) -> CT {
+        const T sv = shfl_up_t(v, ol);
+        return CT(on ? sv : id);
+    };
+    CT M[D][D];
+    int piv[D];
+#pragma unroll
+    for (int i = 0; i < D; i++)
+#pragma unroll
+        for (int j = 0; j < D; j++) {
+            CT acc = (i == j) ? CT(1) : CT(0);
+#pragma unroll
+            for (int k = 0; k < D; k++) acc = fma(xs(y.C[i][k], T(0)), CT(y.J[k][j]), acc);
+            M[i][j] = acc;
+        }
+    step();
+    lu_factor<D, CT>(M, piv);
+    // vectors: u = eta_y - J_y b_x, z = M^-1 (b_x + C_x eta_y), w = M^-1 C_x u
+    CT u[D], z[D], w[D];
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+        CT cu = CT(y.eta[i]), cz = xs(y.b[i], T(0));
+#pragma unroll
+        for (int k = 0; k < D; k++) {
+            cu = fma(-CT(y.J[i][k]), xs(y.b[k], T(0)), cu);
+            cz = fma(xs(y.C[i][k], T(0)), CT(y.eta[k]), cz);
+        }
+        u[i] = cu;
+        z[i] = cz;
+    }
+    step();
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+        CT cw = CT(0);
+#pragma unroll
+        for (int k = 0; k < D; k++) cw = fma(xs(y.C[i][k], T(0)), u[k], cw);
+        w[i] = cw;
+    }
+    step();
+    lu_solve<D, CT>(M, piv, z);
+    lu_solve<D, CT>(M, piv, w);
+    T nb[D], ne[D];
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+        CT bb = CT(y.b[i]), ue = u[i];
+#pragma unroll
+        for (int k = 0; k < D; k++) {
+            bb = fma(CT(y.A[i][k]), z[k], bb);
+            ue = fma(-CT(y.J[i][k]), w[k], ue);
+        }
+        nb[i] = T(bb);
+        u[i] = ue;
+    }
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+        CT e = xs(y.eta[i], T(0));
+#pragma unroll
+        for (int k = 0; k < D; k++) e = fma(xs(y.A[k][i], (k == i) ? T(1) : T(0)), u[k], e);
+        ne[i] = T(e);
+    }
+    step();
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+        y.b[i] = nb[i];
+        y.eta[i] = ne[i];
+    }
+    // C = A_y (M^-1 C_x) A_y^T + C_y, M^-1 C_x symmetric (upper part kept)
+    CT Tm[D * (D + 1) / 2];
+#pragma unroll
+    for (int j = 0; j < D; j++) {
+        CT col[D];
+#pragma unroll
+        for (int i = 0; i < D; i++) col[i] = xs(y.C[i][j], T(0));
+        lu_solve<D, CT>(M, piv, col);
+#pragma unroll
+        for (int i = 0; i <= j; i++) Tm[sidx<D>(i, j)] = col[i];
+        step();
+    }
+    T nC[D][D];
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+        CT az[D];
+#pragma unroll
+        for (int j = 0; j < D; j++) {
+            CT acc = CT(0);
+#pragma unroll
+            for (int k = 0; k < D; k++) acc = fma(CT(y.A[i][k]), Tm[sidx<D>(k, j)], acc);
+            az[j] = acc;
+        }
+#pragma unroll
+        for (int j = i; j < D; j++) {
+            CT acc = CT(y.C[i][j]);
+#pragma unroll
+            for (int k = 0; k < D; k++) acc = fma(az[k], CT(y.A[j][k]), acc);
+            nC[i][j] = T(acc);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < D; i++)
+#pragma unroll
+        for (int j = i; j < D; j++) {
+            y.C[i][j] = nC[i][j];
+            y.C[j][i] = nC[i][j];
+        }
+    // J = A_x^T J_y (M^-1 A_x) + J_x, column by column
+    T nJ[D][D];
+#pragma unroll
+    for (int j = 0; j < D; j++) {
+        CT col[D], jz[D];
+#pragma unroll
+        for (int i = 0; i < D; i++) col[i] = xs(y.A[i][j], (i == j) ? T(1) : T(0));
+        lu_solve<D, CT>(M, piv, col);
+#pragma unroll
+        for (int i = 0; i < D; i++) {
+            CT acc = CT(0);
+#pragma unroll
+            for (int k = 0; k < D; k++) acc = fma(CT(y.J[i][k]), col[k], acc);
+            jz[i] = acc;
+        }
+#pragma unroll
+        for (int i = 0; i <= j; i++) {
+            CT acc = xs(y.J[i][j], T(0));
+#pragma unroll
+            for (int k = 0; k < D; k++) acc = fma(xs(y.A[k][i], (k == i) ? T(1) : T(0)), jz[k], acc);
+            nJ[i][j] = T(acc);
+        }
+        step();
+    }
+#pragma unroll
+    for (int i = 0; i < D; i++)
+#pragma unroll
+        for (int j = i; j < D; j++) {
+            y.J[i][j] = nJ[i][j];
+            y.J[j][i] = nJ[i][j];
+        }
+    // A = A_y (M^-1 A_x), column by column
+    T nA[D][D];
+#pragma unroll
+    for (int j = 0; j < D; j++) {
+        CT col[D];
+#pragma unroll
+        for (int i = 0; i < D; i++) col[i] = xs(y.A[i][j], (i == j) ? T(1) : T(0));
+        lu_solve<D, CT>(M, piv, col);
+#pragma unroll
+        for (int i = 0; i < D; i++) {
+            CT acc = CT(0);
+#pragma unroll
+            for (int k = 0; k < D; k++) acc = fma(CT(y.A[i][k]), col[k], acc);
+            nA[i][j] = T(acc);
+        }
+        step();
+    }
+#pragma unroll
+    for (int i = 0; i < D; i++)
+#pragma unroll
+        for (int j = 0; j < D; j++) y.A[i][j] = nA[i][j];
+}
+
 // Global-memory layout of a published aggregate: A (D*D), b (D), C packed
 // (NS), eta (D), J packed (NS).
 template <int D>
