@@ -102,6 +102,15 @@ __device__ __forceinline__ void smoother_tile_fold(const SmoothParams<T> &p, con
 // Finish pass of one tile: each lane takes the smoothed moments entering
 // the tile from the right (carry pass), applies its exclusive lane suffix
 // and runs the backward RTS recursion over its chunk.
+// Steps whose handed-over elements the smoother finish loads ahead of their
+// use, per group (small states only: their per-step work is short against a
+// load's latency).
+template <int D>
+constexpr int smoother_prefetch_group()
+{
+    return D <= 2 ? 4 : (D == 3 ? 2 : 1);
+}
+
 template <class LY, typename T, bool FULL, bool ELEMS, class SV>
 __device__ __forceinline__ void smoother_tile_finish(const SmoothParams<T> &p, const DevModel &mdl,
                                                      cdouble *cst, SV &sv, const STileRange &tr, int tile,
@@ -130,17 +139,8 @@ __device__ __forceinline__ void smoother_tile_finish(const SmoothParams<T> &p, c
         sagg_load<D, T>(lane_rec(p.lanep, slot, AGG, lane + 1), excl, PSSGP_WAVE);
         sagg_apply<D, T>(excl, ms, Ps, ms, Ps);
     }
-    for (int64_t k = k1 - 1; k >= k0; k--) {
-        PSSGP_RELOAD_CONSTANTS();
-        sv.seek(k);
-        SAgg<D, T> e;
-        if constexpr (ELEMS) {
-            sagg_load_nt<D, T>(p.m + elem_index<D>(slot, p.chunk, (int)(k - k0), lane), e, PSSGP_WAVE);
-        } else {
-            cdouble *c = cst;
-            PSSGP_LAUNDER(c);
-            smoother_element<LY, T, SV>(mdl, c, sv, p.t, p.m + k, p.P + k, (size_t)p.n, k, e, bad);
-        }
+    // one step of the backward recursion from its element
+    auto step_out = [&](const SAgg<D, T> &e, int64_t k) {
         sagg_apply<D, T>(e, ms, Ps, ms, Ps);
         T Ph[D];
         mat_vec<D, T>(Ps, h, Ph);
@@ -156,6 +156,50 @@ __device__ __forceinline__ void smoother_tile_finish(const SmoothParams<T> &p, c
             for (int i = 0; i < D; i++)
 #pragma unroll
                 for (int j = i; j < D; j++) p.Ps[(size_t)sidx<D>(i, j) * p.n + k] = Po[i][j];
+        }
+    };
+    // (single series only: in the batched form, chunk 16 over series of
+    // uneven lengths, the grouping measured 5 % slower)
+    constexpr int G = std::is_same<SV, OneSeries>::value ? smoother_prefetch_group<D>() : 1;
+    if constexpr (ELEMS && G > 1) {
+        // small states: the elements of the next G steps are loaded while
+        // the current G are processed (a lane's recursion is otherwise one
+        // dependent load per step); indices below k0 are clamped to k0, so
+        // every load is in the tile's region and none sits in a branch
+        auto load = [&](int64_t k, SAgg<D, T> &e) {
+            const int j = k >= k0 ? (int)(k - k0) : 0;
+            sagg_load_nt<D, T>(p.m + elem_index<D>(slot, p.chunk, j, lane), e, PSSGP_WAVE);
+        };
+        SAgg<D, T> cur[G], nxt[G];
+#pragma unroll
+        for (int g = 0; g < G; g++) load(k1 - 1 - g, cur[g]);
+        for (int64_t kb = k1 - 1; kb >= k0; kb -= G) {
+#pragma unroll
+            for (int g = 0; g < G; g++) load(kb - G - g, nxt[g]);
+#pragma unroll
+            for (int g = 0; g < G; g++) {
+                const int64_t k = kb - g;
+                if (k >= k0) {
+                    sv.seek(k);
+                    step_out(cur[g], k);
+                }
+            }
+#pragma unroll
+            for (int g = 0; g < G; g++) cur[g] = nxt[g];
+        }
+    } else {
+        for (int64_t k = k1 - 1; k >= k0; k--) {
+            PSSGP_RELOAD_CONSTANTS();
+            sv.seek(k);
+            SAgg<D, T> e;
+            if constexpr (ELEMS) {
+                sagg_load_nt<D, T>(p.m + elem_index<D>(slot, p.chunk, (int)(k - k0), lane), e, PSSGP_WAVE);
+            } else {
+                cdouble *c = cst;
+                PSSGP_LAUNDER(c);
+                smoother_element<LY, T, SV>(mdl, c, sv, p.t, p.m + k, p.P + k, (size_t)p.n, k, e, bad);
+            }
+            step_out(e, k);
         }
     }
     __syncthreads();
