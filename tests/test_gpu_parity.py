@@ -10,9 +10,10 @@ import numpy as np
 import pytest
 
 import workloads
-from oracle.model import MATERN12, MATERN32, MATERN52, RBF
+import oracle
+from oracle.model import MATERN12, MATERN32, MATERN52, RBF, OracleModel
 from tests.conftest import gpu_available
-from tests.parity import TOL, check, compare, rel, run_gpu, run_oracle
+from tests.parity import TOL, check, compare, oracle_inputs, rel, run_gpu, run_oracle
 
 pytestmark = pytest.mark.gpu
 
@@ -243,15 +244,16 @@ def test_fused_predict_vs_oracle(layout, dtype):
 
 
 @pytest.mark.parametrize("dtype", ["float64", "float32"])
-@pytest.mark.parametrize("layout", ["m52", "rbf6", "m32+rbf6"])
+@pytest.mark.parametrize("layout", ["m32", "m52", "rbf6", "m32+rbf6"])
 def test_fused_small_sizes_and_edge_cases(layout, dtype):
     """pssgp_predict at sizes around the tile and lane boundaries (one step,
     two steps, one lane short of a tile, a tile, one step past it), and with
     duplicated times and a long stretch of test points, against the oracle
     (FP32: on the FP32-rounded observations, with the FP32 bars), at the
     smallest chunk, the default and the largest. The d = 8 sum kernel takes
-    the path without lane aggregates."""
-    comps = {"m52": [(MATERN52, 0, 0.9, 1.2)], "rbf6": [(RBF, 6, 1.0, 1.0)],
+    the path without lane aggregates; at d = 2 and 3 the smoother finish
+    loads the elements of several steps ahead (ragged lanes clamp)."""
+    comps = {"m32": [(MATERN32, 0, 0.8, 1.1)], "m52": [(MATERN52, 0, 0.9, 1.2)], "rbf6": [(RBF, 6, 1.0, 1.0)],
              "m32+rbf6": [(MATERN32, 0, 2.0, 0.5), (RBF, 6, 0.5, 0.5)]}[layout]
     model = P.make_model(comps, 0.01)
     cases = [(n, "exponential", None) for n in (1, 2, 63, 64, 65, 1023, 1025)]
@@ -261,6 +263,11 @@ def test_fused_small_sizes_and_edge_cases(layout, dtype):
         if hole:
             w["mask"][hole[0]:hole[1]] = 0
         o = run_oracle(w, dtype, filter_moments=False)
+        # a log-likelihood whose per-step terms cancel (a few steps: sum of
+        # |terms| >= 10 |loglik|) is held relative to the sum of |terms|
+        terms = oracle.loglik_terms(OracleModel(comps, 0.01), w["t"], oracle_inputs(w, dtype), w["mask"])
+        tsum = float(np.sum(np.abs(terms)))
+        lscale = abs(o["loglik"]) if tsum < 10 * abs(o["loglik"]) else tsum
         if dtype == "float64":
             bars = {"f_mean": 1e-9, "f_var": 1e-9, "loglik": 1e-9}
         else:
@@ -273,7 +280,7 @@ def test_fused_small_sizes_and_edge_cases(layout, dtype):
             assert P.status(r["ws"]) == 0
             errs = {"f_mean": rel(r["f_mean"].double().cpu().numpy(), o["f_mean"]),
                     "f_var": rel(r["f_var"].double().cpu().numpy(), o["f_var"]),
-                    "loglik": abs(float(r["loglik"].cpu()[0]) - o["loglik"]) / max(abs(o["loglik"]), 1e-300)}
+                    "loglik": abs(float(r["loglik"].cpu()[0]) - o["loglik"]) / max(lscale, 1e-300)}
             print("  ", {k: "%.2e" % v for k, v in errs.items()}, flush=True)
             assert all(errs[k] <= bars[k] for k in bars), (n, gap, chunk, errs)
 
